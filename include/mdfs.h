@@ -1,0 +1,142 @@
+/*
+ * mdfs.h -- C ABI of the MI355X (gfx950) k-tuple information-gain sweep of MDFS
+ * ("MDFS - MultiDimensional Feature Selection", Piliszek, Mnich, Migacz, Tabaszewski, Sulecki,
+ * Polewko-Klim, Rudnicki).
+ *
+ * The library computes, for every variable x_i of an information system with N objects, p
+ * variables and a binary decision y,
+ *
+ *     IG^k_max(y; x_i) = N max_{m, r} ( H(y | x_m1..x_m(k-1)) - H(y | x_i, x_m1..x_m(k-1)) )
+ *
+ * (equation IGmax, section "Theory"), the maximum over every (k-1)-tuple m of other variables
+ * and over n_disc random discretisations r (section "Algorithm and implementation", the
+ * paragraphs on range/shares and on multiple discretisations), together with the tuple and the
+ * discretisation where it is attained (the optional tuple output of ComputeMaxInfoGains,
+ * section "Package functions introduction").  Entropies use pseudocounted class probabilities
+ * p^d = (N^d_v + beta^d) / (N^0_v + beta^0 + N^1_v + beta^1), beta^d = xi N^d / min(N^0, N^1)
+ * (the class-probability and pseudocount equations), natural logarithms, and voxel weights
+ * n_v / N.
+ *
+ * Conventions shared by every entry point
+ *   * Pointers named "device" are HIP device pointers on the current device; the caller owns
+ *     every buffer, including the workspace.  The library never allocates device memory.
+ *   * data   : float32, variable-major [n_var][n_obj] (R's column-major N x p matrix).
+ *   * y      : uint8 [n_obj], values in {0, 1}, both classes non-empty.
+ *   * codes  : uint8 [n_disc][n_var][n_obj], each in [0, divisions].
+ *   * stream : a hipStream_t passed as void*; NULL is the default stream.
+ *   * Argument errors are detected on the host before anything is enqueued and returned as a
+ *     negative mdfs_status; mdfs_last_error() then describes them (thread-local string).
+ *   * Calls that read the decision synchronise `stream` once at entry (to validate y and
+ *     size the launch) and once at exit (to check the device status word); all kernels run
+ *     on `stream`.
+ *   * Supported sizes: 2 <= n_obj <= 16384 and n_obj >= divisions+1; each class < 32768
+ *     objects; k in {2, 3}; divisions in {1, 2, 4} (2, 3 or 5 classes); n_disc >= 1;
+ *     disc_offset >= 0; for k = 3, n_var <= 4096.  Beyond these, MDFS_E_LIMIT.
+ */
+#ifndef MDFS_H
+#define MDFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MDFS_OK = 0,
+    MDFS_E_ARG = -1,     /* null pointer, bad size, range outside [0,1], xi < 0, ... */
+    MDFS_E_Y = -2,       /* y has a value outside {0,1}, or one class is empty */
+    MDFS_E_K = -3,       /* k not supported */
+    MDFS_E_DIV = -4,     /* divisions not supported */
+    MDFS_E_NAN = -5,     /* data holds a NaN */
+    MDFS_E_NOMEM = -6,   /* workspace smaller than mdfs_workspace_size() */
+    MDFS_E_HIP = -7,     /* a HIP runtime call failed */
+    MDFS_E_LIMIT = -8,   /* a size beyond the supported maximum */
+    MDFS_E_OVERFLOW = -9 /* candidate buffer overflow (pathological mass ties); results invalid */
+} mdfs_status;
+
+typedef enum {
+    MDFS_ENGINE_AUTO = 0,   /* k=2: int8 MFMA; k=3: bitset */
+    MDFS_ENGINE_MFMA = 1,   /* one-hot int8 contraction on the matrix cores */
+    MDFS_ENGINE_BITSET = 2  /* per-class bitsets, AND + popcount */
+} mdfs_engine;
+
+/* Problem description.  Fields follow the arguments of ComputeMaxInfoGains
+ * (section "Canonical package usage": dimensions, divisions, discretizations, range,
+ * pseudo.count, seed). */
+typedef struct {
+    int64_t n_obj;       /* N, objects */
+    int64_t n_var;       /* p, variables */
+    int32_t k;           /* dimensions: tuple size, 2 or 3 */
+    int32_t divisions;   /* classes per variable = divisions + 1 */
+    int32_t n_disc;      /* number of random discretisations */
+    int32_t disc_offset; /* index of the first discretisation (run r uses index disc_offset+r) */
+    double range;        /* share spread: shares ~ U(1-range, 1+range), 0 <= range <= 1 */
+    double pseudocount;  /* xi in beta^d = xi N^d / min(N^0,N^1); xi >= 0 */
+    uint64_t seed;       /* seed of the counter-based SplitMix64 draws of the shares */
+    int32_t engine;      /* mdfs_engine */
+    int32_t flags;       /* reserved, must be 0 */
+} mdfs_params;
+
+/* Bytes of device workspace that mdfs_discretize / mdfs_max_ig need for `prm` (0 when the
+ * parameters are invalid; mdfs_last_error() says why).  The workspace holds the class-sorted
+ * one-hot (or bitset) encoding of every discretisation, per-variable marginals, entropy
+ * lookup tables and the candidate buffer of the max reduction. */
+size_t mdfs_workspace_size(const mdfs_params *prm);
+
+/* Randomised rank-based discretisation (section "Algorithm and implementation": shares drawn
+ * from U(1-range, 1+range), divisions distinct cut positions, the variable sorted and the
+ * values at the cut positions used as thresholds).  For discretisation index
+ * q = disc_offset + r and variable v: shares s_j = (1-range) + 2 range u_j with u_j from
+ * SplitMix64 keyed by (seed, q, v, j); cut t_j = floor(N cum_j / S) clamped into [1, N-1] and
+ * made strictly increasing; threshold v_j = sort(x_v)[t_j]; code = #{j : x >= v_j}.
+ *   data  : device float32 [n_var][n_obj] (input)
+ *   codes : device uint8 [n_disc][n_var][n_obj] (output)
+ *   ws    : device workspace of at least mdfs_workspace_size(prm) bytes
+ * Returns MDFS_E_NAN if data holds a NaN (codes then undefined).  Synchronises `stream`. */
+int mdfs_discretize(const mdfs_params *prm, const float *data, uint8_t *codes, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* IG^k_max(y; x_i) for every variable (equation IGmax), maximised over all k-tuples and all
+ * n_disc discretisations, with the argmax.
+ *   data        : device float32 [n_var][n_obj] (input)
+ *   y           : device uint8 [n_obj] (input, decision)
+ *   ig_max      : device float32 [n_var] (output): the maximum IG, in nats, evaluated in
+ *                 binary64 for the maximising tuple and rounded to float32
+ *   argmax      : device int32 [n_var][k-1] (output, nullable): the other members of the
+ *                 maximising tuple, ascending variable indices
+ *   argmax_disc : device int32 [n_var] (output, nullable): absolute discretisation index
+ *                 (disc_offset + r) of the maximum
+ *   ws          : device workspace of at least mdfs_workspace_size(prm) bytes
+ * Ties: candidates within tau = 1e-9 max(1,|max|) of the maximum are tied; the smallest
+ * discretisation index wins, then the lexicographically smallest tuple.
+ * Synchronises `stream` at entry (reads y) and at exit (device status). */
+int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint8_t *y, float *ig_max,
+                int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream);
+
+/* Per-class voxel counts of every pair under one discretisation, as produced by the k=2 count
+ * engine (the counters N^d of section "Algorithm and implementation").  Requires k = 2 in
+ * `prm`; `disc` selects the discretisation (0 <= disc < n_disc).
+ *   counts : device int32 [n_var][n_var][2][c][c], c = divisions+1, class-major; entry
+ *            [i][j][d][a][b] counts objects of class d with code a in x_i and b in x_j; only
+ *            i < j is written (other entries untouched).
+ * For tests and inspection: O(p^2 c^2) output.  Synchronises `stream`. */
+int mdfs_pair_counts(const mdfs_params *prm, const float *data, const uint8_t *y, int32_t disc,
+                     int32_t *counts, void *ws, size_t ws_bytes, void *stream);
+
+/* The float32 screening maxima of the sweep before the binary64 re-score: for every variable
+ * the largest float32 IG over all tuples and discretisations, and the float32 error bound E
+ * that the re-score window is built from (|IG_f32 - IG| <= E for every tuple).
+ *   ig32 : device float32 [n_var] (output);  err_bound : host double* (output, nullable).
+ * Synchronises `stream`. */
+int mdfs_screen_max(const mdfs_params *prm, const float *data, const uint8_t *y, float *ig32,
+                    double *err_bound, void *ws, size_t ws_bytes, void *stream);
+
+/* Thread-local description of the last error returned on this thread ("" after success). */
+const char *mdfs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDFS_H */

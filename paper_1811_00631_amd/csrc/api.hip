@@ -1,0 +1,225 @@
+// api.hip -- the extern "C" entry points declared in include/mdfs.h.
+//
+// Host side only: argument validation, class sizes and pseudocounts (beta^d = xi N^d /
+// min(N^0, N^1), section "Algorithm and implementation"), the float32 screen error bound, the
+// workspace layout, and the launch sequence on the caller's stream.  All arithmetic of the
+// path runs in the kernels.
+#include "../../include/mdfs.h"
+#include "mdfs_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string>
+#include <vector>
+
+using namespace mdfs;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+static int hip_fail(hipError_t e, const char *what)
+{
+    return fail(MDFS_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char *mdfs_last_error(void) { return g_err.c_str(); }
+
+// Validate everything that does not need the data or the decision.
+static int check_params(const mdfs_params *prm)
+{
+    if (!prm) return fail(MDFS_E_ARG, "params is NULL");
+    if (prm->flags != 0) return fail(MDFS_E_ARG, "flags must be 0");
+    if (prm->k != 2 && prm->k != 3) return fail(MDFS_E_K, "k=%d: supported tuple sizes are 2 and 3", prm->k);
+    if (prm->divisions != 1 && prm->divisions != 2 && prm->divisions != 4)
+        return fail(MDFS_E_DIV, "divisions=%d: supported are 1, 2, 4", prm->divisions);
+    if (prm->divisions == 4)
+        return fail(MDFS_E_LIMIT, "divisions=4 (5 classes) is not built into this engine yet");
+    if (prm->n_obj < 2 || prm->n_obj < prm->divisions + 1)
+        return fail(MDFS_E_ARG, "n_obj=%lld too small for %d classes", (long long)prm->n_obj, prm->divisions + 1);
+    if (prm->n_obj > MAX_NOBJ) return fail(MDFS_E_LIMIT, "n_obj=%lld > %d", (long long)prm->n_obj, MAX_NOBJ);
+    if (prm->n_var < prm->k) return fail(MDFS_E_ARG, "n_var=%lld < k", (long long)prm->n_var);
+    if (prm->k == 3 && prm->n_var > MAX_K3_VARS)
+        return fail(MDFS_E_LIMIT, "k=3 with n_var=%lld > %d", (long long)prm->n_var, MAX_K3_VARS);
+    if (prm->k == 3) return fail(MDFS_E_LIMIT, "k=3 engine not built yet");
+    if (prm->n_disc < 1) return fail(MDFS_E_ARG, "n_disc=%d < 1", prm->n_disc);
+    if (prm->disc_offset < 0) return fail(MDFS_E_ARG, "disc_offset < 0");
+    if (!(prm->range >= 0.0 && prm->range <= 1.0)) return fail(MDFS_E_ARG, "range=%g outside [0,1]", prm->range);
+    if (!(prm->pseudocount >= 0.0) || !isfinite(prm->pseudocount))
+        return fail(MDFS_E_ARG, "pseudocount=%g must be finite and >= 0", prm->pseudocount);
+    if (prm->engine < 0 || prm->engine > 2) return fail(MDFS_E_ARG, "engine=%d", prm->engine);
+    return MDFS_OK;
+}
+
+static Layout layout_of(const mdfs_params *prm)
+{
+    return make_layout(prm->n_obj, prm->n_var, prm->k, prm->divisions, prm->n_disc);
+}
+
+extern "C" size_t mdfs_workspace_size(const mdfs_params *prm)
+{
+    if (check_params(prm) != MDFS_OK) return 0;
+    g_err.clear();
+    return layout_of(prm).total;
+}
+
+// Bound E on |IG_f32 - IG| of the float32 screen for a table of V voxels: rounding of the
+// lookup tables (|L|, |Q (A + B)|), one rounding per voxel term, V-1 accumulations, the
+// float32 F of the parent and the final subtraction; doubled for margin.  Sums are bounded by
+// sum_v n_v = N, sum of pseudocounts V*beta and F <= N ln 2.
+static double screen_err_bound(int64_t N, double b0, double b1, int V)
+{
+    const double u = ldexp(1.0, -24);
+    const double beta = b0 + b1;
+    const double lnN = fmax(1.0, log((double)N + beta + 3.0));
+    const double S_L = (double)N * lnN;
+    const double S_AB = ((double)N + V * beta) * lnN + V * 0.75;
+    const double S_t = (double)N * log(2.0);
+    return 2.0 * u * (S_L + 3.0 * S_AB + (V + 2) * S_t);
+}
+
+// Read and validate the decision, then fill in everything the launches need.
+static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_bytes, void *stream,
+                 Problem &P)
+{
+    P = Problem{};
+    P.L = layout_of(prm);
+    if (ws_bytes < P.L.total)
+        return fail(MDFS_E_NOMEM, "workspace %zu bytes < required %zu", ws_bytes, P.L.total);
+    P.ws = static_cast<char *>(ws);
+    P.stream = static_cast<hipStream_t>(stream);
+    P.disc_offset = prm->disc_offset;
+    P.range = prm->range;
+    P.seed = prm->seed;
+    const int64_t N = prm->n_obj;
+    if (y) {
+        std::vector<uint8_t> hy((size_t)N);
+        hipError_t e = hipMemcpyAsync(hy.data(), y, (size_t)N, hipMemcpyDeviceToHost, P.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(P.stream);
+        if (e != hipSuccess) return hip_fail(e, "reading y");
+        int64_t n1 = 0;
+        for (int64_t n = 0; n < N; ++n) {
+            if (hy[n] > 1) return fail(MDFS_E_Y, "y[%lld]=%d is not 0 or 1", (long long)n, (int)hy[n]);
+            n1 += hy[n];
+        }
+        const int64_t n0 = N - n1;
+        if (n0 == 0 || n1 == 0) return fail(MDFS_E_Y, "decision has a single class");
+        if (n0 > MAX_CLASS_OBJ || n1 > MAX_CLASS_OBJ)
+            return fail(MDFS_E_LIMIT, "class sizes %lld/%lld exceed %d", (long long)n0, (long long)n1, MAX_CLASS_OBJ);
+        P.N0 = (int)n0;
+        P.N1 = (int)n1;
+        const double m = (double)(n0 < n1 ? n0 : n1);
+        P.beta0 = prm->pseudocount * (double)n0 / m;
+        P.beta1 = prm->pseudocount * (double)n1 / m;
+        P.K0pad = (P.N0 + KBLK - 1) / KBLK * KBLK;
+        P.KB0 = P.K0pad / KBLK;
+        P.KB = P.KB0 + (P.N1 + KBLK - 1) / KBLK;
+        int V = 1;
+        for (int q = 0; q < prm->k; ++q) V *= prm->divisions + 1;
+        P.err_bound = screen_err_bound(N, P.beta0, P.beta1, V);
+    }
+    return MDFS_OK;
+}
+
+static int read_status(const Problem &P, Status &st)
+{
+    hipError_t e = hipMemcpyAsync(&st, P.ws + P.L.status, sizeof(Status), hipMemcpyDeviceToHost, P.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P.stream);
+    if (e != hipSuccess) return hip_fail(e, "reading status");
+    if (st.nan_flag) return fail(MDFS_E_NAN, "data holds a NaN");
+    return MDFS_OK;
+}
+
+#define LAUNCH(call)                                      \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+// discretise + encode + sweep, leaving the maxima and candidates in the workspace
+static int run_sweep(const Problem &P, const float *data, const uint8_t *y, int32_t *counts, int disc_sel)
+{
+    LAUNCH(launch_init(P));
+    LAUNCH(launch_class_perm(P, y));
+    LAUNCH(launch_tables(P));
+    LAUNCH(launch_discretize(P, data, nullptr, true));
+    LAUNCH(launch_sweep2(P, counts, disc_sel));
+    return MDFS_OK;
+}
+
+extern "C" int mdfs_discretize(const mdfs_params *prm, const float *data, uint8_t *codes, void *ws,
+                               size_t ws_bytes, void *stream)
+{
+    int rc = check_params(prm);
+    if (rc) return rc;
+    if (!data || !codes || !ws) return fail(MDFS_E_ARG, "null pointer");
+    Problem P;
+    if ((rc = setup(prm, nullptr, ws, ws_bytes, stream, P))) return rc;
+    LAUNCH(launch_init(P));
+    LAUNCH(launch_discretize(P, data, codes, false));
+    Status st;
+    if ((rc = read_status(P, st))) return rc;
+    g_err.clear();
+    return MDFS_OK;
+}
+
+extern "C" int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint8_t *y, float *ig_max,
+                           int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_params(prm);
+    if (rc) return rc;
+    if (!data || !y || !ig_max || !ws) return fail(MDFS_E_ARG, "null pointer");
+    Problem P;
+    if ((rc = setup(prm, y, ws, ws_bytes, stream, P))) return rc;
+    if ((rc = run_sweep(P, data, y, nullptr, -1))) return rc;
+    LAUNCH(launch_finalize(P, ig_max, argmax, argmax_disc));
+    Status st;
+    if ((rc = read_status(P, st))) return rc;
+    if (st.overflow) return fail(MDFS_E_OVERFLOW, "candidate buffer overflow (%u appends)", st.n_cand);
+    g_err.clear();
+    return MDFS_OK;
+}
+
+extern "C" int mdfs_pair_counts(const mdfs_params *prm, const float *data, const uint8_t *y, int32_t disc,
+                                int32_t *counts, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_params(prm);
+    if (rc) return rc;
+    if (prm->k != 2) return fail(MDFS_E_K, "pair counts need k=2");
+    if (!data || !y || !counts || !ws) return fail(MDFS_E_ARG, "null pointer");
+    if (disc < 0 || disc >= prm->n_disc) return fail(MDFS_E_ARG, "disc=%d outside [0,%d)", disc, prm->n_disc);
+    Problem P;
+    if ((rc = setup(prm, y, ws, ws_bytes, stream, P))) return rc;
+    if ((rc = run_sweep(P, data, y, counts, disc))) return rc;
+    Status st;
+    if ((rc = read_status(P, st))) return rc;
+    g_err.clear();
+    return MDFS_OK;
+}
+
+extern "C" int mdfs_screen_max(const mdfs_params *prm, const float *data, const uint8_t *y, float *ig32,
+                               double *err_bound, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_params(prm);
+    if (rc) return rc;
+    if (!data || !y || !ig32 || !ws) return fail(MDFS_E_ARG, "null pointer");
+    Problem P;
+    if ((rc = setup(prm, y, ws, ws_bytes, stream, P))) return rc;
+    if ((rc = run_sweep(P, data, y, nullptr, -1))) return rc;
+    LAUNCH(launch_screen_out(P, ig32));
+    Status st;
+    if ((rc = read_status(P, st))) return rc;
+    if (err_bound) *err_bound = P.err_bound;
+    g_err.clear();
+    return MDFS_OK;
+}

@@ -1,0 +1,106 @@
+// mdfs_internal.h -- declarations shared by the HIP sources of libmdfs (gfx950 only).
+//
+// Device memory layout of one problem inside the caller's workspace, the candidate record of
+// the max reduction, order-preserving integer keys for floating-point atomics, and the
+// launchers each .hip file exports to the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace mdfs {
+
+// Objects are permuted class-0-first; each class is padded to a whole K block of 64 objects.
+constexpr int KBLK = 64;
+// Output rows of one sweep tile (one-hot rows = variables x (classes-1) bins).
+constexpr int TILE_ROWS = 128;
+// Variables are padded to a multiple of this (covers every tile width).
+constexpr int VAR_PAD = 128;
+constexpr int MAX_NOBJ = 16384;
+constexpr int MAX_CLASS_OBJ = 32767;
+constexpr int MAX_K3_VARS = 4096;
+
+// Status words at the start of the workspace.
+struct Status {
+    uint32_t nan_flag;    // data held a NaN
+    uint32_t n_cand;      // candidate records appended (may exceed capacity)
+    uint32_t overflow;    // some append did not fit
+    uint32_t pad[61];
+};
+
+// One candidate of the max reduction: variable v reached ig32 with partner(s) under disc r.
+// For k = 2 `partner` is the other variable; for k = 3 it packs (m1 | m2 << 16), m1 < m2.
+struct Cand {
+    int32_t v;
+    int32_t r;
+    uint32_t partner;
+    float ig32;
+};
+
+// Byte offsets of every array inside the workspace (all 256-byte aligned).
+struct Layout {
+    // problem sizes
+    int64_t N, p, p_pad;
+    int k, C, W;          // classes C = divisions+1, one-hot width W = C-1
+    int R;
+    int KB_max;           // K blocks (64 objects) reserved: worst-case class padding
+    int64_t rows_pad;     // p_pad * W
+    int64_t cap;          // candidate capacity
+    int64_t words_max;    // bitset words (32 objects) per class, worst case (k=3)
+    // offsets
+    size_t status, pos, perm, tabEA, tabEB, tabLQ, marg, F1, onehot, G32, max64, keyw, ovf,
+        cand, ig64, bits, ptab, F2, total;
+};
+
+Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R);
+
+// Order-preserving maps from floats to unsigned integers (larger float -> larger key).
+__host__ __device__ inline uint32_t f32_key(float f)
+{
+    uint32_t b = __builtin_bit_cast(uint32_t, f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__host__ __device__ inline float key_f32(uint32_t k)
+{
+    uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __builtin_bit_cast(float, b);
+}
+__host__ __device__ inline uint64_t f64_key(double f)
+{
+    uint64_t b = __builtin_bit_cast(uint64_t, f);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __device__ inline double key_f64(uint64_t k)
+{
+    uint64_t b = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __builtin_bit_cast(double, b);
+}
+
+// Tie tolerance of the argmax: candidates within tau of the maximum are tied.
+__host__ __device__ inline double tie_tau(double m) { return 1e-9 * (fabs(m) > 1.0 ? fabs(m) : 1.0); }
+
+// Everything a launch sequence needs about one problem (sizes, pseudocounts, buffers).
+struct Problem {
+    Layout L;
+    int N0, N1, K0pad, KB0, KB;   // class sizes; class-0 padded size and K blocks
+    double beta0, beta1;
+    int disc_offset;
+    double range;
+    uint64_t seed;
+    double err_bound;             // float32 screen error bound E (per IG)
+    char *ws;
+    hipStream_t stream;
+    template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+};
+
+// ---- launchers (each returns hipSuccess or the launch error)
+hipError_t launch_init(const Problem &P);
+hipError_t launch_class_perm(const Problem &P, const uint8_t *y);
+hipError_t launch_tables(const Problem &P);
+hipError_t launch_discretize(const Problem &P, const float *data, uint8_t *codes, bool encode);
+hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel);
+hipError_t launch_finalize(const Problem &P, float *ig_max, int32_t *argmax, int32_t *argmax_disc);
+hipError_t launch_screen_out(const Problem &P, float *ig32);
+
+}  // namespace mdfs

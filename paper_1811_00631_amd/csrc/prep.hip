@@ -1,0 +1,369 @@
+// prep.hip -- everything before the tuple sweep: workspace layout, status/key initialisation,
+// class-sorted object order, entropy lookup tables and the discretise+encode kernel.
+//
+// Discretisation follows the paper's randomised rank-based scheme (section "Algorithm and
+// implementation", the paragraph on range and shares): per variable and discretisation,
+// `divisions+1` shares drawn from U(1-range, 1+range) fix `divisions` cut positions in the
+// sorted variable, and the values at those positions are the class thresholds.  Share and cut
+// arithmetic is binary64 with explicitly rounded operations (no contraction), so every
+// discretisation is reproducible bit for bit.
+#include "mdfs_internal.h"
+
+#include <math.h>
+
+namespace mdfs {
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
+{
+    Layout L{};
+    L.N = N;
+    L.p = p;
+    L.p_pad = (p + VAR_PAD - 1) / VAR_PAD * VAR_PAD;
+    L.k = k;
+    L.C = divisions + 1;
+    L.W = divisions;
+    L.R = R;
+    L.KB_max = (int)((N + KBLK - 1) / KBLK + 1);
+    L.rows_pad = L.p_pad * L.W;
+    L.cap = (p * 64 > (1 << 16)) ? p * 64 : (1 << 16);
+    L.words_max = (N + 31) / 32 + 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    L.status = take(sizeof(Status));
+    L.pos = take(sizeof(int32_t) * N);
+    L.perm = take(sizeof(int32_t) * (size_t)L.KB_max * KBLK);
+    L.tabEA = take(sizeof(float) * (N + 1));
+    L.tabEB = take(sizeof(float) * (N + 1));
+    L.tabLQ = take(sizeof(float) * 2 * (N + 1));
+    L.marg = take(sizeof(uint32_t) * (size_t)R * L.p_pad * L.C);
+    L.F1 = take(sizeof(float) * (size_t)R * L.p_pad);
+    L.onehot = take((size_t)R * L.KB_max * L.rows_pad * KBLK);
+    L.G32 = take(sizeof(uint32_t) * L.p_pad);
+    L.max64 = take(sizeof(uint64_t) * L.p_pad);
+    L.keyw = take(sizeof(uint64_t) * L.p_pad);
+    L.ovf = take(sizeof(uint32_t) * L.p_pad);
+    L.cand = take(sizeof(Cand) * L.cap);
+    L.ig64 = take(sizeof(double) * L.cap);
+    L.bits = L.ptab = L.F2 = o;
+    L.total = o;
+    return L;
+}
+
+// ------------------------------------------------------------------ init
+__global__ void k_init(Status *st, uint32_t *G32, uint64_t *max64, uint64_t *keyw, uint32_t *ovf,
+                       uint32_t *marg, float *F1, int64_t p_pad, int64_t n_marg)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (i < (int64_t)(sizeof(Status) / 4)) reinterpret_cast<uint32_t *>(st)[i] = 0;
+    for (int64_t v = i; v < p_pad; v += stride) {
+        G32[v] = 0x007fffffu; // key of -inf
+        max64[v] = 0ull;
+        keyw[v] = ~0ull;
+        ovf[v] = 0u;
+    }
+    for (int64_t j = i; j < n_marg; j += stride) marg[j] = 0u;
+    (void)F1;
+}
+
+hipError_t launch_init(const Problem &P)
+{
+    const Layout &L = P.L;
+    int64_t n_marg = (int64_t)L.R * L.p_pad * L.C;
+    int grid = (int)((L.p_pad + 255) / 256);
+    if (grid < 64) grid = 64;
+    hipLaunchKernelGGL(k_init, dim3(grid), dim3(256), 0, P.stream, P.at<Status>(L.status),
+                       P.at<uint32_t>(L.G32), P.at<uint64_t>(L.max64), P.at<uint64_t>(L.keyw),
+                       P.at<uint32_t>(L.ovf), P.at<uint32_t>(L.marg), P.at<float>(L.F1), L.p_pad, n_marg);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ class-sorted order
+// One workgroup: pos[n] = position of object n in the class-sorted order (class 0 first, each
+// class in original order, class 1 starting at K0pad); perm[position] = object or -1 (padding).
+__global__ __launch_bounds__(1024) void k_class_perm(const uint8_t *__restrict__ y, int N, int K0pad,
+                                                     int Kpad, int32_t *pos, int32_t *perm)
+{
+    __shared__ int s1[1024];
+    const int t = threadIdx.x, T = blockDim.x;
+    for (int i = t; i < Kpad; i += T) perm[i] = -1;
+    const int chunk = (N + T - 1) / T;
+    const int lo = t * chunk, hi = min(N, lo + chunk);
+    int ones = 0;
+    for (int n = lo; n < hi; ++n) ones += y[n] != 0;
+    s1[t] = ones;
+    __syncthreads();
+    // exclusive scan (Hillis-Steele on a copy is enough for 1024 entries)
+    for (int off = 1; off < T; off <<= 1) {
+        int v = (t >= off) ? s1[t - off] : 0;
+        __syncthreads();
+        s1[t] += v;
+        __syncthreads();
+    }
+    int ones_before = s1[t] - ones;
+    int zeros_before = (lo < N ? lo : N) - ones_before;
+    __syncthreads();
+    for (int n = lo; n < hi; ++n) {
+        int p;
+        if (y[n]) p = K0pad + ones_before++;
+        else p = zeros_before++;
+        pos[n] = p;
+        perm[p] = n;
+    }
+}
+
+hipError_t launch_class_perm(const Problem &P, const uint8_t *y)
+{
+    hipLaunchKernelGGL(k_class_perm, dim3(1), dim3(1024), 0, P.stream, y, (int)P.L.N, P.K0pad,
+                       P.KB * KBLK, P.at<int32_t>(P.L.pos), P.at<int32_t>(P.L.perm));
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ entropy tables
+// For one voxel with n0 objects of class 0, n1 of class 1 and n = n0 + n1, the pseudocounted
+// class probabilities are p^d = (n^d + beta^d) / (n + beta), beta = beta0 + beta1, and
+//     n h(p) = n ln(n + beta) - n/(n + beta) * [ E(n0 + beta0) + E(n1 + beta1) ],  E(x) = x ln x.
+// EA[n0] = E(n0 + beta0), EB[n1] = E(n1 + beta1), LQ[n] = (n ln(n + beta), n / (n + beta)).
+// Evaluated in binary64, stored as float32 (the float32 screen of the sweep).
+__device__ inline double xlogx(double x) { return x > 0.0 ? x * log(x) : 0.0; }
+
+__global__ void k_tables(int N, int N0, int N1, double b0, double b1, float *EA, float *EB, float2 *LQ)
+{
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n > N) return;
+    EA[n] = n <= N0 ? (float)xlogx(n + b0) : 0.0f;
+    EB[n] = n <= N1 ? (float)xlogx(n + b1) : 0.0f;
+    double s = n + b0 + b1;
+    LQ[n] = n > 0 ? make_float2((float)(n * log(s)), (float)(n / s)) : make_float2(0.f, 0.f);
+}
+
+hipError_t launch_tables(const Problem &P)
+{
+    int N = (int)P.L.N;
+    hipLaunchKernelGGL(k_tables, dim3((N + 256) / 256), dim3(256), 0, P.stream, N, P.N0, P.N1, P.beta0,
+                       P.beta1, P.at<float>(P.L.tabEA), P.at<float>(P.L.tabEB), P.at<float2>(P.L.tabLQ));
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ discretise + encode
+// SplitMix64 (Steele, Lea & Flood 2014): state advances by the golden gamma, output is the
+// variant-13 style finaliser.  The draw for (seed, disc, var, j) absorbs each key component
+// with one step whose state is the previous output plus (component + 1) * gamma.
+__device__ inline uint64_t sm64_fin(uint64_t z)
+{
+    z ^= z >> 30;
+    z *= 0xbf58476d1ce4e5b9ull;
+    z ^= z >> 27;
+    z *= 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+__device__ inline uint64_t share_bits(uint64_t seed, uint64_t disc, uint64_t var, uint64_t j)
+{
+    const uint64_t g = 0x9e3779b97f4a7c15ull;
+    uint64_t h = sm64_fin(seed + g);
+    h = sm64_fin(h + (disc + 1) * g);
+    h = sm64_fin(h + (var + 1) * g);
+    return sm64_fin(h + (j + 1) * g);
+}
+
+// Cut positions of one (discretisation, variable): c shares, cumulative sums, t_j =
+// floor(N cum_j / S) kept in [1, N-1], strictly increasing and leaving room for later classes.
+template <int C>
+__device__ void cut_positions(int N, double range, uint64_t seed, uint64_t disc, uint64_t var, int *t)
+{
+    double s[C];
+    const double lo = __dsub_rn(1.0, range), width = __dmul_rn(2.0, range);
+    for (int j = 0; j < C; ++j) {
+        double u = __dmul_rn((double)(share_bits(seed, disc, var, (uint64_t)j) >> 11), 0x1.0p-53);
+        s[j] = __dadd_rn(lo, __dmul_rn(width, u));
+    }
+    double S = 0.0;
+    for (int j = 0; j < C; ++j) S = __dadd_rn(S, s[j]);
+    double cum = 0.0;
+    int prev = 0;
+    for (int j = 1; j < C; ++j) {
+        cum = __dadd_rn(cum, s[j - 1]);
+        double qv = __ddiv_rn(__dmul_rn((double)N, cum), S);
+        int tj = (int)floor(qv);
+        tj = max(tj, 1);
+        tj = min(tj, N - 1);
+        if (j > 1) tj = max(tj, prev + 1);
+        tj = min(tj, N - (C - j));
+        t[j - 1] = tj;
+        prev = tj;
+    }
+}
+
+template <int C>
+__device__ inline int code_of(float x, const float *thr)
+{
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < C - 1; ++j) c += (x >= thr[j]) ? 1 : 0;
+    return c;
+}
+
+constexpr int DISC_THREADS = 512;
+constexpr int DISC_RCHUNK = 256;   // discretisations whose thresholds are staged at once
+
+// One workgroup per variable.  LDS: xcs[Kpad] (the variable in class-sorted order, for the
+// encodings), srt[M] (sorted copy, M = next power of two >= N), thresholds of a chunk of
+// discretisations.  Outputs (each optional): codes in original object order, one-hot rows in
+// class-sorted order, per-class marginal counts packed (n1 << 16 | n0), and F1 = N H(y|x).
+template <int C>
+__global__ __launch_bounds__(DISC_THREADS) void k_discretize(
+    const float *__restrict__ data, int N, int p, int M, int R, int disc_offset, double range,
+    uint64_t seed, const int32_t *__restrict__ perm, int K0pad, int N0, int N1, int KB,
+    int64_t rows_pad, uint8_t *__restrict__ codes, int8_t *__restrict__ onehot,
+    uint32_t *__restrict__ marg, float *__restrict__ F1, int64_t p_pad, double b0, double b1, Status *st)
+{
+    constexpr int W = C - 1;
+    extern __shared__ float lds[];
+    const int Kpad = KB * KBLK;
+    float *xcs = lds;                       // [Kpad]
+    float *srt = xcs + Kpad;                // [M]
+    float *thr = srt + M;                   // [DISC_RCHUNK][C-1]
+    __shared__ int hist[2][C];
+    const int v = blockIdx.x;
+    const int t = threadIdx.x;
+    const float *x = data + (int64_t)v * N;
+
+    bool bad = false;
+    for (int i = t; i < M; i += DISC_THREADS) {
+        float val = i < N ? x[i] : INFINITY;
+        bad |= (val != val);
+        srt[i] = val;
+    }
+    if (perm)
+        for (int i = t; i < Kpad; i += DISC_THREADS) {
+            int n = perm[i];
+            xcs[i] = n >= 0 ? x[n] : 0.0f;
+        }
+    if (bad) atomicOr(&st->nan_flag, 1u);
+    __syncthreads();
+
+    // bitonic sort of srt[0..M), ascending
+    for (int kk = 2; kk <= M; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = t; i < M; i += DISC_THREADS) {
+                int ixj = i ^ j;
+                if (ixj > i) {
+                    float a = srt[i], b = srt[ixj];
+                    bool up = (i & kk) == 0;
+                    if (up ? (a > b) : (a < b)) {
+                        srt[i] = b;
+                        srt[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    for (int rb = 0; rb < R; rb += DISC_RCHUNK) {
+        const int nr = min(DISC_RCHUNK, R - rb);
+        if (t < nr) {
+            int tc[C - 1];
+            cut_positions<C>(N, range, seed, (uint64_t)(disc_offset + rb + t), (uint64_t)v, tc);
+            for (int j = 0; j < C - 1; ++j) thr[t * (C - 1) + j] = srt[tc[j]];
+        }
+        __syncthreads();
+        for (int rr = 0; rr < nr; ++rr) {
+            const int r = rb + rr;
+            const float *th = thr + rr * (C - 1);
+            if (codes) {
+                uint8_t *out = codes + ((int64_t)r * p + v) * N;
+                for (int n = t; n < N; n += DISC_THREADS) out[n] = (uint8_t)code_of<C>(x[n], th);
+            }
+            if (onehot) {
+                // dword = 4 consecutive class-sorted positions of one (k block, bin) row chunk
+                const int ndw = KB * W * (KBLK / 4);
+                for (int idx = t; idx < ndw; idx += DISC_THREADS) {
+                    const int kb = idx / (W * (KBLK / 4));
+                    const int a = (idx / (KBLK / 4)) % W;
+                    const int q4 = idx % (KBLK / 4);
+                    uint32_t word = 0;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int ps = kb * KBLK + q4 * 4 + e;
+                        const bool valid = (ps < N0) || (ps >= K0pad && ps < K0pad + N1);
+                        const bool hit = valid && code_of<C>(xcs[ps], th) == a;
+                        word |= (hit ? 1u : 0u) << (8 * e);
+                    }
+                    int64_t row = (int64_t)v * W + a;
+                    int64_t off = (((int64_t)r * KB + kb) * rows_pad + row) * KBLK + q4 * 4;
+                    *reinterpret_cast<uint32_t *>(onehot + off) = word;
+                }
+            }
+            if (marg || F1) {
+                if (t < 2 * C) (&hist[0][0])[t] = 0;
+                __syncthreads();
+                int loc[2][C];
+                for (int a = 0; a < C; ++a) loc[0][a] = loc[1][a] = 0;
+                for (int ps = t; ps < Kpad; ps += DISC_THREADS) {
+                    const bool c0 = ps < N0, c1 = ps >= K0pad && ps < K0pad + N1;
+                    if (c0 | c1) {
+                        int cd = code_of<C>(xcs[ps], th);
+                        for (int a = 0; a < C; ++a) {
+                            loc[0][a] += (c0 && cd == a) ? 1 : 0;
+                            loc[1][a] += (c1 && cd == a) ? 1 : 0;
+                        }
+                    }
+                }
+                for (int a = 0; a < C; ++a) {
+                    if (loc[0][a]) atomicAdd(&hist[0][a], loc[0][a]);
+                    if (loc[1][a]) atomicAdd(&hist[1][a], loc[1][a]);
+                }
+                __syncthreads();
+                if (t == 0) {
+                    double Fv = 0.0;
+                    for (int a = 0; a < C; ++a) {
+                        double n0 = hist[0][a], n1 = hist[1][a], n = n0 + n1;
+                        if (marg) marg[((int64_t)r * p_pad + v) * C + a] = ((uint32_t)hist[1][a] << 16) | (uint32_t)hist[0][a];
+                        if (n > 0) {
+                            double s = n + b0 + b1;
+                            Fv += n * log(s) - (n / s) * (xlogx(n0 + b0) + xlogx(n1 + b1));
+                        }
+                    }
+                    if (F1) F1[(int64_t)r * p_pad + v] = (float)Fv;
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int C>
+static hipError_t disc_launch(const Problem &P, const float *data, uint8_t *codes, bool encode)
+{
+    const Layout &L = P.L;
+    int N = (int)L.N;
+    int M = 1;
+    while (M < N) M <<= 1;
+    int Kpad = P.KB * KBLK;
+    size_t lds = sizeof(float) * ((size_t)Kpad + M + DISC_RCHUNK * (C - 1));
+    auto kern = k_discretize<C>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)L.p), dim3(DISC_THREADS), lds, P.stream, data, N, (int)L.p, M,
+                       L.R, P.disc_offset, P.range, P.seed, encode ? P.at<int32_t>(L.perm) : nullptr, P.K0pad, P.N0, P.N1, P.KB,
+                       L.rows_pad, codes, encode ? P.at<int8_t>(L.onehot) : nullptr,
+                       encode ? P.at<uint32_t>(L.marg) : nullptr, encode ? P.at<float>(L.F1) : nullptr,
+                       L.p_pad, P.beta0, P.beta1, P.at<Status>(L.status));
+    return hipGetLastError();
+}
+
+hipError_t launch_discretize(const Problem &P, const float *data, uint8_t *codes, bool encode)
+{
+    switch (P.L.C) {
+    case 2: return disc_launch<2>(P, data, codes, encode);
+    case 3: return disc_launch<3>(P, data, codes, encode);
+    case 5: return disc_launch<5>(P, data, codes, encode);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mdfs

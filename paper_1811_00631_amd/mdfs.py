@@ -1,0 +1,184 @@
+"""Python binding of libmdfs (the C ABI in include/mdfs.h): argument marshalling only.
+
+Every step of the computation runs in the HIP kernels behind the C ABI; torch is used for
+device memory (inputs, outputs, the workspace) and for the current stream.  There is no CPU
+fallback: if libmdfs.so is missing, `load()` raises.
+
+Functions mirror the C entry points:
+    mdfs_workspace_size(...)            -> int
+    mdfs_discretize(data, ...)          -> codes uint8 [n_disc][n_var][n_obj]
+    mdfs_max_ig(data, y, ...)           -> (ig_max f32 [n_var], argmax i32 [n_var][k-1],
+                                            argmax_disc i32 [n_var])
+    mdfs_pair_counts(data, y, disc,...) -> counts i32 [n_var][n_var][2][c][c] (i < j filled)
+    mdfs_screen_max(data, y, ...)       -> (ig32 f32 [n_var], error bound E)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmdfs.so")
+
+MDFS_OK = 0
+STATUS = {0: "MDFS_OK", -1: "MDFS_E_ARG", -2: "MDFS_E_Y", -3: "MDFS_E_K", -4: "MDFS_E_DIV",
+          -5: "MDFS_E_NAN", -6: "MDFS_E_NOMEM", -7: "MDFS_E_HIP", -8: "MDFS_E_LIMIT",
+          -9: "MDFS_E_OVERFLOW"}
+ENGINES = {"auto": 0, "mfma": 1, "bitset": 2}
+
+
+class MdfsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_obj", ctypes.c_int64), ("n_var", ctypes.c_int64), ("k", ctypes.c_int32),
+                ("divisions", ctypes.c_int32), ("n_disc", ctypes.c_int32), ("disc_offset", ctypes.c_int32),
+                ("range", ctypes.c_double), ("pseudocount", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("engine", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+_lib = None
+SYMBOLS = ["mdfs_workspace_size", "mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts",
+           "mdfs_screen_max", "mdfs_last_error"]
+
+
+def load(path: str = LIB_PATH):
+    """Load libmdfs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_1811_00631_amd.build`")
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER(Params)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    L.mdfs_workspace_size.argtypes = [P]
+    L.mdfs_workspace_size.restype = sz
+    L.mdfs_discretize.argtypes = [P, vp, vp, vp, sz, vp]
+    L.mdfs_max_ig.argtypes = [P, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.mdfs_pair_counts.argtypes = [P, vp, vp, ctypes.c_int32, vp, vp, sz, vp]
+    L.mdfs_screen_max.argtypes = [P, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+    L.mdfs_last_error.restype = ctypes.c_char_p
+    for fn in ("mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts", "mdfs_screen_max"):
+        getattr(L, fn).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def make_params(n_obj, n_var, k=2, divisions=2, n_disc=1, disc_offset=0, range_=0.5, pseudocount=0.25,
+                seed=0, engine="auto") -> Params:
+    return Params(int(n_obj), int(n_var), int(k), int(divisions), int(n_disc), int(disc_offset),
+                  float(range_), float(pseudocount), int(seed) & ((1 << 64) - 1), ENGINES[engine], 0)
+
+
+def _check(rc: int):
+    if rc != MDFS_OK:
+        raise MdfsError(rc, load().mdfs_last_error().decode())
+
+
+def mdfs_workspace_size(prm: Params) -> int:
+    """Bytes of device workspace for `prm`; raises MdfsError on invalid parameters."""
+    n = load().mdfs_workspace_size(ctypes.byref(prm))
+    if n == 0:
+        raise MdfsError(-1, load().mdfs_last_error().decode())
+    return n
+
+
+class Workspace:
+    """Grow-only device workspace per device (owned by the caller side, as the C ABI asks)."""
+
+    def __init__(self):
+        self.buf = {}
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        key = torch.device(device).index or 0
+        b = self.buf.get(key)
+        if b is None or b.numel() < nbytes:
+            self.buf.pop(key, None)
+            b = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+            self.buf[key] = b
+        return b
+
+
+_WS = Workspace()
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_inputs(data: torch.Tensor, y: torch.Tensor | None = None):
+    if not (data.is_cuda and data.dtype == torch.float32 and data.dim() == 2):
+        raise ValueError("data must be a CUDA float32 tensor [n_var][n_obj]")
+    data = data.contiguous()
+    if y is not None:
+        if not (y.is_cuda and y.dtype == torch.uint8 and y.dim() == 1 and y.numel() == data.shape[1]):
+            raise ValueError("y must be a CUDA uint8 tensor [n_obj]")
+        y = y.contiguous()
+    return data, y
+
+
+def workspace_for(prm: Params, device) -> torch.Tensor:
+    return _WS.get(mdfs_workspace_size(prm), device)
+
+
+def mdfs_discretize(data: torch.Tensor, divisions: int, n_disc: int, range_: float = 0.5, seed: int = 0,
+                    disc_offset: int = 0, k: int = 2) -> torch.Tensor:
+    data, _ = _dev_inputs(data)
+    n_var, n_obj = data.shape
+    prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, 0.25, seed)
+    ws = workspace_for(prm, data.device)
+    codes = torch.empty((n_disc, n_var, n_obj), dtype=torch.uint8, device=data.device)
+    _check(load().mdfs_discretize(ctypes.byref(prm), _ptr(data), _ptr(codes), _ptr(ws), ws.numel(),
+                                  _stream(data.device)))
+    return codes
+
+
+def mdfs_max_ig(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_disc: int,
+                pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0, disc_offset: int = 0,
+                engine: str = "auto"):
+    data, y = _dev_inputs(data, y)
+    n_var, n_obj = data.shape
+    prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed, engine)
+    ws = workspace_for(prm, data.device)
+    ig = torch.empty(n_var, dtype=torch.float32, device=data.device)
+    am = torch.empty((n_var, k - 1), dtype=torch.int32, device=data.device)
+    ad = torch.empty(n_var, dtype=torch.int32, device=data.device)
+    _check(load().mdfs_max_ig(ctypes.byref(prm), _ptr(data), _ptr(y), _ptr(ig), _ptr(am), _ptr(ad), _ptr(ws),
+                              ws.numel(), _stream(data.device)))
+    return ig, am, ad
+
+
+def mdfs_pair_counts(data: torch.Tensor, y: torch.Tensor, disc: int, divisions: int, n_disc: int,
+                     range_: float = 0.5, seed: int = 0, disc_offset: int = 0) -> torch.Tensor:
+    data, y = _dev_inputs(data, y)
+    n_var, n_obj = data.shape
+    c = divisions + 1
+    prm = make_params(n_obj, n_var, 2, divisions, n_disc, disc_offset, range_, 0.25, seed)
+    ws = workspace_for(prm, data.device)
+    counts = torch.zeros((n_var, n_var, 2, c, c), dtype=torch.int32, device=data.device)
+    _check(load().mdfs_pair_counts(ctypes.byref(prm), _ptr(data), _ptr(y), int(disc), _ptr(counts), _ptr(ws),
+                                   ws.numel(), _stream(data.device)))
+    return counts
+
+
+def mdfs_screen_max(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_disc: int,
+                    pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0, disc_offset: int = 0):
+    data, y = _dev_inputs(data, y)
+    n_var, n_obj = data.shape
+    prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed)
+    ws = workspace_for(prm, data.device)
+    ig32 = torch.empty(n_var, dtype=torch.float32, device=data.device)
+    eb = ctypes.c_double(0.0)
+    _check(load().mdfs_screen_max(ctypes.byref(prm), _ptr(data), _ptr(y), _ptr(ig32), ctypes.byref(eb), _ptr(ws),
+                                  ws.numel(), _stream(data.device)))
+    return ig32, eb.value

@@ -1,0 +1,79 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point the header declares, and
+rejects invalid arguments before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1811_00631_amd import mdfs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mdfs.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mdfs_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mdfs.load()
+    syms = declared_symbols()
+    assert len(syms) >= 6
+    for s in syms:
+        assert hasattr(lib, s), f"{s} declared in include/mdfs.h but not exported"
+    assert sorted(mdfs.SYMBOLS) == syms
+
+
+def test_params_struct_matches_header():
+    # int64 n_obj, n_var; int32 k, divisions, n_disc, disc_offset; double range, pseudocount;
+    # uint64 seed; int32 engine, flags
+    assert ctypes.sizeof(mdfs.Params) == 64
+    assert mdfs.Params.range.offset == 32 and mdfs.Params.seed.offset == 48 and mdfs.Params.flags.offset == 60
+
+
+def test_workspace_size_valid_and_monotone():
+    a = mdfs.mdfs_workspace_size(mdfs.make_params(500, 100, 2, 2, 1))
+    b = mdfs.mdfs_workspace_size(mdfs.make_params(500, 100, 2, 2, 30))
+    c = mdfs.mdfs_workspace_size(mdfs.make_params(2000, 20000, 2, 2, 30))
+    assert 0 < a < b < c
+    # the headline problem fits comfortably in one MI355X (288 GB)
+    assert c < 8 << 30
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(k=4), -3), (dict(k=1), -3), (dict(divisions=3), -4), (dict(divisions=0), -4),
+    (dict(n_obj=2, divisions=2), -1), (dict(n_obj=20000), -8), (dict(range_=1.5), -1),
+    (dict(range_=-0.1), -1), (dict(pseudocount=-1.0), -1), (dict(n_disc=0), -1),
+    (dict(disc_offset=-1), -1), (dict(n_var=1), -1),
+])
+def test_invalid_params_rejected_on_host(kw, code):
+    base = dict(n_obj=100, n_var=10, k=2, divisions=2, n_disc=1, disc_offset=0, range_=0.5,
+                pseudocount=0.25, seed=0)
+    base.update(kw)
+    prm = mdfs.make_params(**base)
+    lib = mdfs.load()
+    assert lib.mdfs_workspace_size(ctypes.byref(prm)) == 0
+    assert lib.mdfs_last_error().decode() != ""
+    null = ctypes.c_void_p(0)
+    rc = lib.mdfs_max_ig(ctypes.byref(prm), null, null, null, null, null, null, 0, null)
+    assert rc == code, lib.mdfs_last_error()
+
+
+def test_null_pointers_rejected_on_host():
+    lib = mdfs.load()
+    prm = mdfs.make_params(100, 10, 2, 2, 1)
+    null = ctypes.c_void_p(0)
+    assert lib.mdfs_max_ig(ctypes.byref(prm), null, null, null, null, null, null, 0, null) == -1
+    assert lib.mdfs_discretize(ctypes.byref(prm), null, null, null, 0, null) == -1
+    assert lib.mdfs_max_ig(None, null, null, null, null, null, null, 0, null) == -1
+
+
+def test_small_workspace_rejected_on_host():
+    lib = mdfs.load()
+    prm = mdfs.make_params(100, 10, 2, 2, 1)
+    fake = ctypes.c_void_p(0x1000)
+    rc = lib.mdfs_discretize(ctypes.byref(prm), fake, fake, fake, 16, null := ctypes.c_void_p(0))
+    assert rc == -6 and "workspace" in lib.mdfs_last_error().decode()
