@@ -76,8 +76,13 @@ typedef struct {
     double pseudocount;  /* xi in beta^d = xi N^d / min(N^0,N^1); xi >= 0 */
     uint64_t seed;       /* seed of the counter-based SplitMix64 draws of the shares */
     int32_t engine;      /* mdfs_engine */
-    int32_t flags;       /* reserved, must be 0 */
+    int32_t flags;       /* bitwise OR of mdfs_flags; other bits must be 0 */
 } mdfs_params;
+
+typedef enum {
+    /* record HIP events on the call's stream around each phase; read with mdfs_phase_times */
+    MDFS_FLAG_TIMING = 1
+} mdfs_flags;
 
 /* Bytes of device workspace that mdfs_discretize / mdfs_max_ig need for `prm` (0 when the
  * parameters are invalid; mdfs_last_error() says why).  The workspace holds the class-sorted
@@ -132,6 +137,13 @@ int mdfs_pair_counts(const mdfs_params *prm, const float *data, const uint8_t *y
  * Synchronises `stream`. */
 int mdfs_screen_max(const mdfs_params *prm, const float *data, const uint8_t *y, float *ig32,
                     double *err_bound, void *ws, size_t ws_bytes, void *stream);
+
+/* Phase durations of the last call on this thread that ran with MDFS_FLAG_TIMING, measured
+ * with HIP events recorded on that call's stream: [0] setup (status, class order, entropy
+ * tables), [1] discretise + encode, [2] tuple sweep, [3] re-score and outputs.
+ *   ms : host float[n_max] (output, milliseconds).  Returns the number of phases written
+ *        (0 when no timed call has completed on this thread). */
+int mdfs_phase_times(float *ms, int n_max);
 
 /* Thread-local description of the last error returned on this thread ("" after success). */
 const char *mdfs_last_error(void);

@@ -10,6 +10,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string>
 #include <vector>
 
@@ -35,23 +36,64 @@ static int hip_fail(hipError_t e, const char *what)
 
 extern "C" const char *mdfs_last_error(void) { return g_err.c_str(); }
 
+// ---- optional per-phase timing with HIP events on the call's stream
+constexpr int N_PHASE = 4;
+static thread_local float g_phase_ms[N_PHASE];
+static thread_local int g_n_phase = 0;
+
+struct PhaseTimer {
+    hipEvent_t ev[N_PHASE + 1] = {};
+    bool on = false;
+    hipStream_t s = nullptr;
+    PhaseTimer(bool enable, hipStream_t stream) : on(enable), s(stream)
+    {
+        if (!on) return;
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) on = false;
+    }
+    void mark(int i)
+    {
+        if (on) (void)hipEventRecord(ev[i], s);
+    }
+    // after the stream has been synchronised
+    void publish()
+    {
+        if (!on) return;
+        for (int i = 0; i < N_PHASE; ++i)
+            if (hipEventElapsedTime(&g_phase_ms[i], ev[i], ev[i + 1]) != hipSuccess) g_phase_ms[i] = -1.f;
+        g_n_phase = N_PHASE;
+    }
+    ~PhaseTimer()
+    {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+extern "C" int mdfs_phase_times(float *ms, int n_max)
+{
+    int n = g_n_phase < n_max ? g_n_phase : n_max;
+    for (int i = 0; i < n; ++i) ms[i] = g_phase_ms[i];
+    return ms ? n : 0;
+}
+
 // Validate everything that does not need the data or the decision.
-static int check_params(const mdfs_params *prm)
+static int check_params(const mdfs_params *prm, bool sweep = true)
 {
     if (!prm) return fail(MDFS_E_ARG, "params is NULL");
-    if (prm->flags != 0) return fail(MDFS_E_ARG, "flags must be 0");
+    if (prm->flags & ~MDFS_FLAG_TIMING) return fail(MDFS_E_ARG, "unknown flag bits 0x%x", prm->flags);
     if (prm->k != 2 && prm->k != 3) return fail(MDFS_E_K, "k=%d: supported tuple sizes are 2 and 3", prm->k);
     if (prm->divisions != 1 && prm->divisions != 2 && prm->divisions != 4)
         return fail(MDFS_E_DIV, "divisions=%d: supported are 1, 2, 4", prm->divisions);
-    if (prm->divisions == 4)
-        return fail(MDFS_E_LIMIT, "divisions=4 (5 classes) is not built into this engine yet");
+    if (sweep && prm->divisions == 4)
+        return fail(MDFS_E_LIMIT, "divisions=4 (5 classes) is not built into the sweep yet");
     if (prm->n_obj < 2 || prm->n_obj < prm->divisions + 1)
         return fail(MDFS_E_ARG, "n_obj=%lld too small for %d classes", (long long)prm->n_obj, prm->divisions + 1);
     if (prm->n_obj > MAX_NOBJ) return fail(MDFS_E_LIMIT, "n_obj=%lld > %d", (long long)prm->n_obj, MAX_NOBJ);
     if (prm->n_var < prm->k) return fail(MDFS_E_ARG, "n_var=%lld < k", (long long)prm->n_var);
     if (prm->k == 3 && prm->n_var > MAX_K3_VARS)
         return fail(MDFS_E_LIMIT, "k=3 with n_var=%lld > %d", (long long)prm->n_var, MAX_K3_VARS);
-    if (prm->k == 3) return fail(MDFS_E_LIMIT, "k=3 engine not built yet");
+    if (sweep && prm->k == 3) return fail(MDFS_E_LIMIT, "k=3 engine not built yet");
     if (prm->n_disc < 1) return fail(MDFS_E_ARG, "n_disc=%d < 1", prm->n_disc);
     if (prm->disc_offset < 0) return fail(MDFS_E_ARG, "disc_offset < 0");
     if (!(prm->range >= 0.0 && prm->range <= 1.0)) return fail(MDFS_E_ARG, "range=%g outside [0,1]", prm->range);
@@ -68,7 +110,7 @@ static Layout layout_of(const mdfs_params *prm)
 
 extern "C" size_t mdfs_workspace_size(const mdfs_params *prm)
 {
-    if (check_params(prm) != MDFS_OK) return 0;
+    if (check_params(prm, false) != MDFS_OK) return 0;
     g_err.clear();
     return layout_of(prm).total;
 }
@@ -98,6 +140,11 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
         return fail(MDFS_E_NOMEM, "workspace %zu bytes < required %zu", ws_bytes, P.L.total);
     P.ws = static_cast<char *>(ws);
     P.stream = static_cast<hipStream_t>(stream);
+    // test hook: a smaller candidate capacity exercises the overflow -> collect-pass path
+    if (const char *cap = getenv("MDFS_TEST_CAP")) {
+        long long c = atoll(cap);
+        if (c > 0 && c < P.L.cap) P.L.cap = c;
+    }
     P.disc_offset = prm->disc_offset;
     P.range = prm->range;
     P.seed = prm->seed;
@@ -131,6 +178,12 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
     return MDFS_OK;
 }
 
+#define LAUNCH(call)                                      \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
 static int read_status(const Problem &P, Status &st)
 {
     hipError_t e = hipMemcpyAsync(&st, P.ws + P.L.status, sizeof(Status), hipMemcpyDeviceToHost, P.stream);
@@ -140,27 +193,38 @@ static int read_status(const Problem &P, Status &st)
     return MDFS_OK;
 }
 
-#define LAUNCH(call)                                      \
-    do {                                                  \
-        hipError_t e_ = (call);                           \
-        if (e_ != hipSuccess) return hip_fail(e_, #call); \
-    } while (0)
-
 // discretise + encode + sweep, leaving the maxima and candidates in the workspace
-static int run_sweep(const Problem &P, const float *data, const uint8_t *y, int32_t *counts, int disc_sel)
+static int run_sweep(const Problem &P, const float *data, const uint8_t *y, int32_t *counts, int disc_sel,
+                     PhaseTimer *tm = nullptr)
 {
+    if (tm) tm->mark(0);
     LAUNCH(launch_init(P));
     LAUNCH(launch_class_perm(P, y));
     LAUNCH(launch_tables(P));
+    if (tm) tm->mark(1);
     LAUNCH(launch_discretize(P, data, nullptr, true));
+    if (tm) tm->mark(2);
+    LAUNCH(launch_reset_queue(P));
     LAUNCH(launch_sweep2(P, counts, disc_sel));
+    // If the opportunistic candidate appends overflowed, sweep again with the final float32
+    // maxima as fixed thresholds: that pass appends exactly the (tuple, discretisation) pairs
+    // within the re-score window.
+    Status st;
+    int rc = read_status(P, st);
+    if (rc) return rc;
+    if (st.overflow) {
+        LAUNCH(launch_reset_candidates(P));
+        LAUNCH(launch_reset_queue(P));
+        LAUNCH(launch_sweep2(P, nullptr, -1, true));
+    }
+    if (tm) tm->mark(3);
     return MDFS_OK;
 }
 
 extern "C" int mdfs_discretize(const mdfs_params *prm, const float *data, uint8_t *codes, void *ws,
                                size_t ws_bytes, void *stream)
 {
-    int rc = check_params(prm);
+    int rc = check_params(prm, false);
     if (rc) return rc;
     if (!data || !codes || !ws) return fail(MDFS_E_ARG, "null pointer");
     Problem P;
@@ -181,10 +245,13 @@ extern "C" int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint
     if (!data || !y || !ig_max || !ws) return fail(MDFS_E_ARG, "null pointer");
     Problem P;
     if ((rc = setup(prm, y, ws, ws_bytes, stream, P))) return rc;
-    if ((rc = run_sweep(P, data, y, nullptr, -1))) return rc;
+    PhaseTimer tm((prm->flags & MDFS_FLAG_TIMING) != 0, P.stream);
+    if ((rc = run_sweep(P, data, y, nullptr, -1, &tm))) return rc;
     LAUNCH(launch_finalize(P, ig_max, argmax, argmax_disc));
+    tm.mark(4);
     Status st;
     if ((rc = read_status(P, st))) return rc;
+    tm.publish();
     if (st.overflow) return fail(MDFS_E_OVERFLOW, "candidate buffer overflow (%u appends)", st.n_cand);
     g_err.clear();
     return MDFS_OK;

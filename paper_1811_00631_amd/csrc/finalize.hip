@@ -38,12 +38,13 @@ __device__ inline int wave_sum(int x)
 // Code of variable v at class-sorted position `lane` of one K block, read back from its
 // one-hot rows (the last bin has no row: none of the W rows set).
 template <int W>
-__device__ inline int code_from_onehot(const int8_t *blk, int64_t v, int lane)
+__device__ inline int code_from_onehot(const int8_t *onehot, int r, int kb, int KB, int64_t rows_pad, int64_t v,
+                                       int lane)
 {
     int c = W;
 #pragma unroll
     for (int a = W - 1; a >= 0; --a)
-        if (blk[(v * W + a) * KBLK + lane]) c = a;
+        if (onehot[onehot_off(r, v * W + a, kb, lane, KB, rows_pad)]) c = a;
     return c;
 }
 
@@ -87,14 +88,13 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a)
         for (int d = 0; d < 2; ++d)
 #pragma unroll
             for (int c = 0; c < NC; ++c) cnt[d][c] = 0;
-        const int8_t *base = a.onehot + (int64_t)x.r * a.KB * a.rows_pad * KBLK;
         for (int kb = 0; kb < a.KB; ++kb) {
-            const int8_t *blk = base + (int64_t)kb * a.rows_pad * KBLK;
             const int ps = kb * KBLK + lane;
             const bool c0 = kb < a.KB0;
             const bool valid = c0 ? (ps < a.N0) : (ps - a.K0pad < a.N1);
-            int cell = code_from_onehot<W>(blk, x.v, lane) * C + code_from_onehot<W>(blk, m1, lane);
-            if (K == 3) cell = cell * C + code_from_onehot<W>(blk, m2, lane);
+            int cell = code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, x.v, lane) * C +
+                       code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, m1, lane);
+            if (K == 3) cell = cell * C + code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, m2, lane);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 cnt[0][c] += (valid && c0 && cell == c) ? 1 : 0;

@@ -26,7 +26,9 @@ struct Status {
     uint32_t nan_flag;    // data held a NaN
     uint32_t n_cand;      // candidate records appended (may exceed capacity)
     uint32_t overflow;    // some append did not fit
-    uint32_t pad[61];
+    uint32_t pad0[13];
+    uint32_t next_tile[16];   // per-XCD work counters of the persistent sweep (reset per pass)
+    uint32_t pad[32];
 };
 
 // One candidate of the max reduction: variable v reached ig32 with partner(s) under disc r.
@@ -54,6 +56,15 @@ struct Layout {
 };
 
 Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R);
+
+// Byte offset of (discretisation r, one-hot row, K block kb, object byte) in the panel-major
+// one-hot encoding [r][row / TILE_ROWS][kb][row % TILE_ROWS][KBLK]: the rows of one sweep
+// panel are contiguous over all K blocks, so a tile streams one contiguous run per operand.
+__host__ __device__ inline int64_t onehot_off(int r, int64_t row, int kb, int byte, int KB, int64_t rows_pad)
+{
+    const int64_t nrb = rows_pad / TILE_ROWS;
+    return ((((int64_t)r * nrb + row / TILE_ROWS) * KB + kb) * TILE_ROWS + row % TILE_ROWS) * KBLK + byte;
+}
 
 // Order-preserving maps from floats to unsigned integers (larger float -> larger key).
 __host__ __device__ inline uint32_t f32_key(float f)
@@ -99,7 +110,9 @@ hipError_t launch_init(const Problem &P);
 hipError_t launch_class_perm(const Problem &P, const uint8_t *y);
 hipError_t launch_tables(const Problem &P);
 hipError_t launch_discretize(const Problem &P, const float *data, uint8_t *codes, bool encode);
-hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel);
+hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bool collect = false);
+hipError_t launch_reset_candidates(const Problem &P);
+hipError_t launch_reset_queue(const Problem &P);
 hipError_t launch_finalize(const Problem &P, float *ig_max, int32_t *argmax, int32_t *argmax_disc);
 hipError_t launch_screen_out(const Problem &P, float *ig32);
 

@@ -27,7 +27,7 @@ Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
     L.R = R;
     L.KB_max = (int)((N + KBLK - 1) / KBLK + 1);
     L.rows_pad = L.p_pad * L.W;
-    L.cap = (p * 64 > (1 << 16)) ? p * 64 : (1 << 16);
+    L.cap = (p * 256 > (1 << 20)) ? p * 256 : (1 << 20);
     L.words_max = (N + 31) / 32 + 1;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
@@ -66,6 +66,32 @@ __global__ void k_init(Status *st, uint32_t *G32, uint64_t *max64, uint64_t *key
     }
     for (int64_t j = i; j < n_marg; j += stride) marg[j] = 0u;
     (void)F1;
+}
+
+// Before a collect pass: empty the candidate buffer and the overflow marks, keep the maxima.
+__global__ void k_reset_candidates(Status *st, uint32_t *ovf, int64_t p_pad)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i == 0) { st->n_cand = 0; st->overflow = 0; }
+    for (int64_t v = i; v < p_pad; v += (int64_t)gridDim.x * blockDim.x) ovf[v] = 0u;
+}
+
+__global__ void k_reset_queue(Status *st)
+{
+    if (threadIdx.x < 16) st->next_tile[threadIdx.x] = 0u;
+}
+
+hipError_t launch_reset_queue(const Problem &P)
+{
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, P.stream, P.at<Status>(P.L.status));
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_candidates(const Problem &P)
+{
+    hipLaunchKernelGGL(k_reset_candidates, dim3(64), dim3(256), 0, P.stream, P.at<Status>(P.L.status),
+                       P.at<uint32_t>(P.L.ovf), P.L.p_pad);
+    return hipGetLastError();
 }
 
 hipError_t launch_init(const Problem &P)
@@ -293,7 +319,7 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
                         word |= (hit ? 1u : 0u) << (8 * e);
                     }
                     int64_t row = (int64_t)v * W + a;
-                    int64_t off = (((int64_t)r * KB + kb) * rows_pad + row) * KBLK + q4 * 4;
+                    int64_t off = onehot_off(r, row, kb, q4 * 4, KB, rows_pad);
                     *reinterpret_cast<uint32_t *>(onehot + off) = word;
                 }
             }

@@ -24,7 +24,11 @@ namespace mdfs {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int SW_THREADS = 256;          // 4 waves, 2 x 2 wave grid, 64 x 64 outputs per wave
+constexpr int SB = 8;                    // a super-tile is SB x SB tiles
+constexpr int XCDS = 8;                  // workgroup b runs on XCD b % 8
+constexpr int WG_PER_XCD = SB * SB;      // resident workgroups per XCD (2 per CU)
 constexpr int STAGE_BYTES = 2 * TILE_ROWS * KBLK;   // A and B tiles of one K block
+constexpr int NSTAGE = 3;                           // LDS ring of K blocks
 
 struct Sweep2Args {
     const int8_t *onehot;
@@ -37,7 +41,8 @@ struct Sweep2Args {
     int64_t p_pad, rows_pad;
     int R, KB, KB0;
     int nbv;                 // variable blocks of TV = TILE_ROWS / W variables
-    int64_t tiles_per_r, n_tiles, per_xcd;
+    int nsb;                 // super-blocks of SB variable blocks
+    int64_t super_per_r, n_super;
     uint32_t *G32;
     Cand *cand;
     int64_t cap;
@@ -46,6 +51,7 @@ struct Sweep2Args {
     float w_abs;
     int32_t *counts_out;     // debug: full tables of discretisation disc_sel
     int disc_sel;
+    int collect;             // second pass: G32 holds the final maxima; append only
 };
 
 // Swizzled LDS address of 16-byte chunk j (0..3) of tile row `row` (64 bytes per row).
@@ -81,19 +87,10 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     constexpr int TV = TILE_ROWS / W;    // variables per tile side
     constexpr int NP = (W == 1) ? 4 : 1; // pairs held per lane per 16x16 block
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    char *stage = smem;                  // [2 buffers][A 8 KB | B 8 KB]
-    float *EA = reinterpret_cast<float *>(smem + 2 * STAGE_BYTES);
+    char *stage = smem;                  // [NSTAGE buffers][A 8 KB | B 8 KB]
+    float *EA = reinterpret_cast<float *>(smem + NSTAGE * STAGE_BYTES);
     float *EB = EA + (a.N0 + 1);
     float2 *LQ = reinterpret_cast<float2 *>(EB + (a.N1 + 1) + ((a.N0 + a.N1) & 1));
-
-    // XCD-aware tile order: blocks b, b+8, b+16 ... run on one XCD; give each XCD a contiguous
-    // range of the tile enumeration so neighbouring tiles share operand panels in its L2.
-    const int64_t b = blockIdx.x;
-    const int64_t tile = (b & 7) * a.per_xcd + (b >> 3);
-    if (tile >= a.n_tiles) return;
-    const int r = (int)(tile / a.tiles_per_r);
-    int bi, bj;
-    tri_index(tile % a.tiles_per_r, bi, bj);
 
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wr = wave >> 1, wc = wave & 1;
@@ -103,29 +100,38 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     for (int i = t; i <= a.N1; i += SW_THREADS) EB[i] = a.EB[i];
     for (int i = t; i <= a.N; i += SW_THREADS) LQ[i] = a.LQ[i];
 
+    // Persistent, XCD-aware schedule.  The super-tiles sup = x, x+8, x+16 ... belong to XCD x;
+    // the workgroups resident on that XCD take its tiles (super-tile by super-tile, slot by
+    // slot) from one atomic counter, so at any time they work on the same SB x SB block of
+    // tiles and share its SB row panels and SB column panels in the XCD's L2.
+    const int xcd = (int)(__builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 7);  // HW_REG_XCC_ID
+    const int64_t n_mine = ((a.n_super - xcd + XCDS - 1) / XCDS) * (SB * SB);
+    __shared__ int64_t s_next;
+    for (;;) {
+    __syncthreads();   // everyone has read the previous s_next
+    if (t == 0) s_next = atomicAdd(&a.st->next_tile[xcd], 1u);
+    __syncthreads();
+    const int64_t item = s_next;
+    if (item >= n_mine) break;
+    const int64_t sup = xcd + XCDS * (item / (SB * SB));
+    const int slot = (int)(item % (SB * SB));
+    const int r = (int)(sup / a.super_per_r);
+    int SI, SJ;
+    tri_index(sup % a.super_per_r, SI, SJ);
+    const int bi = SI * SB + slot / SB, bj = SJ * SB + slot % SB;
+    if (bi > bj || bj >= a.nbv) continue;   // workgroup-uniform
+
     // ---------------------------------------------------------------- K loop
-    const int64_t rowA0 = (int64_t)bi * TILE_ROWS, rowB0 = (int64_t)bj * TILE_ROWS;
-    const int8_t *base = a.onehot + (int64_t)r * a.KB * a.rows_pad * KBLK;
+    // operand panels: TILE_ROWS one-hot rows x all K blocks, contiguous (panel-major layout)
+    const int64_t nrb = a.rows_pad / TILE_ROWS;
+    const int8_t *panA = a.onehot + ((int64_t)r * nrb + bi) * a.KB * TILE_ROWS * KBLK;
+    const int8_t *panB = a.onehot + ((int64_t)r * nrb + bj) * a.KB * TILE_ROWS * KBLK;
     const int n1blk = a.KB - a.KB0;      // class-1 K blocks, accumulated first
-    auto kb_of = [&](int s) { return s < n1blk ? a.KB0 + s : s - n1blk; };
-    // this thread's two chunks of A and two of B
-    const int id0 = t, id1 = t + SW_THREADS;
-    const int ra0 = id0 >> 2, ja0 = id0 & 3, ra1 = id1 >> 2, ja1 = id1 & 3;
-    uint4 g[4];
-    auto gload = [&](int kb) {
-        const int8_t *blk = base + (int64_t)kb * a.rows_pad * KBLK;
-        g[0] = *reinterpret_cast<const uint4 *>(blk + (rowA0 + ra0) * KBLK + ja0 * 16);
-        g[1] = *reinterpret_cast<const uint4 *>(blk + (rowA0 + ra1) * KBLK + ja1 * 16);
-        g[2] = *reinterpret_cast<const uint4 *>(blk + (rowB0 + ra0) * KBLK + ja0 * 16);
-        g[3] = *reinterpret_cast<const uint4 *>(blk + (rowB0 + ra1) * KBLK + ja1 * 16);
-    };
-    auto sstore = [&](int buf) {
-        char *A = stage + buf * STAGE_BYTES, *B = A + TILE_ROWS * KBLK;
-        *reinterpret_cast<uint4 *>(A + lds_addr(ra0, ja0)) = g[0];
-        *reinterpret_cast<uint4 *>(A + lds_addr(ra1, ja1)) = g[1];
-        *reinterpret_cast<uint4 *>(B + lds_addr(ra0, ja0)) = g[2];
-        *reinterpret_cast<uint4 *>(B + lds_addr(ra1, ja1)) = g[3];
-    };
+    // this thread's two 16-byte chunks of the A tile and two of the B tile
+    const int ra0 = t >> 2, ja0 = t & 3, ra1 = (t + SW_THREADS) >> 2, ja1 = (t + SW_THREADS) & 3;
+    const int offA0 = ra0 * KBLK + ja0 * 16, offA1 = ra1 * KBLK + ja1 * 16;
+    const int sA0 = lds_addr(ra0, ja0), sA1 = lds_addr(ra1, ja1);
+    constexpr int kstride = TILE_ROWS * KBLK;
 
     v4i acc[4][4];
 #pragma unroll
@@ -133,33 +139,66 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[m][n] = v4i{0, 0, 0, 0};
 
-    gload(kb_of(0));
-    sstore(0);
+    // K blocks in processing order: class 1 first, then class 0
+    auto kblock = [&](int s_) { return s_ < n1blk ? a.KB0 + s_ : s_ - n1blk; };
+    auto stage_at = [&](int s_) { return stage + (s_ % NSTAGE) * STAGE_BYTES; };
+    // Software pipeline over a ring of NSTAGE LDS stages.  Iteration s: global loads of block
+    // s+3 go out, the fragments of block s are read from LDS and multiplied, and block s+2
+    // (loaded one iteration earlier) is written to LDS; one barrier per iteration.
+    v4i g0, g1, g2, g3, h0, h1, h2, h3;
+    auto gl = [&](int s_, v4i &x0, v4i &x1, v4i &x2, v4i &x3) {
+        const int64_t kb_off = (int64_t)kblock(s_) * kstride;
+        x0 = *reinterpret_cast<const v4i *>(panA + kb_off + offA0);
+        x1 = *reinterpret_cast<const v4i *>(panA + kb_off + offA1);
+        x2 = *reinterpret_cast<const v4i *>(panB + kb_off + offA0);
+        x3 = *reinterpret_cast<const v4i *>(panB + kb_off + offA1);
+    };
+    auto st4 = [&](int s_, const v4i &x0, const v4i &x1, const v4i &x2, const v4i &x3) {
+        char *A = stage_at(s_), *B = A + TILE_ROWS * KBLK;
+        *reinterpret_cast<v4i *>(A + sA0) = x0;
+        *reinterpret_cast<v4i *>(A + sA1) = x1;
+        *reinterpret_cast<v4i *>(B + sA0) = x2;
+        *reinterpret_cast<v4i *>(B + sA1) = x3;
+    };
+    const int fa_off0 = lds_addr(wr * 64 + c16, q), fb_off0 = lds_addr(wc * 64 + c16, q);
+    v4i fa[4], fb[4];
+    auto frags = [&](int s_, v4i (&xa)[4], v4i (&xb)[4]) {
+        const char *A = stage_at(s_), *B = A + TILE_ROWS * KBLK;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) xa[m] = *reinterpret_cast<const v4i *>(A + fa_off0 + m * 16 * KBLK);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) xb[n] = *reinterpret_cast<const v4i *>(B + fb_off0 + n * 16 * KBLK);
+    };
+    gl(0, g0, g1, g2, g3);
+    st4(0, g0, g1, g2, g3);
+    if (a.KB > 1) { gl(1, g0, g1, g2, g3); st4(1, g0, g1, g2, g3); }
+    if (a.KB > 2) gl(2, g0, g1, g2, g3);
     __syncthreads();
-    for (int s = 0; s < a.KB; ++s) {
-        if (s + 1 < a.KB) gload(kb_of(s + 1));
-        const char *A = stage + (s & 1) * STAGE_BYTES, *B = A + TILE_ROWS * KBLK;
-        v4i fa[4], fb[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            fa[m] = *reinterpret_cast<const v4i *>(A + lds_addr(wr * 64 + m * 16 + c16, q));
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-            fb[n] = *reinterpret_cast<const v4i *>(B + lds_addr(wc * 64 + n * 16 + c16, q));
+    // One pipeline step; the register sets (x = block s+2, y <- block s+3) swap roles between
+    // consecutive steps, so no copy forces an early wait on the loads in flight.
+    auto kstep = [&](int s_, v4i &x0, v4i &x1, v4i &x2, v4i &x3, v4i &y0, v4i &y1, v4i &y2, v4i &y3) {
+        if (s_ + 3 < a.KB) gl(s_ + 3, y0, y1, y2, y3);
+        frags(s_, fa, fb);
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int n = 0; n < 4; ++n)
                 acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[m], fb[n], acc[m][n], 0, 0, 0);
-        if (s == n1blk - 1) {
+        if (s_ == n1blk - 1) {
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
                 for (int n = 0; n < 4; ++n) acc[m][n] = acc[m][n] << 16;
         }
-        if (s + 1 < a.KB) sstore((s + 1) & 1);
+        if (s_ + 2 < a.KB) st4(s_ + 2, x0, x1, x2, x3);
         __syncthreads();
+    };
+    int s = 0;
+    for (; s + 1 < a.KB; s += 2) {
+        kstep(s, g0, g1, g2, g3, h0, h1, h2, h3);
+        kstep(s + 1, h0, h1, h2, h3, g0, g1, g2, g3);
     }
+    if (s < a.KB) kstep(s, g0, g1, g2, g3, h0, h1, h2, h3);
 
     // ---------------------------------------------------------------- epilogue
     // Lane geometry of the 16x16 output block (m, n): lane holds rows 4q..4q+3 of column c16.
@@ -242,10 +281,6 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
 #pragma unroll
     for (int n = 0; n < 4; ++n) cmax[n] = -INFINITY;
     bool hot = false;
-    // W = 2 keeps the lane's 32 IG values for the append pass; W = 1 (64 pairs per lane)
-    // recomputes them instead.
-    constexpr int KEEP = (W == 2) ? 16 : 1;
-    float keepR[KEEP], keepC[KEEP];
 
     const bool emit = EMIT && r == a.disc_sel;
 #pragma unroll
@@ -261,10 +296,10 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
                 const float F2 = pair_F2(tab);
                 const float igR = valid ? Fc[n] - F2 : -INFINITY;   // gain of rv given cv
                 const float igC = valid ? Fr[m][s] - F2 : -INFINITY; // gain of cv given rv
-                if constexpr (W == 2) { keepR[m * 4 + n] = igR; keepC[m * 4 + n] = igC; }
                 rmax[m][s] = fmaxf(rmax[m][s], igR);
                 cmax[n] = fmaxf(cmax[n], igC);
                 hot |= (igR >= thrR[m][s]) | (igC >= thrC[n]);
+
                 if (emit && valid) {
                     int32_t *o = a.counts_out + ((int64_t)rv * a.p + cv) * 2 * C * C;
 #pragma unroll
@@ -306,23 +341,21 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
 #pragma unroll
             for (int s = 0; s < NP; ++s) {
                 float g = key_f32(a.G32[row_var(m, s)]);
-                float top = fmaxf(g, rmax[m][s]);
+                float top = a.collect ? g : fmaxf(g, rmax[m][s]);
                 thrR[m][s] = top - rescore_window(a.w_abs, top);
             }
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             float g = key_f32(a.G32[col_var(n)]);
-            float top = fmaxf(g, cmax[n]);
+            float top = a.collect ? g : fmaxf(g, cmax[n]);
             thrC[n] = top - rescore_window(a.w_abs, top);
         }
-        if constexpr (W != 2) {
-            // recompute from the accumulators; the empty asm stops the compiler from keeping
-            // the first pass's values alive instead
+        // recompute from the accumulators (appends are rare); the empty asm stops the compiler
+        // from keeping the first pass's values alive instead
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(acc[m][n]) : : "memory");
-        }
+            for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(acc[m][n]) : : "memory");
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -331,17 +364,10 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
                 for (int s = 0; s < NP; ++s) {
                     const int64_t rv = row_var(m, s), cv = col_var(n);
                     const bool valid = rv < cv && cv < a.p;
-                    float igR, igC;
-                    if constexpr (W == 2) {
-                        igR = keepR[m * 4 + n];
-                        igC = keepC[m * 4 + n];
-                    } else {
-                        uint32_t tab[C][C];
-                        pair_table(m, n, s, tab);
-                        const float F2 = pair_F2(tab);
-                        igR = Fc[n] - F2;
-                        igC = Fr[m][s] - F2;
-                    }
+                    uint32_t tab[C][C];
+                    pair_table(m, n, s, tab);
+                    const float F2 = pair_F2(tab);
+                    const float igR = Fc[n] - F2, igC = Fr[m][s] - F2;
                     if (valid && igR >= thrR[m][s]) {
                         uint32_t at = atomicAdd(&a.st->n_cand, 1u);
                         if (at < a.cap) a.cand[at] = Cand{(int32_t)rv, r, (uint32_t)cv, igR};
@@ -355,7 +381,8 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
                 }
     }
 
-    // publish the maxima: one lane per variable
+    // publish the maxima: one lane per variable (the collect pass leaves the final maxima alone)
+    if (a.collect) continue;
     const bool row_leader = (W == 1) ? (c16 == 0) : ((c16 >> 1) == 0);
     const bool col_leader = (W == 1) ? (q == 0) : (q == 0 && odd == 0);
 #pragma unroll
@@ -366,10 +393,11 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
 #pragma unroll
     for (int n = 0; n < 4; ++n)
         if (col_leader && cmax[n] > -INFINITY) atomicMax(&a.G32[col_var(n)], f32_key(cmax[n]));
+    }   // work items
 }
 
 template <int W>
-static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_sel)
+static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect)
 {
     const Layout &L = P.L;
     Sweep2Args a{};
@@ -390,9 +418,9 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
     a.KB0 = P.KB0;
     constexpr int TV = TILE_ROWS / W;
     a.nbv = (int)((L.p + TV - 1) / TV);
-    a.tiles_per_r = (int64_t)a.nbv * (a.nbv + 1) / 2;
-    a.n_tiles = a.tiles_per_r * L.R;
-    a.per_xcd = (a.n_tiles + 7) / 8;
+    a.nsb = (a.nbv + SB - 1) / SB;
+    a.super_per_r = (int64_t)a.nsb * (a.nsb + 1) / 2;
+    a.n_super = a.super_per_r * L.R;
     a.G32 = P.at<uint32_t>(L.G32);
     a.cand = P.at<Cand>(L.cand);
     a.cap = L.cap;
@@ -401,20 +429,21 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
     a.w_abs = (float)(2.0 * P.err_bound);
     a.counts_out = counts_out;
     a.disc_sel = disc_sel;
-    size_t lds = 2 * STAGE_BYTES + sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (L.N + 1) + 16;
+    a.collect = collect ? 1 : 0;
+    size_t lds = NSTAGE * STAGE_BYTES + sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (L.N + 1) + 16;
     auto kern = counts_out ? k_sweep2<W, true> : k_sweep2<W, false>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    int64_t grid = a.per_xcd * 8;
+    const int grid = XCDS * WG_PER_XCD;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(SW_THREADS), lds, P.stream, a);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel)
+hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bool collect)
 {
     switch (P.L.W) {
-    case 1: return sweep_launch<1>(P, counts_out, disc_sel);
-    case 2: return sweep_launch<2>(P, counts_out, disc_sel);
+    case 1: return sweep_launch<1>(P, counts_out, disc_sel, collect);
+    case 2: return sweep_launch<2>(P, counts_out, disc_sel, collect);
     default: return hipErrorInvalidValue;
     }
 }

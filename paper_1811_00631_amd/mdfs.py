@@ -44,7 +44,9 @@ class Params(ctypes.Structure):
 
 _lib = None
 SYMBOLS = ["mdfs_workspace_size", "mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts",
-           "mdfs_screen_max", "mdfs_last_error"]
+           "mdfs_screen_max", "mdfs_phase_times", "mdfs_last_error"]
+FLAG_TIMING = 1
+PHASES = ["setup", "discretize", "sweep", "finalize"]
 
 
 def load(path: str = LIB_PATH):
@@ -63,6 +65,8 @@ def load(path: str = LIB_PATH):
     L.mdfs_max_ig.argtypes = [P, vp, vp, vp, vp, vp, vp, sz, vp]
     L.mdfs_pair_counts.argtypes = [P, vp, vp, ctypes.c_int32, vp, vp, sz, vp]
     L.mdfs_screen_max.argtypes = [P, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+    L.mdfs_phase_times.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+    L.mdfs_phase_times.restype = ctypes.c_int
     L.mdfs_last_error.restype = ctypes.c_char_p
     for fn in ("mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts", "mdfs_screen_max"):
         getattr(L, fn).restype = ctypes.c_int
@@ -71,9 +75,16 @@ def load(path: str = LIB_PATH):
 
 
 def make_params(n_obj, n_var, k=2, divisions=2, n_disc=1, disc_offset=0, range_=0.5, pseudocount=0.25,
-                seed=0, engine="auto") -> Params:
+                seed=0, engine="auto", flags=0) -> Params:
     return Params(int(n_obj), int(n_var), int(k), int(divisions), int(n_disc), int(disc_offset),
-                  float(range_), float(pseudocount), int(seed) & ((1 << 64) - 1), ENGINES[engine], 0)
+                  float(range_), float(pseudocount), int(seed) & ((1 << 64) - 1), ENGINES[engine], int(flags))
+
+
+def mdfs_phase_times() -> dict:
+    """Per-phase milliseconds of the last call made with timing on (HIP events on its stream)."""
+    buf = (ctypes.c_float * 8)()
+    n = load().mdfs_phase_times(buf, 8)
+    return {PHASES[i]: float(buf[i]) for i in range(n)}
 
 
 def _check(rc: int):
@@ -145,10 +156,11 @@ def mdfs_discretize(data: torch.Tensor, divisions: int, n_disc: int, range_: flo
 
 def mdfs_max_ig(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_disc: int,
                 pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0, disc_offset: int = 0,
-                engine: str = "auto"):
+                engine: str = "auto", timing: bool = False):
     data, y = _dev_inputs(data, y)
     n_var, n_obj = data.shape
-    prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed, engine)
+    prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed, engine,
+                      FLAG_TIMING if timing else 0)
     ws = workspace_for(prm, data.device)
     ig = torch.empty(n_var, dtype=torch.float32, device=data.device)
     am = torch.empty((n_var, k - 1), dtype=torch.int32, device=data.device)

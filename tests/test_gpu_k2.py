@@ -175,3 +175,19 @@ def test_full_size_sampled(mdfs_gpu, which):
     ref = oracle.max_ig(w.data, w.y, 2, w.divisions, w.n_disc, w.range_, w.xi, w.seed, targets=tg,
                         n_threads=16)
     assert_ig_parity(ig[tg], am[tg], ad[tg], ref, which)
+
+
+def test_candidate_overflow_falls_back_to_collect_pass(mdfs_gpu, monkeypatch):
+    # a tiny candidate buffer overflows during the sweep; the second (collect) pass with the
+    # final float32 maxima must reproduce the oracle exactly
+    w = workloads.xor_small(seed=13, n_obj=500, n_var=120, n_disc=5)
+    monkeypatch.setenv("MDFS_TEST_CAP", str(3 * w.n_var))
+    got = run_gpu(mdfs_gpu, w)
+    monkeypatch.delenv("MDFS_TEST_CAP")
+    ref = oracle.max_ig_all(w.data, w.y, 2, w.divisions, w.n_disc, w.range_, w.xi, w.seed, n_threads=8)
+    assert_ig_parity(*got, ref, "collect-pass")
+    # and a buffer too small even for the final window is reported, not silently wrong
+    monkeypatch.setenv("MDFS_TEST_CAP", "8")
+    with pytest.raises(mdfs_gpu.MdfsError) as e:
+        run_gpu(mdfs_gpu, w)
+    assert e.value.code == -9
