@@ -93,7 +93,10 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
     if (prm->n_var < prm->k) return fail(MDFS_E_ARG, "n_var=%lld < k", (long long)prm->n_var);
     if (prm->k == 3 && prm->n_var > MAX_K3_VARS)
         return fail(MDFS_E_LIMIT, "k=3 with n_var=%lld > %d", (long long)prm->n_var, MAX_K3_VARS);
-    if (sweep && prm->k == 3) return fail(MDFS_E_LIMIT, "k=3 engine not built yet");
+    if (sweep && prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA)
+        return fail(MDFS_E_LIMIT, "k=3 has the bitset engine only in this build");
+    if (sweep && prm->k == 2 && prm->engine == MDFS_ENGINE_BITSET)
+        return fail(MDFS_E_LIMIT, "k=2 has the MFMA engine only in this build");
     if (prm->n_disc < 1) return fail(MDFS_E_ARG, "n_disc=%d < 1", prm->n_disc);
     if (prm->disc_offset < 0) return fail(MDFS_E_ARG, "disc_offset < 0");
     if (!(prm->range >= 0.0 && prm->range <= 1.0)) return fail(MDFS_E_ARG, "range=%g outside [0,1]", prm->range);
@@ -171,9 +174,10 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
         P.K0pad = (P.N0 + KBLK - 1) / KBLK * KBLK;
         P.KB0 = P.K0pad / KBLK;
         P.KB = P.KB0 + (P.N1 + KBLK - 1) / KBLK;
-        int V = 1;
-        for (int q = 0; q < prm->k; ++q) V *= prm->divisions + 1;
-        P.err_bound = screen_err_bound(N, P.beta0, P.beta1, V);
+        const int C = prm->divisions + 1;
+        P.err_bound = screen_err_bound(N, P.beta0, P.beta1, C * C);
+        // k = 3: the triple's own F (C^3 voxels) plus the float32 F of the parent pair
+        if (prm->k == 3) P.err_bound += screen_err_bound(N, P.beta0, P.beta1, C * C * C);
     }
     return MDFS_OK;
 }
@@ -193,6 +197,22 @@ static int read_status(const Problem &P, Status &st)
     return MDFS_OK;
 }
 
+// Pair sweep (k = 2) or, per discretisation, pair data then triple sweep (k = 3).
+static int sweep_pass(const Problem &P, int32_t *counts, int disc_sel, bool collect)
+{
+    if (P.L.k == 2) {
+        LAUNCH(launch_reset_queue(P));
+        LAUNCH(launch_sweep2(P, counts, disc_sel, collect));
+    } else {
+        for (int r = 0; r < P.L.R; ++r) {
+            LAUNCH(launch_reset_queue(P));
+            LAUNCH(launch_pairs(P, r));
+            LAUNCH(launch_sweep3(P, r, collect));
+        }
+    }
+    return MDFS_OK;
+}
+
 // discretise + encode + sweep, leaving the maxima and candidates in the workspace
 static int run_sweep(const Problem &P, const float *data, const uint8_t *y, int32_t *counts, int disc_sel,
                      PhaseTimer *tm = nullptr)
@@ -204,18 +224,18 @@ static int run_sweep(const Problem &P, const float *data, const uint8_t *y, int3
     if (tm) tm->mark(1);
     LAUNCH(launch_discretize(P, data, nullptr, true));
     if (tm) tm->mark(2);
-    LAUNCH(launch_reset_queue(P));
-    LAUNCH(launch_sweep2(P, counts, disc_sel));
+    int rc = sweep_pass(P, counts, disc_sel, false);
+    if (rc) return rc;
     // If the opportunistic candidate appends overflowed, sweep again with the final float32
     // maxima as fixed thresholds: that pass appends exactly the (tuple, discretisation) pairs
     // within the re-score window.
     Status st;
-    int rc = read_status(P, st);
+    rc = read_status(P, st);
     if (rc) return rc;
     if (st.overflow) {
         LAUNCH(launch_reset_candidates(P));
-        LAUNCH(launch_reset_queue(P));
-        LAUNCH(launch_sweep2(P, nullptr, -1, true));
+        rc = sweep_pass(P, nullptr, -1, true);
+        if (rc) return rc;
     }
     if (tm) tm->mark(3);
     return MDFS_OK;

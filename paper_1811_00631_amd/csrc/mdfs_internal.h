@@ -112,6 +112,8 @@ hipError_t launch_tables(const Problem &P);
 hipError_t launch_discretize(const Problem &P, const float *data, uint8_t *codes, bool encode);
 hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bool collect = false);
 hipError_t launch_reset_candidates(const Problem &P);
+hipError_t launch_pairs(const Problem &P, int r);
+hipError_t launch_sweep3(const Problem &P, int r, bool collect);
 hipError_t launch_reset_queue(const Problem &P);
 hipError_t launch_finalize(const Problem &P, float *ig_max, int32_t *argmax, int32_t *argmax_disc);
 hipError_t launch_screen_out(const Problem &P, float *ig32);

@@ -46,7 +46,13 @@ Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
     L.ovf = take(sizeof(uint32_t) * L.p_pad);
     L.cand = take(sizeof(Cand) * L.cap);
     L.ig64 = take(sizeof(double) * L.cap);
-    L.bits = L.ptab = L.F2 = o;
+    if (k == 3) {
+        L.bits = take(sizeof(uint32_t) * (size_t)R * 2 * L.words_max * L.p_pad * L.W);
+        L.ptab = take(sizeof(uint32_t) * (size_t)L.p_pad * L.p_pad * L.W * L.W);
+        L.F2 = take(sizeof(float) * (size_t)L.p_pad * L.p_pad);
+    } else {
+        L.bits = L.ptab = L.F2 = o;
+    }
     L.total = o;
     return L;
 }
@@ -243,7 +249,8 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
     const float *__restrict__ data, int N, int p, int M, int R, int disc_offset, double range,
     uint64_t seed, const int32_t *__restrict__ perm, int K0pad, int N0, int N1, int KB,
     int64_t rows_pad, uint8_t *__restrict__ codes, int8_t *__restrict__ onehot,
-    uint32_t *__restrict__ marg, float *__restrict__ F1, int64_t p_pad, double b0, double b1, Status *st)
+    uint32_t *__restrict__ marg, float *__restrict__ F1, int64_t p_pad, double b0, double b1, Status *st,
+    uint32_t *__restrict__ bits, int64_t words_max)
 {
     constexpr int W = C - 1;
     extern __shared__ float lds[];
@@ -323,6 +330,22 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
                     *reinterpret_cast<uint32_t *>(onehot + off) = word;
                 }
             }
+            if (bits) {
+                // bitset word w of class y: class-sorted positions y_off + 32w .. +31, bin a
+                const int w0 = (N0 + 31) / 32, w1 = (N1 + 31) / 32;
+                for (int idx = t; idx < (w0 + w1) * W; idx += DISC_THREADS) {
+                    const int a = idx % W, wy = idx / W;
+                    const int y = wy < w0 ? 0 : 1, w = y ? wy - w0 : wy;
+                    const int base_ps = (y ? K0pad : 0) + 32 * w, ny = y ? N1 : N0;
+                    uint32_t word = 0;
+                    for (int e = 0; e < 32; ++e) {
+                        const bool valid = 32 * w + e < ny;
+                        const bool hit = valid && code_of<C>(xcs[base_ps + e], th) == a;
+                        word |= (hit ? 1u : 0u) << e;
+                    }
+                    bits[((((int64_t)r * 2 + y) * words_max + w) * p_pad + v) * W + a] = word;
+                }
+            }
             if (marg || F1) {
                 if (t < 2 * C) (&hist[0][0])[t] = 0;
                 __syncthreads();
@@ -378,7 +401,8 @@ static hipError_t disc_launch(const Problem &P, const float *data, uint8_t *code
                        L.R, P.disc_offset, P.range, P.seed, encode ? P.at<int32_t>(L.perm) : nullptr, P.K0pad, P.N0, P.N1, P.KB,
                        L.rows_pad, codes, encode ? P.at<int8_t>(L.onehot) : nullptr,
                        encode ? P.at<uint32_t>(L.marg) : nullptr, encode ? P.at<float>(L.F1) : nullptr,
-                       L.p_pad, P.beta0, P.beta1, P.at<Status>(L.status));
+                       L.p_pad, P.beta0, P.beta1, P.at<Status>(L.status),
+                       (encode && L.k == 3) ? P.at<uint32_t>(L.bits) : nullptr, L.words_max);
     return hipGetLastError();
 }
 

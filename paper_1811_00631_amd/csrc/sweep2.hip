@@ -52,7 +52,13 @@ struct Sweep2Args {
     int32_t *counts_out;     // debug: full tables of discretisation disc_sel
     int disc_sel;
     int collect;             // second pass: G32 holds the final maxima; append only
+    int r_base;              // first discretisation of this launch
+    uint32_t *ptab;          // pair mode: packed (W x W) counts [p_pad][p_pad][W*W]
+    float *F2out;            // pair mode: float32 F of each pair table [p_pad][p_pad]
 };
+
+// What one launch of the pair sweep produces.
+enum SweepMode { SWEEP_MAX = 0, SWEEP_DEBUG_COUNTS = 1, SWEEP_PAIRS = 2 };
 
 // Swizzled LDS address of 16-byte chunk j (0..3) of tile row `row` (64 bytes per row).
 __device__ inline int lds_addr(int row, int j) { return row * KBLK + ((j ^ ((row >> 1) & 3)) << 4); }
@@ -80,7 +86,7 @@ __device__ inline void tri_index(int64_t tt, int &bi, int &bj)
     bi = (int)(tt - j * (j + 1) / 2);
 }
 
-template <int W, bool EMIT>
+template <int W, int MODE>
 __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
 {
     constexpr int C = W + 1;
@@ -115,7 +121,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     if (item >= n_mine) break;
     const int64_t sup = xcd + XCDS * (item / (SB * SB));
     const int slot = (int)(item % (SB * SB));
-    const int r = (int)(sup / a.super_per_r);
+    const int r = a.r_base + (int)(sup / a.super_per_r);
     int SI, SJ;
     tri_index(sup % a.super_per_r, SI, SJ);
     const int bi = SI * SB + slot / SB, bj = SJ * SB + slot % SB;
@@ -282,7 +288,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     for (int n = 0; n < 4; ++n) cmax[n] = -INFINITY;
     bool hot = false;
 
-    const bool emit = EMIT && r == a.disc_sel;
+    const bool emit = MODE == SWEEP_DEBUG_COUNTS && r == a.disc_sel;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -294,6 +300,18 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
                 const int64_t rv = row_var(m, s), cv = col_var(n);
                 const bool valid = rv < cv && cv < a.p;
                 const float F2 = pair_F2(tab);
+                if constexpr (MODE == SWEEP_PAIRS) {
+                    // parent data of the k = 3 sweep: the W x W packed counts and F of the pair
+                    if (valid) {
+                        uint32_t *o = a.ptab + (rv * a.p_pad + cv) * (W * W);
+#pragma unroll
+                        for (int x = 0; x < W; ++x)
+#pragma unroll
+                            for (int y = 0; y < W; ++y) o[x * W + y] = tab[x][y];
+                        a.F2out[rv * a.p_pad + cv] = F2;
+                    }
+                    continue;
+                }
                 const float igR = valid ? Fc[n] - F2 : -INFINITY;   // gain of rv given cv
                 const float igC = valid ? Fr[m][s] - F2 : -INFINITY; // gain of cv given rv
                 rmax[m][s] = fmaxf(rmax[m][s], igR);
@@ -312,6 +330,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
                 }
             }
 
+    if constexpr (MODE == SWEEP_PAIRS) continue;
     // wave-level maxima per variable: lanes sharing a row variable differ in the bits that
     // select the column; lanes sharing a column variable differ in the row-selecting bits
 #pragma unroll
@@ -397,7 +416,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
 }
 
 template <int W>
-static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect)
+static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r)
 {
     const Layout &L = P.L;
     Sweep2Args a{};
@@ -420,7 +439,10 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
     a.nbv = (int)((L.p + TV - 1) / TV);
     a.nsb = (a.nbv + SB - 1) / SB;
     a.super_per_r = (int64_t)a.nsb * (a.nsb + 1) / 2;
-    a.n_super = a.super_per_r * L.R;
+    a.n_super = a.super_per_r * (pair_r >= 0 ? 1 : L.R);
+    a.r_base = pair_r >= 0 ? pair_r : 0;
+    a.ptab = pair_r >= 0 ? P.at<uint32_t>(L.ptab) : nullptr;
+    a.F2out = pair_r >= 0 ? P.at<float>(L.F2) : nullptr;
     a.G32 = P.at<uint32_t>(L.G32);
     a.cand = P.at<Cand>(L.cand);
     a.cap = L.cap;
@@ -431,7 +453,8 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
     a.disc_sel = disc_sel;
     a.collect = collect ? 1 : 0;
     size_t lds = NSTAGE * STAGE_BYTES + sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (L.N + 1) + 16;
-    auto kern = counts_out ? k_sweep2<W, true> : k_sweep2<W, false>;
+    auto kern = pair_r >= 0 ? k_sweep2<W, SWEEP_PAIRS>
+                            : (counts_out ? k_sweep2<W, SWEEP_DEBUG_COUNTS> : k_sweep2<W, SWEEP_MAX>);
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int grid = XCDS * WG_PER_XCD;
@@ -442,8 +465,17 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
 hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bool collect)
 {
     switch (P.L.W) {
-    case 1: return sweep_launch<1>(P, counts_out, disc_sel, collect);
-    case 2: return sweep_launch<2>(P, counts_out, disc_sel, collect);
+    case 1: return sweep_launch<1>(P, counts_out, disc_sel, collect, -1);
+    case 2: return sweep_launch<2>(P, counts_out, disc_sel, collect, -1);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pairs(const Problem &P, int r)
+{
+    switch (P.L.W) {
+    case 1: return sweep_launch<1>(P, nullptr, -1, false, r);
+    case 2: return sweep_launch<2>(P, nullptr, -1, false, r);
     default: return hipErrorInvalidValue;
     }
 }

@@ -1,0 +1,336 @@
+// sweep3.hip -- the k = 3 tuple sweep with per-class bitsets (AND + popcount).
+//
+// For one discretisation, every triple i < j < l gets its per-class voxel table (the counters
+// N^d of section "Algorithm and implementation").  Each variable is stored as W = C-1 bin
+// bitsets per class over class-sorted objects ([class][word][variable][bin] u32).  One wave
+// takes a pair (i, j); its lanes take 64 third variables l > j at a time.  The pair bitsets
+// B_i[a] & B_j[b] are wave-uniform (scalar loads and ANDs), the lane's B_l[e] words are
+// coalesced vector loads, and V_BCNT_U32_B32 accumulates popcount(B_i[a] & B_j[b] & B_l[e])
+// for the W^3 bin triples a, b, e < W.  Both classes share one counter: class 1 first, shift by
+// 16, then class 0, as in the pair sweep.  The remaining C^3 - W^3 voxels follow exactly from
+// the three pair tables (emitted by the pair sweep for this discretisation) and the marginals.
+//
+// Epilogue: F3 = sum_v n_v h(p_v) in float32 from the lookup tables; the parents are the pair
+// F values of the same float32 screen, IG(i|j,l) = F(j,l) - F3 and likewise for j and l
+// (equation IGmax with k = 3).  Maxima and candidate appends follow the pair sweep's rules.
+#include "mdfs_internal.h"
+
+namespace mdfs {
+
+struct Sweep3Args {
+    const uint32_t *bits;    // [R][2][words_max][p_pad][W]
+    const uint32_t *ptab;    // [p_pad][p_pad][W*W] packed counts of pairs i < j (this r)
+    const float *F2;         // [p_pad][p_pad] float32 F of pairs i < j (this r)
+    const uint32_t *marg;    // [R][p_pad][C] packed per-class marginals
+    const float *EA, *EB;
+    const float2 *LQ;
+    int N0, N1, N;
+    int p;
+    int64_t p_pad, words_max;
+    int w0, w1;              // bitset words of class 0 / class 1
+    int r;
+    int64_t n_pairs;         // C(p, 2)
+    uint32_t *G32;
+    Cand *cand;
+    int64_t cap;
+    Status *st;
+    uint32_t *ovf;
+    float w_abs;
+    int collect;
+};
+
+constexpr int S3_THREADS = 256;
+
+__device__ inline float vox3(uint32_t P, const float *EA, const float *EB, const float2 *LQ)
+{
+    const uint32_t n0 = P & 0xffffu, n1 = P >> 16;
+    const float2 lq = LQ[n0 + n1];
+    return lq.x - lq.y * (EA[n0] + EB[n1]);
+}
+
+__device__ inline float window3(float w_abs, float g)
+{
+    float ag = fabsf(g);
+    return w_abs + 2e-9f * (ag > 1.f ? ag : 1.f) + 1e-30f;
+}
+
+__device__ inline float wave_max(float x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
+    return x;
+}
+
+// Full C x C packed table of a pair from its W x W packed counts and the two marginals.
+template <int W>
+__device__ inline void full_pair(const uint32_t *pw, const uint32_t *Mx, const uint32_t *My, uint32_t (&n)[W + 1][W + 1])
+{
+    constexpr int C = W + 1;
+#pragma unroll
+    for (int x = 0; x < W; ++x)
+#pragma unroll
+        for (int y = 0; y < W; ++y) n[x][y] = pw[x * W + y];
+#pragma unroll
+    for (int x = 0; x < W; ++x) {
+        uint32_t s = Mx[x];
+#pragma unroll
+        for (int y = 0; y < W; ++y) s -= n[x][y];
+        n[x][W] = s;
+    }
+#pragma unroll
+    for (int y = 0; y < C; ++y) {
+        uint32_t s = My[y];
+#pragma unroll
+        for (int x = 0; x < W; ++x) s -= n[x][y];
+        n[W][y] = s;
+    }
+}
+
+__device__ inline void append3(const Sweep3Args &a, int v, uint32_t partner, float ig)
+{
+    uint32_t at = atomicAdd(&a.st->n_cand, 1u);
+    if (at < a.cap) a.cand[at] = Cand{v, a.r, partner, ig};
+    else { atomicOr(&a.ovf[v], 1u); atomicOr(&a.st->overflow, 1u); }
+}
+
+template <int W>
+__global__ __launch_bounds__(S3_THREADS) void k_sweep3(Sweep3Args a)
+{
+    constexpr int C = W + 1;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    float *EA = reinterpret_cast<float *>(smem);
+    float *EB = EA + (a.N0 + 1);
+    float2 *LQ = reinterpret_cast<float2 *>(EB + (a.N1 + 1) + ((a.N0 + a.N1) & 1));
+    const int t = threadIdx.x, lane = t & 63;
+    for (int i = t; i <= a.N0; i += S3_THREADS) EA[i] = a.EA[i];
+    for (int i = t; i <= a.N1; i += S3_THREADS) EB[i] = a.EB[i];
+    for (int i = t; i <= a.N; i += S3_THREADS) LQ[i] = a.LQ[i];
+    __syncthreads();
+
+    const uint32_t *margr = a.marg + (int64_t)a.r * a.p_pad * C;
+    const int64_t plane = a.p_pad * W;                 // u32 per bitset word plane
+    const uint32_t *bits1 = a.bits + ((int64_t)a.r * 2 + 1) * a.words_max * plane;
+    const uint32_t *bits0 = a.bits + ((int64_t)a.r * 2 + 0) * a.words_max * plane;
+
+    for (;;) {
+        // one pair per wave, taken in order of increasing j (largest amount of work first)
+        uint32_t u = 0;
+        if (lane == 0) u = atomicAdd(&a.st->next_tile[0], 1u);
+        u = __builtin_amdgcn_readfirstlane(u);
+        if ((int64_t)u >= a.n_pairs) break;
+        int64_t jj = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
+        while ((jj + 1) * (jj + 2) / 2 <= (int64_t)u) ++jj;
+        while (jj * (jj + 1) / 2 > (int64_t)u) --jj;
+        const int i = __builtin_amdgcn_readfirstlane((int)((int64_t)u - jj * (jj + 1) / 2));
+        const int j = __builtin_amdgcn_readfirstlane((int)jj + 1);
+        if (j + 1 >= a.p) continue;   // no third variable
+
+        uint32_t Mi[C], Mj[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) { Mi[c] = margr[(int64_t)i * C + c]; Mj[c] = margr[(int64_t)j * C + c]; }
+        uint32_t Nij[C][C];
+        full_pair<W>(a.ptab + ((int64_t)i * a.p_pad + j) * (W * W), Mi, Mj, Nij);
+        const float F2ij = a.F2[(int64_t)i * a.p_pad + j];
+        float Gi = key_f32(a.G32[i]), Gj = key_f32(a.G32[j]);
+        float runi = -INFINITY, runj = -INFINITY;
+
+        for (int l0 = j + 1; l0 < a.p; l0 += 64) {
+            const int l = l0 + lane;
+            const bool act = l < a.p;
+            const int lc = act ? l : (a.p - 1);   // in-bounds stand-in for idle lanes
+
+            // ---- counts of the W^3 leading bin triples (class 1, shift, class 0)
+            uint32_t cnt[W][W][W];
+#pragma unroll
+            for (int x = 0; x < W; ++x)
+#pragma unroll
+                for (int y = 0; y < W; ++y)
+#pragma unroll
+                    for (int z = 0; z < W; ++z) cnt[x][y][z] = 0;
+#pragma unroll
+            for (int cls = 1; cls >= 0; --cls) {
+                const uint32_t *bw = cls ? bits1 : bits0;
+                const int nw = cls ? a.w1 : a.w0;
+                for (int w = 0; w < nw; ++w) {
+                    const uint32_t *row = bw + (int64_t)w * plane;
+                    uint32_t bi[W], bj[W], bl[W];
+#pragma unroll
+                    for (int x = 0; x < W; ++x) {
+                        bi[x] = __builtin_amdgcn_readfirstlane(row[(int64_t)i * W + x]);
+                        bj[x] = __builtin_amdgcn_readfirstlane(row[(int64_t)j * W + x]);
+                        bl[x] = row[(int64_t)lc * W + x];
+                    }
+#pragma unroll
+                    for (int x = 0; x < W; ++x)
+#pragma unroll
+                        for (int y = 0; y < W; ++y) {
+                            const uint32_t pij = bi[x] & bj[y];
+#pragma unroll
+                            for (int z = 0; z < W; ++z)
+                                cnt[x][y][z] += __builtin_popcount(pij & bl[z]);   // v_bcnt_u32_b32
+                        }
+                }
+                if (cls == 1) {
+#pragma unroll
+                    for (int x = 0; x < W; ++x)
+#pragma unroll
+                        for (int y = 0; y < W; ++y)
+#pragma unroll
+                            for (int z = 0; z < W; ++z) cnt[x][y][z] <<= 16;
+                }
+            }
+
+            // ---- full C^3 table from the leading counts, the three pair tables and marginals
+            uint32_t Ml[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) Ml[c] = margr[(int64_t)lc * C + c];
+            uint32_t Nil[C][C], Njl[C][C];
+            full_pair<W>(a.ptab + ((int64_t)i * a.p_pad + lc) * (W * W), Mi, Ml, Nil);
+            full_pair<W>(a.ptab + ((int64_t)j * a.p_pad + lc) * (W * W), Mj, Ml, Njl);
+            uint32_t T[C][C][C];
+#pragma unroll
+            for (int x = 0; x < W; ++x)
+#pragma unroll
+                for (int y = 0; y < W; ++y)
+#pragma unroll
+                    for (int z = 0; z < W; ++z) T[x][y][z] = cnt[x][y][z];
+#pragma unroll
+            for (int x = 0; x < W; ++x)
+#pragma unroll
+                for (int y = 0; y < W; ++y) {
+                    uint32_t s = Nij[x][y];
+#pragma unroll
+                    for (int z = 0; z < W; ++z) s -= T[x][y][z];
+                    T[x][y][W] = s;
+                }
+#pragma unroll
+            for (int x = 0; x < W; ++x)
+#pragma unroll
+                for (int z = 0; z < W; ++z) {
+                    uint32_t s = Nil[x][z];
+#pragma unroll
+                    for (int y = 0; y < W; ++y) s -= T[x][y][z];
+                    T[x][W][z] = s;
+                }
+#pragma unroll
+            for (int y = 0; y < W; ++y)
+#pragma unroll
+                for (int z = 0; z < W; ++z) {
+                    uint32_t s = Njl[y][z];
+#pragma unroll
+                    for (int x = 0; x < W; ++x) s -= T[x][y][z];
+                    T[W][y][z] = s;
+                }
+#pragma unroll
+            for (int x = 0; x < W; ++x) {
+                uint32_t s = Nil[x][W];
+#pragma unroll
+                for (int y = 0; y < W; ++y) s -= T[x][y][W];
+                T[x][W][W] = s;
+            }
+#pragma unroll
+            for (int y = 0; y < W; ++y) {
+                uint32_t s = Njl[y][W];
+#pragma unroll
+                for (int x = 0; x < W; ++x) s -= T[x][y][W];
+                T[W][y][W] = s;
+            }
+#pragma unroll
+            for (int z = 0; z < W; ++z) {
+                uint32_t s = Njl[W][z];
+#pragma unroll
+                for (int x = 0; x < W; ++x) s -= T[x][W][z];
+                T[W][W][z] = s;
+            }
+            {
+                uint32_t s = Njl[W][W];
+#pragma unroll
+                for (int x = 0; x < W; ++x) s -= T[x][W][W];
+                T[W][W][W] = s;
+            }
+            float F3 = 0.f;
+#pragma unroll
+            for (int x = 0; x < C; ++x)
+#pragma unroll
+                for (int y = 0; y < C; ++y)
+#pragma unroll
+                    for (int z = 0; z < C; ++z) F3 += vox3(T[x][y][z], EA, EB, LQ);
+
+            const float Fjl = a.F2[(int64_t)j * a.p_pad + lc], Fil = a.F2[(int64_t)i * a.p_pad + lc];
+            const float igi = act ? Fjl - F3 : -INFINITY;    // gain of x_i given (x_j, x_l)
+            const float igj = act ? Fil - F3 : -INFINITY;    // gain of x_j given (x_i, x_l)
+            const float igl = act ? F2ij - F3 : -INFINITY;   // gain of x_l given (x_i, x_j)
+
+            // ---- member l: one value per lane
+            {
+                const float Gl = key_f32(a.G32[lc]);
+                if (act && igl >= Gl - window3(a.w_abs, Gl)) {
+                    append3(a, l, ((uint32_t)i << 16) | (uint32_t)j, igl);
+                    if (!a.collect && igl > Gl) atomicMax(&a.G32[l], f32_key(igl));
+                }
+            }
+            // ---- members i and j: chunk maxima over the lanes
+            const float mi = wave_max(igi), mj = wave_max(igj);
+            const float topi = a.collect ? Gi : fmaxf(mi, Gi), topj = a.collect ? Gj : fmaxf(mj, Gj);
+            if (act && igi >= topi - window3(a.w_abs, topi)) append3(a, i, ((uint32_t)j << 16) | (uint32_t)l, igi);
+            if (act && igj >= topj - window3(a.w_abs, topj)) append3(a, j, ((uint32_t)i << 16) | (uint32_t)l, igj);
+            runi = fmaxf(runi, mi);
+            runj = fmaxf(runj, mj);
+            if (!a.collect) { Gi = fmaxf(Gi, mi); Gj = fmaxf(Gj, mj); }
+        }
+        if (!a.collect && lane == 0) {
+            if (runi > -INFINITY) atomicMax(&a.G32[i], f32_key(runi));
+            if (runj > -INFINITY) atomicMax(&a.G32[j], f32_key(runj));
+        }
+    }
+}
+
+template <int W>
+static hipError_t sweep3_launch(const Problem &P, int r, bool collect)
+{
+    const Layout &L = P.L;
+    Sweep3Args a{};
+    a.bits = P.at<uint32_t>(L.bits);
+    a.ptab = P.at<uint32_t>(L.ptab);
+    a.F2 = P.at<float>(L.F2);
+    a.marg = P.at<uint32_t>(L.marg);
+    a.EA = P.at<float>(L.tabEA);
+    a.EB = P.at<float>(L.tabEB);
+    a.LQ = P.at<float2>(L.tabLQ);
+    a.N0 = P.N0;
+    a.N1 = P.N1;
+    a.N = (int)L.N;
+    a.p = (int)L.p;
+    a.p_pad = L.p_pad;
+    a.words_max = L.words_max;
+    a.w0 = (P.N0 + 31) / 32;
+    a.w1 = (P.N1 + 31) / 32;
+    a.r = r;
+    a.n_pairs = L.p * (L.p - 1) / 2;
+    a.G32 = P.at<uint32_t>(L.G32);
+    a.cand = P.at<Cand>(L.cand);
+    a.cap = L.cap;
+    a.st = P.at<Status>(L.status);
+    a.ovf = P.at<uint32_t>(L.ovf);
+    a.w_abs = (float)(2.0 * P.err_bound);
+    a.collect = collect ? 1 : 0;
+    size_t lds = sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (L.N + 1) + 16;
+    auto kern = k_sweep3<W>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(1024), dim3(S3_THREADS), lds, P.stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep3(const Problem &P, int r, bool collect)
+{
+    hipError_t e = launch_reset_queue(P);
+    if (e != hipSuccess) return e;
+    switch (P.L.W) {
+    case 1: return sweep3_launch<1>(P, r, collect);
+    case 2: return sweep3_launch<2>(P, r, collect);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mdfs

@@ -1,0 +1,81 @@
+"""k = 3 sweep (bitset engine) on the GPU through the C ABI, against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1811_00631_amd import workloads
+
+from test_gpu_k2 import assert_ig_parity, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def run3(mdfs, w, n_disc=None, xi=None, rng=None, divisions=None, disc_offset=0):
+    data, y = to_dev(w)
+    out = mdfs.mdfs_max_ig(data, y, 3, w.divisions if divisions is None else divisions,
+                           w.n_disc if n_disc is None else n_disc, w.xi if xi is None else xi,
+                           w.range_ if rng is None else rng, w.seed, disc_offset)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in out]
+
+
+CASES3 = {
+    "parity3_small": lambda: workloads.parity3(seed=3, n_obj=400, n_var=14, n_disc=2),
+    "chunks_ragged": lambda: workloads.xor_small(seed=21, n_obj=301, n_var=75, n_disc=2),
+    "two_classes_d2": lambda: workloads.parity3(seed=22, n_obj=257, n_var=40, divisions=1, n_disc=3),
+    "imbalanced": lambda: workloads.null_data(23, 333, 30, ones=41),
+    "three_vars": lambda: workloads.parity3(seed=24, n_obj=100, n_var=3, n_disc=2),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES3))
+def test_k3_matches_oracle(mdfs_gpu, name):
+    w = CASES3[name]()
+    print(f"k3 {name} N={w.n_obj} p={w.n_var} R={w.n_disc} d={w.divisions + 1}", flush=True)
+    got = run3(mdfs_gpu, w)
+    ref = oracle.max_ig_all(w.data, w.y, 3, w.divisions, w.n_disc, w.range_, w.xi, w.seed, n_threads=8)
+    assert_ig_parity(*got, ref, name)
+
+
+def test_k3_parity_triple_found(mdfs_gpu):
+    w = workloads.parity3(seed=31, n_obj=1000, n_var=40, n_disc=2)
+    ig, am, _ = run3(mdfs_gpu, w)
+    for v, others in [(0, [1, 2]), (1, [0, 2]), (2, [0, 1])]:
+        assert am[v].tolist() == others
+    assert ig[:3].min() > 5 * ig[3:].max()
+
+
+def test_k3_screen_within_error_bound(mdfs_gpu):
+    w = workloads.parity3(seed=32, n_obj=600, n_var=24, n_disc=2)
+    data, y = to_dev(w)
+    ig32, E = mdfs_gpu.mdfs_screen_max(data, y, 3, 2, 2, 0.25, 0.5, w.seed)
+    ig32 = ig32.cpu().numpy().astype(np.float64)
+    ref, _, _ = oracle.max_ig_all(w.data, w.y, 3, 2, 2, 0.5, 0.25, w.seed, n_threads=2)
+    err = np.abs(ig32 - ref)
+    print(f"k=3 float32 screen: max |err| {err.max():.3g}, bound E {E:.3g}")
+    assert err.max() <= E
+
+
+def test_k3_deterministic_and_fused_equals_separate(mdfs_gpu):
+    w = workloads.parity3(seed=33, n_obj=300, n_var=30, n_disc=3)
+    a = run3(mdfs_gpu, w)
+    b = run3(mdfs_gpu, w)
+    for x, z in zip(a, b):
+        assert np.array_equal(x, z)
+    sep = [run3(mdfs_gpu, w, n_disc=1, disc_offset=r) for r in range(3)]
+    assert np.array_equal(a[0], np.stack([s[0] for s in sep]).max(axis=0))
+
+
+def test_k3_full_size_sampled(mdfs_gpu):
+    # the parity-triple workload at its full size: N=2000, p=500, 30 discretisations
+    w = workloads.parity3(seed=3)
+    print(f"k3 full size: N={w.n_obj} p={w.n_var} R={w.n_disc}", flush=True)
+    ig, am, ad = run3(mdfs_gpu, w)
+    assert np.isfinite(ig).all()
+    for v, others in [(0, [1, 2]), (1, [0, 2]), (2, [0, 1])]:
+        assert am[v].tolist() == others
+    g = np.random.default_rng(0)
+    tg = np.array([0, 1] + sorted(g.choice(np.arange(3, w.n_var), 3, replace=False).tolist()), dtype=np.int64)
+    ref = oracle.max_ig(w.data, w.y, 3, w.divisions, w.n_disc, w.range_, w.xi, w.seed, targets=tg, n_threads=16)
+    assert_ig_parity(ig[tg], am[tg], ad[tg], ref, "k3 full size")
