@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
 HBM_PEAK_GBS = 8000.0
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 lanes/clk x 2.4 GHz integer VALU = 39.3 Tops/s
 
 
 def parse():
@@ -40,7 +41,34 @@ def parse():
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sweep2_headline_traffic.json"))
+    ap.add_argument("--workload", default="headline", choices=sorted(WORKLOADS),
+                    help="headline is the metric's workload; the others print informational lines")
     return ap.parse_args()
+
+
+def _wl(name):
+    from paper_1811_00631_amd import workloads
+    return {"headline": workloads.headline, "xor_small": workloads.xor_small,
+            "madelon_like": workloads.madelon_like, "parity3": workloads.parity3,
+            "genomics_like": workloads.genomics_like}[name]()
+
+
+WORKLOADS = ["headline", "xor_small", "madelon_like", "parity3", "genomics_like"]
+WORKLOAD_TEXT = {
+    "headline": "genomics-shaped k=2: N=2000, p=20000 log-normal, 10 planted XOR pairs, balanced y, d=3, "
+                "30 random discretisations (range 0.5, xi 0.25)",
+    "xor_small": "k=2: N=500, p=100 Gaussian, XOR pair (0,1) with 10% label noise, d=3, 1 discretisation",
+    "madelon_like": "Madelon-shaped k=2: N=2000, p=500 (5 base + 15 combinations + 480 noise), d=3, 30 discretisations",
+    "parity3": "k=3: N=2000, p=500 Gaussian, parity triple (0,1,2), d=3, 30 discretisations, bitset engine",
+    "genomics_like": "genomics-shaped k=2: N=500, p=20000 log-normal, 10 planted XOR pairs, y 200/300, d=3, "
+                     "30 discretisations",
+}
+
+
+def _sweep_source_hash():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1811_00631_amd", "csrc", "sweep2.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()
 
 
 def cpu_baseline(w, n_vars, n_disc):
@@ -73,11 +101,11 @@ def main():
 
     mdfs.load()
     dev = torch.device("cuda:0")
-    w = workloads.headline()
+    w = _wl(args.workload)
     data = torch.from_numpy(w.data).to(dev)
     y = torch.from_numpy(w.y).to(dev)
-    k, div, R = 2, w.divisions, w.n_disc
-    tuples = math.comb(w.n_var, 2) * R
+    k, div, R = w.k, w.divisions, w.n_disc
+    tuples = math.comb(w.n_var, k) * R
 
     def step():
         return mdfs.mdfs_max_ig(data, y, k, div, R, w.xi, w.range_, w.seed, timing=True)
@@ -98,7 +126,14 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
     ig, am, _ = out
-    found = sum(int(am[a, 0]) == b for a, b in w.planted["pairs"])
+    if "pairs" in w.planted:
+        found = f"{sum(int(am[a, 0]) == b for a, b in w.planted['pairs'])}/{len(w.planted['pairs'])}"
+    elif "triple" in w.planted:
+        found = f"{sum(am[v].tolist() == [u for u in w.planted['triple'] if u != v] for v in w.planted['triple'])}/3"
+    elif "xor_pair" in w.planted:
+        found = f"{int(int(am[0, 0]) == 1) + int(int(am[1, 0]) == 0)}/2"
+    else:
+        found = "n/a"
 
     if args.copy_calib:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -109,18 +144,27 @@ def main():
     ph = {name: float(np.mean([p[name] for p in phases])) for name in phases[0]}
     sweep_ms = ph["sweep"]
     W = div
-    ops_per_pair = 2 * w.n_obj * W * W           # int8 MACs x 2 executed by the engine per pair
-    achieved = tuples * ops_per_pair / (sweep_ms * 1e-3) / 1e12
-    roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-            "frac": achieved / INT8_PEAK_TOPS, "traffic": None, "kernel": "k_sweep2<2>",
-            "per_unit": f"2*N*(d-1)^2 = {ops_per_pair} int8 ops per pair table",
-            "units_per_launch": tuples, "kernel_ms": sweep_ms}
-    if os.path.exists(args.traffic_json):
-        try:
-            tr = json.load(open(args.traffic_json))
+    if k == 2:
+        ops_per_unit = 2 * w.n_obj * W * W           # int8 MACs x 2 executed by the engine per pair
+        achieved = tuples * ops_per_unit / (sweep_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / INT8_PEAK_TOPS, "traffic": None, "kernel": f"k_sweep2<{W}>",
+                "per_unit": f"2*N*(d-1)^2 = {ops_per_unit} int8 ops per pair table",
+                "units_per_launch": tuples, "kernel_ms": sweep_ms}
+    else:
+        # AND + popcount-accumulate per (bin triple, 32-object word): 2 integer ops on 32 lanes
+        words = (int((w.y == 0).sum()) + 31) // 32 + (int((w.y == 1).sum()) + 31) // 32
+        ops_per_unit = 2 * W ** 3 * words
+        achieved = tuples * ops_per_unit / (sweep_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "Tops/s (32-bit integer VALU)",
+                "frac": achieved / ALU_PEAK_TOPS, "traffic": None, "kernel": f"k_sweep3<{W}> (+ pair data)",
+                "per_unit": f"2*(d-1)^3*words = {ops_per_unit} VALU lane-ops per triple",
+                "units_per_launch": tuples, "kernel_ms": sweep_ms}
+    if k == 2 and os.path.exists(args.traffic_json):
+        # counters are only valid for the kernel source they were taken on
+        tr = json.load(open(args.traffic_json))
+        if tr.get("sweep2_sha256") == _sweep_source_hash():
             roof["traffic"] = tr.get("bytes_per_launch")
-        except Exception:
-            pass
 
     line = {
         "metric": "k-tuples evaluated/sec (k=2, N=2000, p=20k, 30 discretizations); p50/p99 latency",
@@ -130,19 +174,21 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "i8",
         "data": "synthetic",
-        "config": {"workload": "genomics-shaped k=2: N=2000, p=20000 log-normal, 10 planted XOR pairs, "
-                               "balanced y, d=3, 30 random discretisations (range 0.5, xi 0.25)",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "k": k, "n_obj": w.n_obj, "n_var": w.n_var, "classes": div + 1, "n_disc": R,
-                   "tuples_per_step": tuples, "counts": "int8 MFMA, int32 accumulate",
+                   "tuples_per_step": tuples,
+                   "counts": "int8 MFMA, int32 accumulate" if k == 2 else "bitset AND + popcount, int32",
                    "entropy": "float32 screen + binary64 re-score"},
         "p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
         "p99_ms": float(np.percentile(np.array(lat) * 1e3, 99)),
         "phase_ms": ph,
-        "planted_pairs_found": f"{found}/{len(w.planted['pairs'])}",
+        "planted_found": found,
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_vars, args.cpu_disc)
+    if k == 3:
+        line["metric"] = "k-tuples evaluated/sec (k=3 workload, informational)"
+    if not args.no_cpu_baseline and k == 2:
+        line["cpu_baseline"] = cpu_baseline(w, min(args.cpu_vars, w.n_var), min(args.cpu_disc, w.n_disc))
     print(json.dumps(line))
 
 
