@@ -259,6 +259,7 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
     float *srt = xcs + Kpad;                // [M]
     float *thr = srt + M;                   // [DISC_RCHUNK][C-1]
     __shared__ int hist[2][C];
+    __shared__ double fterm[C];
     const int v = blockIdx.x;
     const int t = threadIdx.x;
     const float *x = data + (int64_t)v * N;
@@ -349,38 +350,48 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
             if (marg || F1) {
                 if (t < 2 * C) (&hist[0][0])[t] = 0;
                 __syncthreads();
+                // per-class bin counts: one ballot per (class, bin) and 64 positions, summed in
+                // wave-uniform registers, one LDS atomic per wave at the end
                 int loc[2][C];
+#pragma unroll
                 for (int a = 0; a < C; ++a) loc[0][a] = loc[1][a] = 0;
-                for (int ps = t; ps < Kpad; ps += DISC_THREADS) {
+                const int lane = t & 63;
+                for (int base = t - lane; base < Kpad; base += DISC_THREADS) {
+                    const int ps = base + lane;
                     const bool c0 = ps < N0, c1 = ps >= K0pad && ps < K0pad + N1;
-                    if (c0 | c1) {
-                        int cd = code_of<C>(xcs[ps], th);
-                        for (int a = 0; a < C; ++a) {
-                            loc[0][a] += (c0 && cd == a) ? 1 : 0;
-                            loc[1][a] += (c1 && cd == a) ? 1 : 0;
-                        }
-                    }
-                }
-                for (int a = 0; a < C; ++a) {
-                    if (loc[0][a]) atomicAdd(&hist[0][a], loc[0][a]);
-                    if (loc[1][a]) atomicAdd(&hist[1][a], loc[1][a]);
-                }
-                __syncthreads();
-                if (t == 0) {
-                    double Fv = 0.0;
+                    const int cd = (c0 | c1) ? code_of<C>(xcs[ps], th) : -1;
+#pragma unroll
                     for (int a = 0; a < C; ++a) {
-                        double n0 = hist[0][a], n1 = hist[1][a], n = n0 + n1;
-                        if (marg) marg[((int64_t)r * p_pad + v) * C + a] = ((uint32_t)hist[1][a] << 16) | (uint32_t)hist[0][a];
-                        if (n > 0) {
-                            double s = n + b0 + b1;
-                            Fv += n * log(s) - (n / s) * (xlogx(n0 + b0) + xlogx(n1 + b1));
-                        }
+                        loc[0][a] += __popcll(__ballot(c0 && cd == a));
+                        loc[1][a] += __popcll(__ballot(c1 && cd == a));
                     }
-                    if (F1) F1[(int64_t)r * p_pad + v] = (float)Fv;
+                }
+                if (lane == 0) {
+#pragma unroll
+                    for (int a = 0; a < C; ++a) {
+                        if (loc[0][a]) atomicAdd(&hist[0][a], loc[0][a]);
+                        if (loc[1][a]) atomicAdd(&hist[1][a], loc[1][a]);
+                    }
                 }
                 __syncthreads();
+                if (t < C) {
+                    const int a = t;
+                    const double n0 = hist[0][a], n1 = hist[1][a], n = n0 + n1;
+                    if (marg) marg[((int64_t)r * p_pad + v) * C + a] = ((uint32_t)hist[1][a] << 16) | (uint32_t)hist[0][a];
+                    double term = 0.0;
+                    if (n > 0) {
+                        const double s = n + b0 + b1;
+                        term = n * log(s) - (n / s) * (xlogx(n0 + b0) + xlogx(n1 + b1));
+                    }
+                    fterm[a] = term;
+                }
+                __syncthreads();
+                if (t == 0 && F1) {
+                    double Fv = 0.0;
+                    for (int a = 0; a < C; ++a) Fv += fterm[a];
+                    F1[(int64_t)r * p_pad + v] = (float)Fv;
+                }
             }
-        }
         __syncthreads();
     }
 }
