@@ -258,8 +258,8 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
     float *xcs = lds;                       // [Kpad]
     float *srt = xcs + Kpad;                // [M]
     float *thr = srt + M;                   // [DISC_RCHUNK][C-1]
-    __shared__ int hist[2][C];
-    __shared__ double fterm[C];
+    __shared__ int hist[DISC_RCHUNK * 2 * C];
+    __shared__ double fterm[DISC_RCHUNK * C];
     const int v = blockIdx.x;
     const int t = threadIdx.x;
     const float *x = data + (int64_t)v * N;
@@ -347,15 +347,18 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
                     bits[((((int64_t)r * 2 + y) * words_max + w) * p_pad + v) * W + a] = word;
                 }
             }
-            if (marg || F1) {
-                if (t < 2 * C) (&hist[0][0])[t] = 0;
-                __syncthreads();
-                // per-class bin counts: one ballot per (class, bin) and 64 positions, summed in
-                // wave-uniform registers, one LDS atomic per wave at the end
+        }
+        if (marg || F1) {
+            // per-class bin counts of every discretisation of this chunk: one ballot per
+            // (class, bin) and 64 positions, one LDS atomic per wave and (r, class, bin)
+            for (int i = t; i < nr * 2 * C; i += DISC_THREADS) hist[i] = 0;
+            __syncthreads();
+            const int lane = t & 63;
+            for (int rr = 0; rr < nr; ++rr) {
+                const float *th = thr + rr * (C - 1);
                 int loc[2][C];
 #pragma unroll
                 for (int a = 0; a < C; ++a) loc[0][a] = loc[1][a] = 0;
-                const int lane = t & 63;
                 for (int base = t - lane; base < Kpad; base += DISC_THREADS) {
                     const int ps = base + lane;
                     const bool c0 = ps < N0, c1 = ps >= K0pad && ps < K0pad + N1;
@@ -369,29 +372,33 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
                 if (lane == 0) {
 #pragma unroll
                     for (int a = 0; a < C; ++a) {
-                        if (loc[0][a]) atomicAdd(&hist[0][a], loc[0][a]);
-                        if (loc[1][a]) atomicAdd(&hist[1][a], loc[1][a]);
+                        if (loc[0][a]) atomicAdd(&hist[(rr * 2 + 0) * C + a], loc[0][a]);
+                        if (loc[1][a]) atomicAdd(&hist[(rr * 2 + 1) * C + a], loc[1][a]);
                     }
-                }
-                __syncthreads();
-                if (t < C) {
-                    const int a = t;
-                    const double n0 = hist[0][a], n1 = hist[1][a], n = n0 + n1;
-                    if (marg) marg[((int64_t)r * p_pad + v) * C + a] = ((uint32_t)hist[1][a] << 16) | (uint32_t)hist[0][a];
-                    double term = 0.0;
-                    if (n > 0) {
-                        const double s = n + b0 + b1;
-                        term = n * log(s) - (n / s) * (xlogx(n0 + b0) + xlogx(n1 + b1));
-                    }
-                    fterm[a] = term;
-                }
-                __syncthreads();
-                if (t == 0 && F1) {
-                    double Fv = 0.0;
-                    for (int a = 0; a < C; ++a) Fv += fterm[a];
-                    F1[(int64_t)r * p_pad + v] = (float)Fv;
                 }
             }
+            __syncthreads();
+            // packed marginals and the F terms of every (r, bin) in parallel
+            for (int i = t; i < nr * C; i += DISC_THREADS) {
+                const int rr = i / C, a = i % C, r = rb + rr;
+                const int h0 = hist[(rr * 2 + 0) * C + a], h1 = hist[(rr * 2 + 1) * C + a];
+                if (marg) marg[((int64_t)r * p_pad + v) * C + a] = ((uint32_t)h1 << 16) | (uint32_t)h0;
+                const double n0 = h0, n1 = h1, n = n0 + n1;
+                double term = 0.0;
+                if (n > 0) {
+                    const double sden = n + b0 + b1;
+                    term = n * log(sden) - (n / sden) * (xlogx(n0 + b0) + xlogx(n1 + b1));
+                }
+                fterm[i] = term;
+            }
+            __syncthreads();
+            if (F1)
+                for (int rr = t; rr < nr; rr += DISC_THREADS) {
+                    double Fv = 0.0;
+                    for (int a = 0; a < C; ++a) Fv += fterm[rr * C + a];
+                    F1[(int64_t)(rb + rr) * p_pad + v] = (float)Fv;
+                }
+        }
         __syncthreads();
     }
 }
