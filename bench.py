@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
+FP4_PEAK_TFLOPS = 10100.0      # MI355X dense fp4 (and fp6) MFMA, TFLOP/s
 HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 lanes/clk x 2.4 GHz integer VALU = 39.3 Tops/s
 
@@ -38,6 +39,8 @@ def parse():
     ap.add_argument("--cpu-vars", type=int, default=500, help="variables in the oracle's sample")
     ap.add_argument("--cpu-disc", type=int, default=16, help="discretisations in the oracle's sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--engine", default="auto", choices=["auto", "mfma_fp4", "mfma", "bitset"],
+                    help="auto: fp4 MFMA for k=2 while each class has < 4096 objects, bitset for k=3")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sweep2_headline_traffic.json"))
@@ -108,7 +111,7 @@ def main():
     tuples = math.comb(w.n_var, k) * R
 
     def step():
-        return mdfs.mdfs_max_ig(data, y, k, div, R, w.xi, w.range_, w.seed, timing=True)
+        return mdfs.mdfs_max_ig(data, y, k, div, R, w.xi, w.range_, w.seed, engine=args.engine, timing=True)
 
     for _ in range(args.warmup):
         step()
@@ -144,12 +147,16 @@ def main():
     ph = {name: float(np.mean([p[name] for p in phases])) for name in phases[0]}
     sweep_ms = ph["sweep"]
     W = div
+    n0, n1 = int((w.y == 0).sum()), int((w.y == 1).sum())
+    fp4 = k == 2 and (args.engine == "mfma_fp4" or (args.engine == "auto" and max(n0, n1) < 4096))
     if k == 2:
-        ops_per_unit = 2 * w.n_obj * W * W           # int8 MACs x 2 executed by the engine per pair
+        ops_per_unit = 2 * w.n_obj * W * W           # MACs x 2 of the one-hot Gram product per pair
         achieved = tuples * ops_per_unit / (sweep_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / INT8_PEAK_TOPS, "traffic": None, "kernel": f"k_sweep2<{W}>",
-                "per_unit": f"2*N*(d-1)^2 = {ops_per_unit} int8 ops per pair table",
+        peak = FP4_PEAK_TFLOPS if fp4 else INT8_PEAK_TOPS
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s" if fp4 else "TOP/s",
+                "frac": achieved / peak, "traffic": None,
+                "kernel": f"k_sweep2<{W}, max, {'fp4' if fp4 else 'int8'}>",
+                "per_unit": f"2*N*(d-1)^2 = {ops_per_unit} {'fp4' if fp4 else 'int8'} ops per pair table",
                 "units_per_launch": tuples, "kernel_ms": sweep_ms}
     else:
         # AND + popcount-accumulate per (bin triple, 32-object word): 2 integer ops on 32 lanes
@@ -161,9 +168,9 @@ def main():
                 "per_unit": f"2*(d-1)^3*words = {ops_per_unit} VALU lane-ops per triple",
                 "units_per_launch": tuples, "kernel_ms": sweep_ms}
     if k == 2 and os.path.exists(args.traffic_json):
-        # counters are only valid for the kernel source they were taken on
+        # counters are only valid for the kernel source and encoding they were taken on
         tr = json.load(open(args.traffic_json))
-        if tr.get("sweep2_sha256") == _sweep_source_hash():
+        if tr.get("sweep2_sha256") == _sweep_source_hash() and tr.get("encoding", "int8") == ("fp4" if fp4 else "int8"):
             roof["traffic"] = tr.get("bytes_per_launch")
 
     line = {
@@ -172,12 +179,14 @@ def main():
         "unit": "k-tuples evaluated/sec",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "i8",
+        "dtype": "fp4 (E2M1 one-hot), f32 accumulate" if fp4 else ("i8" if k == 2 else "u32 bitsets"),
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "k": k, "n_obj": w.n_obj, "n_var": w.n_var, "classes": div + 1, "n_disc": R,
                    "tuples_per_step": tuples,
-                   "counts": "int8 MFMA, int32 accumulate" if k == 2 else "bitset AND + popcount, int32",
+                   "engine": args.engine,
+                   "counts": ("fp4 MFMA, exact f32 accumulate" if fp4 else "int8 MFMA, int32 accumulate")
+                   if k == 2 else "bitset AND + popcount, int32",
                    "entropy": "float32 screen + binary64 re-score"},
         "p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
         "p99_ms": float(np.percentile(np.array(lat) * 1e3, 99)),

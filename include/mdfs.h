@@ -57,9 +57,12 @@ typedef enum {
 } mdfs_status;
 
 typedef enum {
-    MDFS_ENGINE_AUTO = 0,   /* k=2: int8 MFMA; k=3: bitset */
-    MDFS_ENGINE_MFMA = 1,   /* one-hot int8 contraction on the matrix cores */
-    MDFS_ENGINE_BITSET = 2  /* per-class bitsets, AND + popcount */
+    MDFS_ENGINE_AUTO = 0,     /* k=2: fp4 MFMA if both classes < 4096 objects, else int8 MFMA;
+                                 k=3: bitset */
+    MDFS_ENGINE_MFMA = 1,     /* one-hot int8 contraction on the matrix cores */
+    MDFS_ENGINE_BITSET = 2,   /* per-class bitsets, AND + popcount */
+    MDFS_ENGINE_MFMA_FP4 = 3  /* one-hot E2M1 (fp4) contraction, float32 accumulation (exact
+                                 integers); k=2, each class < 4096 objects, else MDFS_E_LIMIT */
 } mdfs_engine;
 
 /* Problem description.  Fields follow the arguments of ComputeMaxInfoGains

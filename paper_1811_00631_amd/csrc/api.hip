@@ -93,16 +93,16 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
     if (prm->n_var < prm->k) return fail(MDFS_E_ARG, "n_var=%lld < k", (long long)prm->n_var);
     if (prm->k == 3 && prm->n_var > MAX_K3_VARS)
         return fail(MDFS_E_LIMIT, "k=3 with n_var=%lld > %d", (long long)prm->n_var, MAX_K3_VARS);
-    if (sweep && prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA)
+    if (sweep && prm->k == 3 && (prm->engine == MDFS_ENGINE_MFMA || prm->engine == MDFS_ENGINE_MFMA_FP4))
         return fail(MDFS_E_LIMIT, "k=3 has the bitset engine only in this build");
     if (sweep && prm->k == 2 && prm->engine == MDFS_ENGINE_BITSET)
-        return fail(MDFS_E_LIMIT, "k=2 has the MFMA engine only in this build");
+        return fail(MDFS_E_LIMIT, "k=2 has the MFMA engines only in this build");
     if (prm->n_disc < 1) return fail(MDFS_E_ARG, "n_disc=%d < 1", prm->n_disc);
     if (prm->disc_offset < 0) return fail(MDFS_E_ARG, "disc_offset < 0");
     if (!(prm->range >= 0.0 && prm->range <= 1.0)) return fail(MDFS_E_ARG, "range=%g outside [0,1]", prm->range);
     if (!(prm->pseudocount >= 0.0) || !isfinite(prm->pseudocount))
         return fail(MDFS_E_ARG, "pseudocount=%g must be finite and >= 0", prm->pseudocount);
-    if (prm->engine < 0 || prm->engine > 2) return fail(MDFS_E_ARG, "engine=%d", prm->engine);
+    if (prm->engine < 0 || prm->engine > 3) return fail(MDFS_E_ARG, "engine=%d", prm->engine);
     return MDFS_OK;
 }
 
@@ -171,9 +171,18 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
         const double m = (double)(n0 < n1 ? n0 : n1);
         P.beta0 = prm->pseudocount * (double)n0 / m;
         P.beta1 = prm->pseudocount * (double)n1 / m;
-        P.K0pad = (P.N0 + KBLK - 1) / KBLK * KBLK;
-        P.KB0 = P.K0pad / KBLK;
-        P.KB = P.KB0 + (P.N1 + KBLK - 1) / KBLK;
+        // one-hot encoding of the pair contraction: E2M1 nibbles while float32 accumulation of
+        // n1 * 4096 + n0 is exact, int8 bytes otherwise (or when asked for)
+        const bool f4_fits = n0 <= MAX_CLASS_OBJ_F4 && n1 <= MAX_CLASS_OBJ_F4;
+        if (prm->engine == MDFS_ENGINE_MFMA_FP4 && !f4_fits)
+            return fail(MDFS_E_LIMIT, "fp4 engine: class sizes %lld/%lld exceed %d", (long long)n0, (long long)n1,
+                        MAX_CLASS_OBJ_F4);
+        P.fp4 = f4_fits && prm->engine != MDFS_ENGINE_MFMA;
+        P.kobj = P.fp4 ? KOBJ_F4 : KOBJ_I8;
+        P.K0pad = (P.N0 + P.kobj - 1) / P.kobj * P.kobj;
+        P.KB0 = P.K0pad / P.kobj;
+        P.KB = P.KB0 + (P.N1 + P.kobj - 1) / P.kobj;
+        P.Kpad = P.KB * P.kobj;
         const int C = prm->divisions + 1;
         P.err_bound = screen_err_bound(N, P.beta0, P.beta1, C * C);
         // k = 3: the triple's own F (C^3 voxels) plus the float32 F of the parent pair

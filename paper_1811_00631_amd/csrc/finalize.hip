@@ -35,16 +35,17 @@ __device__ inline int wave_sum(int x)
     return x;
 }
 
-// Code of variable v at class-sorted position `lane` of one K block, read back from its
-// one-hot rows (the last bin has no row: none of the W rows set).
+// Code of variable v at position e of K block kb, read back from its one-hot rows (the last
+// bin has no row: none of the W rows set).  int8: byte e; fp4: nibble e of the row chunk.
 template <int W>
 __device__ inline int code_from_onehot(const int8_t *onehot, int r, int kb, int KB, int64_t rows_pad, int64_t v,
-                                       int lane)
+                                       int e, bool fp4)
 {
+    const int byte = fp4 ? (e >> 1) : e, sh = fp4 ? 4 * (e & 1) : 0;
     int c = W;
 #pragma unroll
     for (int a = W - 1; a >= 0; --a)
-        if (onehot[onehot_off(r, v * W + a, kb, lane, KB, rows_pad)]) c = a;
+        if ((onehot[onehot_off(r, v * W + a, kb, byte, KB, rows_pad)] >> sh) & 0xf) c = a;
     return c;
 }
 
@@ -56,7 +57,8 @@ struct RescoreArgs {
     float w_abs;
     const int8_t *onehot;
     int64_t rows_pad;
-    int KB, KB0, K0pad, N0, N1;
+    int KB, K0pad, Kpad, N0, N1, kobj;
+    bool fp4;
     double b0, b1;
     double *ig64;
     uint64_t *max64;
@@ -88,13 +90,13 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a)
         for (int d = 0; d < 2; ++d)
 #pragma unroll
             for (int c = 0; c < NC; ++c) cnt[d][c] = 0;
-        for (int kb = 0; kb < a.KB; ++kb) {
-            const int ps = kb * KBLK + lane;
-            const bool c0 = kb < a.KB0;
+        for (int ps = lane; ps < a.Kpad; ps += 64) {
+            const int kb = ps / a.kobj, e = ps % a.kobj;
+            const bool c0 = ps < a.K0pad;
             const bool valid = c0 ? (ps < a.N0) : (ps - a.K0pad < a.N1);
-            int cell = code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, x.v, lane) * C +
-                       code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, m1, lane);
-            if (K == 3) cell = cell * C + code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, m2, lane);
+            int cell = code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, x.v, e, a.fp4) * C +
+                       code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, m1, e, a.fp4);
+            if (K == 3) cell = cell * C + code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, m2, e, a.fp4);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 cnt[0][c] += (valid && c0 && cell == c) ? 1 : 0;
@@ -174,8 +176,10 @@ hipError_t launch_finalize(const Problem &P, float *ig_max, int32_t *argmax, int
     a.onehot = P.at<int8_t>(L.onehot);
     a.rows_pad = L.rows_pad;
     a.KB = P.KB;
-    a.KB0 = P.KB0;
     a.K0pad = P.K0pad;
+    a.Kpad = P.Kpad;
+    a.kobj = P.kobj;
+    a.fp4 = P.fp4;
     a.N0 = P.N0;
     a.N1 = P.N1;
     a.b0 = P.beta0;

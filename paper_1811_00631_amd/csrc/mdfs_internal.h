@@ -11,8 +11,16 @@
 
 namespace mdfs {
 
-// Objects are permuted class-0-first; each class is padded to a whole K block of 64 objects.
+// One-hot bytes per row and K block.  The int8 encoding holds 64 objects per K block (one byte
+// each), the E2M1 (fp4) encoding 128 (one nibble each).  Objects are permuted class-0-first and
+// each class is padded to a whole K block of the encoding in use.
 constexpr int KBLK = 64;
+constexpr int KOBJ_I8 = 64;
+constexpr int KOBJ_F4 = 128;
+// E2M1 bit pattern of 1.0 (sign 0, biased exponent 01, mantissa 0)
+constexpr uint32_t F4_ONE = 0x2u;
+// The fp4 engine accumulates n1 * 4096 + n0 in float32: exact while both classes are < 4096.
+constexpr int MAX_CLASS_OBJ_F4 = 4095;
 // Output rows of one sweep tile (one-hot rows = variables x (classes-1) bins).
 constexpr int TILE_ROWS = 128;
 // Variables are padded to a multiple of this (covers every tile width).
@@ -46,7 +54,7 @@ struct Layout {
     int64_t N, p, p_pad;
     int k, C, W;          // classes C = divisions+1, one-hot width W = C-1
     int R;
-    int KB_max;           // K blocks (64 objects) reserved: worst-case class padding
+    int64_t Kpad_max;     // class-sorted positions reserved: worst-case padding of either encoding
     int64_t rows_pad;     // p_pad * W
     int64_t cap;          // candidate capacity
     int64_t words_max;    // bitset words (32 objects) per class, worst case (k=3)
@@ -57,9 +65,10 @@ struct Layout {
 
 Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R);
 
-// Byte offset of (discretisation r, one-hot row, K block kb, object byte) in the panel-major
-// one-hot encoding [r][row / TILE_ROWS][kb][row % TILE_ROWS][KBLK]: the rows of one sweep
-// panel are contiguous over all K blocks, so a tile streams one contiguous run per operand.
+// Byte offset of (discretisation r, one-hot row, K block kb, byte) in the panel-major one-hot
+// encoding [r][row / TILE_ROWS][kb][row % TILE_ROWS][KBLK]: the rows of one sweep panel are
+// contiguous over all K blocks, so a tile streams one contiguous run per operand.  Position e of
+// a K block sits in byte e (int8) or in byte e / 2, low nibble for even e (fp4).
 __host__ __device__ inline int64_t onehot_off(int r, int64_t row, int kb, int byte, int KB, int64_t rows_pad)
 {
     const int64_t nrb = rows_pad / TILE_ROWS;
@@ -94,7 +103,10 @@ __host__ __device__ inline double tie_tau(double m) { return 1e-9 * (fabs(m) > 1
 // Everything a launch sequence needs about one problem (sizes, pseudocounts, buffers).
 struct Problem {
     Layout L;
-    int N0, N1, K0pad, KB0, KB;   // class sizes; class-0 padded size and K blocks
+    int N0, N1;                   // class sizes
+    bool fp4;                     // one-hot in E2M1 nibbles (else int8 bytes)
+    int kobj;                     // objects per K block: KOBJ_F4 or KOBJ_I8
+    int K0pad, Kpad, KB0, KB;     // class-0 padded size, all positions, K blocks (class 0, all)
     double beta0, beta1;
     int disc_offset;
     double range;

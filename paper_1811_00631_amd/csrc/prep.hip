@@ -25,7 +25,7 @@ Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
     L.C = divisions + 1;
     L.W = divisions;
     L.R = R;
-    L.KB_max = (int)((N + KBLK - 1) / KBLK + 1);
+    L.Kpad_max = (N + KOBJ_F4 - 1) / KOBJ_F4 * KOBJ_F4 + 2 * KOBJ_F4;
     L.rows_pad = L.p_pad * L.W;
     L.cap = (p * 256 > (1 << 20)) ? p * 256 : (1 << 20);
     L.words_max = (N + 31) / 32 + 1;
@@ -33,13 +33,13 @@ Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     L.status = take(sizeof(Status));
     L.pos = take(sizeof(int32_t) * N);
-    L.perm = take(sizeof(int32_t) * (size_t)L.KB_max * KBLK);
+    L.perm = take(sizeof(int32_t) * (size_t)L.Kpad_max);
     L.tabEA = take(sizeof(float) * (N + 1));
     L.tabEB = take(sizeof(float) * (N + 1));
     L.tabLQ = take(sizeof(float) * 2 * (N + 1));
     L.marg = take(sizeof(uint32_t) * (size_t)R * L.p_pad * L.C);
     L.F1 = take(sizeof(float) * (size_t)R * L.p_pad);
-    L.onehot = take((size_t)R * L.KB_max * L.rows_pad * KBLK);
+    L.onehot = take((size_t)R * L.Kpad_max * L.rows_pad);   // >= one byte per position
     L.G32 = take(sizeof(uint32_t) * L.p_pad);
     L.max64 = take(sizeof(uint64_t) * L.p_pad);
     L.keyw = take(sizeof(uint64_t) * L.p_pad);
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(1024) void k_class_perm(const uint8_t *__restrict__
 hipError_t launch_class_perm(const Problem &P, const uint8_t *y)
 {
     hipLaunchKernelGGL(k_class_perm, dim3(1), dim3(1024), 0, P.stream, y, (int)P.L.N, P.K0pad,
-                       P.KB * KBLK, P.at<int32_t>(P.L.pos), P.at<int32_t>(P.L.perm));
+                       P.Kpad, P.at<int32_t>(P.L.pos), P.at<int32_t>(P.L.perm));
     return hipGetLastError();
 }
 
@@ -247,14 +247,13 @@ constexpr int DISC_RCHUNK = 256;   // discretisations whose thresholds are stage
 template <int C>
 __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
     const float *__restrict__ data, int N, int p, int M, int R, int disc_offset, double range,
-    uint64_t seed, const int32_t *__restrict__ perm, int K0pad, int N0, int N1, int KB,
+    uint64_t seed, const int32_t *__restrict__ perm, int K0pad, int N0, int N1, int KB, int Kpad, int fp4,
     int64_t rows_pad, uint8_t *__restrict__ codes, int8_t *__restrict__ onehot,
     uint32_t *__restrict__ marg, float *__restrict__ F1, int64_t p_pad, double b0, double b1, Status *st,
     uint32_t *__restrict__ bits, int64_t words_max)
 {
     constexpr int W = C - 1;
     extern __shared__ float lds[];
-    const int Kpad = KB * KBLK;
     float *xcs = lds;                       // [Kpad]
     float *srt = xcs + Kpad;                // [M]
     float *thr = srt + M;                   // [DISC_RCHUNK][C-1]
@@ -312,19 +311,22 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
                 for (int n = t; n < N; n += DISC_THREADS) out[n] = (uint8_t)code_of<C>(x[n], th);
             }
             if (onehot) {
-                // dword = 4 consecutive class-sorted positions of one (k block, bin) row chunk
+                // dword q of one (K block, bin) row chunk: class-sorted positions
+                // kb * kobj + q * per .. + per - 1, one byte (int8 1) or one nibble (E2M1 1.0) each
                 const int ndw = KB * W * (KBLK / 4);
+                const int per = fp4 ? 8 : 4, kobj = fp4 ? KOBJ_F4 : KOBJ_I8;
                 for (int idx = t; idx < ndw; idx += DISC_THREADS) {
                     const int kb = idx / (W * (KBLK / 4));
                     const int a = (idx / (KBLK / 4)) % W;
                     const int q4 = idx % (KBLK / 4);
                     uint32_t word = 0;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int ps = kb * KBLK + q4 * 4 + e;
+                    for (int e = 0; e < 8; ++e) {
+                        if (e >= per) break;
+                        const int ps = kb * kobj + q4 * per + e;
                         const bool valid = (ps < N0) || (ps >= K0pad && ps < K0pad + N1);
                         const bool hit = valid && code_of<C>(xcs[ps], th) == a;
-                        word |= (hit ? 1u : 0u) << (8 * e);
+                        if (hit) word |= fp4 ? (F4_ONE << (4 * e)) : (1u << (8 * e));
                     }
                     int64_t row = (int64_t)v * W + a;
                     int64_t off = onehot_off(r, row, kb, q4 * 4, KB, rows_pad);
@@ -410,14 +412,14 @@ static hipError_t disc_launch(const Problem &P, const float *data, uint8_t *code
     int N = (int)L.N;
     int M = 1;
     while (M < N) M <<= 1;
-    int Kpad = P.KB * KBLK;
+    int Kpad = P.Kpad;
     size_t lds = sizeof(float) * ((size_t)Kpad + M + DISC_RCHUNK * (C - 1));
     auto kern = k_discretize<C>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((unsigned)L.p), dim3(DISC_THREADS), lds, P.stream, data, N, (int)L.p, M,
                        L.R, P.disc_offset, P.range, P.seed, encode ? P.at<int32_t>(L.perm) : nullptr, P.K0pad, P.N0, P.N1, P.KB,
-                       L.rows_pad, codes, encode ? P.at<int8_t>(L.onehot) : nullptr,
+                       P.Kpad, P.fp4 ? 1 : 0, L.rows_pad, codes, encode ? P.at<int8_t>(L.onehot) : nullptr,
                        encode ? P.at<uint32_t>(L.marg) : nullptr, encode ? P.at<float>(L.F1) : nullptr,
                        L.p_pad, P.beta0, P.beta1, P.at<Status>(L.status),
                        (encode && L.k == 3) ? P.at<uint32_t>(L.bits) : nullptr, L.words_max);

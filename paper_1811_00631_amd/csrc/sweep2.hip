@@ -3,12 +3,16 @@
 // Counting (the voxel counters N^d of section "Algorithm and implementation", named there the
 // most time-consuming part): with objects sorted by class and each variable one-hot encoded on
 // its first W = C-1 bins, the per-class pair tables are the Gram products X_d^T X_d.  A tile of
-// 128 x 128 one-hot rows is accumulated with V_MFMA_I32_16X16X64_I8 (int8 in, int32 out, exact
-// since counts <= N).  Both classes share one accumulator: class-1 objects are accumulated
-// first, the accumulator is shifted left by 16, then class-0 objects are added, so each int32
-// holds (n1 << 16) | n0 (each class < 32768 objects).  The dropped last bin of each variable
-// is rebuilt exactly from the per-class marginals (packed 16-bit subtraction never borrows
-// because every reconstructed count is >= 0).
+// 128 x 128 one-hot rows is accumulated on the matrix cores in one of two encodings:
+//   fp4:  E2M1 nibbles (1.0 = 0b0010), V_MFMA_F32_16X16X128_F8F6F4, float32 accumulators.
+//         Class-1 objects are accumulated first, the accumulator is scaled by 4096, then
+//         class-0 objects are added: n1 * 4096 + n0 < 2^24 is an exact float32 integer while
+//         each class has < 4096 objects.  Half the operand bytes and twice the rate of int8.
+//   int8: bytes, V_MFMA_I32_16X16X64_I8, int32 accumulators shifted left by 16 between the
+//         classes: (n1 << 16) | n0 for classes < 32768 objects.
+// Either way the epilogue works on packed integers n1 << SH | n0 (SH = 12 or 16).  The dropped
+// last bin of each variable is rebuilt exactly from the per-class marginals (packed
+// subtraction never borrows because every reconstructed count is >= 0).
 //
 // Epilogue (the pseudocounted entropy of the class-probability equation and IG of equation
 // IGmax): per pair F2 = sum_v n_v h(p_v) from float32 lookup tables indexed by integer counts,
@@ -22,6 +26,10 @@
 namespace mdfs {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+template <bool F4> struct AccOf { typedef v4i type; };
+template <> struct AccOf<true> { typedef v4f type; };
 
 constexpr int SW_THREADS = 256;          // 4 waves, 2 x 2 wave grid, 64 x 64 outputs per wave
 constexpr int SB = 8;                    // a super-tile is SB x SB tiles
@@ -63,9 +71,10 @@ enum SweepMode { SWEEP_MAX = 0, SWEEP_DEBUG_COUNTS = 1, SWEEP_PAIRS = 2 };
 // Swizzled LDS address of 16-byte chunk j (0..3) of tile row `row` (64 bytes per row).
 __device__ inline int lds_addr(int row, int j) { return row * KBLK + ((j ^ ((row >> 1) & 3)) << 4); }
 
+template <int SH>
 __device__ inline float vox_term(uint32_t P, const float *EA, const float *EB, const float2 *LQ)
 {
-    const uint32_t n0 = P & 0xffffu, n1 = P >> 16;
+    const uint32_t n0 = P & ((1u << SH) - 1u), n1 = P >> SH;
     const float2 lq = LQ[n0 + n1];
     return lq.x - lq.y * (EA[n0] + EB[n1]);
 }
@@ -86,10 +95,13 @@ __device__ inline void tri_index(int64_t tt, int &bi, int &bj)
     bi = (int)(tt - j * (j + 1) / 2);
 }
 
-template <int W, int MODE>
+template <int W, int MODE, bool F4>
 __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
 {
     constexpr int C = W + 1;
+    constexpr int SH = F4 ? 12 : 16;     // packing n1 << SH | n0 of the counts
+    constexpr uint32_t MASK = (1u << SH) - 1u;
+    typedef typename AccOf<F4>::type Acc;
     constexpr int TV = TILE_ROWS / W;    // variables per tile side
     constexpr int NP = (W == 1) ? 4 : 1; // pairs held per lane per 16x16 block
     extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -139,11 +151,11 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     const int sA0 = lds_addr(ra0, ja0), sA1 = lds_addr(ra1, ja1);
     constexpr int kstride = TILE_ROWS * KBLK;
 
-    v4i acc[4][4];
+    Acc acc[4][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) acc[m][n] = v4i{0, 0, 0, 0};
+        for (int n = 0; n < 4; ++n) acc[m][n] = Acc{0, 0, 0, 0};
 
     // K blocks in processing order: class 1 first, then class 0
     auto kblock = [&](int s_) { return s_ < n1blk ? a.KB0 + s_ : s_ - n1blk; };
@@ -189,12 +201,25 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int n = 0; n < 4; ++n)
-                acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[m], fb[n], acc[m][n], 0, 0, 0);
+            {
+                if constexpr (F4) {
+                    // A/B: 16 rows x 128 objects, lane l holds row l % 16, 32 nibbles of
+                    // objects 32 (l / 16) ..; cbsz = blgp = 4 selects E2M1 for both operands
+                    const v8i a8{fa[m][0], fa[m][1], fa[m][2], fa[m][3], 0, 0, 0, 0};
+                    const v8i b8{fb[n][0], fb[n][1], fb[n][2], fb[n][3], 0, 0, 0, 0};
+                    acc[m][n] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, b8, acc[m][n], 4, 4, 0, 0, 0, 0);
+                } else {
+                    acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[m], fb[n], acc[m][n], 0, 0, 0);
+                }
+            }
         if (s_ == n1blk - 1) {
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int n = 0; n < 4; ++n) acc[m][n] = acc[m][n] << 16;
+                for (int n = 0; n < 4; ++n) {
+                    if constexpr (F4) acc[m][n] = acc[m][n] * 4096.0f;
+                    else acc[m][n] = acc[m][n] << 16;
+                }
         }
         if (s_ + 2 < a.KB) st4(s_ + 2, x0, x1, x2, x3);
         __syncthreads();
@@ -207,6 +232,19 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     if (s < a.KB) kstep(s, g0, g1, g2, g3, h0, h1, h2, h3);
 
     // ---------------------------------------------------------------- epilogue
+    // packed integer counts n1 << SH | n0 (float32 accumulators hold exact integers < 2^24)
+    v4i cnt[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            if constexpr (F4) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) cnt[m][n][e] = (int)(uint32_t)acc[m][n][e];
+            } else {
+                cnt[m][n] = acc[m][n];
+            }
+        }
     // Lane geometry of the 16x16 output block (m, n): lane holds rows 4q..4q+3 of column c16.
     // Row/column index = variable * W + bin within the block.
     const int64_t I0 = (int64_t)bi * TV, J0 = (int64_t)bj * TV;
@@ -222,6 +260,8 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     const uint32_t *margr = a.marg + (int64_t)r * a.p_pad * C;
     const float *F1r = a.F1 + (int64_t)r * a.p_pad;
 
+    // marginals are stored n1 << 16 | n0; repack to the accumulators' SH
+    auto repack = [](uint32_t x) -> uint32_t { return SH == 16 ? x : ((x >> 16) << SH) | (x & 0xffffu); };
     uint32_t Mr[4][NP][C], Mc[4][C];
     float Fr[4][NP], Fc[4];
     float thrR[4][NP], thrC[4];
@@ -231,7 +271,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
         for (int s = 0; s < NP; ++s) {
             int64_t v = row_var(m, s);
 #pragma unroll
-            for (int c = 0; c < C; ++c) Mr[m][s][c] = margr[v * C + c];
+            for (int c = 0; c < C; ++c) Mr[m][s][c] = repack(margr[v * C + c]);
             Fr[m][s] = F1r[v];
             float gk = key_f32(a.G32[v]);
             thrR[m][s] = gk - rescore_window(a.w_abs, gk);
@@ -240,7 +280,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     for (int n = 0; n < 4; ++n) {
         int64_t v = col_var(n);
 #pragma unroll
-        for (int c = 0; c < C; ++c) Mc[n][c] = margr[v * C + c];
+        for (int c = 0; c < C; ++c) Mc[n][c] = repack(margr[v * C + c]);
         Fc[n] = F1r[v];
         float gk = key_f32(a.G32[v]);
         thrC[n] = gk - rescore_window(a.w_abs, gk);
@@ -248,7 +288,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
 
     // Full per-class table of the lane's pair(s) in block (m, n): packed counts tab[a][b].
     auto pair_table = [&](int m, int n, int s, uint32_t (&tab)[C][C]) {
-        const v4i &ac = acc[m][n];
+        const v4i &ac = cnt[m][n];
         if constexpr (W == 1) {
             uint32_t n00 = (uint32_t)ac[s];
             tab[0][0] = n00;
@@ -275,7 +315,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
 #pragma unroll
         for (int x = 0; x < C; ++x)
 #pragma unroll
-            for (int y = 0; y < C; ++y) F += vox_term(tab[x][y], EA, EB, LQ);
+            for (int y = 0; y < C; ++y) F += vox_term<SH>(tab[x][y], EA, EB, LQ);
         return F;
     };
 
@@ -307,7 +347,8 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
 #pragma unroll
                         for (int x = 0; x < W; ++x)
 #pragma unroll
-                            for (int y = 0; y < W; ++y) o[x * W + y] = tab[x][y];
+                            for (int y = 0; y < W; ++y)
+                                o[x * W + y] = ((tab[x][y] >> SH) << 16) | (tab[x][y] & MASK);
                         a.F2out[rv * a.p_pad + cv] = F2;
                     }
                     continue;
@@ -324,8 +365,8 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
                     for (int x = 0; x < C; ++x)
 #pragma unroll
                         for (int y = 0; y < C; ++y) {
-                            o[x * C + y] = (int32_t)(tab[x][y] & 0xffffu);
-                            o[C * C + x * C + y] = (int32_t)(tab[x][y] >> 16);
+                            o[x * C + y] = (int32_t)(tab[x][y] & MASK);
+                            o[C * C + x * C + y] = (int32_t)(tab[x][y] >> SH);
                         }
                 }
             }
@@ -374,7 +415,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(acc[m][n]) : : "memory");
+            for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(cnt[m][n]) : : "memory");
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -415,7 +456,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     }   // work items
 }
 
-template <int W>
+template <int W, bool F4>
 static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r)
 {
     const Layout &L = P.L;
@@ -453,8 +494,8 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
     a.disc_sel = disc_sel;
     a.collect = collect ? 1 : 0;
     size_t lds = NSTAGE * STAGE_BYTES + sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (L.N + 1) + 16;
-    auto kern = pair_r >= 0 ? k_sweep2<W, SWEEP_PAIRS>
-                            : (counts_out ? k_sweep2<W, SWEEP_DEBUG_COUNTS> : k_sweep2<W, SWEEP_MAX>);
+    auto kern = pair_r >= 0 ? k_sweep2<W, SWEEP_PAIRS, F4>
+                            : (counts_out ? k_sweep2<W, SWEEP_DEBUG_COUNTS, F4> : k_sweep2<W, SWEEP_MAX, F4>);
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int grid = XCDS * WG_PER_XCD;
@@ -462,22 +503,25 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
     return hipGetLastError();
 }
 
-hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bool collect)
+template <bool F4>
+static hipError_t sweep_dispatch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r)
 {
     switch (P.L.W) {
-    case 1: return sweep_launch<1>(P, counts_out, disc_sel, collect, -1);
-    case 2: return sweep_launch<2>(P, counts_out, disc_sel, collect, -1);
+    case 1: return sweep_launch<1, F4>(P, counts_out, disc_sel, collect, pair_r);
+    case 2: return sweep_launch<2, F4>(P, counts_out, disc_sel, collect, pair_r);
     default: return hipErrorInvalidValue;
     }
 }
 
+hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bool collect)
+{
+    return P.fp4 ? sweep_dispatch<true>(P, counts_out, disc_sel, collect, -1)
+                 : sweep_dispatch<false>(P, counts_out, disc_sel, collect, -1);
+}
+
 hipError_t launch_pairs(const Problem &P, int r)
 {
-    switch (P.L.W) {
-    case 1: return sweep_launch<1>(P, nullptr, -1, false, r);
-    case 2: return sweep_launch<2>(P, nullptr, -1, false, r);
-    default: return hipErrorInvalidValue;
-    }
+    return P.fp4 ? sweep_dispatch<true>(P, nullptr, -1, false, r) : sweep_dispatch<false>(P, nullptr, -1, false, r);
 }
 
 }  // namespace mdfs

@@ -26,7 +26,7 @@ MDFS_OK = 0
 STATUS = {0: "MDFS_OK", -1: "MDFS_E_ARG", -2: "MDFS_E_Y", -3: "MDFS_E_K", -4: "MDFS_E_DIV",
           -5: "MDFS_E_NAN", -6: "MDFS_E_NOMEM", -7: "MDFS_E_HIP", -8: "MDFS_E_LIMIT",
           -9: "MDFS_E_OVERFLOW"}
-ENGINES = {"auto": 0, "mfma": 1, "bitset": 2}
+ENGINES = {"auto": 0, "mfma": 1, "bitset": 2, "mfma_fp4": 3}
 
 
 class MdfsError(RuntimeError):
@@ -171,11 +171,11 @@ def mdfs_max_ig(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_d
 
 
 def mdfs_pair_counts(data: torch.Tensor, y: torch.Tensor, disc: int, divisions: int, n_disc: int,
-                     range_: float = 0.5, seed: int = 0, disc_offset: int = 0) -> torch.Tensor:
+                     range_: float = 0.5, seed: int = 0, disc_offset: int = 0, engine: str = "auto") -> torch.Tensor:
     data, y = _dev_inputs(data, y)
     n_var, n_obj = data.shape
     c = divisions + 1
-    prm = make_params(n_obj, n_var, 2, divisions, n_disc, disc_offset, range_, 0.25, seed)
+    prm = make_params(n_obj, n_var, 2, divisions, n_disc, disc_offset, range_, 0.25, seed, engine)
     ws = workspace_for(prm, data.device)
     counts = torch.zeros((n_var, n_var, 2, c, c), dtype=torch.int32, device=data.device)
     _check(load().mdfs_pair_counts(ctypes.byref(prm), _ptr(data), _ptr(y), int(disc), _ptr(counts), _ptr(ws),
@@ -184,10 +184,11 @@ def mdfs_pair_counts(data: torch.Tensor, y: torch.Tensor, disc: int, divisions: 
 
 
 def mdfs_screen_max(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_disc: int,
-                    pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0, disc_offset: int = 0):
+                    pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0, disc_offset: int = 0,
+                    engine: str = "auto"):
     data, y = _dev_inputs(data, y)
     n_var, n_obj = data.shape
-    prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed)
+    prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed, engine)
     ws = workspace_for(prm, data.device)
     ig32 = torch.empty(n_var, dtype=torch.float32, device=data.device)
     eb = ctypes.c_double(0.0)

@@ -47,11 +47,12 @@ def test_workspace_size_valid_and_monotone():
     (dict(k=4), -3), (dict(k=1), -3), (dict(divisions=3), -4), (dict(divisions=0), -4), (dict(divisions=4), -8),
     (dict(n_obj=2, divisions=2), -1), (dict(n_obj=20000), -8), (dict(range_=1.5), -1),
     (dict(range_=-0.1), -1), (dict(pseudocount=-1.0), -1), (dict(n_disc=0), -1),
-    (dict(disc_offset=-1), -1), (dict(n_var=1), -1),
+    (dict(disc_offset=-1), -1), (dict(n_var=1), -1), (dict(k=3, engine="mfma_fp4"), -8),
+    (dict(k=3, engine="mfma"), -8), (dict(engine="bitset"), -8),
 ])
 def test_invalid_params_rejected_on_host(kw, code):
     base = dict(n_obj=100, n_var=10, k=2, divisions=2, n_disc=1, disc_offset=0, range_=0.5,
-                pseudocount=0.25, seed=0)
+                pseudocount=0.25, seed=0, engine="auto")
     base.update(kw)
     prm = mdfs.make_params(**base)
     lib = mdfs.load()
@@ -78,3 +79,13 @@ def test_small_workspace_rejected_on_host():
     fake = ctypes.c_void_p(0x1000)
     rc = lib.mdfs_discretize(ctypes.byref(prm), fake, fake, fake, 16, null := ctypes.c_void_p(0))
     assert rc == -6 and "workspace" in lib.mdfs_last_error().decode()
+
+
+def test_unknown_engine_rejected_on_host():
+    lib = mdfs.load()
+    prm = mdfs.make_params(100, 10, 2, 2, 1)
+    prm.engine = 4
+    null = ctypes.c_void_p(0)
+    assert lib.mdfs_workspace_size(ctypes.byref(prm)) == 0
+    assert lib.mdfs_max_ig(ctypes.byref(prm), null, null, null, null, null, null, 0, null) == -1
+    assert "engine" in lib.mdfs_last_error().decode()

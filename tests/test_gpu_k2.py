@@ -1,7 +1,9 @@
 """k = 2 sweep on the GPU through the C ABI, against the FP64 oracle.
 
 Bars: discretisation codes and voxel counts bit-exact; IG_max within
-1e-4 * max(|IG|, 1) of the oracle; argmax tuple and discretisation exact.
+1e-4 * max(|IG|, 1) of the oracle; argmax tuple and discretisation exact.  Both one-hot
+encodings of the pair contraction are covered: "mfma_fp4" (E2M1, float32 accumulation; what
+"auto" picks while each class has < 4096 objects) and "mfma" (int8).
 """
 import numpy as np
 import pytest
@@ -13,6 +15,7 @@ from paper_1811_00631_amd import workloads
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 IG_TOL = 1e-4
+ENGINES = ["mfma_fp4", "mfma"]
 
 
 def to_dev(w):
@@ -31,11 +34,12 @@ def assert_ig_parity(ig, am, ad, ref, label=""):
                            f"oracle {ref_am[bad[:3]]} r{ref_ad[bad[:3]]}")
 
 
-def run_gpu(mdfs, w, n_disc=None, xi=None, rng=None, seed=None, divisions=None, disc_offset=0):
+def run_gpu(mdfs, w, n_disc=None, xi=None, rng=None, seed=None, divisions=None, disc_offset=0, engine="auto"):
     data, y = to_dev(w)
     out = mdfs.mdfs_max_ig(data, y, 2, w.divisions if divisions is None else divisions,
                            w.n_disc if n_disc is None else n_disc, w.xi if xi is None else xi,
-                           w.range_ if rng is None else rng, w.seed if seed is None else seed, disc_offset)
+                           w.range_ if rng is None else rng, w.seed if seed is None else seed, disc_offset,
+                           engine=engine)
     torch.cuda.synchronize()
     return [t.cpu().numpy() for t in out]
 
@@ -56,13 +60,16 @@ def test_codes_bit_exact(mdfs_gpu, n_obj, n_var, div, R, rng):
 
 
 # ------------------------------------------------------------------ counts
-@pytest.mark.parametrize("n_obj,n_var,div,ones", [(300, 150, 2, None), (257, 131, 1, 40), (130, 70, 2, 1)])
-def test_pair_counts_bit_exact(mdfs_gpu, n_obj, n_var, div, ones):
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("n_obj,n_var,div,ones", [(300, 150, 2, None), (257, 131, 1, 40), (130, 70, 2, 1),
+                                                  (4095 + 129, 20, 2, 4095)])
+def test_pair_counts_bit_exact(mdfs_gpu, engine, n_obj, n_var, div, ones):
+    # the last case puts 4095 objects (the fp4 maximum) in class 1 and 129 in class 0
     w = workloads.null_data(5, n_obj, n_var, ones=ones)
     data, y = to_dev(w)
     R, disc = 2, 1
-    print(f"counts N={n_obj} p={n_var} div={div}", flush=True)
-    counts = mdfs_gpu.mdfs_pair_counts(data, y, disc, div, R, 0.5, 9).cpu().numpy()
+    print(f"counts {engine} N={n_obj} p={n_var} div={div}", flush=True)
+    counts = mdfs_gpu.mdfs_pair_counts(data, y, disc, div, R, 0.5, 9, engine=engine).cpu().numpy()
     codes = oracle.discretize(w.data, div, R, 0.5, 9)[disc]
     c = div + 1
     for i in range(n_var):
@@ -83,11 +90,12 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("name", list(CASES))
-def test_max_ig_matches_oracle(mdfs_gpu, name):
+def test_max_ig_matches_oracle(mdfs_gpu, name, engine):
     w = CASES[name]()
-    print(f"max_ig {name} N={w.n_obj} p={w.n_var} R={w.n_disc}", flush=True)
-    got = run_gpu(mdfs_gpu, w)
+    print(f"max_ig {name} {engine} N={w.n_obj} p={w.n_var} R={w.n_disc}", flush=True)
+    got = run_gpu(mdfs_gpu, w, engine=engine)
     ref = oracle.max_ig_all(w.data, w.y, 2, w.divisions, w.n_disc, w.range_, w.xi, w.seed, n_threads=8)
     assert_ig_parity(*got, ref, name)
 
@@ -110,10 +118,11 @@ def test_exact_ties_follow_tie_rule(mdfs_gpu):
     assert got[1][0, 0] == 1 and got[2][0] == 0
 
 
-def test_screen_within_error_bound(mdfs_gpu):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_screen_within_error_bound(mdfs_gpu, engine):
     w = workloads.madelon_like(seed=12, n_obj=700, n_noise=60, n_disc=3)
     data, y = to_dev(w)
-    ig32, E = mdfs_gpu.mdfs_screen_max(data, y, 2, 2, 3, 0.25, 0.5, w.seed)
+    ig32, E = mdfs_gpu.mdfs_screen_max(data, y, 2, 2, 3, 0.25, 0.5, w.seed, engine=engine)
     ig32 = ig32.cpu().numpy().astype(np.float64)
     ref, _, _ = oracle.max_ig_all(w.data, w.y, 2, 2, 3, 0.5, 0.25, w.seed, n_threads=8)
     err = np.abs(ig32 - ref)
@@ -162,11 +171,11 @@ def sampled_targets(w, n_random, seed):
     return np.array(sorted(planted[:6] + g.choice(rest, n_random, replace=False).tolist()), dtype=np.int64)
 
 
-@pytest.mark.parametrize("which", ["headline", "genomics_like"])
-def test_full_size_sampled(mdfs_gpu, which):
+@pytest.mark.parametrize("which,engine", [("headline", "auto"), ("headline", "mfma"), ("genomics_like", "auto")])
+def test_full_size_sampled(mdfs_gpu, which, engine):
     w = workloads.headline() if which == "headline" else workloads.genomics_like(seed=4)
-    print(f"full-size {which}: N={w.n_obj} p={w.n_var} R={w.n_disc}", flush=True)
-    ig, am, ad = run_gpu(mdfs_gpu, w)
+    print(f"full-size {which} {engine}: N={w.n_obj} p={w.n_var} R={w.n_disc}", flush=True)
+    ig, am, ad = run_gpu(mdfs_gpu, w, engine=engine)
     assert np.isfinite(ig).all()
     # every planted pair finds its partner
     for a_, b_ in w.planted["pairs"]:
@@ -191,3 +200,16 @@ def test_candidate_overflow_falls_back_to_collect_pass(mdfs_gpu, monkeypatch):
     with pytest.raises(mdfs_gpu.MdfsError) as e:
         run_gpu(mdfs_gpu, w)
     assert e.value.code == -9
+
+
+def test_large_classes_use_int8_and_fp4_refuses_them(mdfs_gpu):
+    # 4096 objects in class 1: float32 packing n1 * 4096 + n0 would no longer be exact, so
+    # "auto" must take the int8 encoding (parity shows it did) and "mfma_fp4" must refuse
+    w = workloads.null_data(14, 4096 + 300, 48, ones=4096)
+    print(f"large classes N={w.n_obj} p={w.n_var}", flush=True)
+    got = run_gpu(mdfs_gpu, w, n_disc=2)
+    ref = oracle.max_ig_all(w.data, w.y, 2, w.divisions, 2, w.range_, w.xi, w.seed, n_threads=8)
+    assert_ig_parity(*got, ref, "large classes")
+    with pytest.raises(mdfs_gpu.MdfsError) as e:
+        run_gpu(mdfs_gpu, w, n_disc=2, engine="mfma_fp4")
+    assert e.value.code == -8
