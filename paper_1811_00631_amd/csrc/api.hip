@@ -183,6 +183,12 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
         P.KB0 = P.K0pad / P.kobj;
         P.KB = P.KB0 + (P.N1 + P.kobj - 1) / P.kobj;
         P.Kpad = P.KB * P.kobj;
+        // the pair sweep keeps its entropy tables in LDS next to the operand stages
+        const size_t lds = sweep2_lds_bytes(P, false) > sweep2_lds_bytes(P, true) ? sweep2_lds_bytes(P, false)
+                                                                                  : sweep2_lds_bytes(P, true);
+        if (lds > LDS_MAX)
+            return fail(MDFS_E_LIMIT, "n_obj=%lld: the int8 sweep's LDS tables need %zu bytes > %zu",
+                        (long long)N, lds, LDS_MAX);
         const int C = prm->divisions + 1;
         P.err_bound = screen_err_bound(N, P.beta0, P.beta1, C * C);
         // k = 3: the triple's own F (C^3 voxels) plus the float32 F of the parent pair

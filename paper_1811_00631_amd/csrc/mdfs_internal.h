@@ -17,9 +17,10 @@ namespace mdfs {
 constexpr int KBLK = 64;
 constexpr int KOBJ_I8 = 64;
 constexpr int KOBJ_F4 = 128;
-// E2M1 bit pattern of 1.0 (sign 0, biased exponent 01, mantissa 0)
-constexpr uint32_t F4_ONE = 0x2u;
-// The fp4 engine accumulates n1 * 4096 + n0 in float32: exact while both classes are < 4096.
+// E2M1 bit pattern of 2.0 (sign 0, biased exponent 10, mantissa 0): the fp4 one-hot value,
+// so that each product is 4 and counts arrive as byte offsets of float tables.
+constexpr uint32_t F4_TWO = 0x4u;
+// The fp4 engine accumulates n1 * 2^14 + 4 n0 in float32: exact while both classes are < 4096.
 constexpr int MAX_CLASS_OBJ_F4 = 4095;
 // Output rows of one sweep tile (one-hot rows = variables x (classes-1) bins).
 constexpr int TILE_ROWS = 128;
@@ -123,6 +124,9 @@ hipError_t launch_class_perm(const Problem &P, const uint8_t *y);
 hipError_t launch_tables(const Problem &P);
 hipError_t launch_discretize(const Problem &P, const float *data, uint8_t *codes, bool encode);
 hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bool collect = false);
+// LDS bytes per workgroup of the pair sweep (max_mode: the maximum sweep, else debug/pair modes)
+size_t sweep2_lds_bytes(const Problem &P, bool max_mode);
+constexpr size_t LDS_MAX = 160 * 1024;
 hipError_t launch_reset_candidates(const Problem &P);
 hipError_t launch_pairs(const Problem &P, int r);
 hipError_t launch_sweep3(const Problem &P, int r, bool collect);

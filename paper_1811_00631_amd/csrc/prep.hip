@@ -326,7 +326,7 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
                         const int ps = kb * kobj + q4 * per + e;
                         const bool valid = (ps < N0) || (ps >= K0pad && ps < K0pad + N1);
                         const bool hit = valid && code_of<C>(xcs[ps], th) == a;
-                        if (hit) word |= fp4 ? (F4_ONE << (4 * e)) : (1u << (8 * e));
+                        if (hit) word |= fp4 ? (F4_TWO << (4 * e)) : (1u << (8 * e));
                     }
                     int64_t row = (int64_t)v * W + a;
                     int64_t off = onehot_off(r, row, kb, q4 * 4, KB, rows_pad);

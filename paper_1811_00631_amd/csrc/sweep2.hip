@@ -4,15 +4,17 @@
 // most time-consuming part): with objects sorted by class and each variable one-hot encoded on
 // its first W = C-1 bins, the per-class pair tables are the Gram products X_d^T X_d.  A tile of
 // 128 x 128 one-hot rows is accumulated on the matrix cores in one of two encodings:
-//   fp4:  E2M1 nibbles (1.0 = 0b0010), V_MFMA_F32_16X16X128_F8F6F4, float32 accumulators.
-//         Class-1 objects are accumulated first, the accumulator is scaled by 4096, then
-//         class-0 objects are added: n1 * 4096 + n0 < 2^24 is an exact float32 integer while
-//         each class has < 4096 objects.  Half the operand bytes and twice the rate of int8.
-//   int8: bytes, V_MFMA_I32_16X16X64_I8, int32 accumulators shifted left by 16 between the
-//         classes: (n1 << 16) | n0 for classes < 32768 objects.
-// Either way the epilogue works on packed integers n1 << SH | n0 (SH = 12 or 16).  The dropped
-// last bin of each variable is rebuilt exactly from the per-class marginals (packed
-// subtraction never borrows because every reconstructed count is >= 0).
+//   fp4:  E2M1 nibbles holding 2.0 (0b0100), V_MFMA_F32_16X16X128_F8F6F4, float32
+//         accumulators; every product is 4.  Class-1 objects are accumulated first, the
+//         accumulator is scaled by 4096, then class-0 objects are added: n1 * 2^14 + 4 n0 <
+//         2^26, a multiple of 4, is an exact float32 value while each class has < 4096
+//         objects.  Half the operand bytes and twice the rate of int8.  The epilogue converts
+//         it to the packed integer (4 n1) << 16 | 4 n0, whose halves are byte offsets into
+//         the float tables.
+//   int8: bytes holding 1, V_MFMA_I32_16X16X64_I8, int32 accumulators shifted left by 16
+//         between the classes: n1 << 16 | n0 for classes < 32768 objects.
+// The dropped last bin of each variable is rebuilt exactly from the per-class marginals
+// (packed subtraction never borrows because every reconstructed count is >= 0).
 //
 // Epilogue (the pseudocounted entropy of the class-probability equation and IG of equation
 // IGmax): per pair F2 = sum_v n_v h(p_v) from float32 lookup tables indexed by integer counts,
@@ -30,6 +32,13 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 template <bool F4> struct AccOf { typedef v4i type; };
 template <> struct AccOf<true> { typedef v4f type; };
+
+// Template argument ENC of the sweep: 0 = int8 encoding (entropy tables placed at run time
+// after the operand stages); T = 1024, 2048, 4096 = fp4 encoding with LDS entropy tables of
+// capacity T per class at fixed addresses, so each lookup is one ds_read with an immediate
+// offset:  EA [0, 4T)  EB [4T, 8T)  (L, Q) pairs [8T, 24T - 8)  (bytes; the pairs hold the
+// 2T - 1 entries n = 0 .. 2T - 2), operand stages from 24T.
+__host__ __device__ constexpr int stage_base(int ENC) { return ENC ? 24 * ENC : 0; }
 
 constexpr int SW_THREADS = 256;          // 4 waves, 2 x 2 wave grid, 64 x 64 outputs per wave
 constexpr int SB = 8;                    // a super-tile is SB x SB tiles
@@ -61,6 +70,7 @@ struct Sweep2Args {
     int disc_sel;
     int collect;             // second pass: G32 holds the final maxima; append only
     int r_base;              // first discretisation of this launch
+    int snext_off;           // LDS byte offset of the work-item broadcast slot
     uint32_t *ptab;          // pair mode: packed (W x W) counts [p_pad][p_pad][W*W]
     float *F2out;            // pair mode: float32 F of each pair table [p_pad][p_pad]
 };
@@ -71,13 +81,15 @@ enum SweepMode { SWEEP_MAX = 0, SWEEP_DEBUG_COUNTS = 1, SWEEP_PAIRS = 2 };
 // Swizzled LDS address of 16-byte chunk j (0..3) of tile row `row` (64 bytes per row).
 __device__ inline int lds_addr(int row, int j) { return row * KBLK + ((j ^ ((row >> 1) & 3)) << 4); }
 
-template <int SH>
+// One voxel's n h(p) from the float32 tables, int8 packing n1 << 16 | n0.
 __device__ inline float vox_term(uint32_t P, const float *EA, const float *EB, const float2 *LQ)
 {
-    const uint32_t n0 = P & ((1u << SH) - 1u), n1 = P >> SH;
+    const uint32_t n0 = P & 0xffffu, n1 = P >> 16;
     const float2 lq = LQ[n0 + n1];
     return lq.x - lq.y * (EA[n0] + EB[n1]);
 }
+
+
 
 __device__ inline float rescore_window(float w_abs, float g)
 {
@@ -95,28 +107,38 @@ __device__ inline void tri_index(int64_t tt, int &bi, int &bj)
     bi = (int)(tt - j * (j + 1) / 2);
 }
 
-template <int W, int MODE, bool F4>
-__global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
+template <int W, int MODE, int ENC>
+__global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep2(Sweep2Args a)
 {
+    constexpr bool F4 = ENC != 0;
+    constexpr int T = ENC;
     constexpr int C = W + 1;
-    constexpr int SH = F4 ? 12 : 16;     // packing n1 << SH | n0 of the counts
-    constexpr uint32_t MASK = (1u << SH) - 1u;
     typedef typename AccOf<F4>::type Acc;
     constexpr int TV = TILE_ROWS / W;    // variables per tile side
     constexpr int NP = (W == 1) ? 4 : 1; // pairs held per lane per 16x16 block
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    char *stage = smem;                  // [NSTAGE buffers][A 8 KB | B 8 KB]
+    char *stage = smem + stage_base(ENC);   // [NSTAGE buffers][A 8 KB | B 8 KB]
+    // int8: tables after the stages, at run-time offsets
     float *EA = reinterpret_cast<float *>(smem + NSTAGE * STAGE_BYTES);
     float *EB = EA + (a.N0 + 1);
     float2 *LQ = reinterpret_cast<float2 *>(EB + (a.N1 + 1) + ((a.N0 + a.N1) & 1));
+    int64_t *s_next_p = reinterpret_cast<int64_t *>(smem + a.snext_off);
 
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wr = wave >> 1, wc = wave & 1;
     const int q = lane >> 4, c16 = lane & 15;
 
-    for (int i = t; i <= a.N0; i += SW_THREADS) EA[i] = a.EA[i];
-    for (int i = t; i <= a.N1; i += SW_THREADS) EB[i] = a.EB[i];
-    for (int i = t; i <= a.N; i += SW_THREADS) LQ[i] = a.LQ[i];
+    if constexpr (F4) {
+        float *tf = reinterpret_cast<float *>(smem);
+        for (int i = t; i <= a.N0; i += SW_THREADS) tf[i] = a.EA[i];
+        for (int i = t; i <= a.N1; i += SW_THREADS) tf[T + i] = a.EB[i];
+        float2 *lq = reinterpret_cast<float2 *>(smem + 8 * T);
+        for (int i = t; i <= a.N; i += SW_THREADS) lq[i] = a.LQ[i];
+    } else {
+        for (int i = t; i <= a.N0; i += SW_THREADS) EA[i] = a.EA[i];
+        for (int i = t; i <= a.N1; i += SW_THREADS) EB[i] = a.EB[i];
+        for (int i = t; i <= a.N; i += SW_THREADS) LQ[i] = a.LQ[i];
+    }
 
     // Persistent, XCD-aware schedule.  The super-tiles sup = x, x+8, x+16 ... belong to XCD x;
     // the workgroups resident on that XCD take its tiles (super-tile by super-tile, slot by
@@ -124,12 +146,11 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     // tiles and share its SB row panels and SB column panels in the XCD's L2.
     const int xcd = (int)(__builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 7);  // HW_REG_XCC_ID
     const int64_t n_mine = ((a.n_super - xcd + XCDS - 1) / XCDS) * (SB * SB);
-    __shared__ int64_t s_next;
     for (;;) {
     __syncthreads();   // everyone has read the previous s_next
-    if (t == 0) s_next = atomicAdd(&a.st->next_tile[xcd], 1u);
+    if (t == 0) *s_next_p = atomicAdd(&a.st->next_tile[xcd], 1u);
     __syncthreads();
-    const int64_t item = s_next;
+    const int64_t item = *s_next_p;
     if (item >= n_mine) break;
     const int64_t sup = xcd + XCDS * (item / (SB * SB));
     const int slot = (int)(item % (SB * SB));
@@ -145,10 +166,6 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     const int8_t *panA = a.onehot + ((int64_t)r * nrb + bi) * a.KB * TILE_ROWS * KBLK;
     const int8_t *panB = a.onehot + ((int64_t)r * nrb + bj) * a.KB * TILE_ROWS * KBLK;
     const int n1blk = a.KB - a.KB0;      // class-1 K blocks, accumulated first
-    // this thread's two 16-byte chunks of the A tile and two of the B tile
-    const int ra0 = t >> 2, ja0 = t & 3, ra1 = (t + SW_THREADS) >> 2, ja1 = (t + SW_THREADS) & 3;
-    const int offA0 = ra0 * KBLK + ja0 * 16, offA1 = ra1 * KBLK + ja1 * 16;
-    const int sA0 = lds_addr(ra0, ja0), sA1 = lds_addr(ra1, ja1);
     constexpr int kstride = TILE_ROWS * KBLK;
 
     Acc acc[4][4];
@@ -160,23 +177,26 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     // K blocks in processing order: class 1 first, then class 0
     auto kblock = [&](int s_) { return s_ < n1blk ? a.KB0 + s_ : s_ - n1blk; };
     auto stage_at = [&](int s_) { return stage + (s_ % NSTAGE) * STAGE_BYTES; };
-    // Software pipeline over a ring of NSTAGE LDS stages.  Iteration s: global loads of block
-    // s+3 go out, the fragments of block s are read from LDS and multiplied, and block s+2
-    // (loaded one iteration earlier) is written to LDS; one barrier per iteration.
-    v4i g0, g1, g2, g3, h0, h1, h2, h3;
-    auto gl = [&](int s_, v4i &x0, v4i &x1, v4i &x2, v4i &x3) {
-        const int64_t kb_off = (int64_t)kblock(s_) * kstride;
-        x0 = *reinterpret_cast<const v4i *>(panA + kb_off + offA0);
-        x1 = *reinterpret_cast<const v4i *>(panA + kb_off + offA1);
-        x2 = *reinterpret_cast<const v4i *>(panB + kb_off + offA0);
-        x3 = *reinterpret_cast<const v4i *>(panB + kb_off + offA1);
-    };
-    auto st4 = [&](int s_, const v4i &x0, const v4i &x1, const v4i &x2, const v4i &x3) {
-        char *A = stage_at(s_), *B = A + TILE_ROWS * KBLK;
-        *reinterpret_cast<v4i *>(A + sA0) = x0;
-        *reinterpret_cast<v4i *>(A + sA1) = x1;
-        *reinterpret_cast<v4i *>(B + sA0) = x2;
-        *reinterpret_cast<v4i *>(B + sA1) = x3;
+    // Operands go from global memory straight into LDS (global_load_lds_dwordx4): one
+    // instruction fills 1 KB = 16 rows, lane i's 16 bytes landing at offset 16 i.  A stage is
+    // 16 such blocks (A rows 0..127, then B rows 0..127); wave w fills blocks 4w .. 4w+3, so
+    // waves 0-1 fetch the A panel and waves 2-3 the B panel.  The swizzle of the stage layout
+    // is applied on the global side: lane i fetches the chunk that belongs at its slot.
+    const int8_t *pan = wave < 2 ? panA : panB;
+    int goff[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = 16 * ((wave * 4 + i) & 7) + (lane >> 2);
+        const int j = (lane & 3) ^ ((row >> 1) & 3);
+        goff[i] = row * KBLK + j * 16;
+    }
+    auto issue = [&](int s_) {
+        const int8_t *src = pan + (int64_t)kblock(s_) * kstride;
+        char *dst = stage_at(s_) + wave * 4 * 1024;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            __builtin_amdgcn_global_load_lds((const void *)(src + goff[i]),
+                                             (__attribute__((address_space(3))) void *)(dst + i * 1024), 16, 0, 0);
     };
     const int fa_off0 = lds_addr(wr * 64 + c16, q), fb_off0 = lds_addr(wc * 64 + c16, q);
     v4i fa[4], fb[4];
@@ -187,24 +207,28 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
 #pragma unroll
         for (int n = 0; n < 4; ++n) xb[n] = *reinterpret_cast<const v4i *>(B + fb_off0 + n * 16 * KBLK);
     };
-    gl(0, g0, g1, g2, g3);
-    st4(0, g0, g1, g2, g3);
-    if (a.KB > 1) { gl(1, g0, g1, g2, g3); st4(1, g0, g1, g2, g3); }
-    if (a.KB > 2) gl(2, g0, g1, g2, g3);
-    __syncthreads();
-    // One pipeline step; the register sets (x = block s+2, y <- block s+3) swap roles between
-    // consecutive steps, so no copy forces an early wait on the loads in flight.
-    auto kstep = [&](int s_, v4i &x0, v4i &x1, v4i &x2, v4i &x3, v4i &y0, v4i &y1, v4i &y2, v4i &y3) {
-        if (s_ + 3 < a.KB) gl(s_ + 3, y0, y1, y2, y3);
-        frags(s_, fa, fb);
+    // Software pipeline over a ring of NSTAGE = 3 LDS stages, blocks fetched two steps ahead.
+    // Step s: wait until this wave's fetches of block s have landed (loads complete in issue
+    // order, so at most the 4 fetches of block s+1 may still be outstanding), barrier (block s
+    // is complete in LDS; every wave is done reading stage (s+2) % 3 from step s-1), fetch
+    // block s+2 into that stage, then read the fragments of block s and multiply.
+    issue(0);
+    if (a.KB > 1) issue(1);
+    for (int s = 0; s < a.KB; ++s) {
+        if (s + 1 < a.KB) __builtin_amdgcn_s_waitcnt(0x0F74);   // vmcnt(4)
+        else __builtin_amdgcn_s_waitcnt(0x0F70);                // vmcnt(0)
+        // a plain barrier: a fenced one would also wait for the fetches of block s+1
+        __builtin_amdgcn_s_barrier();
+        if (s + 2 < a.KB) issue(s + 2);
+        frags(s, fa, fb);
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int n = 0; n < 4; ++n)
             {
                 if constexpr (F4) {
-                    // A/B: 16 rows x 128 objects, lane l holds row l % 16, 32 nibbles of
-                    // objects 32 (l / 16) ..; cbsz = blgp = 4 selects E2M1 for both operands
+                    // A/B: 16 rows x 128 objects, lane l holds row l % 16 and 32 nibbles of
+                    // one quarter of the objects; cbsz = blgp = 4 selects E2M1 for both operands
                     const v8i a8{fa[m][0], fa[m][1], fa[m][2], fa[m][3], 0, 0, 0, 0};
                     const v8i b8{fb[n][0], fb[n][1], fb[n][2], fb[n][3], 0, 0, 0, 0};
                     acc[m][n] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, b8, acc[m][n], 4, 4, 0, 0, 0, 0);
@@ -212,7 +236,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
                     acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[m], fb[n], acc[m][n], 0, 0, 0);
                 }
             }
-        if (s_ == n1blk - 1) {
+        if (s == n1blk - 1) {
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -221,18 +245,11 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
                     else acc[m][n] = acc[m][n] << 16;
                 }
         }
-        if (s_ + 2 < a.KB) st4(s_ + 2, x0, x1, x2, x3);
-        __syncthreads();
-    };
-    int s = 0;
-    for (; s + 1 < a.KB; s += 2) {
-        kstep(s, g0, g1, g2, g3, h0, h1, h2, h3);
-        kstep(s + 1, h0, h1, h2, h3, g0, g1, g2, g3);
     }
-    if (s < a.KB) kstep(s, g0, g1, g2, g3, h0, h1, h2, h3);
 
     // ---------------------------------------------------------------- epilogue
-    // packed integer counts n1 << SH | n0 (float32 accumulators hold exact integers < 2^24)
+    // packed integer counts: int8 n1 << 16 | n0; fp4 (4 n1) << 16 | 4 n0 from the exact
+    // float32 value u = n1 * 2^14 + 4 n0 as u + (u >> 14) * (2^18 - 2^14)
     v4i cnt[4][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -240,7 +257,10 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
         for (int n = 0; n < 4; ++n) {
             if constexpr (F4) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) cnt[m][n][e] = (int)(uint32_t)acc[m][n][e];
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t u = (uint32_t)acc[m][n][e];
+                    cnt[m][n][e] = (int)(__umul24(u >> 14, 245760u) + u);
+                }
             } else {
                 cnt[m][n] = acc[m][n];
             }
@@ -260,8 +280,8 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     const uint32_t *margr = a.marg + (int64_t)r * a.p_pad * C;
     const float *F1r = a.F1 + (int64_t)r * a.p_pad;
 
-    // marginals are stored n1 << 16 | n0; repack to the accumulators' SH
-    auto repack = [](uint32_t x) -> uint32_t { return SH == 16 ? x : ((x >> 16) << SH) | (x & 0xffffu); };
+    // marginals are stored n1 << 16 | n0; the fp4 packing is 4 times that
+    auto repack = [](uint32_t x) -> uint32_t { return F4 ? x << 2 : x; };
     uint32_t Mr[4][NP][C], Mc[4][C];
     float Fr[4][NP], Fc[4];
     float thrR[4][NP], thrC[4];
@@ -312,10 +332,28 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     };
     auto pair_F2 = [&](const uint32_t (&tab)[C][C]) {
         float F = 0.f;
+        if constexpr (F4) {
+            // the packed count (4 n1) << 16 | 4 n0 gives the byte offsets 4 n0, 4 n1 and 8 n of
+            // EA[n0], EB[n1], (L, Q)[n].  All table reads of the pair first, then the
+            // arithmetic, so that the reads overlap.
+            float ea[C * C], eb[C * C];
+            float2 lq[C * C];
 #pragma unroll
-        for (int x = 0; x < C; ++x)
+            for (int v = 0; v < C * C; ++v) {
+                const uint32_t P = tab[v / C][v % C];
+                const uint32_t a0 = P & 0xffffu, a1 = P >> 16;
+                ea[v] = *reinterpret_cast<const float *>(smem + a0);
+                eb[v] = *reinterpret_cast<const float *>(smem + 4 * T + a1);
+                lq[v] = *reinterpret_cast<const float2 *>(smem + 8 * T + 2 * (a0 + a1));
+            }
 #pragma unroll
-            for (int y = 0; y < C; ++y) F += vox_term<SH>(tab[x][y], EA, EB, LQ);
+            for (int v = 0; v < C * C; ++v) F += lq[v].x - lq[v].y * (ea[v] + eb[v]);
+        } else {
+#pragma unroll
+            for (int x = 0; x < C; ++x)
+#pragma unroll
+                for (int y = 0; y < C; ++y) F += vox_term(tab[x][y], EA, EB, LQ);
+        }
         return F;
     };
 
@@ -347,8 +385,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
 #pragma unroll
                         for (int x = 0; x < W; ++x)
 #pragma unroll
-                            for (int y = 0; y < W; ++y)
-                                o[x * W + y] = ((tab[x][y] >> SH) << 16) | (tab[x][y] & MASK);
+                            for (int y = 0; y < W; ++y) o[x * W + y] = F4 ? tab[x][y] >> 2 : tab[x][y];
                         a.F2out[rv * a.p_pad + cv] = F2;
                     }
                     continue;
@@ -365,8 +402,9 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
                     for (int x = 0; x < C; ++x)
 #pragma unroll
                         for (int y = 0; y < C; ++y) {
-                            o[x * C + y] = (int32_t)(tab[x][y] & MASK);
-                            o[C * C + x * C + y] = (int32_t)(tab[x][y] >> SH);
+                            const uint32_t v = F4 ? tab[x][y] >> 2 : tab[x][y];
+                            o[x * C + y] = (int32_t)(v & 0xffffu);
+                            o[C * C + x * C + y] = (int32_t)(v >> 16);
                         }
                 }
             }
@@ -456,7 +494,26 @@ __global__ __launch_bounds__(SW_THREADS, 2) void k_sweep2(Sweep2Args a)
     }   // work items
 }
 
-template <int W, bool F4>
+// Table capacity of the fp4 layout for these class sizes (0 = does not fit any).
+static int fp4_capacity(const Problem &P)
+{
+    const int need = (P.N0 > P.N1 ? P.N0 : P.N1) + 1;
+    for (int T = 1024; T <= 4096; T *= 2)
+        if (need <= T) return T;
+    return 0;
+}
+
+size_t sweep2_lds_bytes(const Problem &P, bool max_mode)
+{
+    if (P.fp4) {
+        const int T = max_mode ? fp4_capacity(P) : 4096;
+        return (size_t)stage_base(T) + NSTAGE * STAGE_BYTES + 16;
+    }
+    size_t tab = sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (P.L.N + 1);
+    return NSTAGE * STAGE_BYTES + ((tab + 15) & ~size_t(15)) + 16;
+}
+
+template <int W, int ENC>
 static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r)
 {
     const Layout &L = P.L;
@@ -493,9 +550,11 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
     a.counts_out = counts_out;
     a.disc_sel = disc_sel;
     a.collect = collect ? 1 : 0;
-    size_t lds = NSTAGE * STAGE_BYTES + sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (L.N + 1) + 16;
-    auto kern = pair_r >= 0 ? k_sweep2<W, SWEEP_PAIRS, F4>
-                            : (counts_out ? k_sweep2<W, SWEEP_DEBUG_COUNTS, F4> : k_sweep2<W, SWEEP_MAX, F4>);
+    const bool max_mode = pair_r < 0 && !counts_out;
+    const size_t lds = sweep2_lds_bytes(P, max_mode);
+    a.snext_off = (int)(lds - 16);
+    auto kern = pair_r >= 0 ? k_sweep2<W, SWEEP_PAIRS, ENC>
+                            : (counts_out ? k_sweep2<W, SWEEP_DEBUG_COUNTS, ENC> : k_sweep2<W, SWEEP_MAX, ENC>);
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int grid = XCDS * WG_PER_XCD;
@@ -503,25 +562,35 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
     return hipGetLastError();
 }
 
-template <bool F4>
+template <int W>
 static hipError_t sweep_dispatch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r)
 {
+    if (!P.fp4) return sweep_launch<W, 0>(P, counts_out, disc_sel, collect, pair_r);
+    // the maximum sweep is instantiated per table capacity (occupancy); the debug and pair
+    // modes use the largest
+    if (pair_r >= 0 || counts_out) return sweep_launch<W, 4096>(P, counts_out, disc_sel, collect, pair_r);
+    switch (fp4_capacity(P)) {
+    case 1024: return sweep_launch<W, 1024>(P, counts_out, disc_sel, collect, pair_r);
+    case 2048: return sweep_launch<W, 2048>(P, counts_out, disc_sel, collect, pair_r);
+    case 4096: return sweep_launch<W, 4096>(P, counts_out, disc_sel, collect, pair_r);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+static hipError_t sweep_any(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r)
+{
     switch (P.L.W) {
-    case 1: return sweep_launch<1, F4>(P, counts_out, disc_sel, collect, pair_r);
-    case 2: return sweep_launch<2, F4>(P, counts_out, disc_sel, collect, pair_r);
+    case 1: return sweep_dispatch<1>(P, counts_out, disc_sel, collect, pair_r);
+    case 2: return sweep_dispatch<2>(P, counts_out, disc_sel, collect, pair_r);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bool collect)
 {
-    return P.fp4 ? sweep_dispatch<true>(P, counts_out, disc_sel, collect, -1)
-                 : sweep_dispatch<false>(P, counts_out, disc_sel, collect, -1);
+    return sweep_any(P, counts_out, disc_sel, collect, -1);
 }
 
-hipError_t launch_pairs(const Problem &P, int r)
-{
-    return P.fp4 ? sweep_dispatch<true>(P, nullptr, -1, false, r) : sweep_dispatch<false>(P, nullptr, -1, false, r);
-}
+hipError_t launch_pairs(const Problem &P, int r) { return sweep_any(P, nullptr, -1, false, r); }
 
 }  // namespace mdfs
