@@ -85,8 +85,6 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
     if (prm->k != 2 && prm->k != 3) return fail(MDFS_E_K, "k=%d: supported tuple sizes are 2 and 3", prm->k);
     if (prm->divisions != 1 && prm->divisions != 2 && prm->divisions != 4)
         return fail(MDFS_E_DIV, "divisions=%d: supported are 1, 2, 4", prm->divisions);
-    if (sweep && prm->divisions == 4)
-        return fail(MDFS_E_LIMIT, "divisions=4 (5 classes) is not built into the sweep yet");
     if (prm->n_obj < 2 || prm->n_obj < prm->divisions + 1)
         return fail(MDFS_E_ARG, "n_obj=%lld too small for %d classes", (long long)prm->n_obj, prm->divisions + 1);
     if (prm->n_obj > MAX_NOBJ) return fail(MDFS_E_LIMIT, "n_obj=%lld > %d", (long long)prm->n_obj, MAX_NOBJ);

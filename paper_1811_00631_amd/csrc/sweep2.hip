@@ -91,6 +91,40 @@ __device__ inline float vox_term(uint32_t P, const float *EA, const float *EB, c
 
 
 
+// Sum of n h(p) over NV voxels (packed counts).  ENC != 0: fp4 packing (4 n1) << 16 | 4 n0,
+// whose halves and their sum are the byte offsets of EA[n0], EB[n1] and the (L, Q) pair of n
+// in the fixed LDS layout; all table reads first, then the arithmetic, so the reads overlap.
+// A packed count of 0 contributes exactly 0 (L[0] = Q[0] = 0).
+template <int ENC, int NV>
+__device__ inline float sum_vox(const uint32_t (&P)[NV], const char *smem, const float *EA, const float *EB,
+                                const float2 *LQ)
+{
+    float F = 0.f;
+    if constexpr (ENC != 0) {
+        constexpr int T = ENC;
+        float ea[NV], eb[NV];
+        float2 lq[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const uint32_t a0 = P[v] & 0xffffu, a1 = P[v] >> 16;
+            ea[v] = *reinterpret_cast<const float *>(smem + a0);
+            eb[v] = *reinterpret_cast<const float *>(smem + 4 * T + a1);
+            lq[v] = *reinterpret_cast<const float2 *>(smem + 8 * T + 2 * (a0 + a1));
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F += lq[v].x - lq[v].y * (ea[v] + eb[v]);
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F += vox_term(P[v], EA, EB, LQ);
+    }
+    return F;
+}
+
+__device__ inline uint32_t dpp_xor1(uint32_t x) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false); }
+__device__ inline uint32_t dpp_xor2(uint32_t x) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false); }
+__device__ inline float dpp_xor1f(float x) { return __builtin_bit_cast(float, dpp_xor1(__builtin_bit_cast(uint32_t, x))); }
+__device__ inline float dpp_xor2f(float x) { return __builtin_bit_cast(float, dpp_xor2(__builtin_bit_cast(uint32_t, x))); }
+
 __device__ inline float rescore_window(float w_abs, float g)
 {
     float ag = fabsf(g);
@@ -265,6 +299,167 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
                 cnt[m][n] = acc[m][n];
             }
         }
+
+    if constexpr (W == 4) {
+        // Five classes: block (m, n) holds 4 x 4 pairs.  The lane holds the four row bins of row
+        // variable q and column bin b = c16 % 4 of column variable c16 / 4, so a pair's 4 x 4
+        // direct counts lie on one lane quad.  Each lane evaluates its column's voxels (4 direct
+        // and the rebuilt last-row voxel (4, b)), the rebuilt last-column voxel (b, 4) from the
+        // quad's row sums, lane b = 0 also the corner (4, 4); F of the pair is the quad sum,
+        // identical on the four lanes.
+        const int b = c16 & 3;
+        const int64_t I0 = (int64_t)bi * TV, J0 = (int64_t)bj * TV;
+        auto rv_of = [&](int m) -> int64_t { return I0 + wr * 16 + m * 4 + q; };
+        auto cv_of = [&](int n) -> int64_t { return J0 + wc * 16 + n * 4 + (c16 >> 2); };
+        const uint32_t *margr = a.marg + (int64_t)r * a.p_pad * C;
+        const float *F1r = a.F1 + (int64_t)r * a.p_pad;
+        auto repack = [](uint32_t x) -> uint32_t { return F4 ? x << 2 : x; };
+        uint32_t Mrb[4], Mrs[4], Mcb[4], Mc4[4];
+        float Fr[4], Fc[4], thrR[4], thrC[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int64_t v = rv_of(m);
+            uint32_t sum4 = 0;
+#pragma unroll
+            for (int x = 0; x < 4; ++x) sum4 += repack(margr[v * C + x]);
+            Mrs[m] = sum4;
+            Mrb[m] = repack(margr[v * C + b]);
+            Fr[m] = F1r[v];
+            const float gk = key_f32(a.G32[v]);
+            thrR[m] = gk - rescore_window(a.w_abs, gk);
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const int64_t v = cv_of(n);
+            Mcb[n] = repack(margr[v * C + b]);
+            Mc4[n] = repack(margr[v * C + 4]);
+            Fc[n] = F1r[v];
+            const float gk = key_f32(a.G32[v]);
+            thrC[n] = gk - rescore_window(a.w_abs, gk);
+        }
+        // the lane's voxels of pair (m, n) and the quad sum F; vx[0..3] direct (x, b),
+        // vx[4] = (4, b), vx[5] = (b, 4), vx[6] = corner on lane b = 0 (else 0)
+        auto quad_pair = [&](int m, int n, uint32_t (&vx)[7]) -> float {
+            const v4i &ac = cnt[m][n];
+            uint32_t S[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                vx[x] = (uint32_t)ac[x];
+                const uint32_t t_ = vx[x] + dpp_xor1(vx[x]);
+                S[x] = t_ + dpp_xor2(t_);
+            }
+            vx[4] = Mcb[n] - (vx[0] + vx[1] + vx[2] + vx[3]);
+            const uint32_t Sb = b == 0 ? S[0] : (b == 1 ? S[1] : (b == 2 ? S[2] : S[3]));
+            vx[5] = Mrb[m] - Sb;
+            vx[6] = b == 0 ? Mc4[n] - (Mrs[m] - (S[0] + S[1] + S[2] + S[3])) : 0u;
+            float f = sum_vox<ENC, 7>(vx, smem, EA, EB, LQ);
+            f += dpp_xor1f(f);
+            return f + dpp_xor2f(f);
+        };
+        auto dec = [](uint32_t P_) -> uint32_t { return F4 ? P_ >> 2 : P_; };   // -> n1 << 16 | n0
+        float rmax[4], cmax[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) rmax[m] = cmax[m] = -INFINITY;
+        bool hot = false;
+        const bool emit = MODE == SWEEP_DEBUG_COUNTS && r == a.disc_sel;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                uint32_t vx[7];
+                const float F2 = quad_pair(m, n, vx);
+                const int64_t rv = rv_of(m), cv = cv_of(n);
+                const bool valid = rv < cv && cv < a.p;
+                if constexpr (MODE == SWEEP_PAIRS) {
+                    if (valid) {
+                        uint32_t *o = a.ptab + (rv * a.p_pad + cv) * (W * W);
+#pragma unroll
+                        for (int x = 0; x < 4; ++x) o[x * W + b] = dec(vx[x]);
+                        if (b == 0) a.F2out[rv * a.p_pad + cv] = F2;
+                    }
+                    continue;
+                }
+                const float igR = valid ? Fc[n] - F2 : -INFINITY;
+                const float igC = valid ? Fr[m] - F2 : -INFINITY;
+                rmax[m] = fmaxf(rmax[m], igR);
+                cmax[n] = fmaxf(cmax[n], igC);
+                hot |= (igR >= thrR[m]) | (igC >= thrC[n]);
+                if (emit && valid) {
+                    int32_t *o = a.counts_out + ((int64_t)rv * a.p + cv) * 2 * C * C;
+                    auto put = [&](int x, int y, uint32_t P_) {
+                        const uint32_t v_ = dec(P_);
+                        o[x * C + y] = (int32_t)(v_ & 0xffffu);
+                        o[C * C + x * C + y] = (int32_t)(v_ >> 16);
+                    };
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) put(x, b, vx[x]);
+                    put(4, b, vx[4]);
+                    put(b, 4, vx[5]);
+                    if (b == 0) put(4, 4, vx[6]);
+                }
+            }
+        if constexpr (MODE == SWEEP_PAIRS) continue;
+        // wave maxima: a pair's value is replicated on its quad; row variables differ in q,
+        // column variables in c16 / 4
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            float x = rmax[m];
+            x = fmaxf(x, __shfl_xor(x, 4));
+            rmax[m] = fmaxf(x, __shfl_xor(x, 8));
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            float x = cmax[n];
+            x = fmaxf(x, __shfl_xor(x, 16));
+            cmax[n] = fmaxf(x, __shfl_xor(x, 32));
+        }
+        if (__any(hot)) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const float g = key_f32(a.G32[rv_of(m)]);
+                const float top = a.collect ? g : fmaxf(g, rmax[m]);
+                thrR[m] = top - rescore_window(a.w_abs, top);
+            }
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const float g = key_f32(a.G32[cv_of(n)]);
+                const float top = a.collect ? g : fmaxf(g, cmax[n]);
+                thrC[n] = top - rescore_window(a.w_abs, top);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(cnt[m][n]) : : "memory");
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    uint32_t vx[7];
+                    const float F2 = quad_pair(m, n, vx);
+                    const int64_t rv = rv_of(m), cv = cv_of(n);
+                    const bool valid = b == 0 && rv < cv && cv < a.p;   // one lane per pair
+                    const float igR = Fc[n] - F2, igC = Fr[m] - F2;
+                    if (valid && igR >= thrR[m]) {
+                        uint32_t at = atomicAdd(&a.st->n_cand, 1u);
+                        if (at < a.cap) a.cand[at] = Cand{(int32_t)rv, r, (uint32_t)cv, igR};
+                        else { atomicOr(&a.ovf[rv], 1u); atomicOr(&a.st->overflow, 1u); }
+                    }
+                    if (valid && igC >= thrC[n]) {
+                        uint32_t at = atomicAdd(&a.st->n_cand, 1u);
+                        if (at < a.cap) a.cand[at] = Cand{(int32_t)cv, r, (uint32_t)rv, igC};
+                        else { atomicOr(&a.ovf[cv], 1u); atomicOr(&a.st->overflow, 1u); }
+                    }
+                }
+        }
+        if (a.collect) continue;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if (c16 == 0 && rmax[m] > -INFINITY) atomicMax(&a.G32[rv_of(m)], f32_key(rmax[m]));
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+            if (q == 0 && b == 0 && cmax[n] > -INFINITY) atomicMax(&a.G32[cv_of(n)], f32_key(cmax[n]));
+        continue;
+    } else {
     // Lane geometry of the 16x16 output block (m, n): lane holds rows 4q..4q+3 of column c16.
     // Row/column index = variable * W + bin within the block.
     const int64_t I0 = (int64_t)bi * TV, J0 = (int64_t)bj * TV;
@@ -331,30 +526,10 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
         }
     };
     auto pair_F2 = [&](const uint32_t (&tab)[C][C]) {
-        float F = 0.f;
-        if constexpr (F4) {
-            // the packed count (4 n1) << 16 | 4 n0 gives the byte offsets 4 n0, 4 n1 and 8 n of
-            // EA[n0], EB[n1], (L, Q)[n].  All table reads of the pair first, then the
-            // arithmetic, so that the reads overlap.
-            float ea[C * C], eb[C * C];
-            float2 lq[C * C];
+        uint32_t P[C * C];
 #pragma unroll
-            for (int v = 0; v < C * C; ++v) {
-                const uint32_t P = tab[v / C][v % C];
-                const uint32_t a0 = P & 0xffffu, a1 = P >> 16;
-                ea[v] = *reinterpret_cast<const float *>(smem + a0);
-                eb[v] = *reinterpret_cast<const float *>(smem + 4 * T + a1);
-                lq[v] = *reinterpret_cast<const float2 *>(smem + 8 * T + 2 * (a0 + a1));
-            }
-#pragma unroll
-            for (int v = 0; v < C * C; ++v) F += lq[v].x - lq[v].y * (ea[v] + eb[v]);
-        } else {
-#pragma unroll
-            for (int x = 0; x < C; ++x)
-#pragma unroll
-                for (int y = 0; y < C; ++y) F += vox_term(tab[x][y], EA, EB, LQ);
-        }
-        return F;
+        for (int v = 0; v < C * C; ++v) P[v] = tab[v / C][v % C];
+        return sum_vox<ENC, C * C>(P, smem, EA, EB, LQ);
     };
 
     float rmax[4][NP], cmax[4];
@@ -491,6 +666,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
 #pragma unroll
     for (int n = 0; n < 4; ++n)
         if (col_leader && cmax[n] > -INFINITY) atomicMax(&a.G32[col_var(n)], f32_key(cmax[n]));
+    }   // W <= 2
     }   // work items
 }
 
@@ -582,6 +758,7 @@ static hipError_t sweep_any(const Problem &P, int32_t *counts_out, int disc_sel,
     switch (P.L.W) {
     case 1: return sweep_dispatch<1>(P, counts_out, disc_sel, collect, pair_r);
     case 2: return sweep_dispatch<2>(P, counts_out, disc_sel, collect, pair_r);
+    case 4: return sweep_dispatch<4>(P, counts_out, disc_sel, collect, pair_r);
     default: return hipErrorInvalidValue;
     }
 }

@@ -329,6 +329,7 @@ hipError_t launch_sweep3(const Problem &P, int r, bool collect)
     switch (P.L.W) {
     case 1: return sweep3_launch<1>(P, r, collect);
     case 2: return sweep3_launch<2>(P, r, collect);
+    case 4: return sweep3_launch<4>(P, r, collect);
     default: return hipErrorInvalidValue;
     }
 }

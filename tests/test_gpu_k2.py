@@ -5,6 +5,8 @@ Bars: discretisation codes and voxel counts bit-exact; IG_max within
 encodings of the pair contraction are covered: "mfma_fp4" (E2M1, float32 accumulation; what
 "auto" picks while each class has < 4096 objects) and "mfma" (int8).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -62,7 +64,7 @@ def test_codes_bit_exact(mdfs_gpu, n_obj, n_var, div, R, rng):
 # ------------------------------------------------------------------ counts
 @pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("n_obj,n_var,div,ones", [(300, 150, 2, None), (257, 131, 1, 40), (130, 70, 2, 1),
-                                                  (4095 + 129, 20, 2, 4095)])
+                                                  (4095 + 129, 20, 2, 4095), (333, 90, 4, None), (140, 37, 4, 9)])
 def test_pair_counts_bit_exact(mdfs_gpu, engine, n_obj, n_var, div, ones):
     # the last case puts 4095 objects (the fp4 maximum) in class 1 and 129 in class 0
     w = workloads.null_data(5, n_obj, n_var, ones=ones)
@@ -87,6 +89,9 @@ CASES = {
     "imbalanced": lambda: workloads.null_data(4, 401, 66, ones=37),
     "two_vars": lambda: workloads.xor_small(seed=5, n_obj=100, n_var=2),
     "tiny_n": lambda: workloads.xor_small(seed=6, n_obj=5, n_var=9, n_disc=2),
+    "five_classes": lambda: workloads.xor_small(seed=7, n_obj=700, n_var=77, divisions=4, n_disc=3),
+    "five_classes_imbalanced": lambda: dataclasses.replace(workloads.null_data(15, 300, 45, ones=61),
+                                                           divisions=4, n_disc=2),
 }
 
 

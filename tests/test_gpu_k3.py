@@ -26,6 +26,7 @@ CASES3 = {
     "two_classes_d2": lambda: workloads.parity3(seed=22, n_obj=257, n_var=40, divisions=1, n_disc=3),
     "imbalanced": lambda: workloads.null_data(23, 333, 30, ones=41),
     "three_vars": lambda: workloads.parity3(seed=24, n_obj=100, n_var=3, n_disc=2),
+    "five_classes": lambda: workloads.parity3(seed=25, n_obj=500, n_var=26, divisions=4, n_disc=2),
 }
 
 
