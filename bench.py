@@ -62,7 +62,7 @@ WORKLOAD_TEXT = {
                 "30 random discretisations (range 0.5, xi 0.25)",
     "xor_small": "k=2: N=500, p=100 Gaussian, XOR pair (0,1) with 10% label noise, d=3, 1 discretisation",
     "madelon_like": "Madelon-shaped k=2: N=2000, p=500 (5 base + 15 combinations + 480 noise), d=3, 30 discretisations",
-    "parity3": "k=3: N=2000, p=500 Gaussian, parity triple (0,1,2), d=3, 30 discretisations, bitset engine",
+    "parity3": "k=3: N=2000, p=500 Gaussian, parity triple (0,1,2), d=3, 30 discretisations",
     "genomics_like": "genomics-shaped k=2: N=500, p=20000 log-normal, 10 planted XOR pairs, y 200/300, d=3, "
                      "30 discretisations",
 }
@@ -148,7 +148,9 @@ def main():
     sweep_ms = ph["sweep"]
     W = div
     n0, n1 = int((w.y == 0).sum()), int((w.y == 1).sum())
-    fp4 = k == 2 and (args.engine == "mfma_fp4" or (args.engine == "auto" and max(n0, n1) < 4096))
+    fp4 = args.engine == "mfma_fp4" or (args.engine == "auto" and max(n0, n1) < 4096)
+    fp4 = fp4 and (k == 2 or div == 2)
+    k3_mfma = k == 3 and fp4
     if k == 2:
         ops_per_unit = 2 * w.n_obj * W * W           # MACs x 2 of the one-hot Gram product per pair
         achieved = tuples * ops_per_unit / (sweep_ms * 1e-3) / 1e12
@@ -157,6 +159,13 @@ def main():
                 "frac": achieved / peak, "traffic": None,
                 "kernel": f"k_sweep2<{W}, max, {'fp4' if fp4 else 'int8'}>",
                 "per_unit": f"2*N*(d-1)^2 = {ops_per_unit} {'fp4' if fp4 else 'int8'} ops per pair table",
+                "units_per_launch": tuples, "kernel_ms": sweep_ms}
+    elif k3_mfma:
+        ops_per_unit = 2 * w.n_obj * W ** 3          # MACs x 2 of the pair one-hot x one-hot product
+        achieved = tuples * ops_per_unit / (sweep_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP4_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP4_PEAK_TFLOPS, "traffic": None, "kernel": f"k_sweep3m (+ pair data)",
+                "per_unit": f"2*N*(d-1)^3 = {ops_per_unit} fp4 ops per triple table",
                 "units_per_launch": tuples, "kernel_ms": sweep_ms}
     else:
         # AND + popcount-accumulate per (bin triple, 32-object word): 2 integer ops on 32 lanes
@@ -186,7 +195,7 @@ def main():
                    "tuples_per_step": tuples,
                    "engine": args.engine,
                    "counts": ("fp4 MFMA, exact f32 accumulate" if fp4 else "int8 MFMA, int32 accumulate")
-                   if k == 2 else "bitset AND + popcount, int32",
+                   if (k == 2 or k3_mfma) else "bitset AND + popcount, int32",
                    "entropy": "float32 screen + binary64 re-score"},
         "p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
         "p99_ms": float(np.percentile(np.array(lat) * 1e3, 99)),

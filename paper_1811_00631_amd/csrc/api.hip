@@ -91,8 +91,10 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
     if (prm->n_var < prm->k) return fail(MDFS_E_ARG, "n_var=%lld < k", (long long)prm->n_var);
     if (prm->k == 3 && prm->n_var > MAX_K3_VARS)
         return fail(MDFS_E_LIMIT, "k=3 with n_var=%lld > %d", (long long)prm->n_var, MAX_K3_VARS);
-    if (sweep && prm->k == 3 && (prm->engine == MDFS_ENGINE_MFMA || prm->engine == MDFS_ENGINE_MFMA_FP4))
-        return fail(MDFS_E_LIMIT, "k=3 has the bitset engine only in this build");
+    if (sweep && prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA)
+        return fail(MDFS_E_LIMIT, "k=3 on the matrix cores uses the fp4 encoding (engine mfma_fp4)");
+    if (sweep && prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA_FP4 && prm->divisions != 2)
+        return fail(MDFS_E_LIMIT, "k=3 on the matrix cores is built for divisions=2 (3 classes)");
     if (sweep && prm->k == 2 && prm->engine == MDFS_ENGINE_BITSET)
         return fail(MDFS_E_LIMIT, "k=2 has the MFMA engines only in this build");
     if (prm->n_disc < 1) return fail(MDFS_E_ARG, "n_disc=%d < 1", prm->n_disc);
@@ -191,6 +193,13 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
         P.err_bound = screen_err_bound(N, P.beta0, P.beta1, C * C);
         // k = 3: the triple's own F (C^3 voxels) plus the float32 F of the parent pair
         if (prm->k == 3) P.err_bound += screen_err_bound(N, P.beta0, P.beta1, C * C * C);
+        // k = 3 engine: matrix cores for three classes in the fp4 encoding (auto or asked for)
+        P.k3_mfma = prm->k == 3 && prm->divisions == 2 && P.fp4 &&
+                    (prm->engine == MDFS_ENGINE_AUTO || prm->engine == MDFS_ENGINE_MFMA_FP4);
+        if (prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA_FP4 && !P.k3_mfma)
+            return fail(MDFS_E_LIMIT, "k=3 matrix-core engine needs classes < 4096 objects");
+        if (P.k3_mfma && sweep3m_lds_bytes(P) > LDS_MAX)
+            return fail(MDFS_E_LIMIT, "k=3 matrix-core sweep: LDS tables too large");
     }
     return MDFS_OK;
 }
@@ -220,16 +229,40 @@ static int sweep_pass(const Problem &P, int32_t *counts, int disc_sel, bool coll
         for (int r = 0; r < P.L.R; ++r) {
             LAUNCH(launch_reset_queue(P));
             LAUNCH(launch_pairs(P, r));
-            LAUNCH(launch_sweep3(P, r, collect));
+            if (P.k3_mfma) LAUNCH(launch_sweep3m(P, r, collect));
+            else LAUNCH(launch_sweep3(P, r, collect));
         }
     }
     return MDFS_OK;
 }
 
 // discretise + encode + sweep, leaving the maxima and candidates in the workspace
-static int run_sweep(const Problem &P, const float *data, const uint8_t *y, int32_t *counts, int disc_sel,
+// Tile list of the k = 3 matrix-core sweep, built on the host and copied into the workspace.
+static int upload_k3_tiles(Problem &P)
+{
+    std::vector<int64_t> apref;
+    std::vector<int32_t> ablk;
+    sweep3m_tiles(P.L.p, apref, ablk);
+    P.n_ablk3 = (int64_t)ablk.size();
+    P.n_tiles3 = apref.back();
+    if (ablk.empty()) return MDFS_OK;
+    hipError_t e = hipMemcpyAsync(P.ws + P.L.a3pref, apref.data(), apref.size() * sizeof(int64_t),
+                                  hipMemcpyHostToDevice, P.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(P.ws + P.L.a3blk, ablk.data(), ablk.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           P.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P.stream);   // the host vectors go out of scope
+    if (e != hipSuccess) return hip_fail(e, "copying the k=3 tile list");
+    return MDFS_OK;
+}
+
+static int run_sweep(Problem &P, const float *data, const uint8_t *y, int32_t *counts, int disc_sel,
                      PhaseTimer *tm = nullptr)
 {
+    if (P.k3_mfma) {
+        const int rc = upload_k3_tiles(P);
+        if (rc) return rc;
+    }
     if (tm) tm->mark(0);
     LAUNCH(launch_init(P));
     LAUNCH(launch_class_perm(P, y));

@@ -9,6 +9,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <vector>
+
 namespace mdfs {
 
 // One-hot bytes per row and K block.  The int8 encoding holds 64 objects per K block (one byte
@@ -61,7 +63,7 @@ struct Layout {
     int64_t words_max;    // bitset words (32 objects) per class, worst case (k=3)
     // offsets
     size_t status, pos, perm, tabEA, tabEB, tabLQ, marg, F1, onehot, G32, max64, keyw, ovf,
-        cand, ig64, bits, ptab, F2, total;
+        cand, ig64, bits, ptab, F2, a3pref, a3blk, total;
 };
 
 Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R);
@@ -113,6 +115,8 @@ struct Problem {
     double range;
     uint64_t seed;
     double err_bound;             // float32 screen error bound E (per IG)
+    bool k3_mfma;                 // k = 3 on the matrix cores (else bitsets)
+    int64_t n_ablk3, n_tiles3;    // tile list of the k = 3 matrix-core sweep
     char *ws;
     hipStream_t stream;
     template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -130,6 +134,10 @@ constexpr size_t LDS_MAX = 160 * 1024;
 hipError_t launch_reset_candidates(const Problem &P);
 hipError_t launch_pairs(const Problem &P, int r);
 hipError_t launch_sweep3(const Problem &P, int r, bool collect);
+hipError_t launch_sweep3m(const Problem &P, int r, bool collect);
+size_t sweep3m_lds_bytes(const Problem &P);
+// host-side tile list of the k = 3 matrix-core sweep (first tile per A block, A blocks)
+void sweep3m_tiles(int64_t p, std::vector<int64_t> &apref, std::vector<int32_t> &ablk);
 hipError_t launch_reset_queue(const Problem &P);
 hipError_t launch_finalize(const Problem &P, float *ig_max, int32_t *argmax, int32_t *argmax_disc);
 hipError_t launch_screen_out(const Problem &P, float *ig32);

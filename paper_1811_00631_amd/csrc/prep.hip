@@ -50,8 +50,11 @@ Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
         L.bits = take(sizeof(uint32_t) * (size_t)R * 2 * L.words_max * L.p_pad * L.W);
         L.ptab = take(sizeof(uint32_t) * (size_t)L.p_pad * L.p_pad * L.W * L.W);
         L.F2 = take(sizeof(float) * (size_t)L.p_pad * L.p_pad);
+        const int64_t n_ablk_max = L.p_pad * ((L.p_pad + 31) / 32);
+        L.a3pref = take(sizeof(int64_t) * (size_t)(n_ablk_max + 1));
+        L.a3blk = take(sizeof(int32_t) * (size_t)n_ablk_max);
     } else {
-        L.bits = L.ptab = L.F2 = o;
+        L.bits = L.ptab = L.F2 = L.a3pref = L.a3blk = o;
     }
     L.total = o;
     return L;
@@ -261,6 +264,17 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
     __shared__ double fterm[DISC_RCHUNK * C];
     const int v = blockIdx.x;
     const int t = threadIdx.x;
+    if (v >= p) {
+        // padding variable (encode launches cover p_pad): zero one-hot rows, so the sweeps
+        // count 0 for it
+        const int nrow = KB * W * (KBLK / 4);
+        for (int rr = 0; rr < R; ++rr)
+            for (int idx = t; idx < nrow; idx += DISC_THREADS) {
+                const int kb = idx / (W * (KBLK / 4)), a = (idx / (KBLK / 4)) % W, q4 = idx % (KBLK / 4);
+                *reinterpret_cast<uint32_t *>(onehot + onehot_off(rr, (int64_t)v * W + a, kb, q4 * 4, KB, rows_pad)) = 0u;
+            }
+        return;
+    }
     const float *x = data + (int64_t)v * N;
 
     bool bad = false;
@@ -417,7 +431,8 @@ static hipError_t disc_launch(const Problem &P, const float *data, uint8_t *code
     auto kern = k_discretize<C>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)L.p), dim3(DISC_THREADS), lds, P.stream, data, N, (int)L.p, M,
+    const int64_t nblk = encode ? L.p_pad : L.p;   // encode: also zero the padding variables' rows
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(DISC_THREADS), lds, P.stream, data, N, (int)L.p, M,
                        L.R, P.disc_offset, P.range, P.seed, encode ? P.at<int32_t>(L.perm) : nullptr, P.K0pad, P.N0, P.N1, P.KB,
                        P.Kpad, P.fp4 ? 1 : 0, L.rows_pad, codes, encode ? P.at<int8_t>(L.onehot) : nullptr,
                        encode ? P.at<uint32_t>(L.marg) : nullptr, encode ? P.at<float>(L.F1) : nullptr,

@@ -1,0 +1,513 @@
+// sweep3m.hip -- the k = 3 tuple sweep on the matrix cores (one-hot pair x one-hot variable).
+//
+// For one discretisation, the per-class table of every triple i < j < l (the counters N^d of
+// section "Algorithm and implementation") is, on its first W = C-1 bins of every variable, the
+// contraction over objects of the pair one-hot column (x_i = a and x_j = b) with the one-hot
+// column (x_l = e).  In the E2M1 (fp4) one-hot encoding of the pair sweep (2.0 or 0 per
+// object) the pair column is the bitwise AND of the two variables' columns, so the same
+// V_MFMA_F32_16X16X128_F8F6F4 contraction gives n1 * 2^14 + 4 n0 per (a, b, e) exactly.
+//
+// Tile: one i; A rows (j, a, b) for 32 consecutive j (128 rows), B rows (l, e) for 64
+// consecutive l (128 rows).  The j rows and the two rows of i are staged in LDS (fetched
+// straight into LDS two K blocks ahead, as in the pair sweep) and ANDed when the A fragments
+// are read.  The remaining C^3 - W^3 voxels follow exactly from the three pair tables (from
+// the pair sweep of the same discretisation) and the marginals.  Epilogue: F3 = sum_v n_v h(p_v)
+// in float32 from the LDS tables; IG(i|j,l) = F(j,l) - F3 and likewise for j and l (equation
+// IGmax with k = 3), maxima and candidate appends as in the bitset engine.  Three classes
+// (W = 2) only; other widths use the bitset engine.
+#include "mdfs_internal.h"
+
+#include <vector>
+
+namespace mdfs {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int M3_THREADS = 256;
+constexpr int M3_JV = 32;                        // j variables per A tile (4 rows each)
+constexpr int M3_LV = 64;                        // l variables per B tile (2 rows each)
+constexpr int M3_JROWS = 2 * M3_JV;              // one-hot rows of the j block
+constexpr int M3_STAGE = (M3_JROWS + TILE_ROWS) * KBLK + 2 * KBLK + 128;   // j rows | l rows | i rows | pad
+constexpr int M3_NSTAGE = 3;
+
+struct Sweep3mArgs {
+    const int8_t *onehot;
+    const uint32_t *ptab;    // [p_pad][p_pad][4] packed (n1 << 16 | n0) 2 x 2 counts of pairs (this r)
+    const float *F2;         // [p_pad][p_pad] float32 F of pairs (this r)
+    const uint32_t *marg;    // [R][p_pad][3]
+    const float *EA, *EB;
+    const float2 *LQ;
+    const int64_t *apref;    // [n_ablk + 1] first tile of each A block (i, jb)
+    const int32_t *ablk;     // [n_ablk] i * 256 + jb
+    int64_t n_ablk, n_tiles;
+    int N0, N1, N;
+    int p;
+    int64_t p_pad, rows_pad;
+    int KB, KB0, r, nLB;
+    uint32_t *G32;
+    Cand *cand;
+    int64_t cap;
+    Status *st;
+    uint32_t *ovf;
+    float w_abs;
+    int collect;
+    int snext_off;
+};
+
+__device__ inline int lds_sw(int row, int j) { return row * KBLK + ((j ^ ((row >> 1) & 3)) << 4); }
+
+__device__ inline float win3(float w_abs, float g)
+{
+    const float ag = fabsf(g);
+    return w_abs + 2e-9f * (ag > 1.f ? ag : 1.f) + 1e-30f;
+}
+
+__device__ inline uint32_t swap1(uint32_t x) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false); }
+__device__ inline float swap1f(float x) { return __builtin_bit_cast(float, swap1(__builtin_bit_cast(uint32_t, x))); }
+
+// Sum of n h(p) over NV packed counts (4 n1) << 16 | 4 n0 with the fixed LDS table layout of
+// capacity T (EA at 0, EB at 4T, (L, Q) pairs at 8T); a packed 0 contributes exactly 0.
+template <int T, int NV>
+__device__ inline float vox_sum(const uint32_t (&P)[NV], const char *tab)
+{
+    float ea[NV], eb[NV];
+    float2 lq[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const uint32_t a0 = P[v] & 0xffffu, a1 = P[v] >> 16;
+        ea[v] = *reinterpret_cast<const float *>(tab + a0);
+        eb[v] = *reinterpret_cast<const float *>(tab + 4 * T + a1);
+        lq[v] = *reinterpret_cast<const float2 *>(tab + 8 * T + 2 * (a0 + a1));
+    }
+    float F = 0.f;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F += lq[v].x - lq[v].y * (ea[v] + eb[v]);
+    return F;
+}
+
+// Full 3 x 3 packed table of a pair from its 2 x 2 direct counts and the two marginals.
+__device__ inline void full3(const uint32_t (&d)[4], const uint32_t (&Mx)[3], const uint32_t (&My)[3], uint32_t (&n)[3][3])
+{
+    n[0][0] = d[0]; n[0][1] = d[1]; n[1][0] = d[2]; n[1][1] = d[3];
+    n[0][2] = Mx[0] - d[0] - d[1];
+    n[1][2] = Mx[1] - d[2] - d[3];
+    n[2][0] = My[0] - d[0] - d[2];
+    n[2][1] = My[1] - d[1] - d[3];
+    n[2][2] = My[2] - n[0][2] - n[1][2];
+}
+
+__device__ inline void append(const Sweep3mArgs &a, int v, uint32_t partner, float ig)
+{
+    const uint32_t at = atomicAdd(&a.st->n_cand, 1u);
+    if (at < a.cap) a.cand[at] = Cand{v, a.r, partner, ig};
+    else { atomicOr(&a.ovf[v], 1u); atomicOr(&a.st->overflow, 1u); }
+}
+
+template <int T>
+__global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
+{
+    constexpr int C = 3;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    char *stage = smem + 24 * T;
+    int64_t *s_next = reinterpret_cast<int64_t *>(smem + a.snext_off);
+
+    const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wr = wave >> 1, wc = wave & 1;
+    const int q = lane >> 4, c16 = lane & 15, e = c16 & 1;
+
+    {
+        float *tf = reinterpret_cast<float *>(smem);
+        for (int i = t; i <= a.N0; i += M3_THREADS) tf[i] = a.EA[i];
+        for (int i = t; i <= a.N1; i += M3_THREADS) tf[T + i] = a.EB[i];
+        float2 *lq = reinterpret_cast<float2 *>(smem + 8 * T);
+        for (int i = t; i <= a.N; i += M3_THREADS) lq[i] = a.LQ[i];
+    }
+    auto repack = [](uint32_t x) -> uint32_t { return x << 2; };   // n1 << 16 | n0 -> fp4 packing
+    const uint32_t *margr = a.marg + (int64_t)a.r * a.p_pad * C;
+    const int64_t nrb = a.rows_pad / TILE_ROWS;
+    constexpr int kstride = TILE_ROWS * KBLK;
+    const int n1blk = a.KB - a.KB0;
+
+    for (;;) {
+        __syncthreads();
+        if (t == 0) *s_next = atomicAdd(&a.st->next_tile[0], 1u);
+        __syncthreads();
+        const int64_t u = *s_next;
+        if (u >= a.n_tiles) break;
+        // A block: last k with apref[k] <= u
+        int64_t lo = 0, hi = a.n_ablk - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (a.apref[mid] <= u) lo = mid; else hi = mid - 1;
+        }
+        const int ab = a.ablk[lo];
+        const int i = ab >> 8, jb = ab & 255;
+        const int lb = jb / 2 + (int)(u - a.apref[lo]);
+
+        // ---------------------------------------------------------------- K loop
+        // operand sources in the panel-major one-hot encoding
+        const int8_t *panJ = a.onehot + ((int64_t)a.r * nrb + jb / 2) * a.KB * kstride + (jb & 1) * M3_JROWS * KBLK;
+        const int8_t *panL = a.onehot + ((int64_t)a.r * nrb + lb) * a.KB * kstride;
+        const int8_t *panI = a.onehot + ((int64_t)a.r * nrb + (2 * i) / TILE_ROWS) * a.KB * kstride +
+                             ((2 * i) % TILE_ROWS) * KBLK;
+        auto kblock = [&](int s_) { return s_ < n1blk ? a.KB0 + s_ : s_ - n1blk; };
+        auto stage_at = [&](int s_) { return stage + (s_ % M3_NSTAGE) * M3_STAGE; };
+        // 13 fetches of 1 KB per K block: 4 for the 64 j rows, 8 for the 128 l rows (stage
+        // rows 64..191), 1 for the two rows of i (lanes 0..7).  Wave w takes fetches w, w+4,
+        // w+8, w+12 (wave 0 four, the others three).
+        const int nfetch = wave == 0 ? 4 : 3;
+        auto issue = [&](int s_) {
+            const int64_t kb_off = (int64_t)kblock(s_) * kstride;
+            char *st_ = stage_at(s_);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int f = wave + 4 * k;
+                if (f > 12) break;
+                if (f < 12) {
+                    // j rows (f < 4) or l rows: 16 stage rows, swizzle applied on the global side
+                    const int srow = 16 * f + (lane >> 2);
+                    const int j = (lane & 3) ^ ((srow >> 1) & 3);
+                    const int8_t *src = f < 4 ? panJ + kb_off + srow * KBLK + j * 16
+                                              : panL + kb_off + (srow - M3_JROWS) * KBLK + j * 16;
+                    __builtin_amdgcn_global_load_lds((const void *)src,
+                                                     (__attribute__((address_space(3))) void *)(st_ + f * 1024), 16, 0, 0);
+                } else if (lane < 8) {
+                    // the two rows of i, unswizzled (rows 0 and 1 have swizzle 0)
+                    const int8_t *src = panI + kb_off + (lane >> 2) * KBLK + (lane & 3) * 16;
+                    __builtin_amdgcn_global_load_lds((const void *)src,
+                                                     (__attribute__((address_space(3))) void *)(st_ + 12 * 1024), 16, 0, 0);
+                }
+            }
+        };
+        v4f acc[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = v4f{0.f, 0.f, 0.f, 0.f};
+        // A fragment of block m: lane reads A-tile row rho = 64 wr + 16 m + c16, i.e. j-local
+        // 16 wr + 4 m + c16 / 4 with bins a = (c16 >> 1) & 1 (of i) and b = c16 & 1 (of j)
+        const int ia = (c16 >> 1) & 1;
+        int offJ[4], offL[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) offJ[m] = lds_sw(2 * (16 * wr + 4 * m + (c16 >> 2)) + (c16 & 1), q);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) offL[n] = M3_JROWS * KBLK + lds_sw(wc * 64 + 16 * n + c16, q);
+        const int offI = (M3_JROWS + TILE_ROWS) * KBLK + lds_sw(ia, q);
+
+        issue(0);
+        if (a.KB > 1) issue(1);
+        for (int s = 0; s < a.KB; ++s) {
+            // this wave's fetches of block s complete (loads return in order); then a plain
+            // barrier (a fenced one would also drain the fetches of block s+1)
+            if (s + 1 < a.KB) {
+                if (nfetch == 4) __builtin_amdgcn_s_waitcnt(0x0F74);   // vmcnt(4)
+                else __builtin_amdgcn_s_waitcnt(0x0F73);               // vmcnt(3)
+            } else {
+                __builtin_amdgcn_s_waitcnt(0x0F70);
+            }
+            __builtin_amdgcn_s_barrier();
+            if (s + 2 < a.KB) issue(s + 2);
+            const char *st_ = stage_at(s);
+            const v4i fi = *reinterpret_cast<const v4i *>(st_ + offI);
+            v4i fa[4], fb[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) fa[m] = *reinterpret_cast<const v4i *>(st_ + offJ[m]) & fi;
+#pragma unroll
+            for (int n = 0; n < 4; ++n) fb[n] = *reinterpret_cast<const v4i *>(st_ + offL[n]);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    const v8i a8{fa[m][0], fa[m][1], fa[m][2], fa[m][3], 0, 0, 0, 0};
+                    const v8i b8{fb[n][0], fb[n][1], fb[n][2], fb[n][3], 0, 0, 0, 0};
+                    acc[m][n] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, b8, acc[m][n], 4, 4, 0, 0, 0, 0);
+                }
+            if (s == n1blk - 1) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) acc[m][n] = acc[m][n] * 4096.0f;
+            }
+        }
+
+        // ---------------------------------------------------------------- epilogue
+        // lane (q, c16) of block (m, n): D[a][b] = T[a][b][e] of the triple (i, j_m, l_n),
+        // (a, b) = register index, packed (4 n1) << 16 | 4 n0
+        v4i cnt[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    const uint32_t uu = (uint32_t)acc[m][n][x];
+                    cnt[m][n][x] = (int)(__umul24(uu >> 14, 245760u) + uu);
+                }
+        int jv[4], lv[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) jv[m] = jb * M3_JV + 16 * wr + 4 * m + q;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) lv[n] = lb * M3_LV + 32 * wc + 8 * n + (c16 >> 1);
+        // indices past p are clamped for the loads; such triples are invalid and masked
+        auto clampv = [&](int v) { return v < a.p ? v : a.p - 1; };
+        uint32_t Mi[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Mi[c] = repack(margr[(int64_t)i * C + c]);
+        uint32_t Mj[4][3], Ml[4][3], Pij[4][4], Pil[4][4];
+        float Fij[4], Fil[4], thrJ[4], thrL[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int j = clampv(jv[m]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Mj[m][c] = repack(margr[(int64_t)j * C + c]);
+            const int ii = i < j ? i : j, jj = i < j ? j : i;
+            const v4i pw = *reinterpret_cast<const v4i *>(a.ptab + ((int64_t)ii * a.p_pad + jj) * 4);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) Pij[m][x] = repack((uint32_t)pw[x]);
+            Fij[m] = a.F2[(int64_t)ii * a.p_pad + jj];
+            const float g = key_f32(a.G32[j]);
+            thrJ[m] = g - win3(a.w_abs, g);
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const int l = clampv(lv[n]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Ml[n][c] = repack(margr[(int64_t)l * C + c]);
+            const int ii = i < l ? i : l, ll = i < l ? l : i;
+            const v4i pw = *reinterpret_cast<const v4i *>(a.ptab + ((int64_t)ii * a.p_pad + ll) * 4);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) Pil[n][x] = repack((uint32_t)pw[x]);
+            Fil[n] = a.F2[(int64_t)ii * a.p_pad + ll];
+            const float g = key_f32(a.G32[l]);
+            thrL[n] = g - win3(a.w_abs, g);
+        }
+        float Gi = key_f32(a.G32[i]);
+        float thrI = Gi - win3(a.w_abs, Gi);
+
+        // F3 of triple (i, j_m, l_n) on the lane pair (e = 0, 1) and the parents' F
+        auto triple = [&](int m, int n, float &Fjl) -> float {
+            const bool valid = i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;
+            const int j = clampv(jv[m]), l = clampv(lv[n]);
+            const int jj = j < l ? j : l, ll = j < l ? l : j;
+            const v4i pw = *reinterpret_cast<const v4i *>(a.ptab + ((int64_t)jj * a.p_pad + ll) * 4);
+            Fjl = a.F2[(int64_t)jj * a.p_pad + ll];
+            uint32_t dj[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) dj[x] = repack((uint32_t)pw[x]);
+            uint32_t Nij[3][3], Nil[3][3], Njl[3][3];
+            full3(Pij[m], Mi, Mj[m], Nij);
+            full3(Pil[n], Mi, Ml[n], Nil);
+            full3(dj, Mj[m], Ml[n], Njl);
+            const v4i &ac = cnt[m][n];
+            uint32_t D[2][2], Dp[2][2];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                D[x >> 1][x & 1] = (uint32_t)ac[x];
+                Dp[x >> 1][x & 1] = swap1((uint32_t)ac[x]);     // partner lane: T[a][b][1-e]
+            }
+            const uint32_t Nil_ae0 = e ? Nil[0][1] : Nil[0][0], Nil_ae1 = e ? Nil[1][1] : Nil[1][0];
+            const uint32_t Njl_be0 = e ? Njl[0][1] : Njl[0][0], Njl_be1 = e ? Njl[1][1] : Njl[1][0];
+            const uint32_t Njl_2e = e ? Njl[2][1] : Njl[2][0];
+            uint32_t V[14];
+            // slab z = e
+            V[0] = D[0][0]; V[1] = D[0][1]; V[2] = D[1][0]; V[3] = D[1][1];
+            V[4] = Nil_ae0 - D[0][0] - D[0][1];          // T[0][2][e]
+            V[5] = Nil_ae1 - D[1][0] - D[1][1];          // T[1][2][e]
+            V[6] = Njl_be0 - D[0][0] - D[1][0];          // T[2][0][e]
+            V[7] = Njl_be1 - D[0][1] - D[1][1];          // T[2][1][e]
+            V[8] = Njl_2e - V[4] - V[5];                 // T[2][2][e]
+            // slab z = 2: T[a][b][2] from the (i, j) table
+            uint32_t Z[2][2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) Z[x][y] = Nij[x][y] - D[x][y] - Dp[x][y];
+            const uint32_t Z02 = Nil[0][2] - Z[0][0] - Z[0][1];   // T[0][2][2]
+            const uint32_t Z12 = Nil[1][2] - Z[1][0] - Z[1][1];   // T[1][2][2]
+            const uint32_t Z20 = Njl[0][2] - Z[0][0] - Z[1][0];   // T[2][0][2]
+            const uint32_t Z21 = Njl[1][2] - Z[0][1] - Z[1][1];   // T[2][1][2]
+            const uint32_t Z22 = Njl[2][2] - Z02 - Z12;           // T[2][2][2]
+            V[9] = e ? Z02 : Z[0][0];
+            V[10] = e ? Z12 : Z[0][1];
+            V[11] = e ? Z20 : Z[1][0];
+            V[12] = e ? Z21 : Z[1][1];
+            V[13] = e ? 0u : Z22;
+            // an invalid triple may combine unrelated tables: its counts are not counts
+#pragma unroll
+            for (int k = 0; k < 14; ++k) V[k] = valid ? V[k] : 0u;
+            const float f = vox_sum<T, 14>(V, smem);
+            return f + swap1f(f);
+        };
+
+        float mi = -INFINITY, mj[4], ml[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) mj[m] = ml[m] = -INFINITY;
+        bool hot = false;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                float Fjl;
+                const float F3 = triple(m, n, Fjl);
+                const bool valid = i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;
+                const float gi = valid ? Fjl - F3 : -INFINITY;       // gain of x_i given (x_j, x_l)
+                const float gj = valid ? Fil[n] - F3 : -INFINITY;    // gain of x_j given (x_i, x_l)
+                const float gl = valid ? Fij[m] - F3 : -INFINITY;    // gain of x_l given (x_i, x_j)
+                mi = fmaxf(mi, gi);
+                mj[m] = fmaxf(mj[m], gj);
+                ml[n] = fmaxf(ml[n], gl);
+                hot |= (gi >= thrI) | (gj >= thrJ[m]) | (gl >= thrL[n]);
+            }
+        // wave maxima: i is the tile's; j_m is shared by the lanes of one q; l_n by the lanes of
+        // one c16 / 2 (the two lanes of a pair hold the same values)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mi = fmaxf(mi, __shfl_xor(mi, o));
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            float x = mj[m];
+            x = fmaxf(x, __shfl_xor(x, 2));
+            x = fmaxf(x, __shfl_xor(x, 4));
+            mj[m] = fmaxf(x, __shfl_xor(x, 8));
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            float x = ml[n];
+            x = fmaxf(x, __shfl_xor(x, 16));
+            ml[n] = fmaxf(x, __shfl_xor(x, 32));
+        }
+        if (__any(hot)) {
+            {
+                const float g = key_f32(a.G32[i]);
+                const float top = a.collect ? g : fmaxf(g, mi);
+                thrI = top - win3(a.w_abs, top);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const float g = key_f32(a.G32[clampv(jv[m])]);
+                const float top = a.collect ? g : fmaxf(g, mj[m]);
+                thrJ[m] = top - win3(a.w_abs, top);
+            }
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const float g = key_f32(a.G32[clampv(lv[n])]);
+                const float top = a.collect ? g : fmaxf(g, ml[n]);
+                thrL[n] = top - win3(a.w_abs, top);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(cnt[m][n]) : : "memory");
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    float Fjl;
+                    const float F3 = triple(m, n, Fjl);
+                    const int j = jv[m], l = lv[n];
+                    const bool valid = e == 0 && i < j && j < l && l < a.p;   // one lane per triple
+                    const float gi = Fjl - F3, gj = Fil[n] - F3, gl = Fij[m] - F3;
+                    if (valid && gi >= thrI) append(a, i, ((uint32_t)j << 16) | (uint32_t)l, gi);
+                    if (valid && gj >= thrJ[m]) append(a, j, ((uint32_t)i << 16) | (uint32_t)l, gj);
+                    if (valid && gl >= thrL[n]) append(a, l, ((uint32_t)i << 16) | (uint32_t)j, gl);
+                }
+        }
+        if (a.collect) continue;
+        if (lane == 0 && mi > -INFINITY) atomicMax(&a.G32[i], f32_key(mi));
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if (c16 == 0 && mj[m] > -INFINITY) atomicMax(&a.G32[jv[m]], f32_key(mj[m]));
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+            if (q == 0 && e == 0 && ml[n] > -INFINITY) atomicMax(&a.G32[lv[n]], f32_key(ml[n]));
+    }
+}
+
+int m3_capacity(const Problem &P)
+{
+    const int need = (P.N0 > P.N1 ? P.N0 : P.N1) + 1;
+    for (int T = 1024; T <= 4096; T *= 2)
+        if (need <= T) return T;
+    return 0;
+}
+
+template <int T>
+hipError_t m3_launch(const Problem &P, int r, bool collect)
+{
+    const Layout &L = P.L;
+    Sweep3mArgs a{};
+    a.onehot = P.at<int8_t>(L.onehot);
+    a.ptab = P.at<uint32_t>(L.ptab);
+    a.F2 = P.at<float>(L.F2);
+    a.marg = P.at<uint32_t>(L.marg);
+    a.EA = P.at<float>(L.tabEA);
+    a.EB = P.at<float>(L.tabEB);
+    a.LQ = P.at<float2>(L.tabLQ);
+    a.apref = P.at<int64_t>(L.a3pref);
+    a.ablk = P.at<int32_t>(L.a3blk);
+    a.n_ablk = P.n_ablk3;
+    a.n_tiles = P.n_tiles3;
+    a.N0 = P.N0;
+    a.N1 = P.N1;
+    a.N = (int)L.N;
+    a.p = (int)L.p;
+    a.p_pad = L.p_pad;
+    a.rows_pad = L.rows_pad;
+    a.KB = P.KB;
+    a.KB0 = P.KB0;
+    a.r = r;
+    a.nLB = (int)((L.p + M3_LV - 1) / M3_LV);
+    a.G32 = P.at<uint32_t>(L.G32);
+    a.cand = P.at<Cand>(L.cand);
+    a.cap = L.cap;
+    a.st = P.at<Status>(L.status);
+    a.ovf = P.at<uint32_t>(L.ovf);
+    a.w_abs = (float)(2.0 * P.err_bound);
+    a.collect = collect ? 1 : 0;
+    const size_t lds = (size_t)24 * T + M3_NSTAGE * M3_STAGE + 16;
+    a.snext_off = (int)(lds - 16);
+    hipError_t e = hipFuncSetAttribute((const void *)k_sweep3m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sweep3m<T>, dim3(512), dim3(M3_THREADS), lds, P.stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t sweep3m_lds_bytes(const Problem &P) { return (size_t)24 * m3_capacity(P) + M3_NSTAGE * M3_STAGE + 16; }
+
+// Tile list of the triple sweep: A blocks (i, jb) with jb >= (i + 1) / 32 (some j > i) and
+// jb * 32 < p - 1, each with l blocks lb = jb / 2 .. nLB - 1.  Host-side; apref[k] = first
+// tile of A block k, apref[n_ablk] = number of tiles.
+void sweep3m_tiles(int64_t p, std::vector<int64_t> &apref, std::vector<int32_t> &ablk)
+{
+    const int64_t nJB = (p + M3_JV - 1) / M3_JV, nLB = (p + M3_LV - 1) / M3_LV;
+    apref.clear();
+    ablk.clear();
+    int64_t at = 0;
+    for (int64_t i = 0; i + 2 < p; ++i)
+        for (int64_t jb = (i + 1) / M3_JV; jb < nJB; ++jb) {
+            if (jb * M3_JV >= p - 1) break;
+            apref.push_back(at);
+            ablk.push_back((int32_t)(i * 256 + jb));
+            at += nLB - jb / 2;
+        }
+    apref.push_back(at);
+}
+
+hipError_t launch_sweep3m(const Problem &P, int r, bool collect)
+{
+    hipError_t e = launch_reset_queue(P);
+    if (e != hipSuccess) return e;
+    switch (m3_capacity(P)) {
+    case 1024: return m3_launch<1024>(P, r, collect);
+    case 2048: return m3_launch<2048>(P, r, collect);
+    case 4096: return m3_launch<4096>(P, r, collect);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mdfs

@@ -47,7 +47,7 @@ def test_workspace_size_valid_and_monotone():
     (dict(k=4), -3), (dict(k=1), -3), (dict(divisions=3), -4), (dict(divisions=0), -4),
     (dict(n_obj=2, divisions=2), -1), (dict(n_obj=20000), -8), (dict(range_=1.5), -1),
     (dict(range_=-0.1), -1), (dict(pseudocount=-1.0), -1), (dict(n_disc=0), -1),
-    (dict(disc_offset=-1), -1), (dict(n_var=1), -1), (dict(k=3, engine="mfma_fp4"), -8),
+    (dict(disc_offset=-1), -1), (dict(n_var=1), -1), (dict(k=3, engine="mfma_fp4", divisions=4), -8),
     (dict(k=3, engine="mfma"), -8), (dict(engine="bitset"), -8),
 ])
 def test_invalid_params_rejected_on_host(kw, code):

@@ -1,4 +1,8 @@
-"""k = 3 sweep (bitset engine) on the GPU through the C ABI, against the FP64 oracle."""
+"""k = 3 sweep on the GPU through the C ABI, against the FP64 oracle.
+
+Two count engines: "bitset" (per-class bitsets, AND + popcount; every class count) and
+"mfma_fp4" (pair one-hot x one-hot on the matrix cores; three classes, classes < 4096 objects),
+which "auto" picks where it applies."""
 import numpy as np
 import pytest
 import torch
@@ -11,11 +15,14 @@ from test_gpu_k2 import assert_ig_parity, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def run3(mdfs, w, n_disc=None, xi=None, rng=None, divisions=None, disc_offset=0):
+ENGINES3 = ["bitset", "mfma_fp4"]
+
+
+def run3(mdfs, w, n_disc=None, xi=None, rng=None, divisions=None, disc_offset=0, engine="auto"):
     data, y = to_dev(w)
     out = mdfs.mdfs_max_ig(data, y, 3, w.divisions if divisions is None else divisions,
                            w.n_disc if n_disc is None else n_disc, w.xi if xi is None else xi,
-                           w.range_ if rng is None else rng, w.seed, disc_offset)
+                           w.range_ if rng is None else rng, w.seed, disc_offset, engine=engine)
     torch.cuda.synchronize()
     return [t.cpu().numpy() for t in out]
 
@@ -30,27 +37,32 @@ CASES3 = {
 }
 
 
+@pytest.mark.parametrize("engine", ENGINES3)
 @pytest.mark.parametrize("name", list(CASES3))
-def test_k3_matches_oracle(mdfs_gpu, name):
+def test_k3_matches_oracle(mdfs_gpu, name, engine):
     w = CASES3[name]()
-    print(f"k3 {name} N={w.n_obj} p={w.n_var} R={w.n_disc} d={w.divisions + 1}", flush=True)
-    got = run3(mdfs_gpu, w)
+    if engine == "mfma_fp4" and w.divisions != 2:
+        pytest.skip("the matrix-core k=3 engine is built for three classes")
+    print(f"k3 {name} {engine} N={w.n_obj} p={w.n_var} R={w.n_disc} d={w.divisions + 1}", flush=True)
+    got = run3(mdfs_gpu, w, engine=engine)
     ref = oracle.max_ig_all(w.data, w.y, 3, w.divisions, w.n_disc, w.range_, w.xi, w.seed, n_threads=8)
     assert_ig_parity(*got, ref, name)
 
 
-def test_k3_parity_triple_found(mdfs_gpu):
+@pytest.mark.parametrize("engine", ENGINES3)
+def test_k3_parity_triple_found(mdfs_gpu, engine):
     w = workloads.parity3(seed=31, n_obj=1000, n_var=40, n_disc=2)
-    ig, am, _ = run3(mdfs_gpu, w)
+    ig, am, _ = run3(mdfs_gpu, w, engine=engine)
     for v, others in [(0, [1, 2]), (1, [0, 2]), (2, [0, 1])]:
         assert am[v].tolist() == others
     assert ig[:3].min() > 5 * ig[3:].max()
 
 
-def test_k3_screen_within_error_bound(mdfs_gpu):
+@pytest.mark.parametrize("engine", ENGINES3)
+def test_k3_screen_within_error_bound(mdfs_gpu, engine):
     w = workloads.parity3(seed=32, n_obj=600, n_var=24, n_disc=2)
     data, y = to_dev(w)
-    ig32, E = mdfs_gpu.mdfs_screen_max(data, y, 3, 2, 2, 0.25, 0.5, w.seed)
+    ig32, E = mdfs_gpu.mdfs_screen_max(data, y, 3, 2, 2, 0.25, 0.5, w.seed, engine=engine)
     ig32 = ig32.cpu().numpy().astype(np.float64)
     ref, _, _ = oracle.max_ig_all(w.data, w.y, 3, 2, 2, 0.5, 0.25, w.seed, n_threads=2)
     err = np.abs(ig32 - ref)
@@ -58,21 +70,23 @@ def test_k3_screen_within_error_bound(mdfs_gpu):
     assert err.max() <= E
 
 
-def test_k3_deterministic_and_fused_equals_separate(mdfs_gpu):
+@pytest.mark.parametrize("engine", ENGINES3)
+def test_k3_deterministic_and_fused_equals_separate(mdfs_gpu, engine):
     w = workloads.parity3(seed=33, n_obj=300, n_var=30, n_disc=3)
-    a = run3(mdfs_gpu, w)
-    b = run3(mdfs_gpu, w)
+    a = run3(mdfs_gpu, w, engine=engine)
+    b = run3(mdfs_gpu, w, engine=engine)
     for x, z in zip(a, b):
         assert np.array_equal(x, z)
-    sep = [run3(mdfs_gpu, w, n_disc=1, disc_offset=r) for r in range(3)]
+    sep = [run3(mdfs_gpu, w, n_disc=1, disc_offset=r, engine=engine) for r in range(3)]
     assert np.array_equal(a[0], np.stack([s[0] for s in sep]).max(axis=0))
 
 
-def test_k3_full_size_sampled(mdfs_gpu):
+@pytest.mark.parametrize("engine", ENGINES3)
+def test_k3_full_size_sampled(mdfs_gpu, engine):
     # the parity-triple workload at its full size: N=2000, p=500, 30 discretisations
     w = workloads.parity3(seed=3)
-    print(f"k3 full size: N={w.n_obj} p={w.n_var} R={w.n_disc}", flush=True)
-    ig, am, ad = run3(mdfs_gpu, w)
+    print(f"k3 full size {engine}: N={w.n_obj} p={w.n_var} R={w.n_disc}", flush=True)
+    ig, am, ad = run3(mdfs_gpu, w, engine=engine)
     assert np.isfinite(ig).all()
     for v, others in [(0, [1, 2]), (1, [0, 2]), (2, [0, 1])]:
         assert am[v].tolist() == others
@@ -80,3 +94,23 @@ def test_k3_full_size_sampled(mdfs_gpu):
     tg = np.array([0, 1] + sorted(g.choice(np.arange(3, w.n_var), 3, replace=False).tolist()), dtype=np.int64)
     ref = oracle.max_ig(w.data, w.y, 3, w.divisions, w.n_disc, w.range_, w.xi, w.seed, targets=tg, n_threads=16)
     assert_ig_parity(ig[tg], am[tg], ad[tg], ref, "k3 full size")
+
+
+def test_k3_engines_agree_bit_for_bit_on_argmax(mdfs_gpu):
+    # same float32 screen tables, same binary64 re-score: both engines must give identical
+    # results (the re-scored maxima do not depend on how the counts were obtained)
+    w = workloads.parity3(seed=34, n_obj=777, n_var=50, n_disc=3)
+    a = run3(mdfs_gpu, w, engine="bitset")
+    b = run3(mdfs_gpu, w, engine="mfma_fp4")
+    for x, z in zip(a, b):
+        assert np.array_equal(x, z)
+
+
+def test_k3_mfma_engine_limits(mdfs_gpu):
+    w = workloads.parity3(seed=35, n_obj=200, n_var=12, divisions=4, n_disc=1)
+    with pytest.raises(mdfs_gpu.MdfsError) as e:
+        run3(mdfs_gpu, w, engine="mfma_fp4")
+    assert e.value.code == -8
+    with pytest.raises(mdfs_gpu.MdfsError) as e:
+        run3(mdfs_gpu, workloads.parity3(seed=35, n_obj=200, n_var=12, n_disc=1), engine="mfma")
+    assert e.value.code == -8
