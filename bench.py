@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--cpu-vars", type=int, default=500, help="variables in the oracle's sample")
     ap.add_argument("--cpu-disc", type=int, default=16, help="discretisations in the oracle's sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--engine", default="auto", choices=["auto", "mfma_fp4", "mfma", "bitset"],
                     help="auto: fp4 MFMA for k=2 while each class has < 4096 objects, bitset for k=3")
     ap.add_argument("--copy-calib", action="store_true",
@@ -56,7 +57,7 @@ def _wl(name):
             "genomics_like": workloads.genomics_like}[name]()
 
 
-WORKLOADS = ["headline", "xor_small", "madelon_like", "parity3", "genomics_like"]
+WORKLOADS = ["headline", "xor_small", "madelon_like", "parity3", "genomics_like", "serving"]
 WORKLOAD_TEXT = {
     "headline": "genomics-shaped k=2: N=2000, p=20000 log-normal, 10 planted XOR pairs, balanced y, d=3, "
                 "30 random discretisations (range 0.5, xi 0.25)",
@@ -65,6 +66,9 @@ WORKLOAD_TEXT = {
     "parity3": "k=3: N=2000, p=500 Gaussian, parity triple (0,1,2), d=3, 30 discretisations",
     "genomics_like": "genomics-shaped k=2: N=500, p=20000 log-normal, 10 planted XOR pairs, y 200/300, d=3, "
                      "30 discretisations",
+    "serving": "serving trace: 256 requests, Poisson arrivals at 0.8 x measured capacity, 32 resident "
+               "datasets N~logU[100,5000], p~logU[100,20000] (k=3 requests on datasets with p<=1000), "
+               "k in {2,3}, d in {2,3,5}, 1-30 discretisations, Gaussian data with planted XOR pairs",
 }
 
 
@@ -89,6 +93,58 @@ def cpu_baseline(w, n_vars, n_disc):
                       f"N={w.n_obj}, k=2, d={w.divisions + 1}: {tuples} pair tables in {dt:.2f} s"}
 
 
+def serving_bench(args):
+    """The serving trace: capacity of the plain one-at-a-time sweep, then Poisson arrivals at
+    0.8 x that capacity served with continuous batching (4 slots) and, for comparison, with
+    the plain sweep (1 slot)."""
+    import numpy as np
+    from paper_1811_00631_amd import serving, workloads
+
+    ds = workloads.serving_datasets()
+    base = workloads.serving_requests(ds, n_requests=args.serve_requests)
+    print(f"# serving: {len(ds)} datasets, {len(base)} requests", file=sys.stderr, flush=True)
+
+    def make(srv, ids, rate):
+        out = []
+        for r in base:
+            q = serving.Request(dataset=ids[r["dataset"]], k=r["k"], divisions=r["divisions"], n_disc=r["n_disc"],
+                                seed=r["seed"], arrival=r["arrival"] * (1.0 / rate if rate else 0.0))
+            out.append(q)
+        return out
+
+    def session(slots, rate):
+        srv = serving.Server(slots=slots)
+        try:
+            ids = [srv.add_dataset(X, y) for X, y, _ in ds]
+            # warm-up: one small request per engine path
+            serving.run_trace(srv, make(srv, ids, 0)[:4], timeout=600)
+            reqs = make(srv, ids, rate)
+            st = serving.run_trace(srv, reqs, timeout=900)
+            print(f"# serving slots={slots} rate={rate}: {st}", file=sys.stderr, flush=True)
+            return st, reqs
+        finally:
+            srv.close()
+
+    plain_cap, _ = session(1, 0)                        # back to back: capacity of the plain sweep
+    rate = 0.8 * len(base) / plain_cap["makespan_s"]   # requests/s; base arrivals are at rate 1
+    mixed, _ = session(4, rate)
+    plain, _ = session(1, rate)
+    line = {
+        "metric": "serving: k-tuples evaluated/sec over the trace; p50/p99 request latency",
+        "value": mixed["tuples_per_s"], "unit": "k-tuples evaluated/sec", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": mixed["makespan_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "mixed (fp4/int8 MFMA, bitsets)", "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["serving"], "requests": len(base), "arrival_rate_hz": rate,
+                   "slots": 4},
+        "p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"],
+        "plain_sweep_same_arrivals": {"tuples_per_s": plain["tuples_per_s"], "p50_ms": plain["p50_ms"],
+                                      "p99_ms": plain["p99_ms"]},
+        "plain_sweep_capacity_tuples_per_s": plain_cap["tuples_per_s"],
+        "total_tuples": mixed["tuples"],
+    }
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -103,6 +159,9 @@ def main():
     from paper_1811_00631_amd import mdfs, workloads
 
     mdfs.load()
+    if args.workload == "serving":
+        serving_bench(args)
+        return
     dev = torch.device("cuda:0")
     w = _wl(args.workload)
     data = torch.from_numpy(w.data).to(dev)

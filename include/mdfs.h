@@ -80,6 +80,10 @@ typedef struct {
     uint64_t seed;       /* seed of the counter-based SplitMix64 draws of the shares */
     int32_t engine;      /* mdfs_engine */
     int32_t flags;       /* bitwise OR of mdfs_flags; other bits must be 0 */
+    int32_t workgroups;  /* workgroups of the persistent sweep kernels: 0 = the whole GPU, else
+                            8..4096; smaller grids let concurrent calls on other streams share
+                            the GPU (results do not depend on it) */
+    int32_t reserved;    /* must be 0 */
 } mdfs_params;
 
 typedef enum {

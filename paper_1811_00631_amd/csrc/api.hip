@@ -103,6 +103,9 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
     if (!(prm->pseudocount >= 0.0) || !isfinite(prm->pseudocount))
         return fail(MDFS_E_ARG, "pseudocount=%g must be finite and >= 0", prm->pseudocount);
     if (prm->engine < 0 || prm->engine > 3) return fail(MDFS_E_ARG, "engine=%d", prm->engine);
+    if (prm->workgroups != 0 && (prm->workgroups < 8 || prm->workgroups > 4096))
+        return fail(MDFS_E_ARG, "workgroups=%d: 0 (whole GPU) or 8..4096", prm->workgroups);
+    if (prm->reserved != 0) return fail(MDFS_E_ARG, "reserved field must be 0");
     return MDFS_OK;
 }
 
@@ -149,6 +152,7 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
         if (c > 0 && c < P.L.cap) P.L.cap = c;
     }
     P.disc_offset = prm->disc_offset;
+    P.workgroups = prm->workgroups;
     P.range = prm->range;
     P.seed = prm->seed;
     const int64_t N = prm->n_obj;

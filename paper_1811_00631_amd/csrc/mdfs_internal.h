@@ -116,6 +116,7 @@ struct Problem {
     uint64_t seed;
     double err_bound;             // float32 screen error bound E (per IG)
     bool k3_mfma;                 // k = 3 on the matrix cores (else bitsets)
+    int workgroups;               // persistent sweep grid (0 = the whole GPU)
     int64_t n_ablk3, n_tiles3;    // tile list of the k = 3 matrix-core sweep
     char *ws;
     hipStream_t stream;

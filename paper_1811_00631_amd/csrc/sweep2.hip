@@ -174,19 +174,33 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
         for (int i = t; i <= a.N; i += SW_THREADS) LQ[i] = a.LQ[i];
     }
 
-    // Persistent, XCD-aware schedule.  The super-tiles sup = x, x+8, x+16 ... belong to XCD x;
-    // the workgroups resident on that XCD take its tiles (super-tile by super-tile, slot by
-    // slot) from one atomic counter, so at any time they work on the same SB x SB block of
-    // tiles and share its SB row panels and SB column panels in the XCD's L2.
+    // Persistent, XCD-aware schedule.  The super-tiles sup = x, x+8, x+16 ... form queue x; the
+    // workgroups resident on XCD x take its tiles (super-tile by super-tile, slot by slot) from
+    // one atomic counter, so at any time they work on the same SB x SB block of tiles and share
+    // its SB row panels and SB column panels in the XCD's L2.  A workgroup whose queue is
+    // drained moves on to the next queues, so every tile is taken whatever the grid size and
+    // wherever its workgroups run.
     const int xcd = (int)(__builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 7);  // HW_REG_XCC_ID
-    const int64_t n_mine = ((a.n_super - xcd + XCDS - 1) / XCDS) * (SB * SB);
+    int my_q = xcd, q_seen = 0;   // thread 0's position in the queue walk
     for (;;) {
     __syncthreads();   // everyone has read the previous s_next
-    if (t == 0) *s_next_p = atomicAdd(&a.st->next_tile[xcd], 1u);
+    if (t == 0) {
+        int64_t it = -1;
+        while (q_seen < XCDS) {
+            const int64_t nq = ((a.n_super - my_q + XCDS - 1) / XCDS) * (SB * SB);
+            it = (int64_t)atomicAdd(&a.st->next_tile[my_q], 1u);
+            if (it < nq) break;
+            it = -1;
+            my_q = (my_q + 1) & (XCDS - 1);
+            ++q_seen;
+        }
+        s_next_p[0] = it;
+        s_next_p[1] = my_q;
+    }
     __syncthreads();
-    const int64_t item = *s_next_p;
-    if (item >= n_mine) break;
-    const int64_t sup = xcd + XCDS * (item / (SB * SB));
+    const int64_t item = s_next_p[0];
+    if (item < 0) break;
+    const int64_t sup = s_next_p[1] + XCDS * (item / (SB * SB));
     const int slot = (int)(item % (SB * SB));
     const int r = a.r_base + (int)(sup / a.super_per_r);
     int SI, SJ;
@@ -733,7 +747,7 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
                             : (counts_out ? k_sweep2<W, SWEEP_DEBUG_COUNTS, ENC> : k_sweep2<W, SWEEP_MAX, ENC>);
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    const int grid = XCDS * WG_PER_XCD;
+    const int grid = P.workgroups > 0 ? P.workgroups : XCDS * WG_PER_XCD;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(SW_THREADS), lds, P.stream, a);
     return hipGetLastError();
 }

@@ -318,7 +318,7 @@ static hipError_t sweep3_launch(const Problem &P, int r, bool collect)
     auto kern = k_sweep3<W>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(1024), dim3(S3_THREADS), lds, P.stream, a);
+    hipLaunchKernelGGL(kern, dim3(P.workgroups > 0 ? 2 * P.workgroups : 1024), dim3(S3_THREADS), lds, P.stream, a);
     return hipGetLastError();
 }
 

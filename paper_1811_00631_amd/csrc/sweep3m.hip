@@ -471,7 +471,7 @@ hipError_t m3_launch(const Problem &P, int r, bool collect)
     a.snext_off = (int)(lds - 16);
     hipError_t e = hipFuncSetAttribute((const void *)k_sweep3m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sweep3m<T>, dim3(512), dim3(M3_THREADS), lds, P.stream, a);
+    hipLaunchKernelGGL(k_sweep3m<T>, dim3(P.workgroups > 0 ? P.workgroups : 512), dim3(M3_THREADS), lds, P.stream, a);
     return hipGetLastError();
 }
 

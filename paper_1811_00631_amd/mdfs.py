@@ -39,7 +39,8 @@ class Params(ctypes.Structure):
     _fields_ = [("n_obj", ctypes.c_int64), ("n_var", ctypes.c_int64), ("k", ctypes.c_int32),
                 ("divisions", ctypes.c_int32), ("n_disc", ctypes.c_int32), ("disc_offset", ctypes.c_int32),
                 ("range", ctypes.c_double), ("pseudocount", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("engine", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("engine", ctypes.c_int32), ("flags", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -75,9 +76,10 @@ def load(path: str = LIB_PATH):
 
 
 def make_params(n_obj, n_var, k=2, divisions=2, n_disc=1, disc_offset=0, range_=0.5, pseudocount=0.25,
-                seed=0, engine="auto", flags=0) -> Params:
+                seed=0, engine="auto", flags=0, workgroups=0) -> Params:
     return Params(int(n_obj), int(n_var), int(k), int(divisions), int(n_disc), int(disc_offset),
-                  float(range_), float(pseudocount), int(seed) & ((1 << 64) - 1), ENGINES[engine], int(flags))
+                  float(range_), float(pseudocount), int(seed) & ((1 << 64) - 1), ENGINES[engine], int(flags),
+                  int(workgroups), 0)
 
 
 def mdfs_phase_times() -> dict:
@@ -156,17 +158,23 @@ def mdfs_discretize(data: torch.Tensor, divisions: int, n_disc: int, range_: flo
 
 def mdfs_max_ig(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_disc: int,
                 pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0, disc_offset: int = 0,
-                engine: str = "auto", timing: bool = False):
+                engine: str = "auto", timing: bool = False, workgroups: int = 0, ws: torch.Tensor | None = None,
+                stream=None):
+    """IG_max, argmax tuple and argmax discretisation of every variable.  `ws` (a caller-owned
+    uint8 device workspace of at least mdfs_workspace_size bytes) and `stream` (a torch CUDA
+    stream) default to a per-device cached workspace and the current stream."""
     data, y = _dev_inputs(data, y)
     n_var, n_obj = data.shape
     prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed, engine,
-                      FLAG_TIMING if timing else 0)
-    ws = workspace_for(prm, data.device)
+                      FLAG_TIMING if timing else 0, workgroups)
+    if ws is None:
+        ws = workspace_for(prm, data.device)
+    strm = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(data.device)
     ig = torch.empty(n_var, dtype=torch.float32, device=data.device)
     am = torch.empty((n_var, k - 1), dtype=torch.int32, device=data.device)
     ad = torch.empty(n_var, dtype=torch.int32, device=data.device)
     _check(load().mdfs_max_ig(ctypes.byref(prm), _ptr(data), _ptr(y), _ptr(ig), _ptr(am), _ptr(ad), _ptr(ws),
-                              ws.numel(), _stream(data.device)))
+                              ws.numel(), strm))
     return ig, am, ad
 
 

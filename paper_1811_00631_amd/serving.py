@@ -1,0 +1,226 @@
+"""Serving loop for feature-selection requests: continuous batching on one GPU.
+
+Datasets are uploaded once and stay resident in HBM; a request names a dataset and the sweep
+parameters (k, divisions, discretisations, pseudocount, seed).  The server admits queued
+requests into free slots while their HBM footprint (the library's workspace plus the outputs)
+fits the memory budget, first fit in arrival order (a request passed over too often blocks
+later ones until it fits).  Each slot is a host thread with its own HIP stream; the C-ABI call
+releases the GIL, so the sweeps of admitted requests run concurrently on the device, each
+with a bounded persistent grid so that small requests are not stuck behind large ones.
+Results do not depend on the mix: every call is deterministic and the persistent grids take
+all of their tiles whatever their size.
+
+Host orchestration only: every step of every sweep runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import threading
+import time
+
+import numpy as np
+import torch
+
+from . import mdfs
+
+
+@dataclasses.dataclass
+class Request:
+    dataset: int
+    k: int
+    divisions: int
+    n_disc: int
+    pseudocount: float = 0.25
+    range_: float = 0.5
+    seed: int = 0
+    engine: str = "auto"
+    arrival: float = 0.0          # seconds after the start of a trace
+    # filled by the server
+    id: int = -1
+    t_admit: float = math.nan
+    t_done: float = math.nan
+    footprint: int = 0
+    result: tuple | None = None   # (ig_max, argmax, argmax_disc) as numpy arrays
+    error: str | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.arrival
+
+
+@dataclasses.dataclass
+class Dataset:
+    data: torch.Tensor            # float32 [n_var][n_obj] on the device
+    y: torch.Tensor               # uint8 [n_obj] on the device
+
+    @property
+    def n_var(self) -> int:
+        return self.data.shape[0]
+
+    @property
+    def n_obj(self) -> int:
+        return self.data.shape[1]
+
+
+def tuples_of(ds: Dataset, req: Request) -> int:
+    return math.comb(ds.n_var, req.k) * req.n_disc
+
+
+class Server:
+    def __init__(self, device: str = "cuda:0", slots: int = 4, hbm_budget: int | None = None,
+                 workgroups: int | None = None, max_bypass: int = 8):
+        mdfs.load()
+        self.device = torch.device(device)
+        self.slots = slots
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            hbm_budget = int(0.8 * free)
+        self.budget = hbm_budget
+        # persistent grid per call: the GPU's 512 resident sweep workgroups shared by the slots
+        self.workgroups = workgroups if workgroups is not None else max(64, (512 // slots) // 8 * 8)
+        self.max_bypass = max_bypass
+        self.datasets: dict[int, Dataset] = {}
+        self.resident = 0
+        self._lock = threading.Condition()
+        self._queue: collections.deque[Request] = collections.deque()
+        self._in_use = 0
+        self._bypassed: dict[int, int] = {}
+        self._next_id = 0
+        self._closing = False
+        self._t0 = time.perf_counter()
+        self.done: list[Request] = []
+        self._threads = [threading.Thread(target=self._worker, args=(s,), daemon=True) for s in range(slots)]
+        self._streams = [torch.cuda.Stream(self.device) for _ in range(slots)]   # default priority
+        for th in self._threads:
+            th.start()
+
+    # -------------------------------------------------------------- datasets
+    def add_dataset(self, data: np.ndarray, y: np.ndarray) -> int:
+        """Upload a dataset once; it stays resident until remove_dataset."""
+        d = torch.from_numpy(np.ascontiguousarray(data, dtype=np.float32)).to(self.device)
+        yy = torch.from_numpy(np.ascontiguousarray(y, dtype=np.uint8)).to(self.device)
+        torch.cuda.synchronize(self.device)
+        with self._lock:
+            did = len(self.datasets)
+            while did in self.datasets:
+                did += 1
+            self.datasets[did] = Dataset(d, yy)
+            self.resident += d.numel() * 4 + yy.numel()
+        return did
+
+    def remove_dataset(self, did: int):
+        with self._lock:
+            ds = self.datasets.pop(did)
+            self.resident -= ds.data.numel() * 4 + ds.y.numel()
+
+    # -------------------------------------------------------------- requests
+    def footprint(self, req: Request) -> int:
+        ds = self.datasets[req.dataset]
+        prm = mdfs.make_params(ds.n_obj, ds.n_var, req.k, req.divisions, req.n_disc, 0, req.range_,
+                               req.pseudocount, req.seed, req.engine, 0, self.workgroups)
+        ws = mdfs.mdfs_workspace_size(prm)
+        return ws + ds.n_var * 4 * (req.k + 1) + 4096
+
+    def submit(self, req: Request) -> Request:
+        req.footprint = self.footprint(req)
+        if req.footprint + self.resident > self.budget:
+            raise ValueError(f"request needs {req.footprint} bytes, more than the HBM budget allows")
+        with self._lock:
+            req.id = self._next_id
+            self._next_id += 1
+            self._queue.append(req)
+            self._lock.notify_all()
+        return req
+
+    def now(self) -> float:
+        return time.perf_counter() - self._t0
+
+    def reset_clock(self):
+        self._t0 = time.perf_counter()
+
+    def _take(self) -> Request | None:
+        """First queued request whose footprint fits (called with the lock held)."""
+        free = self.budget - self.resident - self._in_use
+        for idx, req in enumerate(self._queue):
+            if req.footprint <= free:
+                for earlier in list(self._queue)[:idx]:
+                    self._bypassed[earlier.id] = self._bypassed.get(earlier.id, 0) + 1
+                del self._queue[idx]
+                self._bypassed.pop(req.id, None)
+                return req
+            if self._bypassed.get(req.id, 0) >= self.max_bypass:
+                return None   # this one waits for memory; nobody passes it any more
+        return None
+
+    def _worker(self, slot: int):
+        stream = self._streams[slot]
+        while True:
+            with self._lock:
+                req = None
+                while req is None:
+                    if self._closing and not self._queue:
+                        return
+                    req = self._take()
+                    if req is None:
+                        self._lock.wait()
+                self._in_use += req.footprint
+                req.t_admit = self.now()
+            try:
+                self._run(req, stream)
+            except Exception as exc:   # reported on the request, the server keeps serving
+                req.error = f"{type(exc).__name__}: {exc}"
+            with self._lock:
+                self._in_use -= req.footprint
+                req.t_done = self.now()
+                self.done.append(req)
+                self._lock.notify_all()
+
+    def _run(self, req: Request, stream: torch.cuda.Stream):
+        ds = self.datasets[req.dataset]
+        with torch.cuda.stream(stream):
+            prm = mdfs.make_params(ds.n_obj, ds.n_var, req.k, req.divisions, req.n_disc, 0, req.range_,
+                                   req.pseudocount, req.seed, req.engine, 0, self.workgroups)
+            ws = torch.empty(mdfs.mdfs_workspace_size(prm), dtype=torch.uint8, device=self.device)
+            ig, am, ad = mdfs.mdfs_max_ig(ds.data, ds.y, req.k, req.divisions, req.n_disc, req.pseudocount,
+                                          req.range_, req.seed, 0, engine=req.engine,
+                                          workgroups=self.workgroups, ws=ws, stream=stream)
+            req.result = (ig.cpu().numpy(), am.cpu().numpy(), ad.cpu().numpy())
+            del ws
+
+    def wait_all(self, n: int, timeout: float | None = None):
+        """Block until n requests have finished."""
+        with self._lock:
+            ok = self._lock.wait_for(lambda: len(self.done) >= n, timeout)
+        if not ok:
+            raise TimeoutError(f"{len(self.done)} of {n} requests finished")
+
+    def close(self):
+        with self._lock:
+            self._closing = True
+            self._lock.notify_all()
+        for th in self._threads:
+            th.join()
+
+
+def run_trace(server: Server, reqs: list[Request], timeout: float = 600.0) -> dict:
+    """Submit requests at their arrival times (seconds from now) and wait for all of them.
+    Returns latency percentiles and throughput over the makespan."""
+    server.done.clear()
+    server.reset_clock()
+    for req in sorted(reqs, key=lambda r: r.arrival):
+        delay = req.arrival - server.now()
+        if delay > 0:
+            time.sleep(delay)
+        server.submit(req)
+    server.wait_all(len(reqs), timeout)
+    bad = [r for r in reqs if r.error]
+    if bad:
+        raise RuntimeError(f"{len(bad)} requests failed, first: {bad[0].error}")
+    lat = np.array([r.latency for r in reqs])
+    makespan = max(r.t_done for r in reqs) - min(r.arrival for r in reqs)
+    tuples = sum(tuples_of(server.datasets[r.dataset], r) for r in reqs)
+    return {"requests": len(reqs), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "makespan_s": makespan, "tuples": tuples, "tuples_per_s": tuples / makespan}

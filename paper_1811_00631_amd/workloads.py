@@ -140,3 +140,48 @@ WORKLOADS = {
     "genomics_like": genomics_like,
     "headline": headline,
 }
+
+
+def serving_datasets(seed: int = 6, n_datasets: int = 32, n_range=(100, 5000), p_range=(100, 20000),
+                     k3_max_vars: int = 1000):
+    """Datasets of the serving trace: N and p log-uniform in the given ranges, Gaussian
+    variables, y balanced in expectation from one planted XOR pair [x_a>0] xor [x_b>0] (10%
+    label noise); datasets with p <= k3_max_vars also carry a second, exact XOR pair.  Every
+    other dataset is capped at k3_max_vars variables so that k = 3 requests exist."""
+    g = np.random.default_rng(seed)
+    out = []
+    for t in range(n_datasets):
+        n = int(round(np.exp(g.uniform(np.log(n_range[0]), np.log(n_range[1])))))
+        p_hi = p_range[1] if t % 2 == 0 else min(p_range[1], k3_max_vars)
+        p = int(round(np.exp(g.uniform(np.log(p_range[0]), np.log(p_hi)))))
+        X = g.standard_normal((p, n)).astype(np.float32)
+        a, b = (int(v) for v in g.choice(p, size=2, replace=False))
+        y = ((X[a] > 0) ^ (X[b] > 0)).astype(np.uint8)
+        y ^= (g.random(n) < 0.1).astype(np.uint8)
+        if y.min() == y.max():
+            y[0] ^= 1
+        pairs = [sorted((a, b))]
+        if p <= k3_max_vars and p >= 4:
+            c, d = (int(v) for v in g.choice(np.setdiff1d(np.arange(p), [a, b]), size=2, replace=False))
+            X[d] = np.abs(X[d]) * np.where((X[c] > 0) ^ (y > 0), 1.0, -1.0).astype(np.float32)
+            pairs.append(sorted((c, d)))
+        out.append((X, y, {"pairs": pairs}))
+    return out
+
+
+def serving_requests(datasets, seed: int = 6, n_requests: int = 256, rate_hz: float = 1.0,
+                     k3_max_vars: int = 1000):
+    """Request parameters of the serving trace: dataset uniform, k in {2, 3} (k = 3 only on
+    datasets with at most k3_max_vars variables), divisions in {1, 2, 4}, 1..30 discretisations,
+    Poisson arrivals at rate_hz.  Returns dicts (dataset, k, divisions, n_disc, seed, arrival)."""
+    g = np.random.default_rng(seed + 1000)
+    t = 0.0
+    reqs = []
+    for i in range(n_requests):
+        t += g.exponential(1.0 / rate_hz)
+        ds = int(g.integers(len(datasets)))
+        p = datasets[ds][0].shape[0]
+        k = int(g.choice([2, 3])) if p <= k3_max_vars else 2
+        reqs.append({"dataset": ds, "k": k, "divisions": int(g.choice([1, 2, 4])),
+                     "n_disc": int(g.integers(1, 31)), "seed": int(g.integers(1 << 31)), "arrival": t})
+    return reqs

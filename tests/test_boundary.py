@@ -29,9 +29,10 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_struct_matches_header():
     # int64 n_obj, n_var; int32 k, divisions, n_disc, disc_offset; double range, pseudocount;
-    # uint64 seed; int32 engine, flags
-    assert ctypes.sizeof(mdfs.Params) == 64
+    # uint64 seed; int32 engine, flags, workgroups, reserved
+    assert ctypes.sizeof(mdfs.Params) == 72
     assert mdfs.Params.range.offset == 32 and mdfs.Params.seed.offset == 48 and mdfs.Params.flags.offset == 60
+    assert mdfs.Params.workgroups.offset == 64
 
 
 def test_workspace_size_valid_and_monotone():
@@ -47,7 +48,7 @@ def test_workspace_size_valid_and_monotone():
     (dict(k=4), -3), (dict(k=1), -3), (dict(divisions=3), -4), (dict(divisions=0), -4),
     (dict(n_obj=2, divisions=2), -1), (dict(n_obj=20000), -8), (dict(range_=1.5), -1),
     (dict(range_=-0.1), -1), (dict(pseudocount=-1.0), -1), (dict(n_disc=0), -1),
-    (dict(disc_offset=-1), -1), (dict(n_var=1), -1), (dict(k=3, engine="mfma_fp4", divisions=4), -8),
+    (dict(disc_offset=-1), -1), (dict(n_var=1), -1), (dict(workgroups=4), -1), (dict(workgroups=5000), -1), (dict(k=3, engine="mfma_fp4", divisions=4), -8),
     (dict(k=3, engine="mfma"), -8), (dict(engine="bitset"), -8),
 ])
 def test_invalid_params_rejected_on_host(kw, code):

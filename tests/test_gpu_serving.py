@@ -1,0 +1,80 @@
+"""Serving loop on the GPU: results in a concurrent mix equal the results of each request run
+alone (bit for bit), admission respects the HBM budget, and planted pairs are found."""
+import numpy as np
+import pytest
+
+from paper_1811_00631_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def small_trace():
+    ds = workloads.serving_datasets(seed=41, n_datasets=4, n_range=(150, 900), p_range=(40, 300),
+                                    k3_max_vars=120)
+    reqs = workloads.serving_requests(ds, seed=41, n_requests=14, rate_hz=1e6, k3_max_vars=120)
+    return ds, reqs
+
+
+def run(serving, ds, reqs, slots, budget=None):
+    srv = serving.Server(slots=slots, hbm_budget=budget)
+    try:
+        ids = [srv.add_dataset(X, y) for X, y, _ in ds]
+        rq = [serving.Request(dataset=ids[r["dataset"]], k=r["k"], divisions=r["divisions"], n_disc=r["n_disc"],
+                              seed=r["seed"], arrival=0.0 if slots > 1 else 0.0) for r in reqs]
+        if slots == 1:
+            out = []
+            for q in rq:        # one at a time: submit, wait, next
+                srv.submit(q)
+                srv.wait_all(len(out) + 1, timeout=300)
+                out.append(q)
+        else:
+            serving.run_trace(srv, rq, timeout=300)
+        return rq, srv
+    finally:
+        srv.close()
+
+
+def test_mix_equals_alone(mdfs_gpu):
+    from paper_1811_00631_amd import serving
+    ds, reqs = small_trace()
+    print(f"serving mix: {len(reqs)} requests on {len(ds)} datasets", flush=True)
+    alone, _ = run(serving, ds, reqs, slots=1)
+    mixed, srv = run(serving, ds, reqs, slots=4)
+    assert all(q.error is None for q in alone + mixed), [q.error for q in alone + mixed if q.error]
+    for a, m in zip(alone, mixed):
+        for x, z in zip(a.result, m.result):
+            assert np.array_equal(x, z), (a, m)
+    # requests overlapped on the device: some request was admitted before another finished
+    spans = sorted((q.t_admit, q.t_done) for q in mixed)
+    assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+
+
+def test_planted_pairs_found_through_server(mdfs_gpu):
+    from paper_1811_00631_amd import serving
+    ds, reqs = small_trace()
+    reqs = [dict(r, k=2, divisions=2, n_disc=4) for r in reqs[:4]]
+    mixed, _ = run(serving, ds, reqs, slots=2)
+    for r, q in zip(reqs, mixed):
+        a, b = ds[r["dataset"]][2]["pairs"][0]
+        ig, am, _ = q.result
+        assert am[a, 0] == b and am[b, 0] == a
+
+
+def test_admission_respects_budget(mdfs_gpu):
+    from paper_1811_00631_amd import serving
+    ds, reqs = small_trace()
+    srv = serving.Server(slots=4, hbm_budget=1 << 62)
+    try:
+        ids = [srv.add_dataset(X, y) for X, y, _ in ds]
+        rq = [serving.Request(dataset=ids[r["dataset"]], k=r["k"], divisions=r["divisions"], n_disc=r["n_disc"],
+                              seed=r["seed"]) for r in reqs]
+        foot = [srv.footprint(q) for q in rq]
+    finally:
+        srv.close()
+    # a budget that holds the datasets and only the largest request: requests run one at a time
+    budget = srv.resident + max(foot)
+    mixed, srv2 = run(serving, ds, reqs, slots=4, budget=budget)
+    spans = sorted((q.t_admit, q.t_done, q.footprint) for q in mixed)
+    for i in range(len(spans)):
+        live = [s for s in spans if s[0] <= spans[i][0] < s[1]]
+        assert sum(s[2] for s in live) + srv2.resident <= budget
