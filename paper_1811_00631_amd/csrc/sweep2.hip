@@ -37,7 +37,8 @@ template <> struct AccOf<true> { typedef v4f type; };
 // after the operand stages); T = 1024, 2048, 4096 = fp4 encoding with LDS entropy tables of
 // capacity T per class at fixed addresses, so each lookup is one ds_read with an immediate
 // offset:  EA [0, 4T)  EB [4T, 8T)  (L, Q) pairs [8T, 24T - 8)  (bytes; the pairs hold the
-// 2T - 1 entries n = 0 .. 2T - 2), operand stages from 24T.
+// 2T - 1 entries n = 0 .. 2T - 2), operand stages from 24T.  EA and EB stay separate: a
+// gather at an 8-byte stride would use half of the LDS banks.
 __host__ __device__ constexpr int stage_base(int ENC) { return ENC ? 24 * ENC : 0; }
 
 constexpr int SW_THREADS = 256;          // 4 waves, 2 x 2 wave grid, 64 x 64 outputs per wave
@@ -92,8 +93,9 @@ __device__ inline float vox_term(uint32_t P, const float *EA, const float *EB, c
 
 
 // Sum of n h(p) over NV voxels (packed counts).  ENC != 0: fp4 packing (4 n1) << 16 | 4 n0,
-// whose halves and their sum are the byte offsets of EA[n0], EB[n1] and the (L, Q) pair of n
-// in the fixed LDS layout; all table reads first, then the arithmetic, so the reads overlap.
+// whose halves are the byte offsets of EA[n0], EB[n1] and twice their sum that of the (L, Q)
+// pair of n in the fixed LDS layout; all table reads first, then the arithmetic, so the
+// reads overlap.
 // A packed count of 0 contributes exactly 0 (L[0] = Q[0] = 0).
 template <int ENC, int NV>
 __device__ inline float sum_vox(const uint32_t (&P)[NV], const char *smem, const float *EA, const float *EB,
@@ -247,7 +249,6 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
                                              (__attribute__((address_space(3))) void *)(dst + i * 1024), 16, 0, 0);
     };
     const int fa_off0 = lds_addr(wr * 64 + c16, q), fb_off0 = lds_addr(wc * 64 + c16, q);
-    v4i fa[4], fb[4];
     auto frags = [&](int s_, v4i (&xa)[4], v4i (&xb)[4]) {
         const char *A = stage_at(s_), *B = A + TILE_ROWS * KBLK;
 #pragma unroll
@@ -255,36 +256,29 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
 #pragma unroll
         for (int n = 0; n < 4; ++n) xb[n] = *reinterpret_cast<const v4i *>(B + fb_off0 + n * 16 * KBLK);
     };
-    // Software pipeline over a ring of NSTAGE = 3 LDS stages, blocks fetched two steps ahead.
-    // Step s: wait until this wave's fetches of block s have landed (loads complete in issue
-    // order, so at most the 4 fetches of block s+1 may still be outstanding), barrier (block s
-    // is complete in LDS; every wave is done reading stage (s+2) % 3 from step s-1), fetch
-    // block s+2 into that stage, then read the fragments of block s and multiply.
-    issue(0);
-    if (a.KB > 1) issue(1);
-    for (int s = 0; s < a.KB; ++s) {
-        if (s + 1 < a.KB) __builtin_amdgcn_s_waitcnt(0x0F74);   // vmcnt(4)
-        else __builtin_amdgcn_s_waitcnt(0x0F70);                // vmcnt(0)
-        // a plain barrier: a fenced one would also wait for the fetches of block s+1
-        __builtin_amdgcn_s_barrier();
-        if (s + 2 < a.KB) issue(s + 2);
-        frags(s, fa, fb);
+    // Software pipeline over a ring of NSTAGE = 3 LDS stages; blocks are fetched two steps ahead
+    // and their fragments read one step ahead.  Step s: the MFMAs of block s (fragments read
+    // during step s-1) go out; meanwhile the wave waits until its fetches of block s+1 have
+    // landed (loads complete in issue order, so at most the 4 fetches of block s+2 may still be
+    // outstanding), passes a barrier (block s+1 is complete in LDS, and every wave has read
+    // the fragments of block s, so its stage is free), reads the fragments of block s+1 and
+    // fetches block s+3 into the stage of block s.
+    auto mma = [&](int s_, const v4i (&xa)[4], const v4i (&xb)[4]) {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n)
-            {
+            for (int n = 0; n < 4; ++n) {
                 if constexpr (F4) {
                     // A/B: 16 rows x 128 objects, lane l holds row l % 16 and 32 nibbles of
                     // one quarter of the objects; cbsz = blgp = 4 selects E2M1 for both operands
-                    const v8i a8{fa[m][0], fa[m][1], fa[m][2], fa[m][3], 0, 0, 0, 0};
-                    const v8i b8{fb[n][0], fb[n][1], fb[n][2], fb[n][3], 0, 0, 0, 0};
+                    const v8i a8{xa[m][0], xa[m][1], xa[m][2], xa[m][3], 0, 0, 0, 0};
+                    const v8i b8{xb[n][0], xb[n][1], xb[n][2], xb[n][3], 0, 0, 0, 0};
                     acc[m][n] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, b8, acc[m][n], 4, 4, 0, 0, 0, 0);
                 } else {
-                    acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[m], fb[n], acc[m][n], 0, 0, 0);
+                    acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xa[m], xb[n], acc[m][n], 0, 0, 0);
                 }
             }
-        if (s == n1blk - 1) {
+        if (s_ == n1blk - 1) {
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -293,7 +287,31 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
                     else acc[m][n] = acc[m][n] << 16;
                 }
         }
+    };
+    // the plain barrier: a fenced one would also drain the fetches still in flight
+    auto next_block = [&](int s_, v4i (&ya)[4], v4i (&yb)[4]) {
+        if (s_ + 2 < a.KB) __builtin_amdgcn_s_waitcnt(0x0F74);   // vmcnt(4)
+        else __builtin_amdgcn_s_waitcnt(0x0F70);                 // vmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        frags(s_ + 1, ya, yb);
+        if (s_ + 3 < a.KB) issue(s_ + 3);
+    };
+    v4i fa0[4], fb0[4], fa1[4], fb1[4];
+    issue(0);
+    if (a.KB > 1) issue(1);
+    if (a.KB > 1) __builtin_amdgcn_s_waitcnt(0x0F74);
+    else __builtin_amdgcn_s_waitcnt(0x0F70);
+    __builtin_amdgcn_s_barrier();
+    frags(0, fa0, fb0);
+    if (a.KB > 2) issue(2);
+    int s = 0;
+    for (; s + 1 < a.KB; s += 2) {
+        mma(s, fa0, fb0);
+        next_block(s, fa1, fb1);
+        mma(s + 1, fa1, fb1);
+        if (s + 2 < a.KB) next_block(s + 1, fa0, fb0);
     }
+    if (s < a.KB) mma(s, fa0, fb0);
 
     // ---------------------------------------------------------------- epilogue
     // packed integer counts: int8 n1 << 16 | n0; fp4 (4 n1) << 16 | 4 n0 from the exact
@@ -329,7 +347,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
         const float *F1r = a.F1 + (int64_t)r * a.p_pad;
         auto repack = [](uint32_t x) -> uint32_t { return F4 ? x << 2 : x; };
         uint32_t Mrb[4], Mrs[4], Mcb[4], Mc4[4];
-        float Fr[4], Fc[4], thrR[4], thrC[4];
+        float Fr[4], Fc[4], thrR[4], thrC[4], gR[4], gC[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int64_t v = rv_of(m);
@@ -340,6 +358,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
             Mrb[m] = repack(margr[v * C + b]);
             Fr[m] = F1r[v];
             const float gk = key_f32(a.G32[v]);
+            gR[m] = gk;
             thrR[m] = gk - rescore_window(a.w_abs, gk);
         }
 #pragma unroll
@@ -349,6 +368,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
             Mc4[n] = repack(margr[v * C + 4]);
             Fc[n] = F1r[v];
             const float gk = key_f32(a.G32[v]);
+            gC[n] = gk;
             thrC[n] = gk - rescore_window(a.w_abs, gk);
         }
         // the lane's voxels of pair (m, n) and the quad sum F; vx[0..3] direct (x, b),
@@ -468,10 +488,10 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
         if (a.collect) continue;
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-            if (c16 == 0 && rmax[m] > -INFINITY) atomicMax(&a.G32[rv_of(m)], f32_key(rmax[m]));
+            if (c16 == 0 && rmax[m] > gR[m]) atomicMax(&a.G32[rv_of(m)], f32_key(rmax[m]));
 #pragma unroll
         for (int n = 0; n < 4; ++n)
-            if (q == 0 && b == 0 && cmax[n] > -INFINITY) atomicMax(&a.G32[cv_of(n)], f32_key(cmax[n]));
+            if (q == 0 && b == 0 && cmax[n] > gC[n]) atomicMax(&a.G32[cv_of(n)], f32_key(cmax[n]));
         continue;
     } else {
     // Lane geometry of the 16x16 output block (m, n): lane holds rows 4q..4q+3 of column c16.
@@ -493,7 +513,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
     auto repack = [](uint32_t x) -> uint32_t { return F4 ? x << 2 : x; };
     uint32_t Mr[4][NP][C], Mc[4][C];
     float Fr[4][NP], Fc[4];
-    float thrR[4][NP], thrC[4];
+    float thrR[4][NP], thrC[4], gR[4][NP], gC[4];   // thresholds; maxima as read (a lower bound)
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -503,6 +523,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
             for (int c = 0; c < C; ++c) Mr[m][s][c] = repack(margr[v * C + c]);
             Fr[m][s] = F1r[v];
             float gk = key_f32(a.G32[v]);
+            gR[m][s] = gk;
             thrR[m][s] = gk - rescore_window(a.w_abs, gk);
         }
 #pragma unroll
@@ -512,6 +533,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
         for (int c = 0; c < C; ++c) Mc[n][c] = repack(margr[v * C + c]);
         Fc[n] = F1r[v];
         float gk = key_f32(a.G32[v]);
+        gC[n] = gk;
         thrC[n] = gk - rescore_window(a.w_abs, gk);
     }
 
@@ -668,7 +690,8 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
                 }
     }
 
-    // publish the maxima: one lane per variable (the collect pass leaves the final maxima alone)
+    // publish the maxima: one lane per variable, only where the tile raised the maximum read
+    // before (maxima only grow); the collect pass leaves the final maxima alone
     if (a.collect) continue;
     const bool row_leader = (W == 1) ? (c16 == 0) : ((c16 >> 1) == 0);
     const bool col_leader = (W == 1) ? (q == 0) : (q == 0 && odd == 0);
@@ -676,10 +699,10 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int s = 0; s < NP; ++s)
-            if (row_leader && rmax[m][s] > -INFINITY) atomicMax(&a.G32[row_var(m, s)], f32_key(rmax[m][s]));
+            if (row_leader && rmax[m][s] > gR[m][s]) atomicMax(&a.G32[row_var(m, s)], f32_key(rmax[m][s]));
 #pragma unroll
     for (int n = 0; n < 4; ++n)
-        if (col_leader && cmax[n] > -INFINITY) atomicMax(&a.G32[col_var(n)], f32_key(cmax[n]));
+        if (col_leader && cmax[n] > gC[n]) atomicMax(&a.G32[col_var(n)], f32_key(cmax[n]));
     }   // W <= 2
     }   // work items
 }

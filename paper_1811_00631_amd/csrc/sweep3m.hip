@@ -258,7 +258,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) Mi[c] = repack(margr[(int64_t)i * C + c]);
         uint32_t Mj[4][3], Ml[4][3], Pij[4][4], Pil[4][4];
-        float Fij[4], Fil[4], thrJ[4], thrL[4];
+        float Fij[4], Fil[4], thrJ[4], thrL[4], gJ[4], gL[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int j = clampv(jv[m]);
@@ -270,6 +270,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
             for (int x = 0; x < 4; ++x) Pij[m][x] = repack((uint32_t)pw[x]);
             Fij[m] = a.F2[(int64_t)ii * a.p_pad + jj];
             const float g = key_f32(a.G32[j]);
+            gJ[m] = g;
             thrJ[m] = g - win3(a.w_abs, g);
         }
 #pragma unroll
@@ -283,9 +284,10 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
             for (int x = 0; x < 4; ++x) Pil[n][x] = repack((uint32_t)pw[x]);
             Fil[n] = a.F2[(int64_t)ii * a.p_pad + ll];
             const float g = key_f32(a.G32[l]);
+            gL[n] = g;
             thrL[n] = g - win3(a.w_abs, g);
         }
-        float Gi = key_f32(a.G32[i]);
+        const float Gi = key_f32(a.G32[i]);
         float thrI = Gi - win3(a.w_abs, Gi);
 
         // F3 of triple (i, j_m, l_n) on the lane pair (e = 0, 1) and the parents' F
@@ -416,13 +418,14 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
                 }
         }
         if (a.collect) continue;
-        if (lane == 0 && mi > -INFINITY) atomicMax(&a.G32[i], f32_key(mi));
+        // only where the tile raised the maximum read before (maxima only grow)
+        if (lane == 0 && mi > Gi) atomicMax(&a.G32[i], f32_key(mi));
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-            if (c16 == 0 && mj[m] > -INFINITY) atomicMax(&a.G32[jv[m]], f32_key(mj[m]));
+            if (c16 == 0 && mj[m] > gJ[m]) atomicMax(&a.G32[jv[m]], f32_key(mj[m]));
 #pragma unroll
         for (int n = 0; n < 4; ++n)
-            if (q == 0 && e == 0 && ml[n] > -INFINITY) atomicMax(&a.G32[lv[n]], f32_key(ml[n]));
+            if (q == 0 && e == 0 && ml[n] > gL[n]) atomicMax(&a.G32[lv[n]], f32_key(ml[n]));
     }
 }
 
