@@ -137,6 +137,24 @@ int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint8_t *y, flo
 int mdfs_pair_counts(const mdfs_params *prm, const float *data, const uint8_t *y, int32_t disc,
                      int32_t *counts, void *ws, size_t ws_bytes, void *stream);
 
+/* ComputeInterestingTuples (section "Canonical package usage": the tuples whose information
+ * gain is at least a threshold, with the gain per member): every (variable i, partner tuple m,
+ * discretisation q) with IG(i | m) >= ig_thr, IG per equation IGmax in binary64 (the same value
+ * mdfs_max_ig maximises).  One sweep in collect mode appends every tuple whose float32 IG lies
+ * within the screen window of ig_thr; candidates are re-scored in binary64 and filtered.
+ *   ig_thr   : threshold (not NaN; -inf lists every tuple and member, subject to capacity).
+ *   var      : device int32 [max_out] variable i of each record.
+ *   partners : device int32 [max_out][k-1] the partner tuple m, ascending.
+ *   disc     : device int32 [max_out] discretisation index q (disc_offset-based).
+ *   ig       : device double [max_out] IG(i | m).
+ *   n_found  : host int64 (output): records found; when it exceeds max_out only max_out were
+ *              written.  Record order is unspecified.
+ * Returns MDFS_E_OVERFLOW (n_found = candidates appended) when more candidates lie near the
+ * threshold than the workspace holds (256 per variable).  Synchronises `stream`. */
+int mdfs_interesting_tuples(const mdfs_params *prm, const float *data, const uint8_t *y, double ig_thr,
+                            int32_t *var, int32_t *partners, int32_t *disc, double *ig, int64_t max_out,
+                            int64_t *n_found, void *ws, size_t ws_bytes, void *stream);
+
 /* The float32 screening maxima of the sweep before the binary64 re-score: for every variable
  * the largest float32 IG over all tuples and discretisations, and the float32 error bound E
  * that the re-score window is built from (|IG_f32 - IG| <= E for every tuple).

@@ -77,6 +77,9 @@ def lib():
         L.mdfs_oracle_max_ig_all.argtypes = [ip, ip, i64, i64, ctypes.c_int, ctypes.c_int, i64, i64, dbl,
                                              dbl, u64, ip, ip, ip, ctypes.c_int]
         L.mdfs_oracle_max_threads.restype = ctypes.c_int
+        L.mdfs_oracle_interesting.argtypes = [ip, ip, i64, i64, ctypes.c_int, ctypes.c_int, i64, i64, dbl, dbl,
+                                              u64, dbl, i64, ip, ip, ip, ip]
+        L.mdfs_oracle_interesting.restype = i64
         _lib = L
     return _lib
 
@@ -180,6 +183,27 @@ def max_ig_all(data, y, k: int, divisions: int, n_disc: int, rng: float, xi: flo
     _chk(lib().mdfs_oracle_max_ig_all(_p(data), _p(y), n_obj, n_var, k, divisions, n_disc, disc_offset,
                                       rng, xi, seed, _p(ig), _p(am), _p(ad), n_threads))
     return ig, am[:, :k - 1], ad
+
+
+def interesting(data, y, k: int, divisions: int, n_disc: int, rng: float, xi: float, seed: int, ig_thr: float,
+                disc_offset: int = 0, cap: int = 1 << 20):
+    """ComputeInterestingTuples: every (variable, partner tuple, discretisation) with
+    IG(variable | partners) >= ig_thr.  Returns (var [n], partners [n][k-1], disc [n], ig [n]) in
+    the order discretisation, tuple (lexicographic), member."""
+    data = np.ascontiguousarray(data, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.uint8)
+    n_var, n_obj = data.shape
+    var = np.zeros(cap, dtype=np.int64)
+    part = np.zeros((cap, max(k - 1, 1)), dtype=np.int64)
+    disc = np.zeros(cap, dtype=np.int64)
+    igv = np.zeros(cap, dtype=np.float64)
+    n = lib().mdfs_oracle_interesting(_p(data), _p(y), n_obj, n_var, k, divisions, n_disc, disc_offset, rng, xi,
+                                      seed, float(ig_thr), cap, _p(var), _p(part), _p(disc), _p(igv))
+    if n < 0:
+        _chk(int(n))
+    if n > cap:
+        raise RuntimeError(f"{n} interesting tuples exceed the capacity {cap}")
+    return var[:n], part[:n, :k - 1], disc[:n], igv[:n]
 
 
 def max_threads() -> int:

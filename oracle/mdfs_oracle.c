@@ -471,6 +471,69 @@ int mdfs_oracle_max_ig_all(const float *data, const uint8_t *y, int64_t n_obj, i
 }
 
 /* Threads OpenMP would use (1 when built without OpenMP). */
+/* ComputeInterestingTuples (section "Canonical package usage"): every (variable i, partner
+ * tuple m, discretisation r) with IG(i | m) >= ig_thr, IG as in max_ig_all (the table of the
+ * tuple T = {i} u m, marginalised over i for the parent).  Records go out in the order r, then
+ * T lexicographic, then member; at most cap are written, the return value is the number found
+ * (negative on error).  var[q], partners[q][k-1], disc[q], igv[q]. */
+int64_t mdfs_oracle_interesting(const float *data, const uint8_t *y, int64_t n_obj, int64_t n_var, int k,
+                                int divisions, int64_t n_disc, int64_t disc_offset, double range, double xi,
+                                uint64_t seed, double ig_thr, int64_t cap, int64_t *var, int64_t *partners,
+                                int64_t *disc, double *igv)
+{
+    int rc = check_common(data, y, n_obj, n_var, k, divisions, n_disc, xi);
+    if (rc) return rc;
+    double b0, b1;
+    if ((rc = mdfs_oracle_betas(y, n_obj, xi, &b0, &b1))) return rc;
+    const int c = divisions + 1, km1 = k - 1;
+    uint8_t *codes = (uint8_t *)malloc((size_t)(n_disc * n_var * n_obj));
+    if (!codes) return E_NOMEM;
+    rc = mdfs_oracle_discretize(data, n_obj, n_var, divisions, n_disc, disc_offset, range, seed, codes);
+    if (rc) { free(codes); return rc; }
+    int64_t ncell = 1;
+    for (int m = 0; m < k; ++m) ncell *= c;
+    int64_t *tab = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * ncell));
+    int64_t *sub = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * ncell));
+    int64_t found = 0;
+    for (int64_t r = 0; r < n_disc; ++r) {
+        const uint8_t *cr = codes + r * n_var * n_obj;
+        int64_t T[MAXK];
+        for (int q = 0; q < k; ++q) T[q] = q;
+        do {
+            mdfs_oracle_table(cr, y, n_obj, c, k, T, tab);
+            const double FT = mdfs_oracle_F(tab, ncell, b0, b1);
+            for (int mem = 0; mem < k; ++mem) {
+                const int64_t sc = ncell / c;
+                memset(sub, 0, sizeof(int64_t) * (size_t)(2 * sc));
+                for (int64_t cell = 0; cell < ncell; ++cell) {
+                    int64_t digits[MAXK], rem = cell;
+                    for (int q = k - 1; q >= 0; --q) { digits[q] = rem % c; rem /= c; }
+                    int64_t sidx = 0;
+                    for (int q = 0; q < k; ++q)
+                        if (q != mem) sidx = sidx * c + digits[q];
+                    sub[sidx] += tab[cell];
+                    sub[sc + sidx] += tab[ncell + cell];
+                }
+                const double g = mdfs_oracle_F(sub, sc, b0, b1) - FT;
+                if (!(g >= ig_thr)) continue;
+                if (found < cap) {
+                    var[found] = T[mem];
+                    int q2 = 0;
+                    for (int q = 0; q < k; ++q)
+                        if (q != mem) partners[found * km1 + q2++] = T[q];
+                    disc[found] = disc_offset + r;
+                    igv[found] = g;
+                }
+                ++found;
+            }
+        } while (next_subset(T, k, n_var));
+    }
+    free(tab);
+    free(sub);
+    free(codes);
+    return found;
+}
+
 int mdfs_oracle_max_threads(void)
 {
 #ifdef _OPENMP

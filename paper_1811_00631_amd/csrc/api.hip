@@ -344,6 +344,45 @@ extern "C" int mdfs_pair_counts(const mdfs_params *prm, const float *data, const
     return MDFS_OK;
 }
 
+extern "C" int mdfs_interesting_tuples(const mdfs_params *prm, const float *data, const uint8_t *y, double ig_thr,
+                                       int32_t *var, int32_t *partners, int32_t *disc, double *ig, int64_t max_out,
+                                       int64_t *n_found, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_params(prm);
+    if (rc) return rc;
+    if (!data || !y || !ws || !n_found) return fail(MDFS_E_ARG, "null pointer");
+    if (max_out < 0 || (max_out > 0 && (!var || !partners || !disc || !ig)))
+        return fail(MDFS_E_ARG, "max_out=%lld with a null output array", (long long)max_out);
+    if (!(ig_thr == ig_thr)) return fail(MDFS_E_ARG, "ig_thr is NaN");
+    *n_found = 0;
+    Problem P;
+    if ((rc = setup(prm, y, ws, ws_bytes, stream, P))) return rc;
+    if (P.k3_mfma && (rc = upload_k3_tiles(P))) return rc;
+    LAUNCH(launch_init(P));
+    LAUNCH(launch_class_perm(P, y));
+    LAUNCH(launch_tables(P));
+    LAUNCH(launch_discretize(P, data, nullptr, true));
+    // one collect pass with every variable's threshold at ig_thr (the largest float32 not above
+    // it): it appends every tuple whose float32 IG lies within the screen window of ig_thr,
+    // a superset of those whose binary64 IG reaches it
+    float t = (float)ig_thr;
+    if ((double)t > ig_thr) t = nextafterf(t, -INFINITY);
+    LAUNCH(launch_fill_g(P, f32_key(t)));
+    if ((rc = sweep_pass(P, nullptr, -1, true))) return rc;
+    Status st;
+    if ((rc = read_status(P, st))) return rc;
+    if (st.overflow) {
+        *n_found = st.n_cand;
+        return fail(MDFS_E_OVERFLOW, "more than %lld candidates near ig_thr; raise the threshold",
+                    (long long)P.L.cap);
+    }
+    LAUNCH(launch_emit(P, ig_thr, var, partners, disc, ig, max_out));
+    if ((rc = read_status(P, st))) return rc;
+    *n_found = st.n_emit;
+    g_err.clear();
+    return MDFS_OK;
+}
+
 extern "C" int mdfs_screen_max(const mdfs_params *prm, const float *data, const uint8_t *y, float *ig32,
                                double *err_bound, void *ws, size_t ws_bytes, void *stream)
 {

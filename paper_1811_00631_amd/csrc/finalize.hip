@@ -164,7 +164,7 @@ static void rescore_launch(const Problem &P, const RescoreArgs &a)
     hipLaunchKernelGGL((k_rescore<C, K>), dim3(1024), dim3(256), 0, P.stream, a);
 }
 
-hipError_t launch_finalize(const Problem &P, float *ig_max, int32_t *argmax, int32_t *argmax_disc)
+static RescoreArgs rescore_args(const Problem &P)
 {
     const Layout &L = P.L;
     RescoreArgs a{};
@@ -187,6 +187,12 @@ hipError_t launch_finalize(const Problem &P, float *ig_max, int32_t *argmax, int
     a.ig64 = P.at<double>(L.ig64);
     a.max64 = P.at<uint64_t>(L.max64);
     a.k = L.k;
+    return a;
+}
+
+static hipError_t rescore_all(const Problem &P, const RescoreArgs &a)
+{
+    const Layout &L = P.L;
     if (L.k == 2) {
         switch (L.C) {
         case 2: rescore_launch<2, 2>(P, a); break;
@@ -202,13 +208,55 @@ hipError_t launch_finalize(const Problem &P, float *ig_max, int32_t *argmax, int
         default: return hipErrorInvalidValue;
         }
     }
-    hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Problem &P, float *ig_max, int32_t *argmax, int32_t *argmax_disc)
+{
+    const Layout &L = P.L;
+    const RescoreArgs a = rescore_args(P);
+    hipError_t e = rescore_all(P, a);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_select, dim3(256), dim3(256), 0, P.stream, a.cand, a.st, a.cap, a.ig64, a.max64,
                        P.at<uint64_t>(L.keyw));
     hipLaunchKernelGGL(k_output, dim3((unsigned)((L.p + 255) / 256)), dim3(256), 0, P.stream, L.p, L.k,
                        P.disc_offset, a.max64, P.at<uint64_t>(L.keyw), P.at<uint32_t>(L.ovf), ig_max, argmax,
                        argmax_disc);
+    return hipGetLastError();
+}
+
+// ComputeInterestingTuples output: every re-scored candidate with IG >= thr, compacted (the
+// order is that of the atomic counter, i.e. unspecified).
+__global__ void k_emit(const Cand *cand, Status *st, int64_t cap, const double *ig64, double thr, int k,
+                       int disc_offset, int32_t *var, int32_t *partners, int32_t *disc, double *ig, int64_t max_out)
+{
+    const int64_t nc = min((int64_t)st->n_cand, cap);
+    for (int64_t ci = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; ci < nc;
+         ci += (int64_t)gridDim.x * blockDim.x) {
+        const double g = ig64[ci];
+        if (!(g >= thr)) continue;
+        const Cand x = cand[ci];
+        const uint32_t at = atomicAdd(&st->n_emit, 1u);
+        if ((int64_t)at >= max_out) continue;
+        var[at] = x.v;
+        if (k == 2) partners[at] = (int32_t)x.partner;
+        else {
+            partners[2 * (int64_t)at] = (int32_t)(x.partner >> 16);
+            partners[2 * (int64_t)at + 1] = (int32_t)(x.partner & 0xffff);
+        }
+        disc[at] = disc_offset + x.r;
+        ig[at] = g;
+    }
+}
+
+hipError_t launch_emit(const Problem &P, double thr, int32_t *var, int32_t *partners, int32_t *disc, double *ig,
+                       int64_t max_out)
+{
+    const RescoreArgs a = rescore_args(P);
+    hipError_t e = rescore_all(P, a);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_emit, dim3(256), dim3(256), 0, P.stream, a.cand, P.at<Status>(P.L.status), a.cap, a.ig64,
+                       thr, P.L.k, P.disc_offset, var, partners, disc, ig, max_out);
     return hipGetLastError();
 }
 

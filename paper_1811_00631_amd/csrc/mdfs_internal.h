@@ -37,7 +37,8 @@ struct Status {
     uint32_t nan_flag;    // data held a NaN
     uint32_t n_cand;      // candidate records appended (may exceed capacity)
     uint32_t overflow;    // some append did not fit
-    uint32_t pad0[13];
+    uint32_t n_emit;      // records written by the interesting-tuples emit pass
+    uint32_t pad0[12];
     uint32_t next_tile[16];   // per-XCD work counters of the persistent sweep (reset per pass)
     uint32_t pad[32];
 };
@@ -141,6 +142,11 @@ size_t sweep3m_lds_bytes(const Problem &P);
 void sweep3m_tiles(int64_t p, std::vector<int64_t> &apref, std::vector<int32_t> &ablk);
 hipError_t launch_reset_queue(const Problem &P);
 hipError_t launch_finalize(const Problem &P, float *ig_max, int32_t *argmax, int32_t *argmax_disc);
+// every variable's threshold key set to `key` (the interesting-tuples collect pass)
+hipError_t launch_fill_g(const Problem &P, uint32_t key);
+// binary64 re-score of the candidates, then every record with IG >= thr written out
+hipError_t launch_emit(const Problem &P, double thr, int32_t *var, int32_t *partners, int32_t *disc, double *ig,
+                       int64_t max_out);
 hipError_t launch_screen_out(const Problem &P, float *ig32);
 
 }  // namespace mdfs

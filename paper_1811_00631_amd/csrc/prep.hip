@@ -90,6 +90,18 @@ __global__ void k_reset_queue(Status *st)
     if (threadIdx.x < 16) st->next_tile[threadIdx.x] = 0u;
 }
 
+__global__ void k_fill_g(uint32_t *G32, int64_t p_pad, uint32_t key)
+{
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < p_pad; v += (int64_t)gridDim.x * blockDim.x)
+        G32[v] = key;
+}
+
+hipError_t launch_fill_g(const Problem &P, uint32_t key)
+{
+    hipLaunchKernelGGL(k_fill_g, dim3(64), dim3(256), 0, P.stream, P.at<uint32_t>(P.L.G32), P.L.p_pad, key);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset_queue(const Problem &P)
 {
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, P.stream, P.at<Status>(P.L.status));

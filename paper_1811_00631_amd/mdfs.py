@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
 
 _lib = None
 SYMBOLS = ["mdfs_workspace_size", "mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts",
-           "mdfs_screen_max", "mdfs_phase_times", "mdfs_last_error"]
+           "mdfs_screen_max", "mdfs_interesting_tuples", "mdfs_phase_times", "mdfs_last_error"]
 FLAG_TIMING = 1
 PHASES = ["setup", "discretize", "sweep", "finalize"]
 
@@ -66,10 +66,12 @@ def load(path: str = LIB_PATH):
     L.mdfs_max_ig.argtypes = [P, vp, vp, vp, vp, vp, vp, sz, vp]
     L.mdfs_pair_counts.argtypes = [P, vp, vp, ctypes.c_int32, vp, vp, sz, vp]
     L.mdfs_screen_max.argtypes = [P, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+    L.mdfs_interesting_tuples.argtypes = [P, vp, vp, ctypes.c_double, vp, vp, vp, vp, ctypes.c_int64,
+                                          ctypes.POINTER(ctypes.c_int64), vp, sz, vp]
     L.mdfs_phase_times.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     L.mdfs_phase_times.restype = ctypes.c_int
     L.mdfs_last_error.restype = ctypes.c_char_p
-    for fn in ("mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts", "mdfs_screen_max"):
+    for fn in ("mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts", "mdfs_screen_max", "mdfs_interesting_tuples"):
         getattr(L, fn).restype = ctypes.c_int
     _lib = L
     return L
@@ -189,6 +191,31 @@ def mdfs_pair_counts(data: torch.Tensor, y: torch.Tensor, disc: int, divisions: 
     _check(load().mdfs_pair_counts(ctypes.byref(prm), _ptr(data), _ptr(y), int(disc), _ptr(counts), _ptr(ws),
                                    ws.numel(), _stream(data.device)))
     return counts
+
+
+def mdfs_interesting_tuples(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_disc: int,
+                            ig_thr: float, pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0,
+                            disc_offset: int = 0, engine: str = "auto", max_out: int = 1 << 20):
+    """Every (variable, partner tuple, discretisation) with IG >= ig_thr: device tensors
+    (var int32 [n], partners int32 [n][k-1], disc int32 [n], ig float64 [n]) in unspecified order.
+    Raises MdfsError(-8) if more than max_out records exist."""
+    data, y = _dev_inputs(data, y)
+    n_var, n_obj = data.shape
+    prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed, engine)
+    ws = workspace_for(prm, data.device)
+    dev = data.device
+    var = torch.empty(max_out, dtype=torch.int32, device=dev)
+    part = torch.empty((max_out, k - 1), dtype=torch.int32, device=dev)
+    disc = torch.empty(max_out, dtype=torch.int32, device=dev)
+    ig = torch.empty(max_out, dtype=torch.float64, device=dev)
+    n = ctypes.c_int64(0)
+    _check(load().mdfs_interesting_tuples(ctypes.byref(prm), _ptr(data), _ptr(y), float(ig_thr), _ptr(var),
+                                          _ptr(part), _ptr(disc), _ptr(ig), int(max_out), ctypes.byref(n), _ptr(ws),
+                                          ws.numel(), _stream(dev)))
+    if n.value > max_out:
+        raise MdfsError(-8, f"{n.value} interesting tuples exceed max_out={max_out}")
+    m = n.value
+    return var[:m], part[:m], disc[:m], ig[:m]
 
 
 def mdfs_screen_max(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_disc: int,

@@ -1,0 +1,41 @@
+"""ComputeInterestingTuples on the GPU through the C ABI against the FP64 oracle: the same set of
+(variable, partner tuple, discretisation) records, IG within 1e-4 * max(1, |IG|)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1811_00631_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def as_dict(var, part, disc, ig):
+    return {(int(v), tuple(int(x) for x in p), int(d)): float(g) for v, p, d, g in zip(var, part, disc, ig)}
+
+
+@pytest.mark.parametrize("k,engine,div", [(2, "mfma_fp4", 2), (2, "mfma", 2), (2, "auto", 4), (3, "mfma_fp4", 2),
+                                          (3, "bitset", 2), (3, "bitset", 1)])
+def test_interesting_matches_oracle(mdfs_gpu, k, engine, div):
+    w = workloads.xor_small(seed=61, n_obj=400, n_var=40 if k == 2 else 18, divisions=div, n_disc=3)
+    ref_all = oracle.interesting(w.data, w.y, k, div, 3, w.range_, w.xi, w.seed, -np.inf)
+    thr = float(np.quantile(ref_all[3], 0.97))
+    ref = as_dict(*oracle.interesting(w.data, w.y, k, div, 3, w.range_, w.xi, w.seed, thr))
+    print(f"interesting k={k} {engine} d={div + 1}: thr={thr:.4f}, {len(ref)} records", flush=True)
+    data, y = torch.from_numpy(w.data).cuda(), torch.from_numpy(w.y).cuda()
+    got = mdfs_gpu.mdfs_interesting_tuples(data, y, k, div, 3, thr, w.xi, w.range_, w.seed, engine=engine)
+    got = as_dict(*[t.cpu().numpy() for t in got])
+    assert set(got) == set(ref)
+    for key, g in got.items():
+        assert abs(g - ref[key]) <= 1e-4 * max(1.0, abs(ref[key])), key
+
+
+def test_interesting_none_above_the_maximum(mdfs_gpu):
+    w = workloads.xor_small(seed=62, n_obj=300, n_var=30, n_disc=2)
+    data, y = torch.from_numpy(w.data).cuda(), torch.from_numpy(w.y).cuda()
+    ig, _, _ = mdfs_gpu.mdfs_max_ig(data, y, 2, 2, 2, w.xi, w.range_, w.seed)
+    top = float(ig.max().item())
+    got = mdfs_gpu.mdfs_interesting_tuples(data, y, 2, 2, 2, top * 1.001 + 1e-3, w.xi, w.range_, w.seed)
+    assert got[0].numel() == 0
+    got = mdfs_gpu.mdfs_interesting_tuples(data, y, 2, 2, 2, top * 0.999, w.xi, w.range_, w.seed)
+    assert got[0].numel() >= 1

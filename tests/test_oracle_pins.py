@@ -5,6 +5,7 @@ routine for a special case (scikit-learn / SciPy), a closed form, an invariant t
 exactly, a published generator test vector, or a statistical law the paper states.
 """
 import itertools
+import math
 import json
 import os
 
@@ -300,3 +301,31 @@ def test_errors():
     with pytest.raises(oracle.OracleError) as e:
         oracle.max_ig(X, y, 4, 1, 1, 0.5, 0.25, 1)
     assert e.value.code == -3
+
+
+# ------------------------------------------------------------------ ComputeInterestingTuples
+def test_interesting_tuples_cover_every_member_and_agree_with_the_maxima():
+    # at threshold -inf every (member, partner tuple, discretisation) is listed once, and the
+    # largest listed IG of each variable is IG_max (pinned above through max_ig_all)
+    w = workloads.xor_small(seed=51, n_obj=150, n_var=9, n_disc=2)
+    for k in (2, 3):
+        var, part, disc, ig = oracle.interesting(w.data, w.y, k, 2, 2, 0.5, 0.25, w.seed, -np.inf)
+        assert len(var) == math.comb(9, k) * k * 2
+        ref, _, _ = oracle.max_ig_all(w.data, w.y, k, 2, 2, 0.5, 0.25, w.seed)
+        best = np.full(9, -np.inf)
+        np.maximum.at(best, var, ig)
+        assert np.array_equal(best, ref)
+        # partner tuples are ascending and exclude the member
+        assert np.all(np.diff(part, axis=1) > 0) if k == 3 else True
+        assert not np.any(part == var[:, None])
+
+
+def test_interesting_tuples_threshold_filters_exactly():
+    w = workloads.xor_small(seed=52, n_obj=200, n_var=10, n_disc=3)
+    allv = oracle.interesting(w.data, w.y, 2, 2, 3, 0.5, 0.25, w.seed, -np.inf)
+    thr = float(np.quantile(allv[3], 0.9))
+    sel = oracle.interesting(w.data, w.y, 2, 2, 3, 0.5, 0.25, w.seed, thr)
+    keep = allv[3] >= thr
+    assert len(sel[0]) == int(keep.sum())
+    for a, b in zip(sel, (x[keep] for x in allv)):
+        assert np.array_equal(a, b)
