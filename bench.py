@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-disc", type=int, default=16, help="discretisations in the oracle's sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick engine and persistent grid size with the autotuner (cached per shape)")
     ap.add_argument("--engine", default="auto", choices=["auto", "mfma_fp4", "mfma", "bitset"],
                     help="auto: fp4 MFMA for k=2 while each class has < 4096 objects, bitset for k=3")
     ap.add_argument("--copy-calib", action="store_true",
@@ -171,8 +173,16 @@ def main():
     k, div, R = w.k, w.divisions, w.n_disc
     tuples = math.comb(w.n_var, k) * R
 
+    workgroups, tuned = 0, None
+    if args.autotune:
+        from paper_1811_00631_amd import autotune
+        tuned = autotune.Tuner(os.path.join(ROOT, "gpurun_out", "autotune.json")).best(w.n_obj, w.n_var, k, div, R)
+        args.engine, workgroups = tuned["engine"], tuned["workgroups"]
+        print(f"# autotune: {tuned['engine']} x {workgroups} workgroups", file=sys.stderr, flush=True)
+
     def step():
-        return mdfs.mdfs_max_ig(data, y, k, div, R, w.xi, w.range_, w.seed, engine=args.engine, timing=True)
+        return mdfs.mdfs_max_ig(data, y, k, div, R, w.xi, w.range_, w.seed, engine=args.engine, timing=True,
+                                workgroups=workgroups)
 
     for _ in range(args.warmup):
         step()
@@ -254,7 +264,8 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "k": k, "n_obj": w.n_obj, "n_var": w.n_var, "classes": div + 1, "n_disc": R,
                    "tuples_per_step": tuples,
-                   "engine": args.engine,
+                   "engine": args.engine, "workgroups": workgroups or "whole GPU",
+                   "autotuned": bool(tuned),
                    "counts": ("fp4 MFMA, exact f32 accumulate" if fp4 else "int8 MFMA, int32 accumulate")
                    if (k == 2 or k3_mfma) else "bitset AND + popcount, int32",
                    "entropy": "float32 screen + binary64 re-score"},

@@ -78,3 +78,20 @@ def test_admission_respects_budget(mdfs_gpu):
     for i in range(len(spans)):
         live = [s for s in spans if s[0] <= spans[i][0] < s[1]]
         assert sum(s[2] for s in live) + srv2.resident <= budget
+
+
+def test_autotuner_picks_a_valid_config_and_results_do_not_depend_on_it(mdfs_gpu, tmp_path):
+    import torch
+    from paper_1811_00631_amd import autotune
+    tuner = autotune.Tuner(path=str(tmp_path / "tune.json"), reps=1)
+    best = tuner.best(600, 300, 2, 2, 2)
+    assert best["engine"] in ("mfma_fp4", "mfma") and best["workgroups"] in autotune.GRIDS
+    assert tuner.best(600, 300, 2, 2, 2) is best                    # cached
+    assert autotune.Tuner(path=str(tmp_path / "tune.json")).best(600, 300, 2, 2, 2)["engine"] == best["engine"]
+    w = workloads.xor_small(seed=71, n_obj=600, n_var=300, n_disc=2)
+    data, y = torch.from_numpy(w.data).cuda(), torch.from_numpy(w.y).cuda()
+    outs = [[t.cpu().numpy() for t in mdfs_gpu.mdfs_max_ig(data, y, 2, 2, 2, **c)] for c in
+            autotune.candidates(600, 2, 2, int(w.y.sum()))]
+    for o in outs[1:]:
+        for x, z in zip(outs[0], o):
+            assert np.array_equal(x, z)

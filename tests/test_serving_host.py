@@ -44,3 +44,15 @@ def test_first_fit_admission_order():
     assert srv._take() is None          # 95 > 100 - 10 resident: still waiting
     srv.resident = 0
     assert srv._take().id == 0
+
+
+def test_autotune_candidates_and_buckets():
+    from paper_1811_00631_amd import autotune
+    c2 = autotune.candidates(2000, 2, 2, 1000)
+    assert {c["engine"] for c in c2} == {"mfma_fp4", "mfma"}
+    assert {c["engine"] for c in autotune.candidates(9000, 2, 2, 4500)} == {"mfma"}   # classes >= 4096
+    assert {c["engine"] for c in autotune.candidates(2000, 3, 2, 1000)} == {"mfma_fp4", "bitset"}
+    assert {c["engine"] for c in autotune.candidates(2000, 3, 4, 1000)} == {"bitset"}
+    assert all(c["workgroups"] % 8 == 0 and 8 <= c["workgroups"] <= 4096 for c in c2)
+    assert autotune.bucket(2000, 20000, 2, 2, 30) == (2048, 32768, 2, 2, 4)
+    assert autotune.bucket(1025, 100, 3, 1, 1) == (2048, 128, 3, 1, 1)
