@@ -71,7 +71,7 @@ typedef enum {
 typedef struct {
     int64_t n_obj;       /* N, objects */
     int64_t n_var;       /* p, variables */
-    int32_t k;           /* dimensions: tuple size, 2 or 3 */
+    int32_t k;           /* dimensions: tuple size 1, 2 or 3 (k = 1: each variable alone) */
     int32_t divisions;   /* classes per variable = divisions + 1 */
     int32_t n_disc;      /* number of random discretisations */
     int32_t disc_offset; /* index of the first discretisation (run r uses index disc_offset+r) */
@@ -111,7 +111,9 @@ int mdfs_discretize(const mdfs_params *prm, const float *data, uint8_t *codes, v
                     size_t ws_bytes, void *stream);
 
 /* IG^k_max(y; x_i) for every variable (equation IGmax), maximised over all k-tuples and all
- * n_disc discretisations, with the argmax.
+ * n_disc discretisations, with the argmax.  k = 1 is the one-dimensional analysis:
+ * IG(x_i) = N (H(y) - H(y | x_i)) in binary64, maximised over the discretisations only (argmax
+ * is not written).
  *   data        : device float32 [n_var][n_obj] (input)
  *   y           : device uint8 [n_obj] (input, decision)
  *   ig_max      : device float32 [n_var] (output): the maximum IG, in nats, evaluated in
@@ -150,7 +152,7 @@ int mdfs_pair_counts(const mdfs_params *prm, const float *data, const uint8_t *y
  *   n_found  : host int64 (output): records found; when it exceeds max_out only max_out were
  *              written.  Record order is unspecified.
  * Returns MDFS_E_OVERFLOW (n_found = candidates appended) when more candidates lie near the
- * threshold than the workspace holds (256 per variable).  Synchronises `stream`. */
+ * threshold than the workspace holds (max(256 n_var, 2^20) records).  Synchronises `stream`. */
 int mdfs_interesting_tuples(const mdfs_params *prm, const float *data, const uint8_t *y, double ig_thr,
                             int32_t *var, int32_t *partners, int32_t *disc, double *ig, int64_t max_out,
                             int64_t *n_found, void *ws, size_t ws_bytes, void *stream);

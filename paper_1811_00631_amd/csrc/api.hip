@@ -82,7 +82,7 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
 {
     if (!prm) return fail(MDFS_E_ARG, "params is NULL");
     if (prm->flags & ~MDFS_FLAG_TIMING) return fail(MDFS_E_ARG, "unknown flag bits 0x%x", prm->flags);
-    if (prm->k != 2 && prm->k != 3) return fail(MDFS_E_K, "k=%d: supported tuple sizes are 2 and 3", prm->k);
+    if (prm->k < 1 || prm->k > 3) return fail(MDFS_E_K, "k=%d: supported tuple sizes are 1, 2 and 3", prm->k);
     if (prm->divisions != 1 && prm->divisions != 2 && prm->divisions != 4)
         return fail(MDFS_E_DIV, "divisions=%d: supported are 1, 2, 4", prm->divisions);
     if (prm->n_obj < 2 || prm->n_obj < prm->divisions + 1)
@@ -188,7 +188,7 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
         P.KB = P.KB0 + (P.N1 + P.kobj - 1) / P.kobj;
         P.Kpad = P.KB * P.kobj;
         // the pair sweep keeps its entropy tables in LDS next to the operand stages
-        const size_t lds = sweep2_lds_bytes(P, false) > sweep2_lds_bytes(P, true) ? sweep2_lds_bytes(P, false)
+        const size_t lds = prm->k == 1 ? 0 : sweep2_lds_bytes(P, false) > sweep2_lds_bytes(P, true) ? sweep2_lds_bytes(P, false)
                                                                                   : sweep2_lds_bytes(P, true);
         if (lds > LDS_MAX)
             return fail(MDFS_E_LIMIT, "n_obj=%lld: the int8 sweep's LDS tables need %zu bytes > %zu",
@@ -307,6 +307,14 @@ extern "C" int mdfs_discretize(const mdfs_params *prm, const float *data, uint8_
     return MDFS_OK;
 }
 
+// k = 1: F of the decision alone (one voxel holding every object), binary64.
+static double root_F(const Problem &P)
+{
+    const double n0 = P.N0, n1 = P.N1, n = n0 + n1, s = n + P.beta0 + P.beta1;
+    auto xlx = [](double x) { return x > 0.0 ? x * log(x) : 0.0; };
+    return n * log(s) - (n / s) * (xlx(n0 + P.beta0) + xlx(n1 + P.beta1));
+}
+
 extern "C" int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint8_t *y, float *ig_max,
                            int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream)
 {
@@ -315,6 +323,24 @@ extern "C" int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint
     if (!data || !y || !ig_max || !ws) return fail(MDFS_E_ARG, "null pointer");
     Problem P;
     if ((rc = setup(prm, y, ws, ws_bytes, stream, P))) return rc;
+    if (prm->k == 1) {
+        // no tuples: discretise, per-variable F in binary64, maximum over discretisations
+        PhaseTimer tm((prm->flags & MDFS_FLAG_TIMING) != 0, P.stream);
+        tm.mark(0);
+        LAUNCH(launch_init(P));
+        LAUNCH(launch_class_perm(P, y));
+        tm.mark(1);
+        LAUNCH(launch_discretize(P, data, nullptr, true));
+        tm.mark(2);
+        tm.mark(3);
+        LAUNCH(launch_ig1(P, root_F(P), ig_max, argmax_disc));
+        tm.mark(4);
+        Status st;
+        if ((rc = read_status(P, st))) return rc;
+        tm.publish();
+        g_err.clear();
+        return MDFS_OK;
+    }
     PhaseTimer tm((prm->flags & MDFS_FLAG_TIMING) != 0, P.stream);
     if ((rc = run_sweep(P, data, y, nullptr, -1, &tm))) return rc;
     LAUNCH(launch_finalize(P, ig_max, argmax, argmax_disc));
@@ -332,6 +358,7 @@ extern "C" int mdfs_pair_counts(const mdfs_params *prm, const float *data, const
 {
     int rc = check_params(prm);
     if (rc) return rc;
+    if (prm->k == 1) return fail(MDFS_E_K, "k=1 has no tuples (mdfs_max_ig covers it)");
     if (prm->k != 2) return fail(MDFS_E_K, "pair counts need k=2");
     if (!data || !y || !counts || !ws) return fail(MDFS_E_ARG, "null pointer");
     if (disc < 0 || disc >= prm->n_disc) return fail(MDFS_E_ARG, "disc=%d outside [0,%d)", disc, prm->n_disc);
@@ -350,6 +377,7 @@ extern "C" int mdfs_interesting_tuples(const mdfs_params *prm, const float *data
 {
     int rc = check_params(prm);
     if (rc) return rc;
+    if (prm->k == 1) return fail(MDFS_E_K, "k=1 has no tuples (mdfs_max_ig covers it)");
     if (!data || !y || !ws || !n_found) return fail(MDFS_E_ARG, "null pointer");
     if (max_out < 0 || (max_out > 0 && (!var || !partners || !disc || !ig)))
         return fail(MDFS_E_ARG, "max_out=%lld with a null output array", (long long)max_out);
@@ -388,6 +416,7 @@ extern "C" int mdfs_screen_max(const mdfs_params *prm, const float *data, const 
 {
     int rc = check_params(prm);
     if (rc) return rc;
+    if (prm->k == 1) return fail(MDFS_E_K, "k=1 has no tuples (mdfs_max_ig covers it)");
     if (!data || !y || !ig32 || !ws) return fail(MDFS_E_ARG, "null pointer");
     Problem P;
     if ((rc = setup(prm, y, ws, ws_bytes, stream, P))) return rc;

@@ -260,6 +260,29 @@ hipError_t launch_emit(const Problem &P, double thr, int32_t *var, int32_t *part
     return hipGetLastError();
 }
 
+// k = 1 (the one-dimensional analysis): IG(x_i) = F(y) - F(x_i) in binary64 for every
+// discretisation; the maximum, and the smallest discretisation within tau of it.
+__global__ void k_ig1(int64_t p, int R, int64_t p_pad, const double *F1d, double F0, int disc_offset,
+                      float *ig_max, int32_t *argmax_disc)
+{
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= p) return;
+    double M = -INFINITY;
+    for (int r = 0; r < R; ++r) M = fmax(M, F0 - F1d[(int64_t)r * p_pad + v]);
+    int best = 0;
+    for (int r = 0; r < R; ++r)
+        if (F0 - F1d[(int64_t)r * p_pad + v] >= M - tie_tau(M)) { best = r; break; }
+    ig_max[v] = (float)M;
+    if (argmax_disc) argmax_disc[v] = disc_offset + best;
+}
+
+hipError_t launch_ig1(const Problem &P, double F0, float *ig_max, int32_t *argmax_disc)
+{
+    hipLaunchKernelGGL(k_ig1, dim3((unsigned)((P.L.p + 255) / 256)), dim3(256), 0, P.stream, P.L.p, P.L.R, P.L.p_pad,
+                       P.at<double>(P.L.F1d), F0, P.disc_offset, ig_max, argmax_disc);
+    return hipGetLastError();
+}
+
 __global__ void k_screen_out(int64_t p, const uint32_t *G32, float *ig32)
 {
     const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;

@@ -64,7 +64,7 @@ struct Layout {
     int64_t words_max;    // bitset words (32 objects) per class, worst case (k=3)
     // offsets
     size_t status, pos, perm, tabEA, tabEB, tabLQ, marg, F1, onehot, G32, max64, keyw, ovf,
-        cand, ig64, bits, ptab, F2, a3pref, a3blk, total;
+        cand, ig64, bits, ptab, F2, a3pref, a3blk, F1d, total;
 };
 
 Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R);
@@ -148,5 +148,7 @@ hipError_t launch_fill_g(const Problem &P, uint32_t key);
 hipError_t launch_emit(const Problem &P, double thr, int32_t *var, int32_t *partners, int32_t *disc, double *ig,
                        int64_t max_out);
 hipError_t launch_screen_out(const Problem &P, float *ig32);
+// k = 1: IG(i) = F(root) - F(x_i) per discretisation, max and tie rule over discretisations
+hipError_t launch_ig1(const Problem &P, double F0, float *ig_max, int32_t *argmax_disc);
 
 }  // namespace mdfs

@@ -39,7 +39,9 @@ Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
     L.tabLQ = take(sizeof(float) * 2 * (N + 1));
     L.marg = take(sizeof(uint32_t) * (size_t)R * L.p_pad * L.C);
     L.F1 = take(sizeof(float) * (size_t)R * L.p_pad);
-    L.onehot = take((size_t)R * L.Kpad_max * L.rows_pad);   // >= one byte per position
+    // >= one byte per position; k = 1 needs no tuple encoding, only binary64 F of each variable
+    L.onehot = take(k == 1 ? 0 : (size_t)R * L.Kpad_max * L.rows_pad);
+    L.F1d = take(k == 1 ? sizeof(double) * (size_t)R * L.p_pad : 0);
     L.G32 = take(sizeof(uint32_t) * L.p_pad);
     L.max64 = take(sizeof(uint64_t) * L.p_pad);
     L.keyw = take(sizeof(uint64_t) * L.p_pad);
@@ -264,7 +266,8 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
     const float *__restrict__ data, int N, int p, int M, int R, int disc_offset, double range,
     uint64_t seed, const int32_t *__restrict__ perm, int K0pad, int N0, int N1, int KB, int Kpad, int fp4,
     int64_t rows_pad, uint8_t *__restrict__ codes, int8_t *__restrict__ onehot,
-    uint32_t *__restrict__ marg, float *__restrict__ F1, int64_t p_pad, double b0, double b1, Status *st,
+    uint32_t *__restrict__ marg, float *__restrict__ F1, double *__restrict__ F1d, int64_t p_pad, double b0,
+    double b1, Status *st,
     uint32_t *__restrict__ bits, int64_t words_max)
 {
     constexpr int W = C - 1;
@@ -279,6 +282,7 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
     if (v >= p) {
         // padding variable (encode launches cover p_pad): zero one-hot rows, so the sweeps
         // count 0 for it
+        if (!onehot) return;
         const int nrow = KB * W * (KBLK / 4);
         for (int rr = 0; rr < R; ++rr)
             for (int idx = t; idx < nrow; idx += DISC_THREADS) {
@@ -425,6 +429,7 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
                     double Fv = 0.0;
                     for (int a = 0; a < C; ++a) Fv += fterm[rr * C + a];
                     F1[(int64_t)(rb + rr) * p_pad + v] = (float)Fv;
+                    if (F1d) F1d[(int64_t)(rb + rr) * p_pad + v] = Fv;
                 }
         }
         __syncthreads();
@@ -446,9 +451,9 @@ static hipError_t disc_launch(const Problem &P, const float *data, uint8_t *code
     const int64_t nblk = encode ? L.p_pad : L.p;   // encode: also zero the padding variables' rows
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(DISC_THREADS), lds, P.stream, data, N, (int)L.p, M,
                        L.R, P.disc_offset, P.range, P.seed, encode ? P.at<int32_t>(L.perm) : nullptr, P.K0pad, P.N0, P.N1, P.KB,
-                       P.Kpad, P.fp4 ? 1 : 0, L.rows_pad, codes, encode ? P.at<int8_t>(L.onehot) : nullptr,
+                       P.Kpad, P.fp4 ? 1 : 0, L.rows_pad, codes, (encode && L.k != 1) ? P.at<int8_t>(L.onehot) : nullptr,
                        encode ? P.at<uint32_t>(L.marg) : nullptr, encode ? P.at<float>(L.F1) : nullptr,
-                       L.p_pad, P.beta0, P.beta1, P.at<Status>(L.status),
+                       (encode && L.k == 1) ? P.at<double>(L.F1d) : nullptr, L.p_pad, P.beta0, P.beta1, P.at<Status>(L.status),
                        (encode && L.k == 3) ? P.at<uint32_t>(L.bits) : nullptr, L.words_max);
     return hipGetLastError();
 }

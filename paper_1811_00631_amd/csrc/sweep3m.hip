@@ -257,22 +257,25 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
         uint32_t Mi[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) Mi[c] = repack(margr[(int64_t)i * C + c]);
-        uint32_t Mj[4][3], Ml[4][3], Pij[4][4], Pil[4][4];
-        float Fij[4], Fil[4], thrJ[4], thrL[4], gJ[4], gL[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        // per-l data for the whole tile; per-j data (one m block at a time) loaded in the loops
+        uint32_t Ml[4][3], Pil[4][4];
+        float Fil[4], thrL[4], gL[4], gJ[4];
+        struct JData {
+            uint32_t M[3], P[4];
+            float F;
+        };
+        auto load_j = [&](int m, JData &d) {
             const int j = clampv(jv[m]);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) Mj[m][c] = repack(margr[(int64_t)j * C + c]);
+            for (int c = 0; c < 3; ++c) d.M[c] = repack(margr[(int64_t)j * C + c]);
             const int ii = i < j ? i : j, jj = i < j ? j : i;
             const v4i pw = *reinterpret_cast<const v4i *>(a.ptab + ((int64_t)ii * a.p_pad + jj) * 4);
 #pragma unroll
-            for (int x = 0; x < 4; ++x) Pij[m][x] = repack((uint32_t)pw[x]);
-            Fij[m] = a.F2[(int64_t)ii * a.p_pad + jj];
-            const float g = key_f32(a.G32[j]);
-            gJ[m] = g;
-            thrJ[m] = g - win3(a.w_abs, g);
-        }
+            for (int x = 0; x < 4; ++x) d.P[x] = repack((uint32_t)pw[x]);
+            d.F = a.F2[(int64_t)ii * a.p_pad + jj];
+        };
+#pragma unroll
+        for (int m = 0; m < 4; ++m) gJ[m] = key_f32(a.G32[clampv(jv[m])]);
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             const int l = clampv(lv[n]);
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
         float thrI = Gi - win3(a.w_abs, Gi);
 
         // F3 of triple (i, j_m, l_n) on the lane pair (e = 0, 1) and the parents' F
-        auto triple = [&](int m, int n, float &Fjl) -> float {
+        auto triple = [&](int m, int n, const JData &jd, float &Fjl) -> float {
             const bool valid = i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;
             const int j = clampv(jv[m]), l = clampv(lv[n]);
             const int jj = j < l ? j : l, ll = j < l ? l : j;
@@ -301,9 +304,9 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
 #pragma unroll
             for (int x = 0; x < 4; ++x) dj[x] = repack((uint32_t)pw[x]);
             uint32_t Nij[3][3], Nil[3][3], Njl[3][3];
-            full3(Pij[m], Mi, Mj[m], Nij);
+            full3(jd.P, Mi, jd.M, Nij);
             full3(Pil[n], Mi, Ml[n], Nil);
-            full3(dj, Mj[m], Ml[n], Njl);
+            full3(dj, jd.M, Ml[n], Njl);
             const v4i &ac = cnt[m][n];
             uint32_t D[2][2], Dp[2][2];
 #pragma unroll
@@ -341,7 +344,12 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
             // an invalid triple may combine unrelated tables: its counts are not counts
 #pragma unroll
             for (int k = 0; k < 14; ++k) V[k] = valid ? V[k] : 0u;
-            const float f = vox_sum<T, 14>(V, smem);
+            // two batches of 7 (the table reads of a batch are issued together; 14 at once
+            // would not leave room for the tile's counts)
+            uint32_t V0[7], V1[7];
+#pragma unroll
+            for (int k = 0; k < 7; ++k) { V0[k] = V[k]; V1[k] = V[7 + k]; }
+            const float f = vox_sum<T, 7>(V0, smem) + vox_sum<T, 7>(V1, smem);
             return f + swap1f(f);
         };
 
@@ -350,20 +358,24 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
         for (int m = 0; m < 4; ++m) mj[m] = ml[m] = -INFINITY;
         bool hot = false;
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 4; ++m) {
+            JData jd;
+            load_j(m, jd);
+            const float thrJ = gJ[m] - win3(a.w_abs, gJ[m]);
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
                 float Fjl;
-                const float F3 = triple(m, n, Fjl);
+                const float F3 = triple(m, n, jd, Fjl);
                 const bool valid = i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;
                 const float gi = valid ? Fjl - F3 : -INFINITY;       // gain of x_i given (x_j, x_l)
                 const float gj = valid ? Fil[n] - F3 : -INFINITY;    // gain of x_j given (x_i, x_l)
-                const float gl = valid ? Fij[m] - F3 : -INFINITY;    // gain of x_l given (x_i, x_j)
+                const float gl = valid ? jd.F - F3 : -INFINITY;      // gain of x_l given (x_i, x_j)
                 mi = fmaxf(mi, gi);
                 mj[m] = fmaxf(mj[m], gj);
                 ml[n] = fmaxf(ml[n], gl);
-                hot |= (gi >= thrI) | (gj >= thrJ[m]) | (gl >= thrL[n]);
+                hot |= (gi >= thrI) | (gj >= thrJ) | (gl >= thrL[n]);
             }
+        }
         // wave maxima: i is the tile's; j_m is shared by the lanes of one q; l_n by the lanes of
         // one c16 / 2 (the two lanes of a pair hold the same values)
 #pragma unroll
@@ -387,6 +399,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
                 const float top = a.collect ? g : fmaxf(g, mi);
                 thrI = top - win3(a.w_abs, top);
             }
+            float thrJ[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const float g = key_f32(a.G32[clampv(jv[m])]);
@@ -404,18 +417,21 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
 #pragma unroll
                 for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(cnt[m][n]) : : "memory");
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
+            for (int m = 0; m < 4; ++m) {
+                JData jd;
+                load_j(m, jd);
 #pragma unroll
                 for (int n = 0; n < 4; ++n) {
                     float Fjl;
-                    const float F3 = triple(m, n, Fjl);
+                    const float F3 = triple(m, n, jd, Fjl);
                     const int j = jv[m], l = lv[n];
                     const bool valid = e == 0 && i < j && j < l && l < a.p;   // one lane per triple
-                    const float gi = Fjl - F3, gj = Fil[n] - F3, gl = Fij[m] - F3;
+                    const float gi = Fjl - F3, gj = Fil[n] - F3, gl = jd.F - F3;
                     if (valid && gi >= thrI) append(a, i, ((uint32_t)j << 16) | (uint32_t)l, gi);
                     if (valid && gj >= thrJ[m]) append(a, j, ((uint32_t)i << 16) | (uint32_t)l, gj);
                     if (valid && gl >= thrL[n]) append(a, l, ((uint32_t)i << 16) | (uint32_t)j, gl);
                 }
+            }
         }
         if (a.collect) continue;
         // only where the tile raised the maximum read before (maxima only grow)

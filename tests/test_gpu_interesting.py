@@ -10,6 +10,13 @@ from paper_1811_00631_amd import workloads
 pytestmark = pytest.mark.gpu
 
 
+def midpoint_threshold(igs, rank):
+    """A threshold halfway between the rank-th largest value and the next one: records sit
+    clearly on one side (binary64 values of the two sides agree to ~1e-13, not exactly)."""
+    s = np.sort(np.asarray(igs))[::-1]
+    return float(0.5 * (s[rank - 1] + s[rank]))
+
+
 def as_dict(var, part, disc, ig):
     return {(int(v), tuple(int(x) for x in p), int(d)): float(g) for v, p, d, g in zip(var, part, disc, ig)}
 
@@ -19,7 +26,7 @@ def as_dict(var, part, disc, ig):
 def test_interesting_matches_oracle(mdfs_gpu, k, engine, div):
     w = workloads.xor_small(seed=61, n_obj=400, n_var=40 if k == 2 else 18, divisions=div, n_disc=3)
     ref_all = oracle.interesting(w.data, w.y, k, div, 3, w.range_, w.xi, w.seed, -np.inf)
-    thr = float(np.quantile(ref_all[3], 0.97))
+    thr = midpoint_threshold(ref_all[3], max(3, len(ref_all[3]) // 30))
     ref = as_dict(*oracle.interesting(w.data, w.y, k, div, 3, w.range_, w.xi, w.seed, thr))
     print(f"interesting k={k} {engine} d={div + 1}: thr={thr:.4f}, {len(ref)} records", flush=True)
     data, y = torch.from_numpy(w.data).cuda(), torch.from_numpy(w.y).cuda()
@@ -39,3 +46,25 @@ def test_interesting_none_above_the_maximum(mdfs_gpu):
     assert got[0].numel() == 0
     got = mdfs_gpu.mdfs_interesting_tuples(data, y, 2, 2, 2, top * 0.999, w.xi, w.range_, w.seed)
     assert got[0].numel() >= 1
+
+
+def test_interesting_capacity_errors(mdfs_gpu, monkeypatch):
+    # threshold -inf at p=100, R=3: 29700 records, more than a candidate buffer held to 5000
+    # records -> -9; a small max_out with a feasible threshold -> the binding refuses to
+    # truncate silently (-8)
+    w = workloads.xor_small(seed=63, n_obj=200, n_var=100, n_disc=3)
+    data, y = torch.from_numpy(w.data).cuda(), torch.from_numpy(w.y).cuda()
+    monkeypatch.setenv("MDFS_TEST_CAP", "5000")
+    with pytest.raises(mdfs_gpu.MdfsError) as e:
+        mdfs_gpu.mdfs_interesting_tuples(data, y, 2, 2, 3, -np.inf, w.xi, w.range_, w.seed)
+    assert e.value.code == -9
+    monkeypatch.delenv("MDFS_TEST_CAP")
+    allr = mdfs_gpu.mdfs_interesting_tuples(data, y, 2, 2, 3, -np.inf, w.xi, w.range_, w.seed)
+    assert allr[0].numel() == 4950 * 2 * 3
+    ref = oracle.interesting(w.data, w.y, 2, 2, 3, w.range_, w.xi, w.seed, 0.0)
+    thr = midpoint_threshold(ref[3], 20)
+    with pytest.raises(mdfs_gpu.MdfsError) as e:
+        mdfs_gpu.mdfs_interesting_tuples(data, y, 2, 2, 3, thr, w.xi, w.range_, w.seed, max_out=5)
+    assert e.value.code == -8
+    got = mdfs_gpu.mdfs_interesting_tuples(data, y, 2, 2, 3, thr, w.xi, w.range_, w.seed)
+    assert got[0].numel() == int((ref[3] >= thr).sum())

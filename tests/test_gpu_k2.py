@@ -218,3 +218,18 @@ def test_large_classes_use_int8_and_fp4_refuses_them(mdfs_gpu):
     with pytest.raises(mdfs_gpu.MdfsError) as e:
         run_gpu(mdfs_gpu, w, n_disc=2, engine="mfma_fp4")
     assert e.value.code == -8
+
+
+@pytest.mark.parametrize("div,rng,ones", [(2, 0.5, None), (1, 0.0, 60), (4, 0.7, None)])
+def test_k1_matches_oracle(mdfs_gpu, div, rng, ones):
+    # the one-dimensional analysis: no tuples, binary64 F of each variable, max over discretisations
+    w = workloads.null_data(16, 450, 70, ones=ones)
+    X = w.data.copy()
+    X[3] = (w.y * 2.0 - 1.0) + 0.3 * X[3]          # an informative variable
+    data, y = torch.from_numpy(X).to(DEV), torch.from_numpy(w.y).to(DEV)
+    ig, am, ad = mdfs_gpu.mdfs_max_ig(data, y, 1, div, 5, 0.25, rng, 7)
+    ref_ig, _, ref_ad = oracle.max_ig_all(X, w.y, 1, div, 5, rng, 0.25, 7, n_threads=4)
+    ig = ig.cpu().numpy().astype(np.float64)
+    assert np.abs(ig - ref_ig).max() <= 1e-4 * max(1.0, np.abs(ref_ig).max())
+    assert np.array_equal(ad.cpu().numpy(), ref_ad)
+    assert int(np.argmax(ig)) == 3
