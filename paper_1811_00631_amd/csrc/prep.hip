@@ -257,13 +257,47 @@ __device__ inline int code_of(float x, const float *thr)
 constexpr int DISC_THREADS = 512;
 constexpr int DISC_RCHUNK = 256;   // discretisations whose thresholds are staged at once
 
+// Value of rank k (0-based) in the union of two ascending arrays A[na], B[nb] (k < na + nb):
+// merge-path selection.  The number i of A elements among the k+1 smallest (A first on ties)
+// is the count of i with A[i] <= B[k-i], a predicate that holds for a prefix of the feasible
+// range [max(0, k+1-nb), min(k+1, na)); the answer is the larger of the last element taken
+// from each side.  Equal to sort(A u B)[k].
+__device__ inline float kth_of_two(const float *A, int na, const float *B, int nb, int k)
+{
+    int lo = max(0, k + 1 - nb), hi = min(k + 1, na);
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (A[mid] <= B[k - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo == 0) return B[k];
+    if (k - lo < 0) return A[lo - 1];
+    return fmaxf(A[lo - 1], B[k - lo]);
+}
+
+// Number of elements of the ascending array A[n] that are < v.
+__device__ inline int count_below(const float *A, int n, float v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (A[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // One workgroup per variable.  LDS: xcs[Kpad] (the variable in class-sorted order, for the
-// encodings), srt[M] (sorted copy, M = next power of two >= N), thresholds of a chunk of
-// discretisations.  Outputs (each optional): codes in original object order, one-hot rows in
-// class-sorted order, per-class marginal counts packed (n1 << 16 | n0), and F1 = N H(y|x).
+// encodings), srt[N] (class 0's values then class 1's, each sorted ascending; one segment of N
+// values when the class order is not given), thresholds of a chunk of discretisations.
+// Threshold q_j is the value of rank t_j of the whole variable, selected from the two sorted
+// classes; the per-class counts at or above each threshold come from binary searches, so the
+// marginals cost O(c log N) per discretisation.  Outputs (each optional): codes in original
+// object order, one-hot rows in class-sorted order, per-class marginal counts packed
+// (n1 << 16 | n0), and F1 = N H(y|x).
 template <int C>
 __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
-    const float *__restrict__ data, int N, int p, int M, int R, int disc_offset, double range,
+    const float *__restrict__ data, int N, int p, int R, int disc_offset, double range,
     uint64_t seed, const int32_t *__restrict__ perm, int K0pad, int N0, int N1, int KB, int Kpad, int fp4,
     int64_t rows_pad, uint8_t *__restrict__ codes, int8_t *__restrict__ onehot,
     uint32_t *__restrict__ marg, float *__restrict__ F1, double *__restrict__ F1d, int64_t p_pad, double b0,
@@ -273,8 +307,8 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
     constexpr int W = C - 1;
     extern __shared__ float lds[];
     float *xcs = lds;                       // [Kpad]
-    float *srt = xcs + Kpad;                // [M]
-    float *thr = srt + M;                   // [DISC_RCHUNK][C-1]
+    float *srt = xcs + Kpad;                // [N]
+    float *thr = srt + N;                   // [DISC_RCHUNK][C-1]
     __shared__ int hist[DISC_RCHUNK * 2 * C];
     __shared__ double fterm[DISC_RCHUNK * C];
     const int v = blockIdx.x;
@@ -292,45 +326,72 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
         return;
     }
     const float *x = data + (int64_t)v * N;
+    // segments of srt: [0, n0) and [n0, n0 + n1)
+    const int n0 = perm ? N0 : N, n1 = perm ? N1 : 0;
 
     bool bad = false;
-    for (int i = t; i < M; i += DISC_THREADS) {
-        float val = i < N ? x[i] : INFINITY;
-        bad |= (val != val);
-        srt[i] = val;
-    }
-    if (perm)
+    if (perm) {
         for (int i = t; i < Kpad; i += DISC_THREADS) {
-            int n = perm[i];
-            xcs[i] = n >= 0 ? x[n] : 0.0f;
+            const int n = perm[i];
+            const float val = n >= 0 ? x[n] : 0.0f;
+            bad |= (val != val);
+            xcs[i] = val;
+            if (i < N0) srt[i] = val;
+            else if (i >= K0pad && i < K0pad + N1) srt[N0 + i - K0pad] = val;
         }
+    } else {
+        for (int i = t; i < N; i += DISC_THREADS) {
+            const float val = x[i];
+            bad |= (val != val);
+            srt[i] = val;
+        }
+    }
     if (bad) atomicOr(&st->nan_flag, 1u);
     __syncthreads();
 
-    // bitonic sort of srt[0..M), ascending
-    for (int kk = 2; kk <= M; kk <<= 1) {
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            for (int i = t; i < M; i += DISC_THREADS) {
-                int ixj = i ^ j;
-                if (ixj > i) {
-                    float a = srt[i], b = srt[ixj];
-                    bool up = (i & kk) == 0;
-                    if (up ? (a > b) : (a < b)) {
-                        srt[i] = b;
-                        srt[ixj] = a;
+    // Both segments sorted ascending by one bitonic network each (the form whose first step at
+    // every merge size compares mirrored positions, so every compare-exchange is ascending).
+    // A segment of n values runs the network of the next power of two with virtual +inf
+    // padding; a pair whose upper index is >= n never exchanges, so it is skipped.
+    {
+        int m0 = 1, m1 = 1;
+        while (m0 < n0) m0 <<= 1;
+        while (m1 < n1) m1 <<= 1;
+        if (n1 == 0) m1 = 0;
+        const int mx = max(m0, m1);
+        for (int kk = 2; kk <= mx; kk <<= 1) {
+            const int h0 = kk <= m0 ? m0 >> 1 : 0, h1 = kk <= m1 ? m1 >> 1 : 0;
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                for (int q = t; q < h0 + h1; q += DISC_THREADS) {
+                    const bool sg = q >= h0;
+                    const int qq = sg ? q - h0 : q, n = sg ? n1 : n0;
+                    float *a = srt + (sg ? n0 : 0);
+                    const int i = ((qq & ~(j - 1)) << 1) | (qq & (j - 1));
+                    const int partner = (j == (kk >> 1)) ? (i ^ (kk - 1)) : (i + j);
+                    if (partner < n) {
+                        const float lo_v = a[i], hi_v = a[partner];
+                        if (lo_v > hi_v) {
+                            a[i] = hi_v;
+                            a[partner] = lo_v;
+                        }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
 
     for (int rb = 0; rb < R; rb += DISC_RCHUNK) {
         const int nr = min(DISC_RCHUNK, R - rb);
-        if (t < nr) {
+        // thresholds, and per class the count of values >= each threshold (hist[.., j + 1])
+        for (int i = t; i < nr * (C - 1); i += DISC_THREADS) {
+            const int rr = i / (C - 1), j = i % (C - 1);
             int tc[C - 1];
-            cut_positions<C>(N, range, seed, (uint64_t)(disc_offset + rb + t), (uint64_t)v, tc);
-            for (int j = 0; j < C - 1; ++j) thr[t * (C - 1) + j] = srt[tc[j]];
+            cut_positions<C>(N, range, seed, (uint64_t)(disc_offset + rb + rr), (uint64_t)v, tc);
+            const float q = kth_of_two(srt, n0, srt + n0, n1, tc[j]);
+            thr[rr * (C - 1) + j] = q;
+            hist[(rr * 2 + 0) * C + j + 1] = n0 - count_below(srt, n0, q);
+            hist[(rr * 2 + 1) * C + j + 1] = n1 - count_below(srt + n0, n1, q);
         }
         __syncthreads();
         for (int rr = 0; rr < nr; ++rr) {
@@ -340,30 +401,47 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
                 uint8_t *out = codes + ((int64_t)r * p + v) * N;
                 for (int n = t; n < N; n += DISC_THREADS) out[n] = (uint8_t)code_of<C>(x[n], th);
             }
-            if (onehot) {
-                // dword q of one (K block, bin) row chunk: class-sorted positions
-                // kb * kobj + q * per .. + per - 1, one byte (int8 1) or one nibble (E2M1 1.0) each
-                const int ndw = KB * W * (KBLK / 4);
-                const int per = fp4 ? 8 : 4, kobj = fp4 ? KOBJ_F4 : KOBJ_I8;
-                for (int idx = t; idx < ndw; idx += DISC_THREADS) {
-                    const int kb = idx / (W * (KBLK / 4));
-                    const int a = (idx / (KBLK / 4)) % W;
-                    const int q4 = idx % (KBLK / 4);
-                    uint32_t word = 0;
+        }
+        if (onehot) {
+            // a thread per group of `per` consecutive class-sorted positions (one dword of a
+            // (K block, bin) row chunk: one byte (int8 1) or one nibble (E2M1 2.0) each): the
+            // codes are taken once per position and scattered into the W rows' dwords
+            const int per = fp4 ? 8 : 4;
+            const int ngrp = KB * (KBLK / 4);
+            for (int g = t; g < ngrp; g += DISC_THREADS) {
+                const int kb = g / (KBLK / 4), q4 = g % (KBLK / 4);
+                float xv[8];
+                bool ok[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int ps = g * per + e;
+                    ok[e] = e < per && ((ps < N0) || (ps >= K0pad && ps < K0pad + N1));
+                    xv[e] = ok[e] ? xcs[ps] : 0.0f;
+                }
+                for (int rr = 0; rr < nr; ++rr) {
+                    const float *th = thr + rr * (C - 1);
+                    uint32_t word[W];
+#pragma unroll
+                    for (int a = 0; a < W; ++a) word[a] = 0;
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
-                        if (e >= per) break;
-                        const int ps = kb * kobj + q4 * per + e;
-                        const bool valid = (ps < N0) || (ps >= K0pad && ps < K0pad + N1);
-                        const bool hit = valid && code_of<C>(xcs[ps], th) == a;
-                        if (hit) word |= fp4 ? (F4_TWO << (4 * e)) : (1u << (8 * e));
+                        const int c = ok[e] ? code_of<C>(xv[e], th) : W;
+                        const uint32_t bit = fp4 ? (F4_TWO << (4 * e)) : (1u << (8 * e));
+#pragma unroll
+                        for (int a = 0; a < W; ++a) word[a] |= (c == a) ? bit : 0u;
                     }
-                    int64_t row = (int64_t)v * W + a;
-                    int64_t off = onehot_off(r, row, kb, q4 * 4, KB, rows_pad);
-                    *reinterpret_cast<uint32_t *>(onehot + off) = word;
+#pragma unroll
+                    for (int a = 0; a < W; ++a) {
+                        const int64_t off = onehot_off(rb + rr, (int64_t)v * W + a, kb, q4 * 4, KB, rows_pad);
+                        *reinterpret_cast<uint32_t *>(onehot + off) = word[a];
+                    }
                 }
             }
-            if (bits) {
+        }
+        if (bits) {
+            for (int rr = 0; rr < nr; ++rr) {
+                const int r = rb + rr;
+                const float *th = thr + rr * (C - 1);
                 // bitset word w of class y: class-sorted positions y_off + 32w .. +31, bin a
                 const int w0 = (N0 + 31) / 32, w1 = (N1 + 31) / 32;
                 for (int idx = t; idx < (w0 + w1) * W; idx += DISC_THREADS) {
@@ -381,45 +459,19 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
             }
         }
         if (marg || F1) {
-            // per-class bin counts of every discretisation of this chunk: one ballot per
-            // (class, bin) and 64 positions, one LDS atomic per wave and (r, class, bin)
-            for (int i = t; i < nr * 2 * C; i += DISC_THREADS) hist[i] = 0;
-            __syncthreads();
-            const int lane = t & 63;
-            for (int rr = 0; rr < nr; ++rr) {
-                const float *th = thr + rr * (C - 1);
-                int loc[2][C];
-#pragma unroll
-                for (int a = 0; a < C; ++a) loc[0][a] = loc[1][a] = 0;
-                for (int base = t - lane; base < Kpad; base += DISC_THREADS) {
-                    const int ps = base + lane;
-                    const bool c0 = ps < N0, c1 = ps >= K0pad && ps < K0pad + N1;
-                    const int cd = (c0 | c1) ? code_of<C>(xcs[ps], th) : -1;
-#pragma unroll
-                    for (int a = 0; a < C; ++a) {
-                        loc[0][a] += __popcll(__ballot(c0 && cd == a));
-                        loc[1][a] += __popcll(__ballot(c1 && cd == a));
-                    }
-                }
-                if (lane == 0) {
-#pragma unroll
-                    for (int a = 0; a < C; ++a) {
-                        if (loc[0][a]) atomicAdd(&hist[(rr * 2 + 0) * C + a], loc[0][a]);
-                        if (loc[1][a]) atomicAdd(&hist[(rr * 2 + 1) * C + a], loc[1][a]);
-                    }
-                }
-            }
-            __syncthreads();
-            // packed marginals and the F terms of every (r, bin) in parallel
+            // bin a of class d holds G_d(a) - G_d(a+1) values, G_d(a) = count >= threshold a
+            // (G_d(0) = n_d, G_d(C) = 0); packed marginals and the F terms of every (r, bin)
             for (int i = t; i < nr * C; i += DISC_THREADS) {
                 const int rr = i / C, a = i % C, r = rb + rr;
-                const int h0 = hist[(rr * 2 + 0) * C + a], h1 = hist[(rr * 2 + 1) * C + a];
+                const int *g0 = hist + (rr * 2 + 0) * C, *g1 = hist + (rr * 2 + 1) * C;
+                const int h0 = (a == 0 ? n0 : g0[a]) - (a + 1 < C ? g0[a + 1] : 0);
+                const int h1 = (a == 0 ? n1 : g1[a]) - (a + 1 < C ? g1[a + 1] : 0);
                 if (marg) marg[((int64_t)r * p_pad + v) * C + a] = ((uint32_t)h1 << 16) | (uint32_t)h0;
-                const double n0 = h0, n1 = h1, n = n0 + n1;
+                const double d0 = h0, d1 = h1, n = d0 + d1;
                 double term = 0.0;
                 if (n > 0) {
                     const double sden = n + b0 + b1;
-                    term = n * log(sden) - (n / sden) * (xlogx(n0 + b0) + xlogx(n1 + b1));
+                    term = n * log(sden) - (n / sden) * (xlogx(d0 + b0) + xlogx(d1 + b1));
                 }
                 fterm[i] = term;
             }
@@ -440,16 +492,14 @@ template <int C>
 static hipError_t disc_launch(const Problem &P, const float *data, uint8_t *codes, bool encode)
 {
     const Layout &L = P.L;
-    int N = (int)L.N;
-    int M = 1;
-    while (M < N) M <<= 1;
-    int Kpad = P.Kpad;
-    size_t lds = sizeof(float) * ((size_t)Kpad + M + DISC_RCHUNK * (C - 1));
+    const int N = (int)L.N;
+    const int Kpad = P.Kpad;
+    size_t lds = sizeof(float) * ((size_t)Kpad + N + DISC_RCHUNK * (C - 1));
     auto kern = k_discretize<C>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int64_t nblk = encode ? L.p_pad : L.p;   // encode: also zero the padding variables' rows
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(DISC_THREADS), lds, P.stream, data, N, (int)L.p, M,
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(DISC_THREADS), lds, P.stream, data, N, (int)L.p,
                        L.R, P.disc_offset, P.range, P.seed, encode ? P.at<int32_t>(L.perm) : nullptr, P.K0pad, P.N0, P.N1, P.KB,
                        P.Kpad, P.fp4 ? 1 : 0, L.rows_pad, codes, (encode && L.k != 1) ? P.at<int8_t>(L.onehot) : nullptr,
                        encode ? P.at<uint32_t>(L.marg) : nullptr, encode ? P.at<float>(L.F1) : nullptr,
