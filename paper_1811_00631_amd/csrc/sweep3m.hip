@@ -364,9 +364,12 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
             const float thrJ = gJ[m] - win3(a.w_abs, gJ[m]);
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
+                const bool valid = i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;
+                // wave-uniform skip of a block without any valid triple (near the diagonal of
+                // the (j, l) blocks and past p): its maxima would stay -inf
+                if (!__any(valid)) continue;
                 float Fjl;
                 const float F3 = triple(m, n, jd, Fjl);
-                const bool valid = i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;
                 const float gi = valid ? Fjl - F3 : -INFINITY;       // gain of x_i given (x_j, x_l)
                 const float gj = valid ? Fil[n] - F3 : -INFINITY;    // gain of x_j given (x_i, x_l)
                 const float gl = valid ? jd.F - F3 : -INFINITY;      // gain of x_l given (x_i, x_j)
@@ -422,9 +425,10 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
                 load_j(m, jd);
 #pragma unroll
                 for (int n = 0; n < 4; ++n) {
+                    const int j = jv[m], l = lv[n];
+                    if (!__any(i < j && j < l && l < a.p)) continue;   // as in the first pass
                     float Fjl;
                     const float F3 = triple(m, n, jd, Fjl);
-                    const int j = jv[m], l = lv[n];
                     const bool valid = e == 0 && i < j && j < l && l < a.p;   // one lane per triple
                     const float gi = Fjl - F3, gj = Fil[n] - F3, gl = jd.F - F3;
                     if (valid && gi >= thrI) append(a, i, ((uint32_t)j << 16) | (uint32_t)l, gi);
