@@ -49,7 +49,8 @@ def run_gpu(mdfs, w, n_disc=None, xi=None, rng=None, seed=None, divisions=None, 
 # ------------------------------------------------------------------ discretisation
 @pytest.mark.parametrize("n_obj,n_var,div,R,rng", [(500, 37, 2, 3, 0.5), (1000, 5, 1, 2, 1.0),
                                                   (129, 130, 2, 2, 0.0), (64, 3, 4, 2, 0.7),
-                                                  (3, 2, 2, 1, 0.5)])
+                                                  (3, 2, 2, 1, 0.5), (16384, 3, 2, 2, 0.5),
+                                                  (16383, 2, 4, 1, 1.0)])
 def test_codes_bit_exact(mdfs_gpu, n_obj, n_var, div, R, rng):
     g = np.random.default_rng(n_obj + n_var)
     X = g.standard_normal((n_var, n_obj)).astype(np.float32)
@@ -220,10 +221,13 @@ def test_large_classes_use_int8_and_fp4_refuses_them(mdfs_gpu):
     assert e.value.code == -8
 
 
-@pytest.mark.parametrize("div,rng,ones", [(2, 0.5, None), (1, 0.0, 60), (4, 0.7, None)])
-def test_k1_matches_oracle(mdfs_gpu, div, rng, ones):
+@pytest.mark.parametrize("div,rng,ones,n_obj,n_var", [(2, 0.5, None, 450, 70), (1, 0.0, 60, 450, 70),
+                                                     (4, 0.7, None, 450, 70), (2, 0.5, 5000, 16384, 6)])
+def test_k1_matches_oracle(mdfs_gpu, div, rng, ones, n_obj, n_var):
     # the one-dimensional analysis: no tuples, binary64 F of each variable, max over discretisations
-    w = workloads.null_data(16, 450, 70, ones=ones)
+    # (the last case: the largest N, class sizes 11384 / 5000, through the class-sorted marginals)
+    print(f"k1 N={n_obj} p={n_var} div={div}", flush=True)
+    w = workloads.null_data(16, n_obj, n_var, ones=ones)
     X = w.data.copy()
     X[3] = (w.y * 2.0 - 1.0) + 0.3 * X[3]          # an informative variable
     data, y = torch.from_numpy(X).to(DEV), torch.from_numpy(w.y).to(DEV)
