@@ -157,6 +157,50 @@ int mdfs_interesting_tuples(const mdfs_params *prm, const float *data, const uin
                             int32_t *var, int32_t *partners, int32_t *disc, double *ig, int64_t max_out,
                             int64_t *n_found, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Significance of IG^k_max (host-side, binary64; host pointers, no device work) ----
+ * Section "Theory", the paragraphs after equation IGmax: for an irrelevant variable and one
+ * k-tuple, 2 IG is chi-square distributed (natural logarithms); IG^k_max, the largest of many
+ * such values, follows an extreme value distribution whose one free parameter, the number of
+ * independent tests n_eff, is fitted to the irrelevant part of the data; this yields p-values,
+ * IG_lim for a significance level, and p-values adjusted by Holm or Benjamini-Hochberg(-Yekutieli)
+ * (section "Canonical package usage": ComputePValue, then p.adjust).  Model used here:
+ * Pr(IG_max <= x) = F(2x)^n_eff, F the chi-square CDF with mdfs_chi2_df(k, divisions) degrees of
+ * freedom; n_eff by maximum likelihood, n_eff = -m / sum_v ln F(2 IG_v) over the m selected
+ * variables with IG_v > 0. */
+
+typedef enum {
+    MDFS_ADJ_NONE = 0,   /* p-values unchanged */
+    MDFS_ADJ_HOLM = 1,   /* Holm step-down (FWER) */
+    MDFS_ADJ_BH = 2,     /* Benjamini-Hochberg (FDR) */
+    MDFS_ADJ_BY = 3      /* Benjamini-Hochberg-Yekutieli (FDR under dependence) */
+} mdfs_adjust;
+
+/* Degrees of freedom of 2 IG for one tuple of irrelevant variables and a binary decision:
+ * (c - 1) c^(k-1), c = divisions + 1.  Returns the df (> 0), or MDFS_E_K / MDFS_E_DIV for k
+ * outside [1, 5] or divisions outside [1, 15]. */
+int mdfs_chi2_df(int k, int divisions);
+
+/* p-value of every variable's IG^k_max.
+ *   ig          : host double [n], IG^k_max in nats (the values mdfs_max_ig returns)
+ *   fit_mask    : host uint8 [n] or NULL: the variables taken as irrelevant for the fit of n_eff
+ *                 (1 = use); NULL = all variables.  Variables with IG <= 0 never enter the fit.
+ *   n_eff_fixed : > 0 uses this n_eff (e.g. 1 for a single tuple and discretisation), <= 0 fits it
+ *   p_out       : host double [n] (output) 1 - F(2 IG)^n_eff, accurate far below 1e-16; 1 for IG <= 0
+ *   n_eff_out   : host double (output, nullable) the n_eff used
+ * Returns MDFS_E_ARG for null pointers, n < 1, a NaN IG or no usable variable in the fit. */
+int mdfs_pvalues(const double *ig, int64_t n, int k, int divisions, const uint8_t *fit_mask, double n_eff_fixed,
+                 double *p_out, double *n_eff_out);
+
+/* IG_lim: the IG^k_max whose p-value is alpha under n_eff (0 < alpha < 1, 0 < n_eff < inf).
+ *   ig_lim : host double (output).  Returns MDFS_E_ARG for arguments out of range. */
+int mdfs_ig_lim(int k, int divisions, double n_eff, double alpha, double *ig_lim);
+
+/* Adjusted p-values (method: mdfs_adjust), the definitions of R's p.adjust: Holm
+ * max_{j<=i} min(1, (n-j+1) p_(j)); BH min_{j>=i} min(1, n/j p_(j)); BY as BH times sum_{j<=n} 1/j.
+ *   p : host double [n] in [0, 1];  out : host double [n] (output; may alias p).
+ * Returns MDFS_E_ARG for null pointers, n < 1, an unknown method or a p outside [0, 1]. */
+int mdfs_p_adjust(const double *p, int64_t n, int method, double *out);
+
 /* The float32 screening maxima of the sweep before the binary64 re-score: for every variable
  * the largest float32 IG over all tuples and discretisations, and the float32 error bound E
  * that the re-score window is built from (|IG_f32 - IG| <= E for every tuple).

@@ -1,6 +1,6 @@
 """Build libmdfs.so (gfx950) in-tree with hipcc.
 
-Each .hip source under csrc/ is compiled to an object in _build/ and the objects are linked
+Each source under csrc/ (HIP, and the host-only stats.cpp) is compiled to an object in _build/ and the objects are linked
 into paper_1811_00631_amd/libmdfs.so.  Run `python -m paper_1811_00631_amd.build`.
 """
 from __future__ import annotations
@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libmdfs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["prep.hip", "sweep2.hip", "sweep3.hip", "sweep3m.hip", "finalize.hip", "api.hip"]
+SOURCES = ["prep.hip", "sweep2.hip", "sweep3.hip", "sweep3m.hip", "finalize.hip", "api.hip", "stats.cpp"]
 
 # Packed fp32 instructions are disabled for every device pass (hipcc's host pass warns that it
 # does not know the feature; that is harmless).
@@ -28,7 +28,7 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-
 
 
 def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -18,6 +18,10 @@ using namespace mdfs;
 
 static thread_local std::string g_err;
 
+namespace mdfs {
+void set_error(const std::string &msg) { g_err = msg; }
+}
+
 static int fail(int code, const char *fmt, ...)
 {
     char buf[512];

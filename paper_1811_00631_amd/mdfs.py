@@ -11,12 +11,17 @@ Functions mirror the C entry points:
                                             argmax_disc i32 [n_var])
     mdfs_pair_counts(data, y, disc,...) -> counts i32 [n_var][n_var][2][c][c] (i < j filled)
     mdfs_screen_max(data, y, ...)       -> (ig32 f32 [n_var], error bound E)
+    mdfs_chi2_df(k, divisions)          -> int
+    mdfs_pvalues(ig, k, divisions, ...) -> (p float64 [n], n_eff)       (host arrays)
+    mdfs_ig_lim(k, divisions, n_eff, a) -> float
+    mdfs_p_adjust(p, method)            -> adjusted float64 [n]          (host arrays)
 """
 from __future__ import annotations
 
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -27,6 +32,7 @@ STATUS = {0: "MDFS_OK", -1: "MDFS_E_ARG", -2: "MDFS_E_Y", -3: "MDFS_E_K", -4: "M
           -5: "MDFS_E_NAN", -6: "MDFS_E_NOMEM", -7: "MDFS_E_HIP", -8: "MDFS_E_LIMIT",
           -9: "MDFS_E_OVERFLOW"}
 ENGINES = {"auto": 0, "mfma": 1, "bitset": 2, "mfma_fp4": 3}
+ADJUST = {"none": 0, "holm": 1, "BH": 2, "BY": 3}
 
 
 class MdfsError(RuntimeError):
@@ -45,7 +51,8 @@ class Params(ctypes.Structure):
 
 _lib = None
 SYMBOLS = ["mdfs_workspace_size", "mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts",
-           "mdfs_screen_max", "mdfs_interesting_tuples", "mdfs_phase_times", "mdfs_last_error"]
+           "mdfs_screen_max", "mdfs_interesting_tuples", "mdfs_phase_times", "mdfs_last_error",
+           "mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust"]
 FLAG_TIMING = 1
 PHASES = ["setup", "discretize", "sweep", "finalize"]
 
@@ -71,6 +78,13 @@ def load(path: str = LIB_PATH):
     L.mdfs_phase_times.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     L.mdfs_phase_times.restype = ctypes.c_int
     L.mdfs_last_error.restype = ctypes.c_char_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.mdfs_chi2_df.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.mdfs_pvalues.argtypes = [vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, vp, ctypes.c_double, vp, dp]
+    L.mdfs_ig_lim.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+    L.mdfs_p_adjust.argtypes = [vp, ctypes.c_int64, ctypes.c_int, vp]
+    for fn in ("mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust"):
+        getattr(L, fn).restype = ctypes.c_int
     for fn in ("mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts", "mdfs_screen_max", "mdfs_interesting_tuples"):
         getattr(L, fn).restype = ctypes.c_int
     _lib = L
@@ -230,3 +244,50 @@ def mdfs_screen_max(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int,
     _check(load().mdfs_screen_max(ctypes.byref(prm), _ptr(data), _ptr(y), _ptr(ig32), ctypes.byref(eb), _ptr(ws),
                                   ws.numel(), _stream(data.device)))
     return ig32, eb.value
+
+
+# ------------------------------------------------------------------ significance (host, binary64)
+def _host_f64(x) -> np.ndarray:
+    if isinstance(x, torch.Tensor):
+        x = x.detach().cpu().numpy()
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def mdfs_chi2_df(k: int, divisions: int) -> int:
+    """Degrees of freedom of 2 IG for one tuple of irrelevant variables."""
+    rc = load().mdfs_chi2_df(int(k), int(divisions))
+    if rc <= 0:
+        _check(rc)
+    return rc
+
+
+def mdfs_pvalues(ig, k: int, divisions: int, fit_mask=None, n_eff: float | None = None):
+    """p-values of IG^k_max (host arrays).  fit_mask selects the variables taken as irrelevant
+    for the fit of n_eff (None = all); a given n_eff is used as is.  Returns (p, n_eff)."""
+    x = _host_f64(ig).ravel()
+    out = np.empty_like(x)
+    mask = None
+    if fit_mask is not None:
+        mask = np.ascontiguousarray(np.asarray(fit_mask).ravel() != 0, dtype=np.uint8)
+        if mask.shape != x.shape:
+            raise ValueError("fit_mask must have one entry per variable")
+    ne = ctypes.c_double(0.0)
+    _check(load().mdfs_pvalues(x.ctypes.data, x.size, int(k), int(divisions),
+                               None if mask is None else mask.ctypes.data,
+                               float(n_eff) if n_eff is not None else 0.0, out.ctypes.data, ctypes.byref(ne)))
+    return out, ne.value
+
+
+def mdfs_ig_lim(k: int, divisions: int, n_eff: float, alpha: float) -> float:
+    """IG_lim: the IG^k_max whose p-value is alpha."""
+    v = ctypes.c_double(0.0)
+    _check(load().mdfs_ig_lim(int(k), int(divisions), float(n_eff), float(alpha), ctypes.byref(v)))
+    return v.value
+
+
+def mdfs_p_adjust(p, method: str = "BY") -> np.ndarray:
+    """Adjusted p-values: "holm", "BH", "BY" or "none" (the definitions of R's p.adjust)."""
+    x = _host_f64(p).ravel()
+    out = np.empty_like(x)
+    _check(load().mdfs_p_adjust(x.ctypes.data, x.size, ADJUST[method], out.ctypes.data))
+    return out

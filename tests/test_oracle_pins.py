@@ -329,3 +329,68 @@ def test_interesting_tuples_threshold_filters_exactly():
     assert len(sel[0]) == int(keep.sum())
     for a, b in zip(sel, (x[keep] for x in allv)):
         assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ significance of IG_max
+from oracle import significance as sig   # noqa: E402
+
+
+def test_significance_df_and_single_tuple_closed_form():
+    # df of 2 IG for one tuple: 6 (k=2, d=3) and 18 (k=3, d=3) are the values the KS pins of the
+    # null distribution above confirm; k=1, d=3 gives 2, where the chi-square tail is e^(-t/2),
+    # so with one test the p-value of IG = x is exactly e^(-x)
+    assert (sig.chi2_df(2, 2), sig.chi2_df(3, 2), sig.chi2_df(1, 2), sig.chi2_df(2, 1)) == (6, 18, 2, 2)
+    x = np.array([0.01, 0.5, 2.0, 7.5, 30.0, 300.0])
+    p, n = sig.pvalues(x, 1, 2, n_eff=1.0)
+    assert n == 1.0
+    assert np.allclose(p, np.exp(-x), rtol=1e-12, atol=0)
+    # and IG_lim(alpha) = -ln(alpha)
+    for a in (0.05, 1e-3, 1e-12):
+        assert math.isclose(sig.ig_lim(1, 2, 1.0, a), -math.log(a), rel_tol=1e-10)
+
+
+def test_significance_fit_recovers_the_number_of_tests():
+    # maxima of n independent chi2_6 / 2 values: the fitted n_eff must recover n (statistical
+    # tolerance: the MLE's relative standard error is 1/sqrt(m) = 1.6% for m = 4000)
+    g = np.random.default_rng(2024)
+    for n in (1, 25, 400):
+        x = (g.chisquare(6, size=(4000, n)) / 2).max(axis=1)
+        ne = sig.fit_n_eff(x, 2, 2)
+        assert abs(ne / n - 1) < 0.06, (n, ne)
+        # under the fitted law the p-values of these maxima are uniform
+        p, _ = sig.pvalues(x, 2, 2, n_eff=ne)
+        assert stats.kstest(p, "uniform").pvalue > 1e-3
+
+
+def test_significance_fit_mask_and_nonpositive_values():
+    x = np.array([3.0, 4.0, 0.0, -1.0, 50.0])
+    mask = np.array([1, 1, 1, 1, 0], dtype=bool)
+    ne = sig.fit_n_eff(x, 2, 2, mask)
+    # only 3.0 and 4.0 enter: n = -2 / (ln F(6) + ln F(8)) for chi2_6
+    ref = -2 / (stats.chi2.logcdf(6.0, 6) + stats.chi2.logcdf(8.0, 6))
+    assert math.isclose(ne, ref, rel_tol=1e-12)
+    p, _ = sig.pvalues(x, 2, 2, n_eff=ne)
+    assert p[2] == 1.0 and p[3] == 1.0 and p[4] < 1e-15
+
+
+def test_p_adjust_hand_example():
+    # p = (0.01, 0.04, 0.03, 0.005), worked by hand: sorted 0.005, 0.01, 0.03, 0.04
+    #   Holm: 4*0.005, 3*0.01, 2*0.03, 1*0.04 -> running max 0.02, 0.03, 0.06, 0.06
+    #   BH:   4/1*0.005, 4/2*0.01, 4/3*0.03, 4/4*0.04 = 0.02, 0.02, 0.04, 0.04 -> running min from the top
+    #   BY:   BH * (1 + 1/2 + 1/3 + 1/4) = BH * 25/12
+    p = [0.01, 0.04, 0.03, 0.005]
+    assert np.allclose(sig.p_adjust(p, "holm"), [0.03, 0.06, 0.06, 0.02], rtol=1e-14)
+    assert np.allclose(sig.p_adjust(p, "BH"), [0.02, 0.04, 0.04, 0.02], rtol=1e-14)
+    assert np.allclose(sig.p_adjust(p, "BY"), np.array([0.02, 0.04, 0.04, 0.02]) * 25 / 12, rtol=1e-14)
+    # BH and BY against SciPy's implementation on random p-values with ties
+    g = np.random.default_rng(7)
+    q = np.round(g.uniform(size=200), 3)
+    assert np.allclose(sig.p_adjust(q, "BH"), stats.false_discovery_control(q, method="bh"), rtol=1e-12)
+    assert np.allclose(sig.p_adjust(q, "BY"), stats.false_discovery_control(q, method="by"), rtol=1e-12)
+
+
+def test_ig_lim_has_p_value_alpha():
+    for k, d, ne, a in ((2, 2, 37.5, 0.05), (3, 2, 1234.0, 1e-6), (2, 4, 3.0, 0.5)):
+        x = sig.ig_lim(k, d, ne, a)
+        p, _ = sig.pvalues(np.array([x]), k, d, n_eff=ne)
+        assert math.isclose(p[0], a, rel_tol=1e-9)
