@@ -157,6 +157,21 @@ int mdfs_interesting_tuples(const mdfs_params *prm, const float *data, const uin
                             int32_t *var, int32_t *partners, int32_t *disc, double *ig, int64_t max_out,
                             int64_t *n_found, void *ws, size_t ws_bytes, void *stream);
 
+/* AddContrastVariables (section "Package functions introduction": variables known to be
+ * irrelevant, for the fit of the IG_max distribution; they are left out of the p-value
+ * adjustment).  The paper cites the construction without defining it; here contrast variable c
+ * copies original variable src(c) = SplitMix64(seed, c, 0x5352434) mod n_var with its objects
+ * permuted by a keyed 4-round Feistel network on 2h-bit indices (2^(2h) >= n_obj), cycle-walked
+ * into [0, n_obj): out[n_var + c][n] = data[src(c)][perm_c(n)].
+ *   data : device float32 [n_var][n_obj] (input)
+ *   out  : device float32 [n_var + n_contrast][n_obj] (output): the originals, then the contrast
+ *          variables; must not overlap data
+ *   src  : host int32 [n_contrast] (output, nullable): src(c) of every contrast variable
+ * Enqueued on `stream` (no synchronisation).  Returns MDFS_E_ARG for null pointers, overlap or
+ * sizes outside 1 <= n_obj <= 2^30, 1 <= n_var < 2^31, 0 <= n_contrast <= 2^24. */
+int mdfs_add_contrast(const float *data, int64_t n_obj, int64_t n_var, int64_t n_contrast, uint64_t seed,
+                      float *out, int32_t *src, void *stream);
+
 /* ---- Significance of IG^k_max (host-side, binary64; host pointers, no device work) ----
  * Section "Theory", the paragraphs after equation IGmax: for an irrelevant variable and one
  * k-tuple, 2 IG is chi-square distributed (natural logarithms); IG^k_max, the largest of many

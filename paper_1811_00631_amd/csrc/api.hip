@@ -311,6 +311,24 @@ extern "C" int mdfs_discretize(const mdfs_params *prm, const float *data, uint8_
     return MDFS_OK;
 }
 
+extern "C" int mdfs_add_contrast(const float *data, int64_t n_obj, int64_t n_var, int64_t n_contrast,
+                                 uint64_t seed, float *out, int32_t *src, void *stream)
+{
+    if (!data || !out) return fail(MDFS_E_ARG, "data and out must be non-null");
+    if (n_obj < 1 || n_obj > (int64_t(1) << 30) || n_var < 1 || n_var > INT32_MAX || n_contrast < 0 ||
+        n_contrast > (int64_t(1) << 24))
+        return fail(MDFS_E_ARG, "need 1 <= n_obj <= 2^30, 1 <= n_var < 2^31, 0 <= n_contrast <= 2^24");
+    const char *d0 = reinterpret_cast<const char *>(data), *d1 = d0 + sizeof(float) * n_obj * n_var;
+    const char *o0 = reinterpret_cast<const char *>(out), *o1 = o0 + sizeof(float) * n_obj * (n_var + n_contrast);
+    if (o0 < d1 && d0 < o1) return fail(MDFS_E_ARG, "out overlaps data");
+    if (src)
+        for (int64_t c = 0; c < n_contrast; ++c) src[c] = (int32_t)contrast_source(seed, c, n_var);
+    hipError_t e = launch_contrast(data, n_obj, n_var, n_contrast, seed, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "contrast variables");
+    g_err.clear();
+    return MDFS_OK;
+}
+
 // k = 1: F of the decision alone (one voxel holding every object), binary64.
 static double root_F(const Problem &P)
 {

@@ -150,5 +150,10 @@ hipError_t launch_emit(const Problem &P, double thr, int32_t *var, int32_t *part
 hipError_t launch_screen_out(const Problem &P, float *ig32);
 // k = 1: IG(i) = F(root) - F(x_i) per discretisation, max and tie rule over discretisations
 hipError_t launch_ig1(const Problem &P, double F0, float *ig_max, int32_t *argmax_disc);
+// contrast variables (contrast.hip): the source variable of contrast variable c, and the launch
+// that writes the originals then the permuted copies into out [n_var + n_contrast][n_obj]
+int64_t contrast_source(uint64_t seed, int64_t c, int64_t n_var);
+hipError_t launch_contrast(const float *data, int64_t n_obj, int64_t n_var, int64_t n_contrast, uint64_t seed,
+                           float *out, hipStream_t stream);
 
 }  // namespace mdfs

@@ -15,6 +15,7 @@ Functions mirror the C entry points:
     mdfs_pvalues(ig, k, divisions, ...) -> (p float64 [n], n_eff)       (host arrays)
     mdfs_ig_lim(k, divisions, n_eff, a) -> float
     mdfs_p_adjust(p, method)            -> adjusted float64 [n]          (host arrays)
+    mdfs_add_contrast(data, n, seed)    -> (data + contrast f32 [n_var+n][n_obj], src i32 [n])
 """
 from __future__ import annotations
 
@@ -52,7 +53,7 @@ class Params(ctypes.Structure):
 _lib = None
 SYMBOLS = ["mdfs_workspace_size", "mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts",
            "mdfs_screen_max", "mdfs_interesting_tuples", "mdfs_phase_times", "mdfs_last_error",
-           "mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust"]
+           "mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust", "mdfs_add_contrast"]
 FLAG_TIMING = 1
 PHASES = ["setup", "discretize", "sweep", "finalize"]
 
@@ -83,7 +84,8 @@ def load(path: str = LIB_PATH):
     L.mdfs_pvalues.argtypes = [vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, vp, ctypes.c_double, vp, dp]
     L.mdfs_ig_lim.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
     L.mdfs_p_adjust.argtypes = [vp, ctypes.c_int64, ctypes.c_int, vp]
-    for fn in ("mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust"):
+    L.mdfs_add_contrast.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, vp, vp, vp]
+    for fn in ("mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust", "mdfs_add_contrast"):
         getattr(L, fn).restype = ctypes.c_int
     for fn in ("mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts", "mdfs_screen_max", "mdfs_interesting_tuples"):
         getattr(L, fn).restype = ctypes.c_int
@@ -291,3 +293,15 @@ def mdfs_p_adjust(p, method: str = "BY") -> np.ndarray:
     out = np.empty_like(x)
     _check(load().mdfs_p_adjust(x.ctypes.data, x.size, ADJUST[method], out.ctypes.data))
     return out
+
+
+def mdfs_add_contrast(data: torch.Tensor, n_contrast: int, seed: int = 0):
+    """The originals followed by n_contrast contrast variables (device), and the source variable
+    of each contrast variable (host int32 numpy array)."""
+    d, _ = _dev_inputs(data)
+    n_var, n_obj = d.shape
+    out = torch.empty((n_var + int(n_contrast), n_obj), dtype=torch.float32, device=d.device)
+    src = np.zeros(max(1, int(n_contrast)), dtype=np.int32)
+    _check(load().mdfs_add_contrast(_ptr(d), n_obj, n_var, int(n_contrast), int(seed) & ((1 << 64) - 1), _ptr(out),
+                                    src.ctypes.data, _stream(d.device)))
+    return out, src[: int(n_contrast)]

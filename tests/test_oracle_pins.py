@@ -394,3 +394,33 @@ def test_ig_lim_has_p_value_alpha():
         x = sig.ig_lim(k, d, ne, a)
         p, _ = sig.pvalues(np.array([x]), k, d, n_eff=ne)
         assert math.isclose(p[0], a, rel_tol=1e-9)
+
+
+# ------------------------------------------------------------------ contrast variables
+from oracle import contrast as ctr   # noqa: E402
+
+
+def test_contrast_generator_is_splitmix64():
+    # the draws use the SplitMix64 output function: state k * gamma gives the published sequence
+    assert [ctr.fin(k * ctr.GAMMA) for k in (1, 2, 3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                                            0x06C45D188009454F]
+
+
+@pytest.mark.parametrize("n_obj", [1, 2, 3, 5, 16, 17, 255, 1000, 4097])
+def test_contrast_permutation_is_a_bijection(n_obj):
+    for c in range(3):
+        perm = ctr.permutation(11, c, n_obj)
+        assert np.array_equal(np.sort(perm), np.arange(n_obj))
+
+
+def test_contrast_variables_keep_values_and_lose_order():
+    g = np.random.default_rng(8)
+    X = g.standard_normal((7, 3000)).astype(np.float32)
+    out, src = ctr.add_contrast(X, 40, seed=5)
+    assert np.array_equal(out[:7], X)
+    assert set(src.tolist()) <= set(range(7)) and len(set(src.tolist())) >= 5
+    for c in range(40):
+        row = out[7 + c]
+        assert np.array_equal(np.sort(row), np.sort(X[src[c]]))      # same values
+        r = np.corrcoef(row, X[src[c]])[0, 1]
+        assert abs(r) < 5 / np.sqrt(3000)                             # not the same order
