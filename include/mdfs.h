@@ -129,6 +129,15 @@ int mdfs_discretize(const mdfs_params *prm, const float *data, uint8_t *codes, v
 int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint8_t *y, float *ig_max,
                 int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream);
 
+/* mdfs_max_ig from caller-supplied codes instead of the randomised discretisation, so that a
+ * discretised dataset can stay resident (or come from another discretiser): the same sweep,
+ * outputs, ties and error behaviour.  range and seed of `prm` are unused.
+ *   codes : device uint8 [n_disc][n_var][n_obj], each in [0, divisions]; a larger value makes the
+ *           call return MDFS_E_ARG (detected on the device, reported at exit)
+ * Discretisation index disc_offset + r names codes[r] in argmax_disc. */
+int mdfs_max_ig_codes(const mdfs_params *prm, const uint8_t *codes, const uint8_t *y, float *ig_max,
+                      int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream);
+
 /* Per-class voxel counts of every pair under one discretisation, as produced by the k=2 count
  * engine (the counters N^d of section "Algorithm and implementation").  Requires k = 2 in
  * `prm`; `disc` selects the discretisation (0 <= disc < n_disc).

@@ -224,7 +224,14 @@ static int read_status(const Problem &P, Status &st)
     if (e == hipSuccess) e = hipStreamSynchronize(P.stream);
     if (e != hipSuccess) return hip_fail(e, "reading status");
     if (st.nan_flag) return fail(MDFS_E_NAN, "data holds a NaN");
+    if (st.code_flag) return fail(MDFS_E_ARG, "codes hold a value above divisions");
     return MDFS_OK;
+}
+
+// The encoding step: discretise the data, or take the caller's codes.
+static hipError_t launch_encode(const Problem &P, const float *data)
+{
+    return P.codes_in ? launch_encode_codes(P) : launch_discretize(P, data, nullptr, true);
 }
 
 // Pair sweep (k = 2) or, per discretisation, pair data then triple sweep (k = 3).
@@ -276,7 +283,7 @@ static int run_sweep(Problem &P, const float *data, const uint8_t *y, int32_t *c
     LAUNCH(launch_class_perm(P, y));
     LAUNCH(launch_tables(P));
     if (tm) tm->mark(1);
-    LAUNCH(launch_discretize(P, data, nullptr, true));
+    LAUNCH(launch_encode(P, data));
     if (tm) tm->mark(2);
     int rc = sweep_pass(P, counts, disc_sel, false);
     if (rc) return rc;
@@ -337,14 +344,15 @@ static double root_F(const Problem &P)
     return n * log(s) - (n / s) * (xlx(n0 + P.beta0) + xlx(n1 + P.beta1));
 }
 
-extern "C" int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint8_t *y, float *ig_max,
-                           int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream)
+static int max_ig_impl(const mdfs_params *prm, const float *data, const uint8_t *codes, const uint8_t *y,
+                       float *ig_max, int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream)
 {
     int rc = check_params(prm);
     if (rc) return rc;
-    if (!data || !y || !ig_max || !ws) return fail(MDFS_E_ARG, "null pointer");
+    if (!(data || codes) || !y || !ig_max || !ws) return fail(MDFS_E_ARG, "null pointer");
     Problem P;
     if ((rc = setup(prm, y, ws, ws_bytes, stream, P))) return rc;
+    P.codes_in = codes;
     if (prm->k == 1) {
         // no tuples: discretise, per-variable F in binary64, maximum over discretisations
         PhaseTimer tm((prm->flags & MDFS_FLAG_TIMING) != 0, P.stream);
@@ -352,7 +360,7 @@ extern "C" int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint
         LAUNCH(launch_init(P));
         LAUNCH(launch_class_perm(P, y));
         tm.mark(1);
-        LAUNCH(launch_discretize(P, data, nullptr, true));
+        LAUNCH(launch_encode(P, data));
         tm.mark(2);
         tm.mark(3);
         LAUNCH(launch_ig1(P, root_F(P), ig_max, argmax_disc));
@@ -373,6 +381,18 @@ extern "C" int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint
     if (st.overflow) return fail(MDFS_E_OVERFLOW, "candidate buffer overflow (%u appends)", st.n_cand);
     g_err.clear();
     return MDFS_OK;
+}
+
+extern "C" int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint8_t *y, float *ig_max,
+                           int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream)
+{
+    return max_ig_impl(prm, data, nullptr, y, ig_max, argmax, argmax_disc, ws, ws_bytes, stream);
+}
+
+extern "C" int mdfs_max_ig_codes(const mdfs_params *prm, const uint8_t *codes, const uint8_t *y, float *ig_max,
+                                 int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream)
+{
+    return max_ig_impl(prm, nullptr, codes, y, ig_max, argmax, argmax_disc, ws, ws_bytes, stream);
 }
 
 extern "C" int mdfs_pair_counts(const mdfs_params *prm, const float *data, const uint8_t *y, int32_t disc,
@@ -411,7 +431,7 @@ extern "C" int mdfs_interesting_tuples(const mdfs_params *prm, const float *data
     LAUNCH(launch_init(P));
     LAUNCH(launch_class_perm(P, y));
     LAUNCH(launch_tables(P));
-    LAUNCH(launch_discretize(P, data, nullptr, true));
+    LAUNCH(launch_encode(P, data));
     // one collect pass with every variable's threshold at ig_thr (the largest float32 not above
     // it): it appends every tuple whose float32 IG lies within the screen window of ig_thr,
     // a superset of those whose binary64 IG reaches it

@@ -38,7 +38,8 @@ struct Status {
     uint32_t n_cand;      // candidate records appended (may exceed capacity)
     uint32_t overflow;    // some append did not fit
     uint32_t n_emit;      // records written by the interesting-tuples emit pass
-    uint32_t pad0[12];
+    uint32_t code_flag;   // caller-supplied codes held a value above divisions
+    uint32_t pad0[11];
     uint32_t next_tile[16];   // per-XCD work counters of the persistent sweep (reset per pass)
     uint32_t pad[32];
 };
@@ -119,6 +120,7 @@ struct Problem {
     bool k3_mfma;                 // k = 3 on the matrix cores (else bitsets)
     int workgroups;               // persistent sweep grid (0 = the whole GPU)
     int64_t n_ablk3, n_tiles3;    // tile list of the k = 3 matrix-core sweep
+    const uint8_t *codes_in = nullptr;   // caller-supplied codes [R][p][N] replace the discretisation
     char *ws;
     hipStream_t stream;
     template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -129,6 +131,8 @@ hipError_t launch_init(const Problem &P);
 hipError_t launch_class_perm(const Problem &P, const uint8_t *y);
 hipError_t launch_tables(const Problem &P);
 hipError_t launch_discretize(const Problem &P, const float *data, uint8_t *codes, bool encode);
+// the encoding, marginals and F1 from caller-supplied codes (P.codes_in) instead of discretising
+hipError_t launch_encode_codes(const Problem &P);
 hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bool collect = false);
 // LDS bytes per workgroup of the pair sweep (max_mode: the maximum sweep, else debug/pair modes)
 size_t sweep2_lds_bytes(const Problem &P, bool max_mode);

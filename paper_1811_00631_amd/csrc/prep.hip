@@ -508,6 +508,145 @@ static hipError_t disc_launch(const Problem &P, const float *data, uint8_t *code
     return hipGetLastError();
 }
 
+// Encoding from caller-supplied codes [R][p][N] (values 0 .. C-1): one workgroup per variable,
+// per discretisation the codes gathered into class-sorted order in LDS, then the same outputs as
+// the encoding half of k_discretize (one-hot rows, bitsets, packed per-class marginals, F1).  A
+// code >= C raises the status flag (the call then fails); it matches no bin.
+template <int C>
+__global__ __launch_bounds__(DISC_THREADS) void k_encode_codes(
+    const uint8_t *__restrict__ codes, int N, int p, int R, const int32_t *__restrict__ perm, int K0pad, int N0,
+    int N1, int KB, int Kpad, int fp4, int64_t rows_pad, int8_t *__restrict__ onehot, uint32_t *__restrict__ marg,
+    float *__restrict__ F1, double *__restrict__ F1d, int64_t p_pad, double b0, double b1, Status *st,
+    uint32_t *__restrict__ bits, int64_t words_max)
+{
+    constexpr int W = C - 1;
+    extern __shared__ uint8_t cls[];        // [Kpad] codes in class-sorted order; C at padding
+    __shared__ int hist[2 * C];
+    __shared__ double fterm[C];
+    const int v = blockIdx.x;
+    const int t = threadIdx.x;
+    if (v >= p) {
+        if (!onehot) return;
+        const int nrow = KB * W * (KBLK / 4);
+        for (int rr = 0; rr < R; ++rr)
+            for (int idx = t; idx < nrow; idx += DISC_THREADS) {
+                const int kb = idx / (W * (KBLK / 4)), a = (idx / (KBLK / 4)) % W, q4 = idx % (KBLK / 4);
+                *reinterpret_cast<uint32_t *>(onehot + onehot_off(rr, (int64_t)v * W + a, kb, q4 * 4, KB, rows_pad)) = 0u;
+            }
+        return;
+    }
+    for (int r = 0; r < R; ++r) {
+        const uint8_t *cv = codes + ((int64_t)r * p + v) * N;
+        bool bad = false;
+        for (int i = t; i < Kpad; i += DISC_THREADS) {
+            const int n = perm[i];
+            const uint8_t c = n >= 0 ? cv[n] : (uint8_t)C;
+            bad |= n >= 0 && c >= C;
+            cls[i] = c;
+        }
+        if (t < 2 * C) hist[t] = 0;
+        if (bad) atomicOr(&st->code_flag, 1u);
+        __syncthreads();
+        if (onehot) {
+            const int per = fp4 ? 8 : 4;
+            for (int g = t; g < KB * (KBLK / 4); g += DISC_THREADS) {
+                const int kb = g / (KBLK / 4), q4 = g % (KBLK / 4);
+                uint32_t word[W];
+#pragma unroll
+                for (int a = 0; a < W; ++a) word[a] = 0;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    if (e >= per) break;
+                    const int c = cls[g * per + e];
+                    const uint32_t bit = fp4 ? (F4_TWO << (4 * e)) : (1u << (8 * e));
+#pragma unroll
+                    for (int a = 0; a < W; ++a) word[a] |= (c == a) ? bit : 0u;
+                }
+#pragma unroll
+                for (int a = 0; a < W; ++a)
+                    *reinterpret_cast<uint32_t *>(onehot + onehot_off(r, (int64_t)v * W + a, kb, q4 * 4, KB, rows_pad)) =
+                        word[a];
+            }
+        }
+        if (bits) {
+            const int w0 = (N0 + 31) / 32, w1 = (N1 + 31) / 32;
+            for (int idx = t; idx < (w0 + w1) * W; idx += DISC_THREADS) {
+                const int a = idx % W, wy = idx / W;
+                const int y = wy < w0 ? 0 : 1, w = y ? wy - w0 : wy;
+                const int base_ps = (y ? K0pad : 0) + 32 * w, ny = y ? N1 : N0;
+                uint32_t word = 0;
+                for (int e = 0; e < 32; ++e) {
+                    const bool hit = 32 * w + e < ny && cls[base_ps + e] == a;
+                    word |= (hit ? 1u : 0u) << e;
+                }
+                bits[((((int64_t)r * 2 + y) * words_max + w) * p_pad + v) * W + a] = word;
+            }
+        }
+        if (marg || F1) {
+            int loc[2][C];
+#pragma unroll
+            for (int a = 0; a < C; ++a) loc[0][a] = loc[1][a] = 0;
+            for (int i = t; i < Kpad; i += DISC_THREADS) {
+                const int c = cls[i], y = i >= K0pad ? 1 : 0;
+#pragma unroll
+                for (int a = 0; a < C; ++a) {
+                    loc[0][a] += (c == a && y == 0) ? 1 : 0;
+                    loc[1][a] += (c == a && y == 1) ? 1 : 0;
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < C; ++a) {
+                if (loc[0][a]) atomicAdd(&hist[a], loc[0][a]);
+                if (loc[1][a]) atomicAdd(&hist[C + a], loc[1][a]);
+            }
+            __syncthreads();
+            if (t < C) {
+                const int h0 = hist[t], h1 = hist[C + t];
+                if (marg) marg[((int64_t)r * p_pad + v) * C + t] = ((uint32_t)h1 << 16) | (uint32_t)h0;
+                const double d0 = h0, d1 = h1, n = d0 + d1;
+                double term = 0.0;
+                if (n > 0) {
+                    const double sden = n + b0 + b1;
+                    term = n * log(sden) - (n / sden) * (xlogx(d0 + b0) + xlogx(d1 + b1));
+                }
+                fterm[t] = term;
+            }
+            __syncthreads();
+            if (t == 0 && F1) {
+                double Fv = 0.0;
+                for (int a = 0; a < C; ++a) Fv += fterm[a];
+                F1[(int64_t)r * p_pad + v] = (float)Fv;
+                if (F1d) F1d[(int64_t)r * p_pad + v] = Fv;
+            }
+        }
+        __syncthreads();   // cls and hist are rewritten for the next discretisation
+    }
+}
+
+template <int C>
+static hipError_t encode_codes_launch(const Problem &P)
+{
+    const Layout &L = P.L;
+    auto kern = k_encode_codes<C>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)L.p_pad), dim3(DISC_THREADS), (size_t)P.Kpad, P.stream, P.codes_in,
+                       (int)L.N, (int)L.p, L.R, P.at<int32_t>(L.perm), P.K0pad, P.N0, P.N1, P.KB, P.Kpad,
+                       P.fp4 ? 1 : 0, L.rows_pad, L.k != 1 ? P.at<int8_t>(L.onehot) : nullptr,
+                       P.at<uint32_t>(L.marg), P.at<float>(L.F1), L.k == 1 ? P.at<double>(L.F1d) : nullptr, L.p_pad,
+                       P.beta0, P.beta1, P.at<Status>(L.status), L.k == 3 ? P.at<uint32_t>(L.bits) : nullptr,
+                       L.words_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode_codes(const Problem &P)
+{
+    switch (P.L.C) {
+    case 2: return encode_codes_launch<2>(P);
+    case 3: return encode_codes_launch<3>(P);
+    case 5: return encode_codes_launch<5>(P);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_discretize(const Problem &P, const float *data, uint8_t *codes, bool encode)
 {
     switch (P.L.C) {

@@ -53,7 +53,8 @@ class Params(ctypes.Structure):
 _lib = None
 SYMBOLS = ["mdfs_workspace_size", "mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts",
            "mdfs_screen_max", "mdfs_interesting_tuples", "mdfs_phase_times", "mdfs_last_error",
-           "mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust", "mdfs_add_contrast"]
+           "mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust", "mdfs_add_contrast",
+           "mdfs_max_ig_codes"]
 FLAG_TIMING = 1
 PHASES = ["setup", "discretize", "sweep", "finalize"]
 
@@ -72,6 +73,7 @@ def load(path: str = LIB_PATH):
     L.mdfs_workspace_size.restype = sz
     L.mdfs_discretize.argtypes = [P, vp, vp, vp, sz, vp]
     L.mdfs_max_ig.argtypes = [P, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.mdfs_max_ig_codes.argtypes = [P, vp, vp, vp, vp, vp, vp, sz, vp]
     L.mdfs_pair_counts.argtypes = [P, vp, vp, ctypes.c_int32, vp, vp, sz, vp]
     L.mdfs_screen_max.argtypes = [P, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
     L.mdfs_interesting_tuples.argtypes = [P, vp, vp, ctypes.c_double, vp, vp, vp, vp, ctypes.c_int64,
@@ -87,7 +89,7 @@ def load(path: str = LIB_PATH):
     L.mdfs_add_contrast.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, vp, vp, vp]
     for fn in ("mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust", "mdfs_add_contrast"):
         getattr(L, fn).restype = ctypes.c_int
-    for fn in ("mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts", "mdfs_screen_max", "mdfs_interesting_tuples"):
+    for fn in ("mdfs_discretize", "mdfs_max_ig", "mdfs_max_ig_codes", "mdfs_pair_counts", "mdfs_screen_max", "mdfs_interesting_tuples"):
         getattr(L, fn).restype = ctypes.c_int
     _lib = L
     return L
@@ -193,6 +195,26 @@ def mdfs_max_ig(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_d
     ad = torch.empty(n_var, dtype=torch.int32, device=data.device)
     _check(load().mdfs_max_ig(ctypes.byref(prm), _ptr(data), _ptr(y), _ptr(ig), _ptr(am), _ptr(ad), _ptr(ws),
                               ws.numel(), strm))
+    return ig, am, ad
+
+
+def mdfs_max_ig_codes(codes: torch.Tensor, y: torch.Tensor, k: int, divisions: int, pseudocount: float = 0.25,
+                      disc_offset: int = 0, engine: str = "auto", workgroups: int = 0):
+    """mdfs_max_ig from device codes uint8 [n_disc][n_var][n_obj] (values 0..divisions)."""
+    if not (isinstance(codes, torch.Tensor) and codes.is_cuda and codes.dtype == torch.uint8 and codes.dim() == 3):
+        raise ValueError("codes must be a CUDA uint8 tensor [n_disc][n_var][n_obj]")
+    codes = codes.contiguous()
+    n_disc, n_var, n_obj = codes.shape
+    if not (y.is_cuda and y.dtype == torch.uint8 and y.dim() == 1 and y.numel() == n_obj):
+        raise ValueError("y must be a CUDA uint8 tensor [n_obj]")
+    y = y.contiguous()
+    prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, 0.0, pseudocount, 0, engine, 0, workgroups)
+    ws = workspace_for(prm, codes.device)
+    ig = torch.empty(n_var, dtype=torch.float32, device=codes.device)
+    am = torch.empty((n_var, k - 1), dtype=torch.int32, device=codes.device)
+    ad = torch.empty(n_var, dtype=torch.int32, device=codes.device)
+    _check(load().mdfs_max_ig_codes(ctypes.byref(prm), _ptr(codes), _ptr(y), _ptr(ig), _ptr(am), _ptr(ad), _ptr(ws),
+                                    ws.numel(), _stream(codes.device)))
     return ig, am, ad
 
 
