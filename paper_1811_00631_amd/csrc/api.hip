@@ -86,7 +86,7 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
 {
     if (!prm) return fail(MDFS_E_ARG, "params is NULL");
     if (prm->flags & ~MDFS_FLAG_TIMING) return fail(MDFS_E_ARG, "unknown flag bits 0x%x", prm->flags);
-    if (prm->k < 1 || prm->k > 3) return fail(MDFS_E_K, "k=%d: supported tuple sizes are 1, 2 and 3", prm->k);
+    if (prm->k < 1 || prm->k > 4) return fail(MDFS_E_K, "k=%d: supported tuple sizes are 1 to 4", prm->k);
     if (prm->divisions != 1 && prm->divisions != 2 && prm->divisions != 4)
         return fail(MDFS_E_DIV, "divisions=%d: supported are 1, 2, 4", prm->divisions);
     if (prm->n_obj < 2 || prm->n_obj < prm->divisions + 1)
@@ -95,6 +95,12 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
     if (prm->n_var < prm->k) return fail(MDFS_E_ARG, "n_var=%lld < k", (long long)prm->n_var);
     if (prm->k == 3 && prm->n_var > MAX_K3_VARS)
         return fail(MDFS_E_LIMIT, "k=3 with n_var=%lld > %d", (long long)prm->n_var, MAX_K3_VARS);
+    if (prm->k == 4 && prm->divisions > 2)
+        return fail(MDFS_E_LIMIT, "k=4 is built for divisions 1 and 2 (2 or 3 classes)");
+    if (prm->k == 4 && prm->n_var > MAX_K4_VARS)
+        return fail(MDFS_E_LIMIT, "k=4 with n_var=%lld > %d", (long long)prm->n_var, MAX_K4_VARS);
+    if (sweep && prm->k == 4 && prm->engine != MDFS_ENGINE_AUTO && prm->engine != MDFS_ENGINE_BITSET)
+        return fail(MDFS_E_LIMIT, "k=4 runs on the bitset engine");
     if (sweep && prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA)
         return fail(MDFS_E_LIMIT, "k=3 on the matrix cores uses the fp4 encoding (engine mfma_fp4)");
     if (sweep && prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA_FP4 && prm->divisions != 2)
@@ -201,6 +207,10 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
         P.err_bound = screen_err_bound(N, P.beta0, P.beta1, C * C);
         // k = 3: the triple's own F (C^3 voxels) plus the float32 F of the parent pair
         if (prm->k == 3) P.err_bound += screen_err_bound(N, P.beta0, P.beta1, C * C * C);
+        // k = 4: the quadruple's F (C^4 voxels) and a sub-triple's float32 F (C^3 voxels)
+        if (prm->k == 4)
+            P.err_bound = screen_err_bound(N, P.beta0, P.beta1, C * C * C * C) +
+                          screen_err_bound(N, P.beta0, P.beta1, C * C * C);
         // k = 3 engine: matrix cores for three classes in the fp4 encoding (auto or asked for)
         P.k3_mfma = prm->k == 3 && prm->divisions == 2 && P.fp4 &&
                     (prm->engine == MDFS_ENGINE_AUTO || prm->engine == MDFS_ENGINE_MFMA_FP4);
@@ -240,6 +250,8 @@ static int sweep_pass(const Problem &P, int32_t *counts, int disc_sel, bool coll
     if (P.L.k == 2) {
         LAUNCH(launch_reset_queue(P));
         LAUNCH(launch_sweep2(P, counts, disc_sel, collect));
+    } else if (P.L.k == 4) {
+        for (int r = 0; r < P.L.R; ++r) LAUNCH(launch_sweep4(P, r, collect));
     } else {
         for (int r = 0; r < P.L.R; ++r) {
             LAUNCH(launch_reset_queue(P));
@@ -420,6 +432,7 @@ extern "C" int mdfs_interesting_tuples(const mdfs_params *prm, const float *data
     int rc = check_params(prm);
     if (rc) return rc;
     if (prm->k == 1) return fail(MDFS_E_K, "k=1 has no tuples (mdfs_max_ig covers it)");
+    if (prm->k == 4) return fail(MDFS_E_K, "k=4 interesting tuples are not built (mdfs_max_ig covers k=4)");
     if (!data || !y || !ws || !n_found) return fail(MDFS_E_ARG, "null pointer");
     if (max_out < 0 || (max_out > 0 && (!var || !partners || !disc || !ig)))
         return fail(MDFS_E_ARG, "max_out=%lld with a null output array", (long long)max_out);

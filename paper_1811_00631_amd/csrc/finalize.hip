@@ -70,7 +70,7 @@ template <int C, int K>
 __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a)
 {
     constexpr int W = C - 1;
-    constexpr int NC = (K == 2) ? C * C : C * C * C;
+    constexpr int NC = (K == 2) ? C * C : (K == 3) ? C * C * C : C * C * C * C;
     const int lane = threadIdx.x & 63;
     const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -82,9 +82,10 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a)
             if (lane == 0) a.ig64[ci] = -INFINITY;
             continue;
         }
-        int64_t m1, m2 = 0;
+        int64_t m1, m2 = 0, m3 = 0;
         if (K == 2) m1 = x.partner;
-        else { m1 = x.partner >> 16; m2 = x.partner & 0xffff; }
+        else if (K == 3) { m1 = x.partner >> 16; m2 = x.partner & 0xffff; }
+        else { m1 = x.partner >> 20; m2 = (x.partner >> 10) & 1023; m3 = x.partner & 1023; }
         int cnt[2][NC];
 #pragma unroll
         for (int d = 0; d < 2; ++d)
@@ -96,7 +97,8 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a)
             const bool valid = c0 ? (ps < a.N0) : (ps - a.K0pad < a.N1);
             int cell = code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, x.v, e, a.fp4) * C +
                        code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, m1, e, a.fp4);
-            if (K == 3) cell = cell * C + code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, m2, e, a.fp4);
+            if (K >= 3) cell = cell * C + code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, m2, e, a.fp4);
+            if (K == 4) cell = cell * C + code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, m3, e, a.fp4);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 cnt[0][c] += (valid && c0 && cell == c) ? 1 : 0;
@@ -151,7 +153,11 @@ __global__ void k_output(int64_t p, int k, int disc_offset, const uint64_t *max6
     if (argmax) {
         const uint32_t pt = (uint32_t)key;
         if (k == 2) argmax[v] = bad ? -1 : (int32_t)pt;
-        else {
+        else if (k == 4) {
+            argmax[3 * v] = bad ? -1 : (int32_t)(pt >> 20);
+            argmax[3 * v + 1] = bad ? -1 : (int32_t)((pt >> 10) & 1023);
+            argmax[3 * v + 2] = bad ? -1 : (int32_t)(pt & 1023);
+        } else {
             argmax[2 * v] = bad ? -1 : (int32_t)(pt >> 16);
             argmax[2 * v + 1] = bad ? -1 : (int32_t)(pt & 0xffff);
         }
@@ -198,6 +204,12 @@ static hipError_t rescore_all(const Problem &P, const RescoreArgs &a)
         case 2: rescore_launch<2, 2>(P, a); break;
         case 3: rescore_launch<3, 2>(P, a); break;
         case 5: rescore_launch<5, 2>(P, a); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else if (L.k == 4) {
+        switch (L.C) {
+        case 2: rescore_launch<2, 4>(P, a); break;
+        case 3: rescore_launch<3, 4>(P, a); break;
         default: return hipErrorInvalidValue;
         }
     } else {

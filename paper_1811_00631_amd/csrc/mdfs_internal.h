@@ -31,6 +31,7 @@ constexpr int VAR_PAD = 128;
 constexpr int MAX_NOBJ = 16384;
 constexpr int MAX_CLASS_OBJ = 32767;
 constexpr int MAX_K3_VARS = 4096;
+constexpr int MAX_K4_VARS = 1024;      // k = 4: three partners packed 10 bits each
 
 // Status words at the start of the workspace.
 struct Status {
@@ -140,6 +141,8 @@ constexpr size_t LDS_MAX = 160 * 1024;
 hipError_t launch_reset_candidates(const Problem &P);
 hipError_t launch_pairs(const Problem &P, int r);
 hipError_t launch_sweep3(const Problem &P, int r, bool collect);
+// k = 4 bitset sweep of discretisation r (sweep4.hip)
+hipError_t launch_sweep4(const Problem &P, int r, bool collect);
 hipError_t launch_sweep3m(const Problem &P, int r, bool collect);
 size_t sweep3m_lds_bytes(const Problem &P);
 // host-side tile list of the k = 3 matrix-core sweep (first tile per A block, A blocks)

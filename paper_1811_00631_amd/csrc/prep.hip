@@ -48,7 +48,11 @@ Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
     L.ovf = take(sizeof(uint32_t) * L.p_pad);
     L.cand = take(sizeof(Cand) * L.cap);
     L.ig64 = take(sizeof(double) * L.cap);
-    if (k == 3) {
+    if (k == 4) {
+        // bitsets only: the quadruple sweep counts every cell directly
+        L.bits = take(sizeof(uint32_t) * (size_t)R * 2 * L.words_max * L.p_pad * L.W);
+        L.ptab = L.F2 = L.a3pref = L.a3blk = o;
+    } else if (k == 3) {
         L.bits = take(sizeof(uint32_t) * (size_t)R * 2 * L.words_max * L.p_pad * L.W);
         L.ptab = take(sizeof(uint32_t) * (size_t)L.p_pad * L.p_pad * L.W * L.W);
         L.F2 = take(sizeof(float) * (size_t)L.p_pad * L.p_pad);
@@ -504,7 +508,7 @@ static hipError_t disc_launch(const Problem &P, const float *data, uint8_t *code
                        P.Kpad, P.fp4 ? 1 : 0, L.rows_pad, codes, (encode && L.k != 1) ? P.at<int8_t>(L.onehot) : nullptr,
                        encode ? P.at<uint32_t>(L.marg) : nullptr, encode ? P.at<float>(L.F1) : nullptr,
                        (encode && L.k == 1) ? P.at<double>(L.F1d) : nullptr, L.p_pad, P.beta0, P.beta1, P.at<Status>(L.status),
-                       (encode && L.k == 3) ? P.at<uint32_t>(L.bits) : nullptr, L.words_max);
+                       (encode && L.k >= 3) ? P.at<uint32_t>(L.bits) : nullptr, L.words_max);
     return hipGetLastError();
 }
 
@@ -632,7 +636,7 @@ static hipError_t encode_codes_launch(const Problem &P)
                        (int)L.N, (int)L.p, L.R, P.at<int32_t>(L.perm), P.K0pad, P.N0, P.N1, P.KB, P.Kpad,
                        P.fp4 ? 1 : 0, L.rows_pad, L.k != 1 ? P.at<int8_t>(L.onehot) : nullptr,
                        P.at<uint32_t>(L.marg), P.at<float>(L.F1), L.k == 1 ? P.at<double>(L.F1d) : nullptr, L.p_pad,
-                       P.beta0, P.beta1, P.at<Status>(L.status), L.k == 3 ? P.at<uint32_t>(L.bits) : nullptr,
+                       P.beta0, P.beta1, P.at<Status>(L.status), L.k >= 3 ? P.at<uint32_t>(L.bits) : nullptr,
                        L.words_max);
     return hipGetLastError();
 }

@@ -45,7 +45,7 @@ def test_workspace_size_valid_and_monotone():
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(k=4), -3), (dict(k=0), -3), (dict(divisions=3), -4), (dict(divisions=0), -4),
+    (dict(k=5), -3), (dict(k=0), -3), (dict(k=4, divisions=4), -8), (dict(k=4, engine="mfma"), -8), (dict(divisions=3), -4), (dict(divisions=0), -4),
     (dict(n_obj=2, divisions=2), -1), (dict(n_obj=20000), -8), (dict(range_=1.5), -1),
     (dict(range_=-0.1), -1), (dict(pseudocount=-1.0), -1), (dict(n_disc=0), -1),
     (dict(disc_offset=-1), -1), (dict(n_var=1), -1), (dict(workgroups=4), -1), (dict(workgroups=5000), -1), (dict(k=3, engine="mfma_fp4", divisions=4), -8),

@@ -1,0 +1,85 @@
+"""k = 4 sweep (bitset engine, two or three classes) on the GPU through the C ABI, against the
+FP64 oracle."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1811_00631_amd import workloads
+
+from test_gpu_k2 import assert_ig_parity, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def run4(mdfs, w, n_disc=None, divisions=None, disc_offset=0, engine="auto"):
+    data, y = to_dev(w)
+    out = mdfs.mdfs_max_ig(data, y, 4, w.divisions if divisions is None else divisions,
+                           w.n_disc if n_disc is None else n_disc, w.xi, w.range_, w.seed, disc_offset,
+                           engine=engine)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in out]
+
+
+CASES4 = {
+    "d3": lambda: workloads.xor_small(seed=61, n_obj=400, n_var=26, n_disc=2),
+    "d2_imbalanced": lambda: dataclasses.replace(workloads.null_data(62, 333, 23, ones=90), divisions=1, n_disc=2),
+    "d3_wide_words": lambda: workloads.xor_small(seed=63, n_obj=1100, n_var=17, n_disc=1),
+    "four_vars": lambda: workloads.xor_small(seed=64, n_obj=200, n_var=4, n_disc=3),
+    "tiny_n": lambda: workloads.xor_small(seed=65, n_obj=7, n_var=9, n_disc=2),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES4))
+def test_k4_matches_oracle(mdfs_gpu, name):
+    w = CASES4[name]()
+    print(f"k4 {name} N={w.n_obj} p={w.n_var} d={w.divisions + 1} R={w.n_disc}", flush=True)
+    got = run4(mdfs_gpu, w)
+    ref = oracle.max_ig_all(w.data, w.y, 4, w.divisions, w.n_disc, w.range_, w.xi, w.seed, n_threads=8)
+    assert_ig_parity(*got, ref, name)
+
+
+def test_k4_finds_a_planted_parity_quadruple(mdfs_gpu):
+    # y = xor of the signs of x0..x3: invisible to every triple, found by the quadruple sweep
+    g = np.random.default_rng(66)
+    n, p = 1200, 30
+    X = g.standard_normal((p, n)).astype(np.float32)
+    y = ((X[0] > 0) ^ (X[1] > 0) ^ (X[2] > 0) ^ (X[3] > 0)).astype(np.uint8)
+    w = workloads.Workload("parity4", X, y, 2, 2, 1, 0.5, 0.25, 3, {})
+    print("k4 planted", flush=True)
+    ig, am, ad = run4(mdfs_gpu, w, divisions=1)
+    top = set(np.argsort(-ig)[:4].tolist())
+    assert top == {0, 1, 2, 3}
+    assert am[0].tolist() == [1, 2, 3]
+    assert ig[:4].min() > 10 * np.median(ig[4:])
+
+
+def test_k4_collect_pass(mdfs_gpu, monkeypatch):
+    w = workloads.xor_small(seed=67, n_obj=300, n_var=22, n_disc=2)
+    monkeypatch.setenv("MDFS_TEST_CAP", str(3 * w.n_var))
+    print("k4 collect pass", flush=True)
+    got = run4(mdfs_gpu, w)
+    monkeypatch.delenv("MDFS_TEST_CAP")
+    ref = oracle.max_ig_all(w.data, w.y, 4, w.divisions, w.n_disc, w.range_, w.xi, w.seed, n_threads=8)
+    assert_ig_parity(*got, ref, "k4 collect pass")
+
+
+def test_k4_limits(mdfs_gpu):
+    # checked on the host by the C entry point before any pointer is used
+    import ctypes
+    lib = mdfs_gpu.load()
+    null = ctypes.c_void_p(0)
+    for kw, code in ((dict(divisions=4), -8), (dict(engine="mfma"), -8), (dict(engine="mfma_fp4"), -8),
+                     (dict(n_var=1025), -8)):
+        base = dict(n_obj=100, n_var=8, k=4, divisions=2, n_disc=1)
+        base.update(kw)
+        prm = mdfs_gpu.make_params(**base)
+        rc = lib.mdfs_max_ig(ctypes.byref(prm), null, null, null, null, null, null, 0, null)
+        assert rc == code, (kw, lib.mdfs_last_error())
+    w = workloads.xor_small(seed=68, n_obj=100, n_var=8)
+    data, y = to_dev(w)
+    with pytest.raises(mdfs_gpu.MdfsError) as e:
+        mdfs_gpu.mdfs_interesting_tuples(data, y, 4, 2, 1, 0.0)
+    assert e.value.code == -3
