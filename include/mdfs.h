@@ -131,6 +131,24 @@ int mdfs_discretize(const mdfs_params *prm, const float *data, uint8_t *codes, v
 int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint8_t *y, float *ig_max,
                 int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream);
 
+/* mdfs_max_ig without any host synchronisation, for callers that enqueue many calls or capture
+ * the launch sequence in a HIP graph (the batching of many problems behind one replay):
+ *   n1     : number of objects with y = 1 (known to the caller, e.g. when y was uploaded); the
+ *            launch is sized from it and y is checked against it on the device.  A mismatch or a
+ *            y value outside {0, 1} writes nothing and is reported by mdfs_check_status (MDFS_E_Y).
+ *   other arguments as mdfs_max_ig; outputs are defined once the stream reaches them.
+ * Nothing is read back: the candidate-overflow collect pass is always enqueued and exits on the
+ * device when not needed; NaN data, bad y and a final overflow are reported by mdfs_check_status.
+ * MDFS_FLAG_TIMING is refused; k = 3 runs on the bitset engine (engine mfma_fp4: MDFS_E_LIMIT).
+ * Argument errors are returned before anything is enqueued, as for the other calls. */
+int mdfs_max_ig_async(const mdfs_params *prm, const float *data, const uint8_t *y, int64_t n1, float *ig_max,
+                      int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream);
+
+/* Status of the last call that used workspace `ws` with parameters `prm` (synchronises `stream`):
+ * MDFS_OK, or MDFS_E_Y / MDFS_E_NAN / MDFS_E_ARG (codes out of range) / MDFS_E_OVERFLOW as the
+ * device flagged it. */
+int mdfs_check_status(const mdfs_params *prm, const void *ws, size_t ws_bytes, void *stream);
+
 /* mdfs_max_ig from caller-supplied codes instead of the randomised discretisation, so that a
  * discretised dataset can stay resident (or come from another discretiser): the same sweep,
  * outputs, ties and error behaviour.  range and seed of `prm` are unused.

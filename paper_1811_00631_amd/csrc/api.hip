@@ -148,7 +148,7 @@ static double screen_err_bound(int64_t N, double b0, double b1, int V)
 
 // Read and validate the decision, then fill in everything the launches need.
 static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_bytes, void *stream,
-                 Problem &P)
+                 Problem &P, int64_t n1_given = -1)
 {
     P = Problem{};
     P.L = layout_of(prm);
@@ -166,16 +166,19 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
     P.range = prm->range;
     P.seed = prm->seed;
     const int64_t N = prm->n_obj;
-    if (y) {
+    int64_t n1 = n1_given;
+    if (y && n1 < 0) {
         std::vector<uint8_t> hy((size_t)N);
         hipError_t e = hipMemcpyAsync(hy.data(), y, (size_t)N, hipMemcpyDeviceToHost, P.stream);
         if (e == hipSuccess) e = hipStreamSynchronize(P.stream);
         if (e != hipSuccess) return hip_fail(e, "reading y");
-        int64_t n1 = 0;
+        n1 = 0;
         for (int64_t n = 0; n < N; ++n) {
             if (hy[n] > 1) return fail(MDFS_E_Y, "y[%lld]=%d is not 0 or 1", (long long)n, (int)hy[n]);
             n1 += hy[n];
         }
+    }
+    if (y) {
         const int64_t n0 = N - n1;
         if (n0 == 0 || n1 == 0) return fail(MDFS_E_Y, "decision has a single class");
         if (n0 > MAX_CLASS_OBJ || n1 > MAX_CLASS_OBJ)
@@ -255,7 +258,7 @@ static int sweep_pass(const Problem &P, int32_t *counts, int disc_sel, bool coll
     } else {
         for (int r = 0; r < P.L.R; ++r) {
             LAUNCH(launch_reset_queue(P));
-            LAUNCH(launch_pairs(P, r));
+            LAUNCH(launch_pairs(P, r, collect));
             if (P.k3_mfma) LAUNCH(launch_sweep3m(P, r, collect));
             else LAUNCH(launch_sweep3(P, r, collect));
         }
@@ -306,7 +309,8 @@ static int run_sweep(Problem &P, const float *data, const uint8_t *y, int32_t *c
     rc = read_status(P, st);
     if (rc) return rc;
     if (st.overflow) {
-        LAUNCH(launch_reset_candidates(P));
+        LAUNCH(launch_collect_decide(P, false));
+        LAUNCH(launch_reset_candidates(P, true));
         rc = sweep_pass(P, nullptr, -1, true);
         if (rc) return rc;
     }
@@ -407,6 +411,59 @@ extern "C" int mdfs_max_ig_codes(const mdfs_params *prm, const uint8_t *codes, c
     return max_ig_impl(prm, nullptr, codes, y, ig_max, argmax, argmax_disc, ws, ws_bytes, stream);
 }
 
+extern "C" int mdfs_max_ig_async(const mdfs_params *prm, const float *data, const uint8_t *y, int64_t n1,
+                                 float *ig_max, int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes,
+                                 void *stream)
+{
+    int rc = check_params(prm);
+    if (rc) return rc;
+    if (!data || !y || !ig_max || !ws) return fail(MDFS_E_ARG, "null pointer");
+    if (prm->flags & MDFS_FLAG_TIMING) return fail(MDFS_E_ARG, "timing reads events back: not in the asynchronous call");
+    if (n1 < 1 || n1 >= prm->n_obj) return fail(MDFS_E_Y, "n1=%lld: both classes must be non-empty", (long long)n1);
+    if (prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA_FP4)
+        return fail(MDFS_E_LIMIT, "k=3 on the matrix cores prepares its tile list on the host: not asynchronous");
+    Problem P;
+    if ((rc = setup(prm, y, ws, ws_bytes, stream, P, n1))) return rc;
+    P.k3_mfma = false;   // the bitset engine needs no host-prepared tile list
+    LAUNCH(launch_init(P));
+    LAUNCH(launch_class_perm(P, y, n1));
+    if (prm->k == 1) {
+        LAUNCH(launch_encode(P, data));
+        LAUNCH(launch_ig1(P, root_F(P), ig_max, argmax_disc));
+    } else {
+        LAUNCH(launch_tables(P));
+        LAUNCH(launch_encode(P, data));
+        if ((rc = sweep_pass(P, nullptr, -1, false))) return rc;
+        // the collect pass is always enqueued; its kernels exit at once unless an append overflowed
+        LAUNCH(launch_collect_decide(P, false));
+        LAUNCH(launch_reset_candidates(P, true));
+        if ((rc = sweep_pass(P, nullptr, -1, true))) return rc;
+        LAUNCH(launch_finalize(P, ig_max, argmax, argmax_disc));
+    }
+    g_err.clear();
+    return MDFS_OK;
+}
+
+extern "C" int mdfs_check_status(const mdfs_params *prm, const void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_params(prm, false);
+    if (rc) return rc;
+    if (!ws) return fail(MDFS_E_ARG, "null pointer");
+    const Layout L = layout_of(prm);
+    if (ws_bytes < L.total) return fail(MDFS_E_NOMEM, "workspace %zu bytes < required %zu", ws_bytes, L.total);
+    Status st;
+    hipError_t e = hipMemcpyAsync(&st, static_cast<const char *>(ws) + L.status, sizeof(Status), hipMemcpyDeviceToHost,
+                                  static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "reading status");
+    if (st.y_flag) return fail(MDFS_E_Y, "y disagrees with n1 or holds a value other than 0 and 1");
+    if (st.nan_flag) return fail(MDFS_E_NAN, "data holds a NaN");
+    if (st.code_flag) return fail(MDFS_E_ARG, "codes hold a value above divisions");
+    if (st.overflow) return fail(MDFS_E_OVERFLOW, "candidate buffer overflow (%u appends)", st.n_cand);
+    g_err.clear();
+    return MDFS_OK;
+}
+
 extern "C" int mdfs_pair_counts(const mdfs_params *prm, const float *data, const uint8_t *y, int32_t disc,
                                 int32_t *counts, void *ws, size_t ws_bytes, void *stream)
 {
@@ -451,6 +508,7 @@ extern "C" int mdfs_interesting_tuples(const mdfs_params *prm, const float *data
     float t = (float)ig_thr;
     if ((double)t > ig_thr) t = nextafterf(t, -INFINITY);
     LAUNCH(launch_fill_g(P, f32_key(t)));
+    LAUNCH(launch_collect_decide(P, true));
     if ((rc = sweep_pass(P, nullptr, -1, true))) return rc;
     Status st;
     if ((rc = read_status(P, st))) return rc;

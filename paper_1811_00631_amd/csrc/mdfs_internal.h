@@ -40,7 +40,9 @@ struct Status {
     uint32_t overflow;    // some append did not fit
     uint32_t n_emit;      // records written by the interesting-tuples emit pass
     uint32_t code_flag;   // caller-supplied codes held a value above divisions
-    uint32_t pad0[11];
+    uint32_t collect_go;  // the gated collect pass runs (set on the device before it)
+    uint32_t y_flag;      // y disagreed with the class-1 count given to an asynchronous call
+    uint32_t pad0[9];
     uint32_t next_tile[16];   // per-XCD work counters of the persistent sweep (reset per pass)
     uint32_t pad[32];
 };
@@ -129,7 +131,9 @@ struct Problem {
 
 // ---- launchers (each returns hipSuccess or the launch error)
 hipError_t launch_init(const Problem &P);
-hipError_t launch_class_perm(const Problem &P, const uint8_t *y);
+// n1_check >= 0: y is also checked on the device against that class-1 count (y_flag on mismatch,
+// then nothing is written)
+hipError_t launch_class_perm(const Problem &P, const uint8_t *y, int64_t n1_check = -1);
 hipError_t launch_tables(const Problem &P);
 hipError_t launch_discretize(const Problem &P, const float *data, uint8_t *codes, bool encode);
 // the encoding, marginals and F1 from caller-supplied codes (P.codes_in) instead of discretising
@@ -138,8 +142,11 @@ hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bo
 // LDS bytes per workgroup of the pair sweep (max_mode: the maximum sweep, else debug/pair modes)
 size_t sweep2_lds_bytes(const Problem &P, bool max_mode);
 constexpr size_t LDS_MAX = 160 * 1024;
-hipError_t launch_reset_candidates(const Problem &P);
-hipError_t launch_pairs(const Problem &P, int r);
+// gated: only when the collect pass will run (Status::collect_go)
+hipError_t launch_reset_candidates(const Problem &P, bool gated = false);
+// Status::collect_go = force ? 1 : (a candidate append overflowed)
+hipError_t launch_collect_decide(const Problem &P, bool force);
+hipError_t launch_pairs(const Problem &P, int r, bool gated = false);
 hipError_t launch_sweep3(const Problem &P, int r, bool collect);
 // k = 4 bitset sweep of discretisation r (sweep4.hip)
 hipError_t launch_sweep4(const Problem &P, int r, bool collect);

@@ -84,8 +84,9 @@ __global__ void k_init(Status *st, uint32_t *G32, uint64_t *max64, uint64_t *key
 }
 
 // Before a collect pass: empty the candidate buffer and the overflow marks, keep the maxima.
-__global__ void k_reset_candidates(Status *st, uint32_t *ovf, int64_t p_pad)
+__global__ void k_reset_candidates(Status *st, uint32_t *ovf, int64_t p_pad, int gated)
 {
+    if (gated && st->collect_go == 0) return;
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i == 0) { st->n_cand = 0; st->overflow = 0; }
     for (int64_t v = i; v < p_pad; v += (int64_t)gridDim.x * blockDim.x) ovf[v] = 0u;
@@ -114,10 +115,21 @@ hipError_t launch_reset_queue(const Problem &P)
     return hipGetLastError();
 }
 
-hipError_t launch_reset_candidates(const Problem &P)
+hipError_t launch_reset_candidates(const Problem &P, bool gated)
 {
     hipLaunchKernelGGL(k_reset_candidates, dim3(64), dim3(256), 0, P.stream, P.at<Status>(P.L.status),
-                       P.at<uint32_t>(P.L.ovf), P.L.p_pad);
+                       P.at<uint32_t>(P.L.ovf), P.L.p_pad, gated ? 1 : 0);
+    return hipGetLastError();
+}
+
+__global__ void k_collect_decide(Status *st, int force)
+{
+    if (threadIdx.x == 0) st->collect_go = (force || st->overflow) ? 1u : 0u;
+}
+
+hipError_t launch_collect_decide(const Problem &P, bool force)
+{
+    hipLaunchKernelGGL(k_collect_decide, dim3(1), dim3(64), 0, P.stream, P.at<Status>(P.L.status), force ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -137,15 +149,19 @@ hipError_t launch_init(const Problem &P)
 // One workgroup: pos[n] = position of object n in the class-sorted order (class 0 first, each
 // class in original order, class 1 starting at K0pad); perm[position] = object or -1 (padding).
 __global__ __launch_bounds__(1024) void k_class_perm(const uint8_t *__restrict__ y, int N, int K0pad,
-                                                     int Kpad, int32_t *pos, int32_t *perm)
+                                                     int Kpad, int32_t *pos, int32_t *perm, int64_t n1_check,
+                                                     Status *st)
 {
     __shared__ int s1[1024];
     const int t = threadIdx.x, T = blockDim.x;
     for (int i = t; i < Kpad; i += T) perm[i] = -1;
     const int chunk = (N + T - 1) / T;
     const int lo = t * chunk, hi = min(N, lo + chunk);
-    int ones = 0;
-    for (int n = lo; n < hi; ++n) ones += y[n] != 0;
+    int ones = 0, bad = 0;
+    for (int n = lo; n < hi; ++n) {
+        ones += y[n] != 0;
+        bad |= y[n] > 1;
+    }
     s1[t] = ones;
     __syncthreads();
     // exclusive scan (Hillis-Steele on a copy is enough for 1024 entries)
@@ -157,7 +173,15 @@ __global__ __launch_bounds__(1024) void k_class_perm(const uint8_t *__restrict__
     }
     int ones_before = s1[t] - ones;
     int zeros_before = (lo < N ? lo : N) - ones_before;
-    __syncthreads();
+    const int total_ones = s1[T - 1];
+    const int any_bad = __syncthreads_or(bad);
+    if (n1_check >= 0 && (any_bad || total_ones != n1_check)) {
+        // the class sizes the launch was sized for are wrong: flag it and write no positions
+        // (perm stays all padding, so the sweeps count nothing and touch nothing out of range)
+        if (t == 0) st->y_flag = 1u;
+        return;
+    }
+    __syncthreads();   // every perm[i] = -1 above is visible before the positions are written
     for (int n = lo; n < hi; ++n) {
         int p;
         if (y[n]) p = K0pad + ones_before++;
@@ -167,10 +191,10 @@ __global__ __launch_bounds__(1024) void k_class_perm(const uint8_t *__restrict__
     }
 }
 
-hipError_t launch_class_perm(const Problem &P, const uint8_t *y)
+hipError_t launch_class_perm(const Problem &P, const uint8_t *y, int64_t n1_check)
 {
     hipLaunchKernelGGL(k_class_perm, dim3(1), dim3(1024), 0, P.stream, y, (int)P.L.N, P.K0pad,
-                       P.Kpad, P.at<int32_t>(P.L.pos), P.at<int32_t>(P.L.perm));
+                       P.Kpad, P.at<int32_t>(P.L.pos), P.at<int32_t>(P.L.perm), n1_check, P.at<Status>(P.L.status));
     return hipGetLastError();
 }
 

@@ -70,6 +70,7 @@ struct Sweep2Args {
     int32_t *counts_out;     // debug: full tables of discretisation disc_sel
     int disc_sel;
     int collect;             // second pass: G32 holds the final maxima; append only
+    int gated;               // run only if Status::collect_go is set (the collect pass)
     int r_base;              // first discretisation of this launch
     int snext_off;           // LDS byte offset of the work-item broadcast slot
     uint32_t *ptab;          // pair mode: packed (W x W) counts [p_pad][p_pad][W*W]
@@ -160,6 +161,7 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
     float2 *LQ = reinterpret_cast<float2 *>(EB + (a.N1 + 1) + ((a.N0 + a.N1) & 1));
     int64_t *s_next_p = reinterpret_cast<int64_t *>(smem + a.snext_off);
 
+    if (a.gated && a.st->collect_go == 0) return;   // workgroup-uniform
     const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wr = wave >> 1, wc = wave & 1;
     const int q = lane >> 4, c16 = lane & 15;
@@ -727,7 +729,8 @@ size_t sweep2_lds_bytes(const Problem &P, bool max_mode)
 }
 
 template <int W, int ENC>
-static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r)
+static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r,
+                               bool gated)
 {
     const Layout &L = P.L;
     Sweep2Args a{};
@@ -763,6 +766,7 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
     a.counts_out = counts_out;
     a.disc_sel = disc_sel;
     a.collect = collect ? 1 : 0;
+    a.gated = gated ? 1 : 0;
     const bool max_mode = pair_r < 0 && !counts_out;
     const size_t lds = sweep2_lds_bytes(P, max_mode);
     a.snext_off = (int)(lds - 16);
@@ -776,35 +780,36 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
 }
 
 template <int W>
-static hipError_t sweep_dispatch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r)
+static hipError_t sweep_dispatch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r,
+                                 bool gated)
 {
-    if (!P.fp4) return sweep_launch<W, 0>(P, counts_out, disc_sel, collect, pair_r);
+    if (!P.fp4) return sweep_launch<W, 0>(P, counts_out, disc_sel, collect, pair_r, gated);
     // the maximum sweep is instantiated per table capacity (occupancy); the debug and pair
     // modes use the largest
-    if (pair_r >= 0 || counts_out) return sweep_launch<W, 4096>(P, counts_out, disc_sel, collect, pair_r);
+    if (pair_r >= 0 || counts_out) return sweep_launch<W, 4096>(P, counts_out, disc_sel, collect, pair_r, gated);
     switch (fp4_capacity(P)) {
-    case 1024: return sweep_launch<W, 1024>(P, counts_out, disc_sel, collect, pair_r);
-    case 2048: return sweep_launch<W, 2048>(P, counts_out, disc_sel, collect, pair_r);
-    case 4096: return sweep_launch<W, 4096>(P, counts_out, disc_sel, collect, pair_r);
+    case 1024: return sweep_launch<W, 1024>(P, counts_out, disc_sel, collect, pair_r, gated);
+    case 2048: return sweep_launch<W, 2048>(P, counts_out, disc_sel, collect, pair_r, gated);
+    case 4096: return sweep_launch<W, 4096>(P, counts_out, disc_sel, collect, pair_r, gated);
     default: return hipErrorInvalidValue;
     }
 }
 
-static hipError_t sweep_any(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r)
+static hipError_t sweep_any(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r, bool gated)
 {
     switch (P.L.W) {
-    case 1: return sweep_dispatch<1>(P, counts_out, disc_sel, collect, pair_r);
-    case 2: return sweep_dispatch<2>(P, counts_out, disc_sel, collect, pair_r);
-    case 4: return sweep_dispatch<4>(P, counts_out, disc_sel, collect, pair_r);
+    case 1: return sweep_dispatch<1>(P, counts_out, disc_sel, collect, pair_r, gated);
+    case 2: return sweep_dispatch<2>(P, counts_out, disc_sel, collect, pair_r, gated);
+    case 4: return sweep_dispatch<4>(P, counts_out, disc_sel, collect, pair_r, gated);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bool collect)
 {
-    return sweep_any(P, counts_out, disc_sel, collect, -1);
+    return sweep_any(P, counts_out, disc_sel, collect, -1, collect);
 }
 
-hipError_t launch_pairs(const Problem &P, int r) { return sweep_any(P, nullptr, -1, false, r); }
+hipError_t launch_pairs(const Problem &P, int r, bool gated) { return sweep_any(P, nullptr, -1, false, r, gated); }
 
 }  // namespace mdfs

@@ -111,6 +111,7 @@ template <int T>
 __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
 {
     constexpr int C = 3;
+    if (a.collect && a.st->collect_go == 0) return;   // collect pass not needed (uniform)
     extern __shared__ __attribute__((aligned(16))) char smem[];
     char *stage = smem + 24 * T;
     int64_t *s_next = reinterpret_cast<int64_t *>(smem + a.snext_off);

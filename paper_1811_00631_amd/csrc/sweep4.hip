@@ -90,6 +90,7 @@ template <int W>
 __global__ __launch_bounds__(S4_THREADS) void k_sweep4(Sweep4Args a)
 {
     constexpr int C = W + 1;
+    if (a.collect && a.st->collect_go == 0) return;   // collect pass not needed (uniform)
     extern __shared__ __attribute__((aligned(16))) char smem[];
     float *EA = reinterpret_cast<float *>(smem);
     float *EB = EA + (a.N0 + 1);

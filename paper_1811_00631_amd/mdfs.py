@@ -54,7 +54,7 @@ _lib = None
 SYMBOLS = ["mdfs_workspace_size", "mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts",
            "mdfs_screen_max", "mdfs_interesting_tuples", "mdfs_phase_times", "mdfs_last_error",
            "mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust", "mdfs_add_contrast",
-           "mdfs_max_ig_codes"]
+           "mdfs_max_ig_codes", "mdfs_max_ig_async", "mdfs_check_status"]
 FLAG_TIMING = 1
 PHASES = ["setup", "discretize", "sweep", "finalize"]
 
@@ -74,6 +74,8 @@ def load(path: str = LIB_PATH):
     L.mdfs_discretize.argtypes = [P, vp, vp, vp, sz, vp]
     L.mdfs_max_ig.argtypes = [P, vp, vp, vp, vp, vp, vp, sz, vp]
     L.mdfs_max_ig_codes.argtypes = [P, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.mdfs_max_ig_async.argtypes = [P, vp, vp, ctypes.c_int64, vp, vp, vp, vp, sz, vp]
+    L.mdfs_check_status.argtypes = [P, vp, sz, vp]
     L.mdfs_pair_counts.argtypes = [P, vp, vp, ctypes.c_int32, vp, vp, sz, vp]
     L.mdfs_screen_max.argtypes = [P, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
     L.mdfs_interesting_tuples.argtypes = [P, vp, vp, ctypes.c_double, vp, vp, vp, vp, ctypes.c_int64,
@@ -89,7 +91,8 @@ def load(path: str = LIB_PATH):
     L.mdfs_add_contrast.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, vp, vp, vp]
     for fn in ("mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust", "mdfs_add_contrast"):
         getattr(L, fn).restype = ctypes.c_int
-    for fn in ("mdfs_discretize", "mdfs_max_ig", "mdfs_max_ig_codes", "mdfs_pair_counts", "mdfs_screen_max", "mdfs_interesting_tuples"):
+    for fn in ("mdfs_discretize", "mdfs_max_ig", "mdfs_max_ig_codes", "mdfs_max_ig_async", "mdfs_check_status",
+               "mdfs_pair_counts", "mdfs_screen_max", "mdfs_interesting_tuples"):
         getattr(L, fn).restype = ctypes.c_int
     _lib = L
     return L
@@ -196,6 +199,38 @@ def mdfs_max_ig(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_d
     _check(load().mdfs_max_ig(ctypes.byref(prm), _ptr(data), _ptr(y), _ptr(ig), _ptr(am), _ptr(ad), _ptr(ws),
                               ws.numel(), strm))
     return ig, am, ad
+
+
+def mdfs_max_ig_async(data: torch.Tensor, y: torch.Tensor, n1: int, k: int, divisions: int, n_disc: int,
+                      pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0, disc_offset: int = 0,
+                      engine: str = "auto", workgroups: int = 0, ws: torch.Tensor | None = None, out=None):
+    """Enqueue mdfs_max_ig on the current stream without any host synchronisation (capturable in
+    a CUDA graph).  `out` = (ig, argmax, argmax_disc) preallocated tensors or None; `ws` a
+    preallocated workspace or None (the cached one).  Check errors later with mdfs_check_status."""
+    data, y = _dev_inputs(data, y)
+    n_var, n_obj = data.shape
+    prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed, engine, 0,
+                      workgroups)
+    if ws is None:
+        ws = workspace_for(prm, data.device)
+    if out is None:
+        out = (torch.empty(n_var, dtype=torch.float32, device=data.device),
+               torch.empty((n_var, k - 1), dtype=torch.int32, device=data.device),
+               torch.empty(n_var, dtype=torch.int32, device=data.device))
+    ig, am, ad = out
+    _check(load().mdfs_max_ig_async(ctypes.byref(prm), _ptr(data), _ptr(y), int(n1), _ptr(ig), _ptr(am), _ptr(ad),
+                                    _ptr(ws), ws.numel(), _stream(data.device)))
+    return ig, am, ad
+
+
+def mdfs_check_status(data_shape, k: int, divisions: int, n_disc: int, ws: torch.Tensor | None = None,
+                disc_offset: int = 0, engine: str = "auto"):
+    """Raise MdfsError if the last asynchronous call on `ws` flagged an error (synchronises)."""
+    n_var, n_obj = data_shape
+    prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, 0.5, 0.25, 0, engine)
+    if ws is None:
+        ws = workspace_for(prm, torch.device("cuda", torch.cuda.current_device()))
+    _check(load().mdfs_check_status(ctypes.byref(prm), _ptr(ws), ws.numel(), _stream(ws.device)))
 
 
 def mdfs_max_ig_codes(codes: torch.Tensor, y: torch.Tensor, k: int, divisions: int, pseudocount: float = 0.25,
