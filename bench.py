@@ -36,8 +36,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-vars", type=int, default=500, help="variables in the oracle's sample")
-    ap.add_argument("--cpu-disc", type=int, default=16, help="discretisations in the oracle's sample")
+    ap.add_argument("--cpu-vars", type=int, default=2000, help="variables in the oracle's sample")
+    ap.add_argument("--cpu-disc", type=int, default=30, help="discretisations in the oracle's sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--autotune", action="store_true",
