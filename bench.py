@@ -62,7 +62,7 @@ def _wl(name):
             "madelon4": lambda: workloads.madelon_like(divisions=1, n_disc=1, k=4)}[name]()
 
 
-WORKLOADS = ["headline", "xor_small", "madelon_like", "parity3", "genomics_like", "madelon4", "serving"]
+WORKLOADS = ["headline", "xor_small", "madelon_like", "parity3", "genomics_like", "madelon4", "batch12", "serving"]
 WORKLOAD_TEXT = {
     "headline": "genomics-shaped k=2: N=2000, p=20000 log-normal, 10 planted XOR pairs, balanced y, d=3, "
                 "30 random discretisations (range 0.5, xi 0.25)",
@@ -73,6 +73,8 @@ WORKLOAD_TEXT = {
                      "30 discretisations",
     "madelon4": "Madelon-shaped k=4: N=2000, p=500 (5 base + 15 combinations + 480 noise), d=2, 1 discretisation "
                 "(the shape of the paper's 4D timing)",
+    "batch12": "12 Madelon-shaped k=2 datasets of uneven size (N 500-2000, p 200-600), d=3, 30 discretisations each: "
+               "one fused persistent launch vs separate calls",
     "serving": "serving trace: 256 requests, Poisson arrivals at 0.8 x the measured batched capacity, 32 resident "
                "datasets N~logU[100,5000], p~logU[100,20000] (k=3 requests on datasets with p<=1000), "
                "k in {2,3}, d in {2,3,5}, 1-30 discretisations, Gaussian data with planted XOR pairs",
@@ -98,6 +100,79 @@ def cpu_baseline(w, n_vars, n_disc):
     return {"value": tuples / dt, "unit": "k-tuples evaluated/sec", "cores": threads, "kind": "oracle",
             "sample": f"first {n_vars} of {w.n_var} variables, {n_disc} of {w.n_disc} discretisations, "
                       f"N={w.n_obj}, k=2, d={w.divisions + 1}: {tuples} pair tables in {dt:.2f} s"}
+
+
+def batch_bench(args):
+    """Several datasets: separate synchronous calls, separate asynchronous calls, one fused call
+    (mdfs_max_ig_batch: one persistent sweep launch over all their tiles), and the fused call
+    replayed as a captured graph.  Every variant's outputs are checked equal."""
+    import numpy as np
+    import torch
+
+    from paper_1811_00631_amd import mdfs, workloads
+    dev = torch.device("cuda:0")
+    g = np.random.default_rng(12)
+    shapes = [(int(g.integers(500, 2001)), int(g.integers(200, 601))) for _ in range(12)]
+    ws_ = [workloads.madelon_like(seed=30 + i, n_obj=n, n_noise=p - 20) for i, (n, p) in enumerate(shapes)]
+    D = [torch.from_numpy(w.data).to(dev) for w in ws_]
+    Y = [torch.from_numpy(w.y).to(dev) for w in ws_]
+    n1 = [int(w.y.sum()) for w in ws_]
+    R = 30
+    tuples = sum(math.comb(w.n_var, 2) * R for w in ws_)
+
+    def separate():
+        return [mdfs.mdfs_max_ig(D[i], Y[i], 2, 2, R, 0.25, 0.5, i) for i in range(12)]
+
+    def separate_async():
+        return [mdfs.mdfs_max_ig_async(D[i], Y[i], n1[i], 2, 2, R, 0.25, 0.5, i,
+                                       ws=torch.empty(mdfs.mdfs_workspace_size(mdfs.make_params(
+                                           D[i].shape[1], D[i].shape[0], 2, 2, R, 0, 0.5, 0.25, i)),
+                                           dtype=torch.uint8, device=dev)) for i in range(12)]
+
+    def fused():
+        return mdfs.mdfs_max_ig_batch(D, Y, n1, 2, 2, [R] * 12, 0.25, 0.5, list(range(12)))[0]
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fused()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gout = fused()
+
+    def graphed():
+        graph.replay()
+        return gout
+
+    ref = separate()
+    res = {}
+    for name, fn in (("separate", separate), ("separate_async", separate_async), ("fused", fused), ("fused_graph", graphed)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        for a, b in zip(ref, out):
+            if not all(torch.equal(u, v) for u, v in zip(a, b)):
+                raise RuntimeError(f"{name}: results differ from separate calls")
+        res[name] = ms
+        print(f"# {name}: {ms:.3f} ms per batch of 12", file=sys.stderr, flush=True)
+    line = {
+        "metric": "k-tuples evaluated/sec (12 k=2 datasets per batch, informational)",
+        "value": tuples / (res["fused"] * 1e-3), "unit": "k-tuples evaluated/sec",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["fused"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp4 (E2M1 one-hot), f32 accumulate", "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["batch12"], "shapes": shapes, "n_disc": R, "tuples_per_step": tuples},
+        "ms_per_batch": res,
+        "tuples_per_s": {k: tuples / (v * 1e-3) for k, v in res.items()},
+    }
+    print(json.dumps(line))
 
 
 def serving_bench(args):
@@ -170,6 +245,9 @@ def main():
     mdfs.load()
     if args.workload == "serving":
         serving_bench(args)
+        return
+    if args.workload == "batch12":
+        batch_bench(args)
         return
     dev = torch.device("cuda:0")
     w = _wl(args.workload)

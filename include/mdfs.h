@@ -144,6 +144,22 @@ int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint8_t *y, flo
 int mdfs_max_ig_async(const mdfs_params *prm, const float *data, const uint8_t *y, int64_t n1, float *ig_max,
                       int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream);
 
+/* Several k = 2 problems (datasets of uneven N and p, their own discretisation counts) in one
+ * asynchronous call whose maximum pass is ONE persistent launch over the concatenated tiles of all
+ * problems, so small problems share the GPU instead of leaving it idle between launches.
+ *   n               : 1 <= n <= 12 problems; all with k = 2, the same divisions and the same
+ *                     encoding (every class < 4096 objects for fp4, or engine mfma for int8)
+ *   prm[i], data[i], y[i], n1[i], ig_max[i], argmax[i], argmax_disc[i], ws[i], ws_bytes[i]:
+ *                     problem i, as for mdfs_max_ig_async (its own workspace)
+ *   batch_ws        : device memory of mdfs_batch_workspace_size() bytes (the work counters)
+ * Per-problem status: mdfs_check_status(&prm[i], ws[i], ...).  Returns MDFS_E_LIMIT for mixed
+ * divisions or encodings; other argument errors as mdfs_max_ig_async, before anything is
+ * enqueued.  Enqueued on `stream` with no host synchronisation (capturable). */
+size_t mdfs_batch_workspace_size(void);
+int mdfs_max_ig_batch(int n, const mdfs_params *prm, const float *const *data, const uint8_t *const *y,
+                      const int64_t *n1, float *const *ig_max, int32_t *const *argmax, int32_t *const *argmax_disc,
+                      void *const *ws, const size_t *ws_bytes, void *batch_ws, size_t batch_ws_bytes, void *stream);
+
 /* Status of the last call that used workspace `ws` with parameters `prm` (synchronises `stream`):
  * MDFS_OK, or MDFS_E_Y / MDFS_E_NAN / MDFS_E_ARG (codes out of range) / MDFS_E_OVERFLOW as the
  * device flagged it. */

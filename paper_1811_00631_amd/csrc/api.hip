@@ -444,6 +444,61 @@ extern "C" int mdfs_max_ig_async(const mdfs_params *prm, const float *data, cons
     return MDFS_OK;
 }
 
+extern "C" size_t mdfs_batch_workspace_size(void) { return 256; }
+
+extern "C" int mdfs_max_ig_batch(int n, const mdfs_params *prm, const float *const *data, const uint8_t *const *y,
+                                 const int64_t *n1, float *const *ig_max, int32_t *const *argmax,
+                                 int32_t *const *argmax_disc, void *const *ws, const size_t *ws_bytes, void *batch_ws,
+                                 size_t batch_ws_bytes, void *stream)
+{
+    if (n < 1 || n > MAX_BATCH) return fail(MDFS_E_ARG, "n=%d: a batch holds 1..%d problems", n, MAX_BATCH);
+    if (!prm || !data || !y || !n1 || !ig_max || !ws || !ws_bytes || !batch_ws)
+        return fail(MDFS_E_ARG, "null pointer");
+    if (batch_ws_bytes < sizeof(Status)) return fail(MDFS_E_NOMEM, "batch workspace %zu bytes < %zu", batch_ws_bytes,
+                                                     sizeof(Status));
+    std::vector<Problem> Ps((size_t)n);
+    std::vector<const Problem *> pp((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        int rc = check_params(&prm[i]);
+        if (rc) return rc;
+        if (prm[i].k != 2) return fail(MDFS_E_K, "problem %d: batches are built for k=2", i);
+        if (prm[i].divisions != prm[0].divisions) return fail(MDFS_E_LIMIT, "problem %d: one divisions per batch", i);
+        if (prm[i].flags & MDFS_FLAG_TIMING) return fail(MDFS_E_ARG, "timing is not available in a batch");
+        if (!data[i] || !y[i] || !ig_max[i] || !ws[i]) return fail(MDFS_E_ARG, "problem %d: null pointer", i);
+        if (n1[i] < 1 || n1[i] >= prm[i].n_obj)
+            return fail(MDFS_E_Y, "problem %d: n1=%lld: both classes must be non-empty", i, (long long)n1[i]);
+        if ((rc = setup(&prm[i], y[i], ws[i], ws_bytes[i], stream, Ps[(size_t)i], n1[i]))) return rc;
+        pp[(size_t)i] = &Ps[(size_t)i];
+        if (Ps[(size_t)i].fp4 != Ps[0].fp4)
+            return fail(MDFS_E_LIMIT, "problem %d: one encoding per batch (fp4 needs classes < 4096 objects)", i);
+    }
+    // per problem: status, class order (checked against n1 on the device), tables, encoding
+    for (int i = 0; i < n; ++i) {
+        const Problem &P = Ps[(size_t)i];
+        LAUNCH(launch_init(P));
+        LAUNCH(launch_class_perm(P, y[i], n1[i]));
+        LAUNCH(launch_tables(P));
+        LAUNCH(launch_encode(P, data[i]));
+    }
+    // the maximum pass of every problem in one persistent launch
+    Problem Q = Ps[0];
+    Q.ws = static_cast<char *>(batch_ws);
+    Q.L.status = 0;
+    LAUNCH(launch_reset_queue(Q));
+    LAUNCH(launch_sweep2_batch(pp.data(), n, static_cast<Status *>(batch_ws)));
+    // per problem: the gated collect pass, then re-score and outputs
+    for (int i = 0; i < n; ++i) {
+        const Problem &P = Ps[(size_t)i];
+        LAUNCH(launch_collect_decide(P, false));
+        LAUNCH(launch_reset_candidates(P, true));
+        int rc = sweep_pass(P, nullptr, -1, true);
+        if (rc) return rc;
+        LAUNCH(launch_finalize(P, ig_max[i], argmax ? argmax[i] : nullptr, argmax_disc ? argmax_disc[i] : nullptr));
+    }
+    g_err.clear();
+    return MDFS_OK;
+}
+
 extern "C" int mdfs_check_status(const mdfs_params *prm, const void *ws, size_t ws_bytes, void *stream)
 {
     int rc = check_params(prm, false);

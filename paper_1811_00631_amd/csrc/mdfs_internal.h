@@ -32,6 +32,7 @@ constexpr int MAX_NOBJ = 16384;
 constexpr int MAX_CLASS_OBJ = 32767;
 constexpr int MAX_K3_VARS = 4096;
 constexpr int MAX_K4_VARS = 1024;      // k = 4: three partners packed 10 bits each
+constexpr int MAX_BATCH = 12;          // problems fused in one persistent pair-sweep launch
 
 // Status words at the start of the workspace.
 struct Status {
@@ -147,6 +148,11 @@ hipError_t launch_reset_candidates(const Problem &P, bool gated = false);
 // Status::collect_go = force ? 1 : (a candidate append overflowed)
 hipError_t launch_collect_decide(const Problem &P, bool force);
 hipError_t launch_pairs(const Problem &P, int r, bool gated = false);
+// The maximum pass of several k = 2 problems in one persistent launch (same d and encoding);
+// `queue` holds the batch's work counters (a Status in device memory).
+hipError_t launch_sweep2_batch(const Problem *const *Ps, int n, Status *queue);
+// Table capacity of the fp4 pair sweep for a problem's class sizes (0 = does not fit).
+int sweep2_fp4_capacity(const Problem &P);
 hipError_t launch_sweep3(const Problem &P, int r, bool collect);
 // k = 4 bitset sweep of discretisation r (sweep4.hip)
 hipError_t launch_sweep4(const Problem &P, int r, bool collect);

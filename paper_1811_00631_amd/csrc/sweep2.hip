@@ -25,6 +25,8 @@
 // binary64 from exact recounts.
 #include "mdfs_internal.h"
 
+#include <algorithm>
+
 namespace mdfs {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -79,6 +81,16 @@ struct Sweep2Args {
 
 // What one launch of the pair sweep produces.
 enum SweepMode { SWEEP_MAX = 0, SWEEP_DEBUG_COUNTS = 1, SWEEP_PAIRS = 2 };
+
+// Several problems in one persistent launch (maximum pass): their super-tiles are concatenated
+// (pref = prefix of each problem's super-tile count) and drawn from one set of queues.  Passed
+// by value in the kernel arguments, so a batch needs no host-to-device copy.
+struct Sweep2Batch {
+    Sweep2Args p[MAX_BATCH];
+    int64_t pref[MAX_BATCH + 1];
+    int nb;
+    Status *queue;           // work counters of the batch
+};
 
 // Swizzled LDS address of 16-byte chunk j (0..3) of tile row `row` (64 bytes per row).
 __device__ inline int lds_addr(int row, int j) { return row * KBLK + ((j ^ ((row >> 1) & 3)) << 4); }
@@ -144,8 +156,8 @@ __device__ inline void tri_index(int64_t tt, int &bi, int &bj)
     bi = (int)(tt - j * (j + 1) / 2);
 }
 
-template <int W, int MODE, int ENC>
-__global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep2(Sweep2Args a)
+template <int W, int MODE, int ENC, bool BATCH>
+__device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 {
     constexpr bool F4 = ENC != 0;
     constexpr int T = ENC;
@@ -155,10 +167,9 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
     constexpr int NP = (W == 1) ? 4 : 1; // pairs held per lane per 16x16 block
     extern __shared__ __attribute__((aligned(16))) char smem[];
     char *stage = smem + stage_base(ENC);   // [NSTAGE buffers][A 8 KB | B 8 KB]
-    // int8: tables after the stages, at run-time offsets
-    float *EA = reinterpret_cast<float *>(smem + NSTAGE * STAGE_BYTES);
-    float *EB = EA + (a.N0 + 1);
-    float2 *LQ = reinterpret_cast<float2 *>(EB + (a.N1 + 1) + ((a.N0 + a.N1) & 1));
+    // int8: tables after the stages, at run-time offsets (per problem)
+    float *EA = nullptr, *EB = nullptr;
+    float2 *LQ = nullptr;
     int64_t *s_next_p = reinterpret_cast<int64_t *>(smem + a.snext_off);
 
     if (a.gated && a.st->collect_go == 0) return;   // workgroup-uniform
@@ -166,17 +177,25 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
     const int wr = wave >> 1, wc = wave & 1;
     const int q = lane >> 4, c16 = lane & 15;
 
-    if constexpr (F4) {
-        float *tf = reinterpret_cast<float *>(smem);
-        for (int i = t; i <= a.N0; i += SW_THREADS) tf[i] = a.EA[i];
-        for (int i = t; i <= a.N1; i += SW_THREADS) tf[T + i] = a.EB[i];
-        float2 *lq = reinterpret_cast<float2 *>(smem + 8 * T);
-        for (int i = t; i <= a.N; i += SW_THREADS) lq[i] = a.LQ[i];
-    } else {
-        for (int i = t; i <= a.N0; i += SW_THREADS) EA[i] = a.EA[i];
-        for (int i = t; i <= a.N1; i += SW_THREADS) EB[i] = a.EB[i];
-        for (int i = t; i <= a.N; i += SW_THREADS) LQ[i] = a.LQ[i];
-    }
+    // the problem's entropy tables into LDS
+    auto load_tables = [&]() {
+        EA = reinterpret_cast<float *>(smem + NSTAGE * STAGE_BYTES);
+        EB = EA + (a.N0 + 1);
+        LQ = reinterpret_cast<float2 *>(EB + (a.N1 + 1) + ((a.N0 + a.N1) & 1));
+        if constexpr (F4) {
+            float *tf = reinterpret_cast<float *>(smem);
+            for (int i = t; i <= a.N0; i += SW_THREADS) tf[i] = a.EA[i];
+            for (int i = t; i <= a.N1; i += SW_THREADS) tf[T + i] = a.EB[i];
+            float2 *lq = reinterpret_cast<float2 *>(smem + 8 * T);
+            for (int i = t; i <= a.N; i += SW_THREADS) lq[i] = a.LQ[i];
+        } else {
+            for (int i = t; i <= a.N0; i += SW_THREADS) EA[i] = a.EA[i];
+            for (int i = t; i <= a.N1; i += SW_THREADS) EB[i] = a.EB[i];
+            for (int i = t; i <= a.N; i += SW_THREADS) LQ[i] = a.LQ[i];
+        }
+    };
+    int cur = 0;   // batch: the problem whose arguments and tables are loaded
+    load_tables();
 
     // Persistent, XCD-aware schedule.  The super-tiles sup = x, x+8, x+16 ... form queue x; the
     // workgroups resident on XCD x take its tiles (super-tile by super-tile, slot by slot) from
@@ -190,9 +209,11 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
     __syncthreads();   // everyone has read the previous s_next
     if (t == 0) {
         int64_t it = -1;
+        const int64_t n_super = BATCH ? bt->pref[bt->nb] : a.n_super;
+        Status *qst = BATCH ? bt->queue : a.st;
         while (q_seen < XCDS) {
-            const int64_t nq = ((a.n_super - my_q + XCDS - 1) / XCDS) * (SB * SB);
-            it = (int64_t)atomicAdd(&a.st->next_tile[my_q], 1u);
+            const int64_t nq = ((n_super - my_q + XCDS - 1) / XCDS) * (SB * SB);
+            it = (int64_t)atomicAdd(&qst->next_tile[my_q], 1u);
             if (it < nq) break;
             it = -1;
             my_q = (my_q + 1) & (XCDS - 1);
@@ -204,7 +225,24 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
     __syncthreads();
     const int64_t item = s_next_p[0];
     if (item < 0) break;
-    const int64_t sup = s_next_p[1] + XCDS * (item / (SB * SB));
+    int64_t sup = s_next_p[1] + XCDS * (item / (SB * SB));
+    if constexpr (BATCH) {
+        // the problem owning this super-tile; arguments and tables follow it (workgroup-uniform;
+        // every wave finished the previous tile before the barriers of the fetch)
+        int lo = 0, hi = bt->nb - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (bt->pref[mid] <= sup) lo = mid;
+            else hi = mid - 1;
+        }
+        if (lo != cur) {
+            cur = lo;
+            a = bt->p[lo];
+            load_tables();
+            __syncthreads();
+        }
+        sup -= bt->pref[lo];
+    }
     const int slot = (int)(item % (SB * SB));
     const int r = a.r_base + (int)(sup / a.super_per_r);
     int SI, SJ;
@@ -709,6 +747,18 @@ __global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2
     }   // work items
 }
 
+template <int W, int MODE, int ENC>
+__global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep2(Sweep2Args a)
+{
+    sweep2_run<W, MODE, ENC, false>(a, nullptr);
+}
+
+template <int W, int ENC>
+__global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep2_batch(Sweep2Batch bt)
+{
+    sweep2_run<W, SWEEP_MAX, ENC, true>(bt.p[0], &bt);
+}
+
 // Table capacity of the fp4 layout for these class sizes (0 = does not fit any).
 static int fp4_capacity(const Problem &P)
 {
@@ -728,9 +778,11 @@ size_t sweep2_lds_bytes(const Problem &P, bool max_mode)
     return NSTAGE * STAGE_BYTES + ((tab + 15) & ~size_t(15)) + 16;
 }
 
-template <int W, int ENC>
-static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r,
-                               bool gated)
+int sweep2_fp4_capacity(const Problem &P) { return fp4_capacity(P); }
+
+// Arguments of one problem's pair sweep.
+template <int W>
+static Sweep2Args sweep_args(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r, bool gated)
 {
     const Layout &L = P.L;
     Sweep2Args a{};
@@ -767,6 +819,14 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
     a.disc_sel = disc_sel;
     a.collect = collect ? 1 : 0;
     a.gated = gated ? 1 : 0;
+    return a;
+}
+
+template <int W, int ENC>
+static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r,
+                               bool gated)
+{
+    Sweep2Args a = sweep_args<W>(P, counts_out, disc_sel, collect, pair_r, gated);
     const bool max_mode = pair_r < 0 && !counts_out;
     const size_t lds = sweep2_lds_bytes(P, max_mode);
     a.snext_off = (int)(lds - 16);
@@ -811,5 +871,59 @@ hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bo
 }
 
 hipError_t launch_pairs(const Problem &P, int r, bool gated) { return sweep_any(P, nullptr, -1, false, r, gated); }
+
+// ---------------------------------------------------------------- several problems, one launch
+template <int W, int ENC>
+static hipError_t batch_launch(const Problem *const *Ps, int n, Status *queue, size_t lds)
+{
+    Sweep2Batch b{};
+    b.nb = n;
+    b.queue = queue;
+    b.pref[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        b.p[i] = sweep_args<W>(*Ps[i], nullptr, -1, false, -1, false);
+        b.p[i].snext_off = (int)(lds - 16);   // one LDS size for the whole launch
+        b.pref[i + 1] = b.pref[i] + b.p[i].n_super;
+    }
+    auto kern = k_sweep2_batch<W, ENC>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int grid = Ps[0]->workgroups > 0 ? Ps[0]->workgroups : XCDS * WG_PER_XCD;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(SW_THREADS), lds, Ps[0]->stream, b);
+    return hipGetLastError();
+}
+
+template <int W>
+static hipError_t batch_dispatch(const Problem *const *Ps, int n, Status *queue)
+{
+    // one encoding and table capacity for all: the largest any problem needs
+    size_t lds = 0;
+    int T = 0;
+    for (int i = 0; i < n; ++i) {
+        lds = std::max(lds, sweep2_lds_bytes(*Ps[i], true));
+        T = std::max(T, fp4_capacity(*Ps[i]));
+    }
+    if (!Ps[0]->fp4) return batch_launch<W, 0>(Ps, n, queue, lds);
+    lds = (size_t)stage_base(T) + NSTAGE * STAGE_BYTES + 16;
+    switch (T) {
+    case 1024: return batch_launch<W, 1024>(Ps, n, queue, lds);
+    case 2048: return batch_launch<W, 2048>(Ps, n, queue, lds);
+    case 4096: return batch_launch<W, 4096>(Ps, n, queue, lds);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep2_batch(const Problem *const *Ps, int n, Status *queue)
+{
+    if (n < 1 || n > MAX_BATCH) return hipErrorInvalidValue;
+    for (int i = 1; i < n; ++i)
+        if (Ps[i]->L.W != Ps[0]->L.W || Ps[i]->fp4 != Ps[0]->fp4) return hipErrorInvalidValue;
+    switch (Ps[0]->L.W) {
+    case 1: return batch_dispatch<1>(Ps, n, queue);
+    case 2: return batch_dispatch<2>(Ps, n, queue);
+    case 4: return batch_dispatch<4>(Ps, n, queue);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 }  // namespace mdfs

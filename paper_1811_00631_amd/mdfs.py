@@ -54,7 +54,8 @@ _lib = None
 SYMBOLS = ["mdfs_workspace_size", "mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts",
            "mdfs_screen_max", "mdfs_interesting_tuples", "mdfs_phase_times", "mdfs_last_error",
            "mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust", "mdfs_add_contrast",
-           "mdfs_max_ig_codes", "mdfs_max_ig_async", "mdfs_check_status"]
+           "mdfs_max_ig_codes", "mdfs_max_ig_async", "mdfs_check_status", "mdfs_max_ig_batch",
+           "mdfs_batch_workspace_size"]
 FLAG_TIMING = 1
 PHASES = ["setup", "discretize", "sweep", "finalize"]
 
@@ -76,6 +77,10 @@ def load(path: str = LIB_PATH):
     L.mdfs_max_ig_codes.argtypes = [P, vp, vp, vp, vp, vp, vp, sz, vp]
     L.mdfs_max_ig_async.argtypes = [P, vp, vp, ctypes.c_int64, vp, vp, vp, vp, sz, vp]
     L.mdfs_check_status.argtypes = [P, vp, sz, vp]
+    L.mdfs_batch_workspace_size.argtypes = []
+    L.mdfs_batch_workspace_size.restype = sz
+    L.mdfs_max_ig_batch.argtypes = [ctypes.c_int, P, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.mdfs_max_ig_batch.restype = ctypes.c_int
     L.mdfs_pair_counts.argtypes = [P, vp, vp, ctypes.c_int32, vp, vp, sz, vp]
     L.mdfs_screen_max.argtypes = [P, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
     L.mdfs_interesting_tuples.argtypes = [P, vp, vp, ctypes.c_double, vp, vp, vp, vp, ctypes.c_int64,
@@ -231,6 +236,31 @@ def mdfs_check_status(data_shape, k: int, divisions: int, n_disc: int, ws: torch
     if ws is None:
         ws = workspace_for(prm, torch.device("cuda", torch.cuda.current_device()))
     _check(load().mdfs_check_status(ctypes.byref(prm), _ptr(ws), ws.numel(), _stream(ws.device)))
+
+
+def mdfs_max_ig_batch(datas, ys, n1s, k: int, divisions: int, n_discs, pseudocount: float = 0.25,
+                      range_: float = 0.5, seeds=None, engine: str = "auto", workgroups: int = 0):
+    """Several k = 2 problems, one fused persistent sweep launch (no host synchronisation).
+    Returns [(ig, argmax, argmax_disc)] and the workspaces (for mdfs_check_status)."""
+    n = len(datas)
+    seeds = seeds if seeds is not None else [0] * n
+    PA = Params * n
+    prms = PA(*[make_params(d.shape[1], d.shape[0], k, divisions, n_discs[i], 0, range_, pseudocount, seeds[i],
+                            engine, 0, workgroups) for i, d in enumerate(datas)])
+    dev = datas[0].device
+    ins = [_dev_inputs(d, y) for d, y in zip(datas, ys)]
+    wss = [torch.empty(mdfs_workspace_size(prms[i]), dtype=torch.uint8, device=dev) for i in range(n)]
+    outs = [(torch.empty(d.shape[0], dtype=torch.float32, device=dev),
+             torch.empty((d.shape[0], k - 1), dtype=torch.int32, device=dev),
+             torch.empty(d.shape[0], dtype=torch.int32, device=dev)) for d, _ in ins]
+    bws = torch.empty(load().mdfs_batch_workspace_size(), dtype=torch.uint8, device=dev)
+    ptrs = lambda ts: (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])   # noqa: E731
+    n1a = (ctypes.c_int64 * n)(*[int(v) for v in n1s])
+    wsb = (ctypes.c_size_t * n)(*[w.numel() for w in wss])
+    _check(load().mdfs_max_ig_batch(n, prms, ptrs([d for d, _ in ins]), ptrs([y for _, y in ins]), n1a,
+                                    ptrs([o[0] for o in outs]), ptrs([o[1] for o in outs]), ptrs([o[2] for o in outs]),
+                                    ptrs(wss), wsb, _ptr(bws), bws.numel(), _stream(dev)))
+    return outs, wss
 
 
 def mdfs_max_ig_codes(codes: torch.Tensor, y: torch.Tensor, k: int, divisions: int, pseudocount: float = 0.25,
