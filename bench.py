@@ -194,31 +194,33 @@ def serving_bench(args):
             out.append(q)
         return out
 
-    def session(slots, rate):
-        srv = serving.Server(slots=slots)
+    def session(slots, rate, fuse):
+        srv = serving.Server(slots=slots, fuse=fuse)
         try:
             ids = [srv.add_dataset(X, y) for X, y, _ in ds]
             # warm-up: one small request per engine path
             serving.run_trace(srv, make(srv, ids, 0)[:4], timeout=600)
             reqs = make(srv, ids, rate)
+            srv.n_fused = 0
             st = serving.run_trace(srv, reqs, timeout=900)
-            print(f"# serving slots={slots} rate={rate}: {st}", file=sys.stderr, flush=True)
+            st["fused_requests"] = srv.n_fused
+            print(f"# serving slots={slots} fuse={fuse} rate={rate}: {st}", file=sys.stderr, flush=True)
             return st, reqs
         finally:
             srv.close()
 
-    plain_cap, _ = session(1, 0)                        # back to back: capacity of the plain sweep
-    batch_cap, _ = session(4, 0)                        # back to back: capacity with 4 slots
+    plain_cap, _ = session(1, 0, False)                 # back to back, one at a time: the plain sweep
+    batch_cap, _ = session(4, 0, True)                  # back to back: 4 slots and fused small requests
     rate = 0.8 * len(base) / batch_cap["makespan_s"]   # requests/s; base arrivals are at rate 1
-    mixed, _ = session(4, rate)
-    plain, _ = session(1, rate)
+    mixed, _ = session(4, rate, True)
+    plain, _ = session(1, rate, False)
     line = {
         "metric": "serving: k-tuples evaluated/sec over the trace; p50/p99 request latency",
         "value": mixed["tuples_per_s"], "unit": "k-tuples evaluated/sec", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": mixed["makespan_s"] * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "mixed (fp4/int8 MFMA, bitsets)", "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT["serving"], "requests": len(base), "arrival_rate_hz": rate,
-                   "slots": 4},
+                   "slots": 4, "fused_requests": mixed["fused_requests"]},
         "p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"],
         "plain_sweep_same_arrivals": {"tuples_per_s": plain["tuples_per_s"], "p50_ms": plain["p50_ms"],
                                       "p99_ms": plain["p99_ms"]},

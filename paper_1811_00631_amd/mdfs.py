@@ -240,12 +240,15 @@ def mdfs_check_status(data_shape, k: int, divisions: int, n_disc: int, ws: torch
 
 def mdfs_max_ig_batch(datas, ys, n1s, k: int, divisions: int, n_discs, pseudocount: float = 0.25,
                       range_: float = 0.5, seeds=None, engine: str = "auto", workgroups: int = 0):
-    """Several k = 2 problems, one fused persistent sweep launch (no host synchronisation).
-    Returns [(ig, argmax, argmax_disc)] and the workspaces (for mdfs_check_status)."""
+    """Several k = 2 problems, one fused persistent sweep launch (no host synchronisation);
+    pseudocount and range_ may be one value or one per problem.  Returns
+    [(ig, argmax, argmax_disc)] and the workspaces (for mdfs_check_status)."""
     n = len(datas)
     seeds = seeds if seeds is not None else [0] * n
+    per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * n   # noqa: E731
+    xis, rngs = per(pseudocount), per(range_)
     PA = Params * n
-    prms = PA(*[make_params(d.shape[1], d.shape[0], k, divisions, n_discs[i], 0, range_, pseudocount, seeds[i],
+    prms = PA(*[make_params(d.shape[1], d.shape[0], k, divisions, n_discs[i], 0, rngs[i], xis[i], seeds[i],
                             engine, 0, workgroups) for i, d in enumerate(datas)])
     dev = datas[0].device
     ins = [_dev_inputs(d, y) for d, y in zip(datas, ys)]

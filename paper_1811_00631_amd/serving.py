@@ -6,7 +6,10 @@ requests into free slots while their HBM footprint (the library's workspace plus
 fits the memory budget, first fit in arrival order (a request passed over too often blocks
 later ones until it fits).  Each slot is a host thread with its own HIP stream; the C-ABI call
 releases the GIL, so the sweeps of admitted requests run concurrently on the device, each
-with a bounded persistent grid so that small requests are not stuck behind large ones.
+with a bounded persistent grid so that small requests are not stuck behind large ones.  Small
+k = 2 requests waiting behind an admitted small one (same divisions, encoding and engine, up to
+12, memory permitting) are fused with it into one mdfs_max_ig_batch call: one persistent sweep
+launch over all their tiles.
 Results do not depend on the mix: every call is deterministic and the persistent grids take
 all of their tiles whatever their size.
 
@@ -54,6 +57,7 @@ class Request:
 class Dataset:
     data: torch.Tensor            # float32 [n_var][n_obj] on the device
     y: torch.Tensor               # uint8 [n_obj] on the device
+    n1: int = 0                   # objects with y = 1 (counted once, at upload)
 
     @property
     def n_var(self) -> int:
@@ -70,7 +74,8 @@ def tuples_of(ds: Dataset, req: Request) -> int:
 
 class Server:
     def __init__(self, device: str = "cuda:0", slots: int = 4, hbm_budget: int | None = None,
-                 workgroups: int | None = None, max_bypass: int = 8):
+                 workgroups: int | None = None, max_bypass: int = 8, fuse: bool = True,
+                 fuse_tuples: float = 5e8):
         mdfs.load()
         self.device = torch.device(device)
         self.slots = slots
@@ -81,6 +86,9 @@ class Server:
         # persistent grid per call: the GPU's 512 resident sweep workgroups shared by the slots
         self.workgroups = workgroups if workgroups is not None else max(64, (512 // slots) // 8 * 8)
         self.max_bypass = max_bypass
+        self.fuse = fuse
+        self.fuse_tuples = fuse_tuples   # requests up to this many tuples may be fused
+        self.n_fused = 0                 # requests that ran inside a fused batch
         self.datasets: dict[int, Dataset] = {}
         self.resident = 0
         self._lock = threading.Condition()
@@ -106,7 +114,7 @@ class Server:
             did = len(self.datasets)
             while did in self.datasets:
                 did += 1
-            self.datasets[did] = Dataset(d, yy)
+            self.datasets[did] = Dataset(d, yy, int(np.count_nonzero(y)))
             self.resident += d.numel() * 4 + yy.numel()
         return did
 
@@ -140,8 +148,19 @@ class Server:
     def reset_clock(self):
         self._t0 = time.perf_counter()
 
-    def _take(self) -> Request | None:
-        """First queued request whose footprint fits (called with the lock held)."""
+    def fuse_key(self, req: Request):
+        """Requests with equal keys can share one fused sweep launch (None: never fused)."""
+        if not self.fuse or req.k != 2 or req.engine == "bitset":
+            return None
+        ds = self.datasets[req.dataset]
+        if tuples_of(ds, req) > self.fuse_tuples:
+            return None
+        fp4 = max(ds.n1, ds.n_obj - ds.n1) < 4096 and req.engine != "mfma"
+        return (req.divisions, fp4, req.engine)
+
+    def _take(self) -> list[Request]:
+        """First queued request whose footprint fits, and the fusable ones queued behind it that
+        also fit (called with the lock held)."""
         free = self.budget - self.resident - self._in_use
         for idx, req in enumerate(self._queue):
             if req.footprint <= free:
@@ -149,32 +168,53 @@ class Server:
                     self._bypassed[earlier.id] = self._bypassed.get(earlier.id, 0) + 1
                 del self._queue[idx]
                 self._bypassed.pop(req.id, None)
-                return req
+                group = [req]
+                key = self.fuse_key(req)
+                if key is not None:
+                    free -= req.footprint
+                    for later in list(self._queue)[idx:]:
+                        if len(group) == 12:
+                            break
+                        if self.fuse_key(later) == key and later.footprint <= free:
+                            self._queue.remove(later)
+                            self._bypassed.pop(later.id, None)
+                            group.append(later)
+                            free -= later.footprint
+                return group
             if self._bypassed.get(req.id, 0) >= self.max_bypass:
-                return None   # this one waits for memory; nobody passes it any more
-        return None
+                return []   # this one waits for memory; nobody passes it any more
+        return []
 
     def _worker(self, slot: int):
         stream = self._streams[slot]
         while True:
             with self._lock:
-                req = None
-                while req is None:
+                group = []
+                while not group:
                     if self._closing and not self._queue:
                         return
-                    req = self._take()
-                    if req is None:
+                    group = self._take()
+                    if not group:
                         self._lock.wait()
-                self._in_use += req.footprint
-                req.t_admit = self.now()
-            try:
-                self._run(req, stream)
-            except Exception as exc:   # reported on the request, the server keeps serving
-                req.error = f"{type(exc).__name__}: {exc}"
+                now = self.now()
+                for req in group:
+                    self._in_use += req.footprint
+                    req.t_admit = now
+            if len(group) == 1:
+                try:
+                    self._run(group[0], stream)
+                except Exception as exc:   # reported on the request, the server keeps serving
+                    group[0].error = f"{type(exc).__name__}: {exc}"
+            else:
+                self._run_fused(group, stream)
             with self._lock:
-                self._in_use -= req.footprint
-                req.t_done = self.now()
-                self.done.append(req)
+                now = self.now()
+                for req in group:
+                    self._in_use -= req.footprint
+                    req.t_done = now
+                    self.done.append(req)
+                if len(group) > 1:
+                    self.n_fused += len(group)
                 self._lock.notify_all()
 
     def _run(self, req: Request, stream: torch.cuda.Stream):
@@ -188,6 +228,25 @@ class Server:
                                           workgroups=self.workgroups, ws=ws, stream=stream)
             req.result = (ig.cpu().numpy(), am.cpu().numpy(), ad.cpu().numpy())
             del ws
+
+    def _run_fused(self, group: list[Request], stream: torch.cuda.Stream):
+        """One mdfs_max_ig_batch call for the group; each request gets its own status."""
+        dss = [self.datasets[r.dataset] for r in group]
+        try:
+            with torch.cuda.stream(stream):
+                outs, wss = mdfs.mdfs_max_ig_batch(
+                    [d.data for d in dss], [d.y for d in dss], [d.n1 for d in dss], 2, group[0].divisions,
+                    [r.n_disc for r in group], [r.pseudocount for r in group], [r.range_ for r in group],
+                    [r.seed for r in group], engine=group[0].engine, workgroups=self.workgroups)
+                for r, d, (ig, am, ad), ws in zip(group, dss, outs, wss):
+                    try:
+                        mdfs.mdfs_check_status((d.n_var, d.n_obj), 2, r.divisions, r.n_disc, ws=ws, engine=r.engine)
+                        r.result = (ig.cpu().numpy(), am.cpu().numpy(), ad.cpu().numpy())
+                    except Exception as exc:
+                        r.error = f"{type(exc).__name__}: {exc}"
+        except Exception as exc:   # the whole call was refused: every request reports it
+            for r in group:
+                r.error = f"{type(exc).__name__}: {exc}"
 
     def wait_all(self, n: int, timeout: float | None = None):
         """Block until n requests have finished."""

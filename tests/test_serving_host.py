@@ -30,20 +30,50 @@ def test_first_fit_admission_order():
 
     from paper_1811_00631_amd.serving import Server
     srv = Server.__new__(Server)
-    srv.budget, srv.resident, srv._in_use, srv.max_bypass = 100, 10, 0, 2
+    srv.budget, srv.resident, srv._in_use, srv.max_bypass, srv.fuse = 100, 10, 0, 2, False
     srv._bypassed = {}
     import collections
     srv._queue = collections.deque([Req(0, 95), Req(1, 30), Req(2, 50)])
-    assert srv._take().id == 1          # 95 does not fit in 90, 30 does
+    ids = lambda g: [r.id for r in g]   # noqa: E731
+    assert ids(srv._take()) == [1]      # 95 does not fit in 90, 30 does
     srv._in_use = 30
-    assert srv._take().id == 2          # 50 fits in 60
+    assert ids(srv._take()) == [2]      # 50 fits in 60
     srv._in_use = 80
     srv._queue.append(Req(3, 5))
-    assert srv._take() is None          # request 0 was passed over twice: it now blocks
+    assert srv._take() == []            # request 0 was passed over twice: it now blocks
     srv._in_use = 0
-    assert srv._take() is None          # 95 > 100 - 10 resident: still waiting
+    assert srv._take() == []            # 95 > 100 - 10 resident: still waiting
     srv.resident = 0
-    assert srv._take().id == 0
+    assert ids(srv._take()) == [0]
+
+
+def test_fusion_groups_small_k2_requests():
+    # small k = 2 requests with the same divisions and encoding queued behind the admitted one
+    # join it (memory permitting, at most 12); others keep their place
+    from paper_1811_00631_amd.serving import Dataset, Request, Server
+    import collections
+
+    srv = Server.__new__(Server)
+    srv.budget, srv.resident, srv._in_use, srv.max_bypass = 1000, 0, 0, 8
+    srv.fuse, srv.fuse_tuples, srv._bypassed = True, 5e8, {}
+    small = Dataset.__new__(Dataset)
+    big = Dataset.__new__(Dataset)
+    for ds, (p, n, n1) in ((small, (100, 500, 250)), (big, (20000, 2000, 1000))):
+        object.__setattr__(ds, "data", np.zeros((p, n)))
+        object.__setattr__(ds, "n1", n1)
+    srv.datasets = {0: small, 1: big}
+
+    def req(i, ds, k=2, div=2, fp=10):
+        r = Request(dataset=ds, k=k, divisions=div, n_disc=3)
+        r.id, r.footprint = i, fp
+        return r
+    srv._queue = collections.deque([req(0, 0), req(1, 1), req(2, 0, div=1), req(3, 0, k=3), req(4, 0)] +
+                                   [req(5 + i, 0) for i in range(14)])
+    g = srv._take()
+    assert [r.id for r in g] == [0, 4] + list(range(5, 15))     # 12: same key, small
+    assert [r.id for r in srv._queue][:3] == [1, 2, 3]           # big, other divisions, k = 3 wait
+    srv._queue = collections.deque([req(20, 0, fp=600), req(21, 0, fp=500), req(22, 0, fp=300)])
+    assert [r.id for r in srv._take()] == [20, 22]               # 500 no longer fits next to 600
 
 
 def test_autotune_candidates_and_buckets():
