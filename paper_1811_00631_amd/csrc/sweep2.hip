@@ -156,6 +156,27 @@ __device__ inline void tri_index(int64_t tt, int &bi, int &bj)
     bi = (int)(tt - j * (j + 1) / 2);
 }
 
+// First of the `mine` consecutive candidate slots of this lane: an exclusive prefix sum of the
+// lanes' counts and one device-scope atomic per wave for the wave's total (every lane of the
+// wave must take part).  Appends otherwise serialise one returning atomic per pair and class of
+// threshold on a single counter.
+__device__ __forceinline__ uint32_t reserve_slots(uint32_t *counter, uint32_t mine, int lane)
+{
+    uint32_t incl = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, d);
+        if (lane >= d) incl += y;
+    }
+    const uint32_t total = (uint32_t)__shfl((int)incl, 63);
+    uint32_t base = 0;
+    if (total != 0) {
+        if (lane == 0) base = atomicAdd(counter, total);
+        base = (uint32_t)__shfl((int)base, 0);
+    }
+    return base + incl - mine;
+}
+
 template <int W, int MODE, int ENC, bool BATCH>
 __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 {
@@ -354,6 +375,16 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     if (s < a.KB) mma(s, fa0, fb0);
 
     // ---------------------------------------------------------------- epilogue
+    // W >= 2: the first pass keeps each pair's float32 F for the append pass in the stage that
+    // follows the last block's, 16 pairs x 64 lanes = 4 KB per wave.  That stage held block
+    // KB - 3 (or nothing): every wave read its fragments and every fetch landed before the last
+    // barrier of the K loop, and the next tile's first fetch follows the barriers at the top of
+    // the tile loop.
+    float *f2buf = reinterpret_cast<float *>(stage_at(a.KB));
+    auto put_cand = [&](uint32_t at, int64_t v, int64_t partner, float ig) {
+        if (at < a.cap) a.cand[at] = Cand{(int32_t)v, r, (uint32_t)partner, ig};
+        else { atomicOr(&a.ovf[v], 1u); atomicOr(&a.st->overflow, 1u); }
+    };
     // packed integer counts: int8 n1 << 16 | n0; fp4 (4 n1) << 16 | 4 n0 from the exact
     // float32 value u = n1 * 2^14 + 4 n0 as u + (u >> 14) * (2^18 - 2^14)
     v4i cnt[4][4];
@@ -442,6 +473,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
             for (int n = 0; n < 4; ++n) {
                 uint32_t vx[7];
                 const float F2 = quad_pair(m, n, vx);
+                if constexpr (MODE != SWEEP_PAIRS) f2buf[(wave * 16 + m * 4 + n) * 64 + lane] = F2;
                 const int64_t rv = rv_of(m), cv = cv_of(n);
                 const bool valid = rv < cv && cv < a.p;
                 if constexpr (MODE == SWEEP_PAIRS) {
@@ -500,30 +532,33 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                 const float top = a.collect ? g : fmaxf(g, cmax[n]);
                 thrC[n] = top - rescore_window(a.w_abs, top);
             }
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-#pragma unroll
-                for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(cnt[m][n]) : : "memory");
+            // which pairs append (bit m * 4 + n), then one slot reservation for the wave
+            uint32_t selR = 0, selC = 0;
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
                 for (int n = 0; n < 4; ++n) {
-                    uint32_t vx[7];
-                    const float F2 = quad_pair(m, n, vx);
+                    const float F2 = f2buf[(wave * 16 + m * 4 + n) * 64 + lane];   // the first pass's
                     const int64_t rv = rv_of(m), cv = cv_of(n);
                     const bool valid = b == 0 && rv < cv && cv < a.p;   // one lane per pair
                     const float igR = Fc[n] - F2, igC = Fr[m] - F2;
-                    if (valid && igR >= thrR[m]) {
-                        uint32_t at = atomicAdd(&a.st->n_cand, 1u);
-                        if (at < a.cap) a.cand[at] = Cand{(int32_t)rv, r, (uint32_t)cv, igR};
-                        else { atomicOr(&a.ovf[rv], 1u); atomicOr(&a.st->overflow, 1u); }
-                    }
-                    if (valid && igC >= thrC[n]) {
-                        uint32_t at = atomicAdd(&a.st->n_cand, 1u);
-                        if (at < a.cap) a.cand[at] = Cand{(int32_t)cv, r, (uint32_t)rv, igC};
-                        else { atomicOr(&a.ovf[cv], 1u); atomicOr(&a.st->overflow, 1u); }
-                    }
+                    if (valid && igR >= thrR[m]) selR |= 1u << (m * 4 + n);
+                    if (valid && igC >= thrC[n]) selC |= 1u << (m * 4 + n);
                 }
+            uint32_t at = reserve_slots(&a.st->n_cand, __popc(selR) + __popc(selC), lane);
+            if (selR | selC) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) {
+                        const uint32_t bit = 1u << (m * 4 + n);
+                        if ((selR | selC) & bit) {
+                            const float F2 = f2buf[(wave * 16 + m * 4 + n) * 64 + lane];
+                            if (selR & bit) put_cand(at++, rv_of(m), cv_of(n), Fc[n] - F2);
+                            if (selC & bit) put_cand(at++, cv_of(n), rv_of(m), Fr[m] - F2);
+                        }
+                    }
+            }
         }
         if (a.collect) continue;
 #pragma unroll
@@ -629,6 +664,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                 const int64_t rv = row_var(m, s), cv = col_var(n);
                 const bool valid = rv < cv && cv < a.p;
                 const float F2 = pair_F2(tab);
+                if constexpr (MODE != SWEEP_PAIRS && W == 2) f2buf[(wave * 16 + m * 4 + n) * 64 + lane] = F2;
                 if constexpr (MODE == SWEEP_PAIRS) {
                     // parent data of the k = 3 sweep: the W x W packed counts and F of the pair
                     if (valid) {
@@ -699,35 +735,52 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
             float top = a.collect ? g : fmaxf(g, cmax[n]);
             thrC[n] = top - rescore_window(a.w_abs, top);
         }
-        // recompute from the accumulators (appends are rare); the empty asm stops the compiler
-        // from keeping the first pass's values alive instead
+        // W = 2: F of each pair from the first pass (LDS); W = 1 (64 values per lane, more than
+        // the stage holds): recomputed from the accumulators in four rounds of 16 (the empty asm
+        // stops the compiler from keeping the first pass's values alive instead), each round's F
+        // parked in the same LDS buffer.  Per round: which pairs append (bit m * 4 + n), one slot
+        // reservation for the wave, then the records.
+        if constexpr (W == 1) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+            for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(cnt[m][n]) : : "memory");
+                for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(cnt[m][n]) : : "memory");
+        }
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int s = 0; s < NP; ++s) {
+            uint32_t selR = 0, selC = 0;
 #pragma unroll
-            for (int n = 0; n < 4; ++n)
+            for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int s = 0; s < NP; ++s) {
+                for (int n = 0; n < 4; ++n) {
+                    float *slot = &f2buf[(wave * 16 + m * 4 + n) * 64 + lane];
+                    if constexpr (W == 1) {
+                        uint32_t tab[C][C];
+                        pair_table(m, n, s, tab);
+                        *slot = pair_F2(tab);
+                    }
+                    const float F2 = *slot;
                     const int64_t rv = row_var(m, s), cv = col_var(n);
                     const bool valid = rv < cv && cv < a.p;
-                    uint32_t tab[C][C];
-                    pair_table(m, n, s, tab);
-                    const float F2 = pair_F2(tab);
                     const float igR = Fc[n] - F2, igC = Fr[m][s] - F2;
-                    if (valid && igR >= thrR[m][s]) {
-                        uint32_t at = atomicAdd(&a.st->n_cand, 1u);
-                        if (at < a.cap) a.cand[at] = Cand{(int32_t)rv, r, (uint32_t)cv, igR};
-                        else { atomicOr(&a.ovf[rv], 1u); atomicOr(&a.st->overflow, 1u); }
-                    }
-                    if (valid && igC >= thrC[n]) {
-                        uint32_t at = atomicAdd(&a.st->n_cand, 1u);
-                        if (at < a.cap) a.cand[at] = Cand{(int32_t)cv, r, (uint32_t)rv, igC};
-                        else { atomicOr(&a.ovf[cv], 1u); atomicOr(&a.st->overflow, 1u); }
-                    }
+                    if (valid && igR >= thrR[m][s]) selR |= 1u << (m * 4 + n);
+                    if (valid && igC >= thrC[n]) selC |= 1u << (m * 4 + n);
                 }
+            uint32_t at = reserve_slots(&a.st->n_cand, __popc(selR) + __popc(selC), lane);
+            if (selR | selC) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) {
+                        const uint32_t bit = 1u << (m * 4 + n);
+                        if ((selR | selC) & bit) {
+                            const float F2 = f2buf[(wave * 16 + m * 4 + n) * 64 + lane];
+                            if (selR & bit) put_cand(at++, row_var(m, s), col_var(n), Fc[n] - F2);
+                            if (selC & bit) put_cand(at++, col_var(n), row_var(m, s), Fr[m][s] - F2);
+                        }
+                    }
+            }
+        }
     }
 
     // publish the maxima: one lane per variable, only where the tile raised the maximum read
