@@ -109,6 +109,28 @@ __host__ __device__ inline double key_f64(uint64_t k)
 // Tie tolerance of the argmax: candidates within tau of the maximum are tied.
 __host__ __device__ inline double tie_tau(double m) { return 1e-9 * (fabs(m) > 1.0 ? fabs(m) : 1.0); }
 
+// First of the `mine` consecutive candidate slots of this lane: an exclusive prefix sum of the
+// lanes' counts and one device-scope atomic per wave for the wave's total (every lane of the
+// wave must take part).  The sweeps append through it so that a wave waits on one returning
+// atomic on the shared counter per round of appends, not one per record.
+__device__ __forceinline__ uint32_t reserve_slots(uint32_t *counter, uint32_t mine, int lane)
+{
+    if (!__any(mine != 0)) return 0;
+    uint32_t incl = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, d);
+        if (lane >= d) incl += y;
+    }
+    const uint32_t total = (uint32_t)__shfl((int)incl, 63);
+    uint32_t base = 0;
+    if (total != 0) {
+        if (lane == 0) base = atomicAdd(counter, total);
+        base = (uint32_t)__shfl((int)base, 0);
+    }
+    return base + incl - mine;
+}
+
 // Everything a launch sequence needs about one problem (sizes, pseudocounts, buffers).
 struct Problem {
     Layout L;

@@ -156,27 +156,6 @@ __device__ inline void tri_index(int64_t tt, int &bi, int &bj)
     bi = (int)(tt - j * (j + 1) / 2);
 }
 
-// First of the `mine` consecutive candidate slots of this lane: an exclusive prefix sum of the
-// lanes' counts and one device-scope atomic per wave for the wave's total (every lane of the
-// wave must take part).  Appends otherwise serialise one returning atomic per pair and class of
-// threshold on a single counter.
-__device__ __forceinline__ uint32_t reserve_slots(uint32_t *counter, uint32_t mine, int lane)
-{
-    uint32_t incl = mine;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)incl, d);
-        if (lane >= d) incl += y;
-    }
-    const uint32_t total = (uint32_t)__shfl((int)incl, 63);
-    uint32_t base = 0;
-    if (total != 0) {
-        if (lane == 0) base = atomicAdd(counter, total);
-        base = (uint32_t)__shfl((int)base, 0);
-    }
-    return base + incl - mine;
-}
-
 template <int W, int MODE, int ENC, bool BATCH>
 __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 {

@@ -86,9 +86,9 @@ __device__ inline void full_pair(const uint32_t *pw, const uint32_t *Mx, const u
     }
 }
 
-__device__ inline void append3(const Sweep3Args &a, int v, uint32_t partner, float ig)
+// candidate record at a reserved slot, or the overflow marks when the buffer is full
+__device__ inline void put3(const Sweep3Args &a, uint32_t at, int v, uint32_t partner, float ig)
 {
-    uint32_t at = atomicAdd(&a.st->n_cand, 1u);
     if (at < a.cap) a.cand[at] = Cand{v, a.r, partner, ig};
     else { atomicOr(&a.ovf[v], 1u); atomicOr(&a.st->overflow, 1u); }
 }
@@ -263,18 +263,19 @@ __global__ __launch_bounds__(S3_THREADS) void k_sweep3(Sweep3Args a)
             const float igl = act ? F2ij - F3 : -INFINITY;   // gain of x_l given (x_i, x_j)
 
             // ---- member l: one value per lane
-            {
-                const float Gl = key_f32(a.G32[lc]);
-                if (act && igl >= Gl - window3(a.w_abs, Gl)) {
-                    append3(a, l, ((uint32_t)i << 16) | (uint32_t)j, igl);
-                    if (!a.collect && igl > Gl) atomicMax(&a.G32[l], f32_key(igl));
-                }
-            }
+            const float Gl = key_f32(a.G32[lc]);
+            const bool al = act && igl >= Gl - window3(a.w_abs, Gl);
+            if (al && !a.collect && igl > Gl) atomicMax(&a.G32[l], f32_key(igl));
             // ---- members i and j: chunk maxima over the lanes
             const float mi = wave_max(igi), mj = wave_max(igj);
             const float topi = a.collect ? Gi : fmaxf(mi, Gi), topj = a.collect ? Gj : fmaxf(mj, Gj);
-            if (act && igi >= topi - window3(a.w_abs, topi)) append3(a, i, ((uint32_t)j << 16) | (uint32_t)l, igi);
-            if (act && igj >= topj - window3(a.w_abs, topj)) append3(a, j, ((uint32_t)i << 16) | (uint32_t)l, igj);
+            const bool ai = act && igi >= topi - window3(a.w_abs, topi);
+            const bool aj = act && igj >= topj - window3(a.w_abs, topj);
+            // one slot reservation per chunk for the wave's records
+            uint32_t at = reserve_slots(&a.st->n_cand, (uint32_t)al + (uint32_t)ai + (uint32_t)aj, lane);
+            if (al) put3(a, at++, l, ((uint32_t)i << 16) | (uint32_t)j, igl);
+            if (ai) put3(a, at++, i, ((uint32_t)j << 16) | (uint32_t)l, igi);
+            if (aj) put3(a, at++, j, ((uint32_t)i << 16) | (uint32_t)l, igj);
             runi = fmaxf(runi, mi);
             runj = fmaxf(runj, mj);
             if (!a.collect) { Gi = fmaxf(Gi, mi); Gj = fmaxf(Gj, mj); }

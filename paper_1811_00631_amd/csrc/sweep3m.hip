@@ -100,9 +100,9 @@ __device__ inline void full3(const uint32_t (&d)[4], const uint32_t (&Mx)[3], co
     n[2][2] = My[2] - n[0][2] - n[1][2];
 }
 
-__device__ inline void append(const Sweep3mArgs &a, int v, uint32_t partner, float ig)
+// candidate record at a reserved slot, or the overflow marks when the buffer is full
+__device__ inline void put(const Sweep3mArgs &a, uint32_t at, int v, uint32_t partner, float ig)
 {
-    const uint32_t at = atomicAdd(&a.st->n_cand, 1u);
     if (at < a.cap) a.cand[at] = Cand{v, a.r, partner, ig};
     else { atomicOr(&a.ovf[v], 1u); atomicOr(&a.st->overflow, 1u); }
 }
@@ -420,21 +420,39 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
             for (int m = 0; m < 4; ++m)
 #pragma unroll
                 for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(cnt[m][n]) : : "memory");
+            // per m: the four triples' gains, which members append (bit 3 n + member), one slot
+            // reservation for the wave, then the records
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 JData jd;
                 load_j(m, jd);
+                float gI[4], gJ[4], gL[4];
+                uint32_t sel = 0;
 #pragma unroll
                 for (int n = 0; n < 4; ++n) {
+                    gI[n] = gJ[n] = gL[n] = 0.f;
                     const int j = jv[m], l = lv[n];
                     if (!__any(i < j && j < l && l < a.p)) continue;   // as in the first pass
                     float Fjl;
                     const float F3 = triple(m, n, jd, Fjl);
                     const bool valid = e == 0 && i < j && j < l && l < a.p;   // one lane per triple
-                    const float gi = Fjl - F3, gj = Fil[n] - F3, gl = jd.F - F3;
-                    if (valid && gi >= thrI) append(a, i, ((uint32_t)j << 16) | (uint32_t)l, gi);
-                    if (valid && gj >= thrJ[m]) append(a, j, ((uint32_t)i << 16) | (uint32_t)l, gj);
-                    if (valid && gl >= thrL[n]) append(a, l, ((uint32_t)i << 16) | (uint32_t)j, gl);
+                    gI[n] = Fjl - F3;
+                    gJ[n] = Fil[n] - F3;
+                    gL[n] = jd.F - F3;
+                    if (valid && gI[n] >= thrI) sel |= 1u << (3 * n);
+                    if (valid && gJ[n] >= thrJ[m]) sel |= 2u << (3 * n);
+                    if (valid && gL[n] >= thrL[n]) sel |= 4u << (3 * n);
+                }
+                uint32_t at = reserve_slots(&a.st->n_cand, __popc(sel), lane);
+                if (sel) {
+                    const int j = jv[m];
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) {
+                        const int l = lv[n];
+                        if (sel & (1u << (3 * n))) put(a, at++, i, ((uint32_t)j << 16) | (uint32_t)l, gI[n]);
+                        if (sel & (2u << (3 * n))) put(a, at++, j, ((uint32_t)i << 16) | (uint32_t)l, gJ[n]);
+                        if (sel & (4u << (3 * n))) put(a, at++, l, ((uint32_t)i << 16) | (uint32_t)j, gL[n]);
+                    }
                 }
             }
         }

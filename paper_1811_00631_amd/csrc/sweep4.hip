@@ -62,9 +62,9 @@ __device__ inline float wave_max4(float x)
 
 __device__ inline uint32_t pack3(int a, int b, int c) { return ((uint32_t)a << 20) | ((uint32_t)b << 10) | (uint32_t)c; }
 
-__device__ inline void append4(const Sweep4Args &a, int v, uint32_t partner, float ig)
+// candidate record at a reserved slot, or the overflow marks when the buffer is full
+__device__ inline void put4(const Sweep4Args &a, uint32_t at, int v, uint32_t partner, float ig)
 {
-    const uint32_t at = atomicAdd(&a.st->n_cand, 1u);
     if (at < a.cap) a.cand[at] = Cand{v, a.r, partner, ig};
     else { atomicOr(&a.ovf[v], 1u); atomicOr(&a.st->overflow, 1u); }
 }
@@ -220,20 +220,22 @@ __global__ __launch_bounds__(S4_THREADS) void k_sweep4(Sweep4Args a)
             const float igm = act ? Fijl - F4 : -INFINITY;
 
             // ---- member m: one value per lane
-            {
-                const float Gm = key_f32(a.G32[mc]);
-                if (act && igm >= Gm - window4(a.w_abs, Gm)) {
-                    append4(a, m, pack3(i, j, l), igm);
-                    if (!a.collect && igm > Gm) atomicMax(&a.G32[m], f32_key(igm));
-                }
-            }
+            const float Gm = key_f32(a.G32[mc]);
+            const bool am = act && igm >= Gm - window4(a.w_abs, Gm);
+            if (am && !a.collect && igm > Gm) atomicMax(&a.G32[m], f32_key(igm));
             // ---- members i, j, l: chunk maxima over the lanes
             const float mi = wave_max4(igi), mj = wave_max4(igj), ml = wave_max4(igl);
             const float topi = a.collect ? Gi : fmaxf(mi, Gi), topj = a.collect ? Gj : fmaxf(mj, Gj),
                         topl = a.collect ? Gl : fmaxf(ml, Gl);
-            if (act && igi >= topi - window4(a.w_abs, topi)) append4(a, i, pack3(j, l, m), igi);
-            if (act && igj >= topj - window4(a.w_abs, topj)) append4(a, j, pack3(i, l, m), igj);
-            if (act && igl >= topl - window4(a.w_abs, topl)) append4(a, l, pack3(i, j, m), igl);
+            const bool ai = act && igi >= topi - window4(a.w_abs, topi);
+            const bool aj = act && igj >= topj - window4(a.w_abs, topj);
+            const bool al = act && igl >= topl - window4(a.w_abs, topl);
+            // one slot reservation per chunk for the wave's records
+            uint32_t at = reserve_slots(&a.st->n_cand, (uint32_t)am + (uint32_t)ai + (uint32_t)aj + (uint32_t)al, lane);
+            if (am) put4(a, at++, m, pack3(i, j, l), igm);
+            if (ai) put4(a, at++, i, pack3(j, l, m), igi);
+            if (aj) put4(a, at++, j, pack3(i, l, m), igj);
+            if (al) put4(a, at++, l, pack3(i, j, m), igl);
             runi = fmaxf(runi, mi);
             runj = fmaxf(runj, mj);
             runl = fmaxf(runl, ml);
