@@ -43,10 +43,13 @@ template <> struct AccOf<true> { typedef v4f type; };
 // gather at an 8-byte stride would use half of the LDS banks.
 __host__ __device__ constexpr int stage_base(int ENC) { return ENC ? 24 * ENC : 0; }
 
-constexpr int SW_THREADS = 256;          // 4 waves, 2 x 2 wave grid, 64 x 64 outputs per wave
+// Waves per workgroup: 8 for three classes (2 x 4 wave grid, 64 x 32 outputs per wave; at most
+// 128 VGPRs, so 4 waves per SIMD), else 4 (2 x 2 grid, 64 x 64 outputs per wave, 2 per SIMD; the
+// two- and five-class epilogues hold more per lane).  The tile and its LDS are the same.
+__host__ __device__ constexpr int sw_waves(int W) { return W == 2 ? 8 : 4; }
 constexpr int SB = 8;                    // a super-tile is SB x SB tiles
 constexpr int XCDS = 8;                  // workgroup b runs on XCD b % 8
-constexpr int WG_PER_XCD = SB * SB;      // resident workgroups per XCD (2 per CU)
+constexpr int WG_PER_XCD = SB * SB;      // resident workgroups per XCD (2 per CU: LDS)
 constexpr int STAGE_BYTES = 2 * TILE_ROWS * KBLK;   // A and B tiles of one K block
 constexpr int NSTAGE = 3;                           // LDS ring of K blocks
 
@@ -165,6 +168,9 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     typedef typename AccOf<F4>::type Acc;
     constexpr int TV = TILE_ROWS / W;    // variables per tile side
     constexpr int NP = (W == 1) ? 4 : 1; // pairs held per lane per 16x16 block
+    constexpr int NWAVE = sw_waves(W), NT = NWAVE * 64;
+    constexpr int NN = 16 / NWAVE;       // 16 x 16 column blocks per wave (row blocks: 4)
+    constexpr int LPW = 16 / NWAVE;      // 1 KB operand fetches per wave and K block
     extern __shared__ __attribute__((aligned(16))) char smem[];
     char *stage = smem + stage_base(ENC);   // [NSTAGE buffers][A 8 KB | B 8 KB]
     // int8: tables after the stages, at run-time offsets (per problem)
@@ -174,7 +180,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 
     if (a.gated && a.st->collect_go == 0) return;   // workgroup-uniform
     const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave / (NWAVE / 2), wc = wave % (NWAVE / 2);
     const int q = lane >> 4, c16 = lane & 15;
 
     // the problem's entropy tables into LDS
@@ -184,14 +190,14 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         LQ = reinterpret_cast<float2 *>(EB + (a.N1 + 1) + ((a.N0 + a.N1) & 1));
         if constexpr (F4) {
             float *tf = reinterpret_cast<float *>(smem);
-            for (int i = t; i <= a.N0; i += SW_THREADS) tf[i] = a.EA[i];
-            for (int i = t; i <= a.N1; i += SW_THREADS) tf[T + i] = a.EB[i];
+            for (int i = t; i <= a.N0; i += NT) tf[i] = a.EA[i];
+            for (int i = t; i <= a.N1; i += NT) tf[T + i] = a.EB[i];
             float2 *lq = reinterpret_cast<float2 *>(smem + 8 * T);
-            for (int i = t; i <= a.N; i += SW_THREADS) lq[i] = a.LQ[i];
+            for (int i = t; i <= a.N; i += NT) lq[i] = a.LQ[i];
         } else {
-            for (int i = t; i <= a.N0; i += SW_THREADS) EA[i] = a.EA[i];
-            for (int i = t; i <= a.N1; i += SW_THREADS) EB[i] = a.EB[i];
-            for (int i = t; i <= a.N; i += SW_THREADS) LQ[i] = a.LQ[i];
+            for (int i = t; i <= a.N0; i += NT) EA[i] = a.EA[i];
+            for (int i = t; i <= a.N1; i += NT) EB[i] = a.EB[i];
+            for (int i = t; i <= a.N; i += NT) LQ[i] = a.LQ[i];
         }
     };
     int cur = 0;   // batch: the problem whose arguments and tables are loaded
@@ -258,43 +264,44 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     const int n1blk = a.KB - a.KB0;      // class-1 K blocks, accumulated first
     constexpr int kstride = TILE_ROWS * KBLK;
 
-    Acc acc[4][4];
+    Acc acc[4][NN];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) acc[m][n] = Acc{0, 0, 0, 0};
+        for (int n = 0; n < NN; ++n) acc[m][n] = Acc{0, 0, 0, 0};
 
     // K blocks in processing order: class 1 first, then class 0
     auto kblock = [&](int s_) { return s_ < n1blk ? a.KB0 + s_ : s_ - n1blk; };
     auto stage_at = [&](int s_) { return stage + (s_ % NSTAGE) * STAGE_BYTES; };
     // Operands go from global memory straight into LDS (global_load_lds_dwordx4): one
     // instruction fills 1 KB = 16 rows, lane i's 16 bytes landing at offset 16 i.  A stage is
-    // 16 such blocks (A rows 0..127, then B rows 0..127); wave w fills blocks 4w .. 4w+3, so
-    // waves 0-1 fetch the A panel and waves 2-3 the B panel.  The swizzle of the stage layout
-    // is applied on the global side: lane i fetches the chunk that belongs at its slot.
-    const int8_t *pan = wave < 2 ? panA : panB;
-    int goff[4];
+    // 16 such blocks (A rows 0..127, then B rows 0..127); wave w fills blocks LPW w ..
+    // LPW w + LPW - 1, so the first half of the waves fetch the A panel and the second half the
+    // B panel.  The swizzle of the stage layout is applied on the global side: lane i fetches
+    // the chunk that belongs at its slot.
+    const int8_t *pan = wave < NWAVE / 2 ? panA : panB;
+    int goff[LPW];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int row = 16 * ((wave * 4 + i) & 7) + (lane >> 2);
+    for (int i = 0; i < LPW; ++i) {
+        const int row = 16 * ((wave * LPW + i) & 7) + (lane >> 2);
         const int j = (lane & 3) ^ ((row >> 1) & 3);
         goff[i] = row * KBLK + j * 16;
     }
     auto issue = [&](int s_) {
         const int8_t *src = pan + (int64_t)kblock(s_) * kstride;
-        char *dst = stage_at(s_) + wave * 4 * 1024;
+        char *dst = stage_at(s_) + wave * LPW * 1024;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < LPW; ++i)
             __builtin_amdgcn_global_load_lds((const void *)(src + goff[i]),
                                              (__attribute__((address_space(3))) void *)(dst + i * 1024), 16, 0, 0);
     };
-    const int fa_off0 = lds_addr(wr * 64 + c16, q), fb_off0 = lds_addr(wc * 64 + c16, q);
-    auto frags = [&](int s_, v4i (&xa)[4], v4i (&xb)[4]) {
+    const int fa_off0 = lds_addr(wr * 64 + c16, q), fb_off0 = lds_addr(wc * 16 * NN + c16, q);
+    auto frags = [&](int s_, v4i (&xa)[4], v4i (&xb)[NN]) {
         const char *A = stage_at(s_), *B = A + TILE_ROWS * KBLK;
 #pragma unroll
         for (int m = 0; m < 4; ++m) xa[m] = *reinterpret_cast<const v4i *>(A + fa_off0 + m * 16 * KBLK);
 #pragma unroll
-        for (int n = 0; n < 4; ++n) xb[n] = *reinterpret_cast<const v4i *>(B + fb_off0 + n * 16 * KBLK);
+        for (int n = 0; n < NN; ++n) xb[n] = *reinterpret_cast<const v4i *>(B + fb_off0 + n * 16 * KBLK);
     };
     // Software pipeline over a ring of NSTAGE = 3 LDS stages; blocks are fetched two steps ahead
     // and their fragments read one step ahead.  Step s: the MFMAs of block s (fragments read
@@ -303,11 +310,11 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     // outstanding), passes a barrier (block s+1 is complete in LDS, and every wave has read
     // the fragments of block s, so its stage is free), reads the fragments of block s+1 and
     // fetches block s+3 into the stage of block s.
-    auto mma = [&](int s_, const v4i (&xa)[4], const v4i (&xb)[4]) {
+    auto mma = [&](int s_, const v4i (&xa)[4], const v4i (&xb)[NN]) {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) {
+            for (int n = 0; n < NN; ++n) {
                 if constexpr (F4) {
                     // A/B: 16 rows x 128 objects, lane l holds row l % 16 and 32 nibbles of
                     // one quarter of the objects; cbsz = blgp = 4 selects E2M1 for both operands
@@ -322,24 +329,24 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int n = 0; n < 4; ++n) {
+                for (int n = 0; n < NN; ++n) {
                     if constexpr (F4) acc[m][n] = acc[m][n] * 4096.0f;
                     else acc[m][n] = acc[m][n] << 16;
                 }
         }
     };
     // the plain barrier: a fenced one would also drain the fetches still in flight
-    auto next_block = [&](int s_, v4i (&ya)[4], v4i (&yb)[4]) {
-        if (s_ + 2 < a.KB) __builtin_amdgcn_s_waitcnt(0x0F74);   // vmcnt(4)
-        else __builtin_amdgcn_s_waitcnt(0x0F70);                 // vmcnt(0)
+    auto next_block = [&](int s_, v4i (&ya)[4], v4i (&yb)[NN]) {
+        if (s_ + 2 < a.KB) __builtin_amdgcn_s_waitcnt(0x0F70 | LPW);   // vmcnt(LPW)
+        else __builtin_amdgcn_s_waitcnt(0x0F70);                       // vmcnt(0)
         __builtin_amdgcn_s_barrier();
         frags(s_ + 1, ya, yb);
         if (s_ + 3 < a.KB) issue(s_ + 3);
     };
-    v4i fa0[4], fb0[4], fa1[4], fb1[4];
+    v4i fa0[4], fb0[NN], fa1[4], fb1[NN];
     issue(0);
     if (a.KB > 1) issue(1);
-    if (a.KB > 1) __builtin_amdgcn_s_waitcnt(0x0F74);
+    if (a.KB > 1) __builtin_amdgcn_s_waitcnt(0x0F70 | LPW);
     else __builtin_amdgcn_s_waitcnt(0x0F70);
     __builtin_amdgcn_s_barrier();
     frags(0, fa0, fb0);
@@ -355,7 +362,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 
     // ---------------------------------------------------------------- epilogue
     // W >= 2: the first pass keeps each pair's float32 F for the append pass in the stage that
-    // follows the last block's, 16 pairs x 64 lanes = 4 KB per wave.  That stage held block
+    // follows the last block's, 4 NN pairs x 64 lanes = 16 KB per workgroup.  That stage held block
     // KB - 3 (or nothing): every wave read its fragments and every fetch landed before the last
     // barrier of the K loop, and the next tile's first fetch follows the barriers at the top of
     // the tile loop.
@@ -366,11 +373,11 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     };
     // packed integer counts: int8 n1 << 16 | n0; fp4 (4 n1) << 16 | 4 n0 from the exact
     // float32 value u = n1 * 2^14 + 4 n0 as u + (u >> 14) * (2^18 - 2^14)
-    v4i cnt[4][4];
+    v4i cnt[4][NN];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
+        for (int n = 0; n < NN; ++n) {
             if constexpr (F4) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
@@ -383,6 +390,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         }
 
     if constexpr (W == 4) {
+        static_assert(NN == 4, "the five-class epilogue assumes 4 x 4 blocks per wave");
         // Five classes: block (m, n) holds 4 x 4 pairs.  The lane holds the four row bins of row
         // variable q and column bin b = c16 % 4 of column variable c16 / 4, so a pair's 4 x 4
         // direct counts lie on one lane quad.  Each lane evaluates its column's voxels (4 direct
@@ -452,7 +460,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
             for (int n = 0; n < 4; ++n) {
                 uint32_t vx[7];
                 const float F2 = quad_pair(m, n, vx);
-                if constexpr (MODE != SWEEP_PAIRS) f2buf[(wave * 16 + m * 4 + n) * 64 + lane] = F2;
+                if constexpr (MODE != SWEEP_PAIRS) f2buf[(wave * 4 * NN + m * NN + n) * 64 + lane] = F2;
                 const int64_t rv = rv_of(m), cv = cv_of(n);
                 const bool valid = rv < cv && cv < a.p;
                 if constexpr (MODE == SWEEP_PAIRS) {
@@ -517,7 +525,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
             for (int m = 0; m < 4; ++m)
 #pragma unroll
                 for (int n = 0; n < 4; ++n) {
-                    const float F2 = f2buf[(wave * 16 + m * 4 + n) * 64 + lane];   // the first pass's
+                    const float F2 = f2buf[(wave * 4 * NN + m * NN + n) * 64 + lane];   // the first pass's
                     const int64_t rv = rv_of(m), cv = cv_of(n);
                     const bool valid = b == 0 && rv < cv && cv < a.p;   // one lane per pair
                     const float igR = Fc[n] - F2, igC = Fr[m] - F2;
@@ -532,7 +540,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                     for (int n = 0; n < 4; ++n) {
                         const uint32_t bit = 1u << (m * 4 + n);
                         if ((selR | selC) & bit) {
-                            const float F2 = f2buf[(wave * 16 + m * 4 + n) * 64 + lane];
+                            const float F2 = f2buf[(wave * 4 * NN + m * NN + n) * 64 + lane];
                             if (selR & bit) put_cand(at++, rv_of(m), cv_of(n), Fc[n] - F2);
                             if (selC & bit) put_cand(at++, cv_of(n), rv_of(m), Fr[m] - F2);
                         }
@@ -557,17 +565,17 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         return I0 + wr * 32 + m * 8 + 2 * q + odd;
     };
     auto col_var = [&](int n) -> int64_t {
-        if (W == 1) return J0 + wc * 64 + n * 16 + c16;
-        return J0 + wc * 32 + n * 8 + (c16 >> 1);
+        if (W == 1) return J0 + wc * 16 * NN + n * 16 + c16;
+        return J0 + wc * 8 * NN + n * 8 + (c16 >> 1);
     };
     const uint32_t *margr = a.marg + (int64_t)r * a.p_pad * C;
     const float *F1r = a.F1 + (int64_t)r * a.p_pad;
 
     // marginals are stored n1 << 16 | n0; the fp4 packing is 4 times that
     auto repack = [](uint32_t x) -> uint32_t { return F4 ? x << 2 : x; };
-    uint32_t Mr[4][NP][C], Mc[4][C];
-    float Fr[4][NP], Fc[4];
-    float thrR[4][NP], thrC[4], gR[4][NP], gC[4];   // thresholds; maxima as read (a lower bound)
+    uint32_t Mr[4][NP][C], Mc[NN][C];
+    float Fr[4][NP], Fc[NN];
+    float thrR[4][NP], thrC[NN], gR[4][NP], gC[NN];   // thresholds; maxima as read (a lower bound)
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -581,7 +589,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
             thrR[m][s] = gk - rescore_window(a.w_abs, gk);
         }
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
+    for (int n = 0; n < NN; ++n) {
         int64_t v = col_var(n);
 #pragma unroll
         for (int c = 0; c < C; ++c) Mc[n][c] = repack(margr[v * C + c]);
@@ -622,20 +630,20 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         return sum_vox<ENC, C * C>(P, smem, EA, EB, LQ);
     };
 
-    float rmax[4][NP], cmax[4];
+    float rmax[4][NP], cmax[NN];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int s = 0; s < NP; ++s) rmax[m][s] = -INFINITY;
 #pragma unroll
-    for (int n = 0; n < 4; ++n) cmax[n] = -INFINITY;
+    for (int n = 0; n < NN; ++n) cmax[n] = -INFINITY;
     bool hot = false;
 
     const bool emit = MODE == SWEEP_DEBUG_COUNTS && r == a.disc_sel;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n)
+        for (int n = 0; n < NN; ++n)
 #pragma unroll
             for (int s = 0; s < NP; ++s) {
                 uint32_t tab[C][C];
@@ -643,7 +651,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                 const int64_t rv = row_var(m, s), cv = col_var(n);
                 const bool valid = rv < cv && cv < a.p;
                 const float F2 = pair_F2(tab);
-                if constexpr (MODE != SWEEP_PAIRS && W == 2) f2buf[(wave * 16 + m * 4 + n) * 64 + lane] = F2;
+                if constexpr (MODE != SWEEP_PAIRS && W == 2) f2buf[(wave * 4 * NN + m * NN + n) * 64 + lane] = F2;
                 if constexpr (MODE == SWEEP_PAIRS) {
                     // parent data of the k = 3 sweep: the W x W packed counts and F of the pair
                     if (valid) {
@@ -690,7 +698,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
             rmax[m][s] = x;
         }
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
+    for (int n = 0; n < NN; ++n) {
         float x = cmax[n];
         if (W == 2) x = fmaxf(x, __shfl_xor(x, 1));
         x = fmaxf(x, __shfl_xor(x, 16));
@@ -709,7 +717,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                 thrR[m][s] = top - rescore_window(a.w_abs, top);
             }
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
+        for (int n = 0; n < NN; ++n) {
             float g = key_f32(a.G32[col_var(n)]);
             float top = a.collect ? g : fmaxf(g, cmax[n]);
             thrC[n] = top - rescore_window(a.w_abs, top);
@@ -717,13 +725,13 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         // W = 2: F of each pair from the first pass (LDS); W = 1 (64 values per lane, more than
         // the stage holds): recomputed from the accumulators in four rounds of 16 (the empty asm
         // stops the compiler from keeping the first pass's values alive instead), each round's F
-        // parked in the same LDS buffer.  Per round: which pairs append (bit m * 4 + n), one slot
+        // parked in the same LDS buffer.  Per round: which pairs append (bit m * NN + n), one slot
         // reservation for the wave, then the records.
         if constexpr (W == 1) {
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(cnt[m][n]) : : "memory");
+                for (int n = 0; n < NN; ++n) asm volatile("" : "+v"(cnt[m][n]) : : "memory");
         }
 #pragma unroll
         for (int s = 0; s < NP; ++s) {
@@ -731,8 +739,8 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int n = 0; n < 4; ++n) {
-                    float *slot = &f2buf[(wave * 16 + m * 4 + n) * 64 + lane];
+                for (int n = 0; n < NN; ++n) {
+                    float *slot = &f2buf[(wave * 4 * NN + m * NN + n) * 64 + lane];
                     if constexpr (W == 1) {
                         uint32_t tab[C][C];
                         pair_table(m, n, s, tab);
@@ -742,18 +750,18 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                     const int64_t rv = row_var(m, s), cv = col_var(n);
                     const bool valid = rv < cv && cv < a.p;
                     const float igR = Fc[n] - F2, igC = Fr[m][s] - F2;
-                    if (valid && igR >= thrR[m][s]) selR |= 1u << (m * 4 + n);
-                    if (valid && igC >= thrC[n]) selC |= 1u << (m * 4 + n);
+                    if (valid && igR >= thrR[m][s]) selR |= 1u << (m * NN + n);
+                    if (valid && igC >= thrC[n]) selC |= 1u << (m * NN + n);
                 }
             uint32_t at = reserve_slots(&a.st->n_cand, __popc(selR) + __popc(selC), lane);
             if (selR | selC) {
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
 #pragma unroll
-                    for (int n = 0; n < 4; ++n) {
-                        const uint32_t bit = 1u << (m * 4 + n);
+                    for (int n = 0; n < NN; ++n) {
+                        const uint32_t bit = 1u << (m * NN + n);
                         if ((selR | selC) & bit) {
-                            const float F2 = f2buf[(wave * 16 + m * 4 + n) * 64 + lane];
+                            const float F2 = f2buf[(wave * 4 * NN + m * NN + n) * 64 + lane];
                             if (selR & bit) put_cand(at++, row_var(m, s), col_var(n), Fc[n] - F2);
                             if (selC & bit) put_cand(at++, col_var(n), row_var(m, s), Fr[m][s] - F2);
                         }
@@ -773,20 +781,20 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         for (int s = 0; s < NP; ++s)
             if (row_leader && rmax[m][s] > gR[m][s]) atomicMax(&a.G32[row_var(m, s)], f32_key(rmax[m][s]));
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
+    for (int n = 0; n < NN; ++n)
         if (col_leader && cmax[n] > gC[n]) atomicMax(&a.G32[col_var(n)], f32_key(cmax[n]));
     }   // W <= 2
     }   // work items
 }
 
 template <int W, int MODE, int ENC>
-__global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep2(Sweep2Args a)
+__global__ __launch_bounds__(sw_waves(W) * 64, 2) __attribute__((amdgpu_waves_per_eu(sw_waves(W) / 2, sw_waves(W) / 2))) void k_sweep2(Sweep2Args a)
 {
     sweep2_run<W, MODE, ENC, false>(a, nullptr);
 }
 
 template <int W, int ENC>
-__global__ __launch_bounds__(SW_THREADS, 2) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep2_batch(Sweep2Batch bt)
+__global__ __launch_bounds__(sw_waves(W) * 64, 2) __attribute__((amdgpu_waves_per_eu(sw_waves(W) / 2, sw_waves(W) / 2))) void k_sweep2_batch(Sweep2Batch bt)
 {
     sweep2_run<W, SWEEP_MAX, ENC, true>(bt.p[0], &bt);
 }
@@ -867,7 +875,7 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int grid = P.workgroups > 0 ? P.workgroups : XCDS * WG_PER_XCD;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(SW_THREADS), lds, P.stream, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sw_waves(W) * 64), lds, P.stream, a);
     return hipGetLastError();
 }
 
@@ -921,7 +929,7 @@ static hipError_t batch_launch(const Problem *const *Ps, int n, Status *queue, s
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int grid = Ps[0]->workgroups > 0 ? Ps[0]->workgroups : XCDS * WG_PER_XCD;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(SW_THREADS), lds, Ps[0]->stream, b);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sw_waves(W) * 64), lds, Ps[0]->stream, b);
     return hipGetLastError();
 }
 
