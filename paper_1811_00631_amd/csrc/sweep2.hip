@@ -304,12 +304,13 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         for (int n = 0; n < NN; ++n) xb[n] = *reinterpret_cast<const v4i *>(B + fb_off0 + n * 16 * KBLK);
     };
     // Software pipeline over a ring of NSTAGE = 3 LDS stages; blocks are fetched two steps ahead
-    // and their fragments read one step ahead.  Step s: the MFMAs of block s (fragments read
-    // during step s-1) go out; meanwhile the wave waits until its fetches of block s+1 have
-    // landed (loads complete in issue order, so at most the 4 fetches of block s+2 may still be
-    // outstanding), passes a barrier (block s+1 is complete in LDS, and every wave has read
-    // the fragments of block s, so its stage is free), reads the fragments of block s+1 and
-    // fetches block s+3 into the stage of block s.
+    // and their fragments read one step ahead.  Step s: the wave waits until its fragment reads
+    // of block s (issued during step s-1) and its fetches of block s+1 have completed (loads
+    // complete in issue order, so the LPW fetches of block s+2 may still be outstanding), passes
+    // a barrier (block s+1 is complete in LDS, and every wave holds the fragments of block s, so
+    // its stage is free), issues the fragment reads of block s+1 and the fetch of block s+3 into
+    // the stage of block s, then the MFMAs of block s: the reads for the next step are in flight
+    // while this step's products go out.
     auto mma = [&](int s_, const v4i (&xa)[4], const v4i (&xb)[NN]) {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
@@ -336,12 +337,15 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         }
     };
     // the plain barrier: a fenced one would also drain the fetches still in flight
-    auto next_block = [&](int s_, v4i (&ya)[4], v4i (&yb)[NN]) {
-        if (s_ + 2 < a.KB) __builtin_amdgcn_s_waitcnt(0x0F70 | LPW);   // vmcnt(LPW)
-        else __builtin_amdgcn_s_waitcnt(0x0F70);                       // vmcnt(0)
-        __builtin_amdgcn_s_barrier();
-        frags(s_ + 1, ya, yb);
-        if (s_ + 3 < a.KB) issue(s_ + 3);
+    auto step = [&](int s_, const v4i (&ca)[4], const v4i (&cb)[NN], v4i (&na)[4], v4i (&nb)[NN]) {
+        if (s_ + 1 < a.KB) {
+            if (s_ + 2 < a.KB) __builtin_amdgcn_s_waitcnt(0x0070 | LPW);   // vmcnt(LPW) lgkmcnt(0)
+            else __builtin_amdgcn_s_waitcnt(0x0070);                       // vmcnt(0) lgkmcnt(0)
+            __builtin_amdgcn_s_barrier();
+            frags(s_ + 1, na, nb);
+            if (s_ + 3 < a.KB) issue(s_ + 3);
+        }
+        mma(s_, ca, cb);
     };
     v4i fa0[4], fb0[NN], fa1[4], fb1[NN];
     issue(0);
@@ -353,12 +357,10 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     if (a.KB > 2) issue(2);
     int s = 0;
     for (; s + 1 < a.KB; s += 2) {
-        mma(s, fa0, fb0);
-        next_block(s, fa1, fb1);
-        mma(s + 1, fa1, fb1);
-        if (s + 2 < a.KB) next_block(s + 1, fa0, fb0);
+        step(s, fa0, fb0, fa1, fb1);
+        step(s + 1, fa1, fb1, fa0, fb0);
     }
-    if (s < a.KB) mma(s, fa0, fb0);
+    if (s < a.KB) step(s, fa0, fb0, fa1, fb1);
 
     // ---------------------------------------------------------------- epilogue
     // W >= 2: the first pass keeps each pair's float32 F for the append pass in the stage that
