@@ -59,10 +59,13 @@ def _wl(name):
     return {"headline": workloads.headline, "xor_small": workloads.xor_small,
             "madelon_like": workloads.madelon_like, "parity3": workloads.parity3,
             "genomics_like": workloads.genomics_like,
-            "madelon4": lambda: workloads.madelon_like(divisions=1, n_disc=1, k=4)}[name]()
+            "madelon4": lambda: workloads.madelon_like(divisions=1, n_disc=1, k=4),
+            "madelon2_d2": lambda: workloads.madelon_like(divisions=1, n_disc=30, k=2),
+            "madelon3_d2": lambda: workloads.madelon_like(divisions=1, n_disc=30, k=3)}[name]()
 
 
-WORKLOADS = ["headline", "xor_small", "madelon_like", "parity3", "genomics_like", "madelon4", "batch12", "serving"]
+WORKLOADS = ["headline", "xor_small", "madelon_like", "parity3", "genomics_like", "madelon4", "madelon2_d2",
+             "madelon3_d2", "batch12", "serving"]
 WORKLOAD_TEXT = {
     "headline": "genomics-shaped k=2: N=2000, p=20000 log-normal, 10 planted XOR pairs, balanced y, d=3, "
                 "30 random discretisations (range 0.5, xi 0.25)",
@@ -73,6 +76,8 @@ WORKLOAD_TEXT = {
                      "30 discretisations",
     "madelon4": "Madelon-shaped k=4: N=2000, p=500 (5 base + 15 combinations + 480 noise), d=2, 1 discretisation "
                 "(the shape of the paper's 4D timing)",
+    "madelon2_d2": "Madelon-shaped k=2: N=2000, p=500, d=2, 30 discretisations (the shape of the paper's 2D timing)",
+    "madelon3_d2": "Madelon-shaped k=3: N=2000, p=500, d=2, 30 discretisations (the shape of the paper's 3D timing)",
     "batch12": "12 Madelon-shaped k=2 datasets of uneven size (N 500-2000, p 200-600), d=3, 30 discretisations each: "
                "one fused persistent launch vs separate calls",
     "serving": "serving trace: 256 requests, Poisson arrivals at 0.8 x the measured batched capacity, 32 resident "
