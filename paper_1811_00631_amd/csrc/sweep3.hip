@@ -39,7 +39,9 @@ struct Sweep3Args {
     int collect;
 };
 
-constexpr int S3_THREADS = 256;
+// threads per workgroup: 8 waves at two classes (59 VGPRs: 8 waves per SIMD at 4 workgroups per
+// CU), else 4
+__host__ __device__ constexpr int s3_threads(int W) { return W == 1 ? 512 : 256; }
 
 __device__ inline float vox3(uint32_t P, const float *EA, const float *EB, const float2 *LQ)
 {
@@ -94,7 +96,7 @@ __device__ inline void put3(const Sweep3Args &a, uint32_t at, int v, uint32_t pa
 }
 
 template <int W>
-__global__ __launch_bounds__(S3_THREADS) void k_sweep3(Sweep3Args a)
+__global__ __launch_bounds__(s3_threads(W)) void k_sweep3(Sweep3Args a)
 {
     constexpr int C = W + 1;
     if (a.collect && a.st->collect_go == 0) return;   // collect pass not needed (uniform)
@@ -103,9 +105,9 @@ __global__ __launch_bounds__(S3_THREADS) void k_sweep3(Sweep3Args a)
     float *EB = EA + (a.N0 + 1);
     float2 *LQ = reinterpret_cast<float2 *>(EB + (a.N1 + 1) + ((a.N0 + a.N1) & 1));
     const int t = threadIdx.x, lane = t & 63;
-    for (int i = t; i <= a.N0; i += S3_THREADS) EA[i] = a.EA[i];
-    for (int i = t; i <= a.N1; i += S3_THREADS) EB[i] = a.EB[i];
-    for (int i = t; i <= a.N; i += S3_THREADS) LQ[i] = a.LQ[i];
+    for (int i = t; i <= a.N0; i += s3_threads(W)) EA[i] = a.EA[i];
+    for (int i = t; i <= a.N1; i += s3_threads(W)) EB[i] = a.EB[i];
+    for (int i = t; i <= a.N; i += s3_threads(W)) LQ[i] = a.LQ[i];
     __syncthreads();
 
     const uint32_t *margr = a.marg + (int64_t)a.r * a.p_pad * C;
@@ -320,7 +322,10 @@ static hipError_t sweep3_launch(const Problem &P, int r, bool collect)
     auto kern = k_sweep3<W>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(P.workgroups > 0 ? 2 * P.workgroups : 1024), dim3(S3_THREADS), lds, P.stream, a);
+    // resident waves per SIMD: 8 at W = 1 (4 workgroups of 8 waves per CU), 5-6 at W = 2 (6 of
+    // 4, registers permitting), 4 otherwise
+    const int grid = P.workgroups > 0 ? 2 * P.workgroups : (W == 2 ? 1536 : 1024);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(s3_threads(W)), lds, P.stream, a);
     return hipGetLastError();
 }
 
