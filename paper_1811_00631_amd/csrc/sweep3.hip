@@ -3,8 +3,9 @@
 // For one discretisation, every triple i < j < l gets its per-class voxel table (the counters
 // N^d of section "Algorithm and implementation").  Each variable is stored as W = C-1 bin
 // bitsets per class over class-sorted objects ([class][word][variable][bin] u32).  One wave
-// takes a pair (i, j); its lanes take 64 third variables l > j at a time.  The pair bitsets
-// B_i[a] & B_j[b] are wave-uniform (scalar loads and ANDs), the lane's B_l[e] words are
+// takes a pair (i, j); its lanes take 64 third variables l > j at a time.  The pair words
+// B_i[a] & B_j[b] are wave-uniform: lane u holds word u of each run of 64 (one coalesced load
+// per run) and the word loop takes them with V_READLANE; the lane's B_l[e] words are
 // coalesced vector loads, and V_BCNT_U32_B32 accumulates popcount(B_i[a] & B_j[b] & B_l[e])
 // for the W^3 bin triples a, b, e < W.  Both classes share one counter: class 1 first, shift by
 // 16, then class 0, as in the pair sweep.  The remaining C^3 - W^3 voxels follow exactly from
@@ -96,7 +97,7 @@ __device__ inline void put3(const Sweep3Args &a, uint32_t at, int v, uint32_t pa
 }
 
 template <int W>
-__global__ __launch_bounds__(s3_threads(W)) void k_sweep3(Sweep3Args a)
+__global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3Args a)
 {
     constexpr int C = W + 1;
     if (a.collect && a.st->collect_go == 0) return;   // collect pass not needed (uniform)
@@ -154,24 +155,40 @@ __global__ __launch_bounds__(s3_threads(W)) void k_sweep3(Sweep3Args a)
             for (int cls = 1; cls >= 0; --cls) {
                 const uint32_t *bw = cls ? bits1 : bits0;
                 const int nw = cls ? a.w1 : a.w0;
-                for (int w = 0; w < nw; ++w) {
-                    const uint32_t *row = bw + (int64_t)w * plane;
-                    uint32_t bi[W], bj[W], bl[W];
+                for (int wb = 0; wb < nw; wb += 64) {
+                    // lane u holds word wb + u of the pair's words B_i[x] & B_j[y] (one coalesced
+                    // load per 64 words); the word loop reads them with readlane
+                    uint32_t pw[W][W];
+                    {
+                        const int wu = wb + lane;
+                        const uint32_t *row = bw + (int64_t)(wu < nw ? wu : nw - 1) * plane;
+                        uint32_t bi[W], bj[W];
 #pragma unroll
-                    for (int x = 0; x < W; ++x) {
-                        bi[x] = __builtin_amdgcn_readfirstlane(row[(int64_t)i * W + x]);
-                        bj[x] = __builtin_amdgcn_readfirstlane(row[(int64_t)j * W + x]);
-                        bl[x] = row[(int64_t)lc * W + x];
-                    }
-#pragma unroll
-                    for (int x = 0; x < W; ++x)
-#pragma unroll
-                        for (int y = 0; y < W; ++y) {
-                            const uint32_t pij = bi[x] & bj[y];
-#pragma unroll
-                            for (int z = 0; z < W; ++z)
-                                cnt[x][y][z] += __builtin_popcount(pij & bl[z]);   // v_bcnt_u32_b32
+                        for (int x = 0; x < W; ++x) {
+                            bi[x] = row[(int64_t)i * W + x];
+                            bj[x] = row[(int64_t)j * W + x];
                         }
+#pragma unroll
+                        for (int x = 0; x < W; ++x)
+#pragma unroll
+                            for (int y = 0; y < W; ++y) pw[x][y] = bi[x] & bj[y];
+                    }
+                    const int wn = nw - wb < 64 ? nw - wb : 64;
+                    for (int u = 0; u < wn; ++u) {
+                        const uint32_t *row = bw + (int64_t)(wb + u) * plane;
+                        uint32_t bl[W];
+#pragma unroll
+                        for (int z = 0; z < W; ++z) bl[z] = row[(int64_t)lc * W + z];
+#pragma unroll
+                        for (int x = 0; x < W; ++x)
+#pragma unroll
+                            for (int y = 0; y < W; ++y) {
+                                const uint32_t pij = __builtin_amdgcn_readlane(pw[x][y], u);
+#pragma unroll
+                                for (int z = 0; z < W; ++z)
+                                    cnt[x][y][z] += __builtin_popcount(pij & bl[z]);   // v_bcnt_u32_b32
+                            }
+                    }
                 }
                 if (cls == 1) {
 #pragma unroll
