@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="pick engine and persistent grid size with the autotuner (cached per shape)")
     ap.add_argument("--engine", default="auto", choices=["auto", "mfma_fp4", "mfma", "bitset"],
-                    help="auto: fp4 MFMA for k=2 while each class has < 4096 objects, bitset for k=3")
+                    help="auto: fp4 MFMA for k=2 and for k=3 at d=2 or 3 while each class has < 4096 objects, else int8 MFMA (k=2) or bitsets")
     ap.add_argument("--graph", action="store_true",
                     help="each step replays a CUDA graph of one asynchronous call (no host synchronisation)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -351,7 +351,7 @@ def main():
     W = div
     n0, n1 = int((w.y == 0).sum()), int((w.y == 1).sum())
     fp4 = args.engine == "mfma_fp4" or (args.engine == "auto" and max(n0, n1) < 4096)
-    fp4 = fp4 and (k == 2 or div == 2)
+    fp4 = fp4 and (k == 2 or (k == 3 and div in (1, 2)))
     k3_mfma = k == 3 and fp4 and not args.graph   # the asynchronous call runs k = 3 on bitsets
     if k == 2:
         ops_per_unit = 2 * w.n_obj * W * W           # MACs x 2 of the one-hot Gram product per pair
@@ -366,7 +366,8 @@ def main():
         ops_per_unit = 2 * w.n_obj * W ** 3          # MACs x 2 of the pair one-hot x one-hot product
         achieved = tuples * ops_per_unit / (sweep_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": FP4_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP4_PEAK_TFLOPS, "traffic": None, "kernel": f"k_sweep3m (+ pair data)",
+                "frac": achieved / FP4_PEAK_TFLOPS, "traffic": None,
+                "kernel": f"k_sweep3m{'1' if W == 1 else ''} (+ pair data)",
                 "per_unit": f"2*N*(d-1)^3 = {ops_per_unit} fp4 ops per triple table",
                 "units_per_launch": tuples, "kernel_ms": sweep_ms}
     elif k == 4:

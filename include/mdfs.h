@@ -59,7 +59,7 @@ typedef enum {
 
 typedef enum {
     MDFS_ENGINE_AUTO = 0,     /* k=2: fp4 MFMA if both classes < 4096 objects, else int8 MFMA;
-                                 k=3: fp4 MFMA for 3 classes under the same condition, else
+                                 k=3: fp4 MFMA for 2 or 3 classes under the same condition, else
                                  bitset; k=4: bitset */
     MDFS_ENGINE_MFMA = 1,     /* one-hot int8 contraction on the matrix cores */
     MDFS_ENGINE_BITSET = 2,   /* per-class bitsets, AND + popcount */

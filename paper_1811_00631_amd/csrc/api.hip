@@ -103,8 +103,8 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
         return fail(MDFS_E_LIMIT, "k=4 runs on the bitset engine");
     if (sweep && prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA)
         return fail(MDFS_E_LIMIT, "k=3 on the matrix cores uses the fp4 encoding (engine mfma_fp4)");
-    if (sweep && prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA_FP4 && prm->divisions != 2)
-        return fail(MDFS_E_LIMIT, "k=3 on the matrix cores is built for divisions=2 (3 classes)");
+    if (sweep && prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA_FP4 && prm->divisions != 1 && prm->divisions != 2)
+        return fail(MDFS_E_LIMIT, "k=3 on the matrix cores is built for divisions=1 or 2 (2 or 3 classes)");
     if (sweep && prm->k == 2 && prm->engine == MDFS_ENGINE_BITSET)
         return fail(MDFS_E_LIMIT, "k=2 has the MFMA engines only in this build");
     if (prm->n_disc < 1) return fail(MDFS_E_ARG, "n_disc=%d < 1", prm->n_disc);
@@ -214,11 +214,11 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
         if (prm->k == 4)
             P.err_bound = screen_err_bound(N, P.beta0, P.beta1, C * C * C * C) +
                           screen_err_bound(N, P.beta0, P.beta1, C * C * C);
-        // k = 3 engine: matrix cores for three classes in the fp4 encoding (auto or asked for)
-        P.k3_mfma = prm->k == 3 && prm->divisions == 2 && P.fp4 &&
+        // k = 3 engine: matrix cores for two or three classes in the fp4 encoding (auto or asked for)
+        P.k3_mfma = prm->k == 3 && (prm->divisions == 1 || prm->divisions == 2) && P.fp4 &&
                     (prm->engine == MDFS_ENGINE_AUTO || prm->engine == MDFS_ENGINE_MFMA_FP4);
         if (prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA_FP4 && !P.k3_mfma)
-            return fail(MDFS_E_LIMIT, "k=3 matrix-core engine needs classes < 4096 objects");
+            return fail(MDFS_E_LIMIT, "k=3 matrix-core engine needs d = 2 or 3 and classes < 4096 objects");
         if (P.k3_mfma && sweep3m_lds_bytes(P) > LDS_MAX)
             return fail(MDFS_E_LIMIT, "k=3 matrix-core sweep: LDS tables too large");
     }
@@ -272,7 +272,7 @@ static int upload_k3_tiles(Problem &P)
 {
     std::vector<int64_t> apref;
     std::vector<int32_t> ablk;
-    sweep3m_tiles(P.L.p, apref, ablk);
+    sweep3m_tiles(P.L.p, P.L.W, apref, ablk);
     P.n_ablk3 = (int64_t)ablk.size();
     P.n_tiles3 = apref.back();
     if (ablk.empty()) return MDFS_OK;

@@ -181,7 +181,7 @@ hipError_t launch_sweep4(const Problem &P, int r, bool collect);
 hipError_t launch_sweep3m(const Problem &P, int r, bool collect);
 size_t sweep3m_lds_bytes(const Problem &P);
 // host-side tile list of the k = 3 matrix-core sweep (first tile per A block, A blocks)
-void sweep3m_tiles(int64_t p, std::vector<int64_t> &apref, std::vector<int32_t> &ablk);
+void sweep3m_tiles(int64_t p, int W, std::vector<int64_t> &apref, std::vector<int32_t> &ablk);
 hipError_t launch_reset_queue(const Problem &P);
 hipError_t launch_finalize(const Problem &P, float *ig_max, int32_t *argmax, int32_t *argmax_disc);
 // every variable's threshold key set to `key` (the interesting-tuples collect pass)

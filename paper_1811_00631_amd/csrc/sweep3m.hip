@@ -468,6 +468,347 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Two classes (W = 1): one one-hot row per variable.  Tile: one i; A rows = the 128 j of block jb
+// (each ANDed with the row of i when its fragment is read), B rows = the 128 l of block lb.  The
+// lane (q, c16) of 16 x 16 block (m, n) holds T[0][0][0] of the four triples (i, j, l) with
+// j = 128 jb + 64 wr + 16 m + 4 q + x (register x) and l = 128 lb + 64 wc + 16 n + c16.  The other
+// seven cells follow from the three pair counts N(0,0) and the bin-0 marginals, each by a
+// subtraction whose two class halves stay >= 0 (no borrow between the packed halves):
+//   T001 = Nij - T000          T010 = Nil - T000          T100 = Njl - T000
+//   T011 = (Mi - Nij) - T010   T101 = (Mj - Nij) - T100   T110 = (Ml - Nil) - T100
+//   T111 = ((N - Mi) - (Mj - Nij)) - T110
+// (a, b, e = bins of i, j, l; Mx = bin-0 count of x; N = class sizes).
+constexpr int M1_V = 128;                                   // j and l variables per tile side
+constexpr int M1_STAGE = 2 * TILE_ROWS * KBLK + KBLK + 64;  // j rows | l rows | i row | pad
+
+template <int T>
+__global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
+{
+    constexpr int C = 2;
+    if (a.collect && a.st->collect_go == 0) return;   // collect pass not needed (uniform)
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    char *stage = smem + 24 * T;
+    int64_t *s_next = reinterpret_cast<int64_t *>(smem + a.snext_off);
+
+    const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wr = wave >> 1, wc = wave & 1;
+    const int q = lane >> 4, c16 = lane & 15;
+
+    {
+        float *tf = reinterpret_cast<float *>(smem);
+        for (int i = t; i <= a.N0; i += M3_THREADS) tf[i] = a.EA[i];
+        for (int i = t; i <= a.N1; i += M3_THREADS) tf[T + i] = a.EB[i];
+        float2 *lq = reinterpret_cast<float2 *>(smem + 8 * T);
+        for (int i = t; i <= a.N; i += M3_THREADS) lq[i] = a.LQ[i];
+    }
+    auto repack = [](uint32_t x) -> uint32_t { return x << 2; };   // n1 << 16 | n0 -> fp4 packing
+    const uint32_t *margr = a.marg + (int64_t)a.r * a.p_pad * C;
+    const uint32_t Ntot = ((uint32_t)a.N1 << 18) | ((uint32_t)a.N0 << 2);
+    const int64_t nrb = a.rows_pad / TILE_ROWS;
+    constexpr int kstride = TILE_ROWS * KBLK;
+    const int n1blk = a.KB - a.KB0;
+    auto clampv = [&](int v) { return v < a.p ? v : a.p - 1; };
+
+    for (;;) {
+        __syncthreads();
+        if (t == 0) *s_next = atomicAdd(&a.st->next_tile[0], 1u);
+        __syncthreads();
+        const int64_t u = *s_next;
+        if (u >= a.n_tiles) break;
+        int64_t lo = 0, hi = a.n_ablk - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (a.apref[mid] <= u) lo = mid; else hi = mid - 1;
+        }
+        const int ab = a.ablk[lo];
+        const int i = ab >> 8, jb = ab & 255;
+        const int lb = jb + (int)(u - a.apref[lo]);
+
+        // ---------------------------------------------------------------- K loop
+        const int8_t *panJ = a.onehot + ((int64_t)a.r * nrb + jb) * a.KB * kstride;
+        const int8_t *panL = a.onehot + ((int64_t)a.r * nrb + lb) * a.KB * kstride;
+        const int8_t *panI = a.onehot + ((int64_t)a.r * nrb + i / TILE_ROWS) * a.KB * kstride + (i % TILE_ROWS) * KBLK;
+        auto kblock = [&](int s_) { return s_ < n1blk ? a.KB0 + s_ : s_ - n1blk; };
+        auto stage_at = [&](int s_) { return stage + (s_ % M3_NSTAGE) * M1_STAGE; };
+        // 17 fetches per K block: 8 of 1 KB for the j rows, 8 for the l rows (stage rows
+        // 128..255), one of 64 bytes for the row of i (lanes 0..3).  Wave w takes fetches w, w+4,
+        // w+8, w+12, and wave 0 also the row of i.
+        const int nfetch = wave == 0 ? 5 : 4;
+        auto issue = [&](int s_) {
+            const int64_t kb_off = (int64_t)kblock(s_) * kstride;
+            char *st_ = stage_at(s_);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int f = wave + 4 * k;
+                const int srow = 16 * f + (lane >> 2);
+                const int j = (lane & 3) ^ ((srow >> 1) & 3);
+                const int8_t *src = f < 8 ? panJ + kb_off + srow * KBLK + j * 16
+                                          : panL + kb_off + (srow - TILE_ROWS) * KBLK + j * 16;
+                __builtin_amdgcn_global_load_lds((const void *)src,
+                                                 (__attribute__((address_space(3))) void *)(st_ + f * 1024), 16, 0, 0);
+            }
+            if (wave == 0 && lane < 4) {
+                const int8_t *src = panI + kb_off + lane * 16;
+                __builtin_amdgcn_global_load_lds((const void *)src,
+                                                 (__attribute__((address_space(3))) void *)(st_ + 16 * 1024), 16, 0, 0);
+            }
+        };
+        v4f acc[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = v4f{0.f, 0.f, 0.f, 0.f};
+        int offJ[4], offL[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) offJ[m] = lds_sw(64 * wr + 16 * m + c16, q);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) offL[n] = TILE_ROWS * KBLK + lds_sw(64 * wc + 16 * n + c16, q);
+        const int offI = 2 * TILE_ROWS * KBLK + 16 * q;
+
+        issue(0);
+        if (a.KB > 1) issue(1);
+        for (int s = 0; s < a.KB; ++s) {
+            // this wave's fetches of block s complete (loads return in order); then a plain
+            // barrier (a fenced one would also drain the fetches of block s+1)
+            if (s + 1 < a.KB) {
+                if (nfetch == 5) __builtin_amdgcn_s_waitcnt(0x0F75);   // vmcnt(5)
+                else __builtin_amdgcn_s_waitcnt(0x0F74);               // vmcnt(4)
+            } else {
+                __builtin_amdgcn_s_waitcnt(0x0F70);
+            }
+            __builtin_amdgcn_s_barrier();
+            if (s + 2 < a.KB) issue(s + 2);
+            const char *st_ = stage_at(s);
+            const v4i fi = *reinterpret_cast<const v4i *>(st_ + offI);
+            v4i fa[4], fb[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) fa[m] = *reinterpret_cast<const v4i *>(st_ + offJ[m]) & fi;
+#pragma unroll
+            for (int n = 0; n < 4; ++n) fb[n] = *reinterpret_cast<const v4i *>(st_ + offL[n]);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    const v8i a8{fa[m][0], fa[m][1], fa[m][2], fa[m][3], 0, 0, 0, 0};
+                    const v8i b8{fb[n][0], fb[n][1], fb[n][2], fb[n][3], 0, 0, 0, 0};
+                    acc[m][n] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, b8, acc[m][n], 4, 4, 0, 0, 0, 0);
+                }
+            if (s == n1blk - 1) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) acc[m][n] = acc[m][n] * 4096.0f;
+            }
+        }
+
+        // ---------------------------------------------------------------- epilogue
+        v4i cnt[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    const uint32_t uu = (uint32_t)acc[m][n][x];
+                    cnt[m][n][x] = (int)(__umul24(uu >> 14, 245760u) + uu);
+                }
+        auto jvar = [&](int m, int x) { return jb * M1_V + 64 * wr + 16 * m + 4 * q + x; };
+        int lv[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) lv[n] = lb * M1_V + 64 * wc + 16 * n + c16;
+        const uint32_t Mi = repack(margr[(int64_t)i * C]);
+        const uint32_t Ni1 = Ntot - Mi;                     // class sizes of x_i = 1
+        uint32_t Ml[4], Nil[4], Ail[4];
+        float Fil[4], gL[4], thrL[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const int l = clampv(lv[n]);
+            Ml[n] = repack(margr[(int64_t)l * C]);
+            const int ii = i < l ? i : l, ll = i < l ? l : i;
+            Nil[n] = repack(a.ptab[(int64_t)ii * a.p_pad + ll]);
+            Ail[n] = Ml[n] - Nil[n];                        // x_i = 1, x_l = 0
+            Fil[n] = a.F2[(int64_t)ii * a.p_pad + ll];
+            const float g = key_f32(a.G32[l]);
+            gL[n] = g;
+            thrL[n] = g - win3(a.w_abs, g);
+        }
+        const float Gi = key_f32(a.G32[i]);
+        float thrI = Gi - win3(a.w_abs, Gi);
+        struct JData {
+            uint32_t Nij[4], Aij[4], Cij[4];   // N(0,0); x_i = 0, x_j = 1; x_i = 1, x_j = 1
+            float F[4], g[4];
+        };
+        auto load_j = [&](int m, JData &d) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                const int j = clampv(jvar(m, x));
+                const uint32_t Mj = repack(margr[(int64_t)j * C]);
+                const int ii = i < j ? i : j, jj = i < j ? j : i;
+                const uint32_t nij = repack(a.ptab[(int64_t)ii * a.p_pad + jj]);
+                d.Nij[x] = nij;
+                d.Aij[x] = Mi - nij;
+                d.Cij[x] = Ni1 - (Mj - nij);
+                d.F[x] = a.F2[(int64_t)ii * a.p_pad + jj];
+                d.g[x] = key_f32(a.G32[j]);
+            }
+        };
+        // F3 of triple (i, j(m, x), l_n) and the F of the pair (j, l)
+        auto triple = [&](int m, int n, int x, const JData &jd, float &Fjl) -> float {
+            const int jraw = jvar(m, x);
+            const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
+            const int j = clampv(jraw), l = clampv(lv[n]);
+            const int jj = j < l ? j : l, ll = j < l ? l : j;
+            const uint32_t Njl = repack(a.ptab[(int64_t)jj * a.p_pad + ll]);
+            Fjl = a.F2[(int64_t)jj * a.p_pad + ll];
+            const uint32_t D = (uint32_t)cnt[m][n][x];
+            uint32_t V[8];
+            V[0] = D;                                   // T000
+            V[1] = jd.Nij[x] - D;                       // T001
+            V[2] = Nil[n] - D;                          // T010
+            V[3] = Njl - D;                             // T100
+            V[4] = jd.Aij[x] - V[2];                    // T011
+            V[5] = (Ni1 - jd.Cij[x]) - V[3];            // T101: Mj - Nij = Ni1 - Cij (x_i = 1, x_j = 0)
+            V[6] = Ail[n] - V[3];                       // T110
+            V[7] = jd.Cij[x] - V[6];                    // T111
+            // an invalid triple may combine unrelated tables: its counts are not counts
+#pragma unroll
+            for (int k = 0; k < 8; ++k) V[k] = valid ? V[k] : 0u;
+            return vox_sum<T, 8>(V, smem);
+        };
+
+        float mi = -INFINITY, mj[4][4], ml[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) ml[n] = -INFINITY;
+        bool hot = false;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            JData jd;
+            load_j(m, jd);
+            float mjx[4], thrJ[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                mjx[x] = -INFINITY;
+                thrJ[x] = jd.g[x] - win3(a.w_abs, jd.g[x]);
+            }
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                // wave-uniform skip of a block without any valid triple
+                if (!__any(i < jvar(m, 3) && jvar(m, 0) < lv[n] && lv[n] < a.p)) continue;
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    const int jraw = jvar(m, x);
+                    const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
+                    float Fjl;
+                    const float F3 = triple(m, n, x, jd, Fjl);
+                    const float gi = valid ? Fjl - F3 : -INFINITY;       // gain of x_i given (x_j, x_l)
+                    const float gj = valid ? Fil[n] - F3 : -INFINITY;    // gain of x_j given (x_i, x_l)
+                    const float gl = valid ? jd.F[x] - F3 : -INFINITY;   // gain of x_l given (x_i, x_j)
+                    mi = fmaxf(mi, gi);
+                    mjx[x] = fmaxf(mjx[x], gj);
+                    ml[n] = fmaxf(ml[n], gl);
+                    hot |= (gi >= thrI) | (gj >= thrJ[x]) | (gl >= thrL[n]);
+                }
+            }
+            // j(m, x) is shared by the 16 lanes of one q
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                float y = mjx[x];
+                y = fmaxf(y, __shfl_xor(y, 1));
+                y = fmaxf(y, __shfl_xor(y, 2));
+                y = fmaxf(y, __shfl_xor(y, 4));
+                mj[m][x] = fmaxf(y, __shfl_xor(y, 8));
+            }
+        }
+        // i is the tile's; l_n is shared by the lanes of one c16
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mi = fmaxf(mi, __shfl_xor(mi, o));
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            float y = ml[n];
+            y = fmaxf(y, __shfl_xor(y, 16));
+            ml[n] = fmaxf(y, __shfl_xor(y, 32));
+        }
+        if (__any(hot)) {
+            {
+                const float g = key_f32(a.G32[i]);
+                const float top = a.collect ? g : fmaxf(g, mi);
+                thrI = top - win3(a.w_abs, top);
+            }
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const float g = key_f32(a.G32[clampv(lv[n])]);
+                const float top = a.collect ? g : fmaxf(g, ml[n]);
+                thrL[n] = top - win3(a.w_abs, top);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(cnt[m][n]) : : "memory");
+            // per block (m, n): the four triples' gains, which members append (bit 3 x + member),
+            // one slot reservation for the wave, then the records
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                JData jd;
+                load_j(m, jd);
+                float thrJ[4];
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    const float g = key_f32(a.G32[clampv(jvar(m, x))]);
+                    const float top = a.collect ? g : fmaxf(g, mj[m][x]);
+                    thrJ[x] = top - win3(a.w_abs, top);
+                }
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    if (!__any(i < jvar(m, 3) && jvar(m, 0) < lv[n] && lv[n] < a.p)) continue;   // as in the first pass
+                    uint32_t sel = 0;
+                    float gI[4], gJ[4], gL[4];
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) {
+                        const int jraw = jvar(m, x);
+                        const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
+                        float Fjl;
+                        const float F3 = triple(m, n, x, jd, Fjl);
+                        gI[x] = Fjl - F3;
+                        gJ[x] = Fil[n] - F3;
+                        gL[x] = jd.F[x] - F3;
+                        if (valid && gI[x] >= thrI) sel |= 1u << (3 * x);
+                        if (valid && gJ[x] >= thrJ[x]) sel |= 2u << (3 * x);
+                        if (valid && gL[x] >= thrL[n]) sel |= 4u << (3 * x);
+                    }
+                    uint32_t at = reserve_slots(&a.st->n_cand, __popc(sel), lane);
+                    if (sel) {
+                        const int l = lv[n];
+#pragma unroll
+                        for (int x = 0; x < 4; ++x) {
+                            const int j = jvar(m, x);
+                            if (sel & (1u << (3 * x))) put(a, at++, i, ((uint32_t)j << 16) | (uint32_t)l, gI[x]);
+                            if (sel & (2u << (3 * x))) put(a, at++, j, ((uint32_t)i << 16) | (uint32_t)l, gJ[x]);
+                            if (sel & (4u << (3 * x))) put(a, at++, l, ((uint32_t)i << 16) | (uint32_t)j, gL[x]);
+                        }
+                    }
+                }
+            }
+        }
+        if (a.collect) continue;
+        // only where the tile raised the maximum read before (maxima only grow)
+        if (lane == 0 && mi > Gi) atomicMax(&a.G32[i], f32_key(mi));
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                const int j = jvar(m, x);
+                if (c16 == 0 && j < a.p && mj[m][x] > -INFINITY) {
+                    const float g = key_f32(a.G32[j]);
+                    if (mj[m][x] > g) atomicMax(&a.G32[j], f32_key(mj[m][x]));
+                }
+            }
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+            if (q == 0 && ml[n] > gL[n]) atomicMax(&a.G32[lv[n]], f32_key(ml[n]));
+    }
+}
+
 int m3_capacity(const Problem &P)
 {
     const int need = (P.N0 > P.N1 ? P.N0 : P.N1) + 1;
@@ -476,7 +817,7 @@ int m3_capacity(const Problem &P)
     return 0;
 }
 
-template <int T>
+template <int T, int W>
 hipError_t m3_launch(const Problem &P, int r, bool collect)
 {
     const Layout &L = P.L;
@@ -501,7 +842,7 @@ hipError_t m3_launch(const Problem &P, int r, bool collect)
     a.KB = P.KB;
     a.KB0 = P.KB0;
     a.r = r;
-    a.nLB = (int)((L.p + M3_LV - 1) / M3_LV);
+    a.nLB = (int)((L.p + (W == 1 ? M1_V : M3_LV) - 1) / (W == 1 ? M1_V : M3_LV));
     a.G32 = P.at<uint32_t>(L.G32);
     a.cand = P.at<Cand>(L.cand);
     a.cap = L.cap;
@@ -509,33 +850,39 @@ hipError_t m3_launch(const Problem &P, int r, bool collect)
     a.ovf = P.at<uint32_t>(L.ovf);
     a.w_abs = (float)(2.0 * P.err_bound);
     a.collect = collect ? 1 : 0;
-    const size_t lds = (size_t)24 * T + M3_NSTAGE * M3_STAGE + 16;
+    const size_t lds = (size_t)24 * T + M3_NSTAGE * (W == 1 ? M1_STAGE : M3_STAGE) + 16;
     a.snext_off = (int)(lds - 16);
-    hipError_t e = hipFuncSetAttribute((const void *)k_sweep3m<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    auto kern = W == 1 ? k_sweep3m1<T> : k_sweep3m<T>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sweep3m<T>, dim3(P.workgroups > 0 ? P.workgroups : 512), dim3(M3_THREADS), lds, P.stream, a);
+    hipLaunchKernelGGL(kern, dim3(P.workgroups > 0 ? P.workgroups : 512), dim3(M3_THREADS), lds, P.stream, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-size_t sweep3m_lds_bytes(const Problem &P) { return (size_t)24 * m3_capacity(P) + M3_NSTAGE * M3_STAGE + 16; }
-
-// Tile list of the triple sweep: A blocks (i, jb) with jb >= (i + 1) / 32 (some j > i) and
-// jb * 32 < p - 1, each with l blocks lb = jb / 2 .. nLB - 1.  Host-side; apref[k] = first
-// tile of A block k, apref[n_ablk] = number of tiles.
-void sweep3m_tiles(int64_t p, std::vector<int64_t> &apref, std::vector<int32_t> &ablk)
+size_t sweep3m_lds_bytes(const Problem &P)
 {
-    const int64_t nJB = (p + M3_JV - 1) / M3_JV, nLB = (p + M3_LV - 1) / M3_LV;
+    return (size_t)24 * m3_capacity(P) + M3_NSTAGE * (P.L.W == 1 ? M1_STAGE : M3_STAGE) + 16;
+}
+
+// Tile list of the triple sweep with JV j variables and LV l variables per tile (W = 2: 32
+// and 64; W = 1: 128 and 128): A blocks (i, jb) with jb >= (i + 1) / JV (some j > i) and
+// jb * JV < p - 1, each with l blocks lb = jb * JV / LV .. nLB - 1.  Host-side; apref[k] =
+// first tile of A block k, apref[n_ablk] = number of tiles.
+void sweep3m_tiles(int64_t p, int W, std::vector<int64_t> &apref, std::vector<int32_t> &ablk)
+{
+    const int64_t JV = W == 1 ? M1_V : M3_JV, LV = W == 1 ? M1_V : M3_LV;
+    const int64_t nJB = (p + JV - 1) / JV, nLB = (p + LV - 1) / LV;
     apref.clear();
     ablk.clear();
     int64_t at = 0;
     for (int64_t i = 0; i + 2 < p; ++i)
-        for (int64_t jb = (i + 1) / M3_JV; jb < nJB; ++jb) {
-            if (jb * M3_JV >= p - 1) break;
+        for (int64_t jb = (i + 1) / JV; jb < nJB; ++jb) {
+            if (jb * JV >= p - 1) break;
             apref.push_back(at);
             ablk.push_back((int32_t)(i * 256 + jb));
-            at += nLB - jb / 2;
+            at += nLB - jb * JV / LV;
         }
     apref.push_back(at);
 }
@@ -544,10 +891,11 @@ hipError_t launch_sweep3m(const Problem &P, int r, bool collect)
 {
     hipError_t e = launch_reset_queue(P);
     if (e != hipSuccess) return e;
+    const bool w1 = P.L.W == 1;
     switch (m3_capacity(P)) {
-    case 1024: return m3_launch<1024>(P, r, collect);
-    case 2048: return m3_launch<2048>(P, r, collect);
-    case 4096: return m3_launch<4096>(P, r, collect);
+    case 1024: return w1 ? m3_launch<1024, 1>(P, r, collect) : m3_launch<1024, 2>(P, r, collect);
+    case 2048: return w1 ? m3_launch<2048, 1>(P, r, collect) : m3_launch<2048, 2>(P, r, collect);
+    case 4096: return w1 ? m3_launch<4096, 1>(P, r, collect) : m3_launch<4096, 2>(P, r, collect);
     default: return hipErrorInvalidValue;
     }
 }

@@ -22,7 +22,7 @@ def as_dict(var, part, disc, ig):
 
 
 @pytest.mark.parametrize("k,engine,div", [(2, "mfma_fp4", 2), (2, "mfma", 2), (2, "auto", 4), (3, "mfma_fp4", 2),
-                                          (3, "bitset", 2), (3, "bitset", 1)])
+                                          (3, "mfma_fp4", 1), (3, "bitset", 2), (3, "bitset", 1)])
 def test_interesting_matches_oracle(mdfs_gpu, k, engine, div):
     w = workloads.xor_small(seed=61, n_obj=400, n_var=40 if k == 2 else 18, divisions=div, n_disc=3)
     ref_all = oracle.interesting(w.data, w.y, k, div, 3, w.range_, w.xi, w.seed, -np.inf)

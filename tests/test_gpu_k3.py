@@ -1,7 +1,8 @@
 """k = 3 sweep on the GPU through the C ABI, against the FP64 oracle.
 
 Two count engines: "bitset" (per-class bitsets, AND + popcount; every class count) and
-"mfma_fp4" (pair one-hot x one-hot on the matrix cores; three classes, classes < 4096 objects),
+"mfma_fp4" (pair one-hot x one-hot on the matrix cores; two or three classes, classes < 4096
+objects),
 which "auto" picks where it applies."""
 import numpy as np
 import pytest
@@ -34,6 +35,9 @@ CASES3 = {
     "imbalanced": lambda: workloads.null_data(23, 333, 30, ones=41),
     "three_vars": lambda: workloads.parity3(seed=24, n_obj=100, n_var=3, n_disc=2),
     "five_classes": lambda: workloads.parity3(seed=25, n_obj=500, n_var=26, divisions=4, n_disc=2),
+    # two classes over three 128-variable blocks with a ragged last one (the two-class matrix-core
+    # tile is 128 j x 128 l)
+    "two_classes_tiles": lambda: workloads.parity3(seed=26, n_obj=203, n_var=261, divisions=1, n_disc=2),
 }
 
 
@@ -41,8 +45,8 @@ CASES3 = {
 @pytest.mark.parametrize("name", list(CASES3))
 def test_k3_matches_oracle(mdfs_gpu, name, engine):
     w = CASES3[name]()
-    if engine == "mfma_fp4" and w.divisions != 2:
-        pytest.skip("the matrix-core k=3 engine is built for three classes")
+    if engine == "mfma_fp4" and w.divisions not in (1, 2):
+        pytest.skip("the matrix-core k=3 engine is built for two or three classes")
     print(f"k3 {name} {engine} N={w.n_obj} p={w.n_var} R={w.n_disc} d={w.divisions + 1}", flush=True)
     got = run3(mdfs_gpu, w, engine=engine)
     ref = oracle.max_ig_all(w.data, w.y, 3, w.divisions, w.n_disc, w.range_, w.xi, w.seed, n_threads=8)
