@@ -56,6 +56,7 @@ struct Sweep3mArgs {
     float w_abs;
     int collect;
     int snext_off;
+    int stage_off;           // two-class kernel: LDS byte offset of the operand stages
 };
 
 __device__ inline int lds_sw(int row, int j) { return row * KBLK + ((j ^ ((row >> 1) & 3)) << 4); }
@@ -481,6 +482,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
 // (a, b, e = bins of i, j, l; Mx = bin-0 count of x; N = class sizes).
 constexpr int M1_V = 128;                                   // j and l variables per tile side
 constexpr int M1_STAGE = 2 * TILE_ROWS * KBLK + KBLK + 64;  // j rows | l rows | i row | pad
+constexpr int M1_NSTAGE = 2;   // operand stages: fetched one K block ahead (two workgroups per CU)
 
 template <int T>
 __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
@@ -488,7 +490,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
     constexpr int C = 2;
     if (a.collect && a.st->collect_go == 0) return;   // collect pass not needed (uniform)
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    char *stage = smem + 24 * T;
+    char *stage = smem + a.stage_off;   // after the (L, Q) pairs of n = 0 .. N
     int64_t *s_next = reinterpret_cast<int64_t *>(smem + a.snext_off);
 
     const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -530,11 +532,10 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
         const int8_t *panL = a.onehot + ((int64_t)a.r * nrb + lb) * a.KB * kstride;
         const int8_t *panI = a.onehot + ((int64_t)a.r * nrb + i / TILE_ROWS) * a.KB * kstride + (i % TILE_ROWS) * KBLK;
         auto kblock = [&](int s_) { return s_ < n1blk ? a.KB0 + s_ : s_ - n1blk; };
-        auto stage_at = [&](int s_) { return stage + (s_ % M3_NSTAGE) * M1_STAGE; };
+        auto stage_at = [&](int s_) { return stage + (s_ % M1_NSTAGE) * M1_STAGE; };
         // 17 fetches per K block: 8 of 1 KB for the j rows, 8 for the l rows (stage rows
         // 128..255), one of 64 bytes for the row of i (lanes 0..3).  Wave w takes fetches w, w+4,
         // w+8, w+12, and wave 0 also the row of i.
-        const int nfetch = wave == 0 ? 5 : 4;
         auto issue = [&](int s_) {
             const int64_t kb_off = (int64_t)kblock(s_) * kstride;
             char *st_ = stage_at(s_);
@@ -566,19 +567,15 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
         for (int n = 0; n < 4; ++n) offL[n] = TILE_ROWS * KBLK + lds_sw(64 * wc + 16 * n + c16, q);
         const int offI = 2 * TILE_ROWS * KBLK + 16 * q;
 
+        // Two stages: step s waits for its own fetches of block s (the only ones outstanding),
+        // passes a barrier (block s is complete, and every wave has finished reading block s-1,
+        // whose stage the fetch of block s+1 then takes) and fetches block s+1 before reading
+        // the fragments of block s.
         issue(0);
-        if (a.KB > 1) issue(1);
         for (int s = 0; s < a.KB; ++s) {
-            // this wave's fetches of block s complete (loads return in order); then a plain
-            // barrier (a fenced one would also drain the fetches of block s+1)
-            if (s + 1 < a.KB) {
-                if (nfetch == 5) __builtin_amdgcn_s_waitcnt(0x0F75);   // vmcnt(5)
-                else __builtin_amdgcn_s_waitcnt(0x0F74);               // vmcnt(4)
-            } else {
-                __builtin_amdgcn_s_waitcnt(0x0F70);
-            }
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
             __builtin_amdgcn_s_barrier();
-            if (s + 2 < a.KB) issue(s + 2);
+            if (s + 1 < a.KB) issue(s + 1);
             const char *st_ = stage_at(s);
             const v4i fi = *reinterpret_cast<const v4i *>(st_ + offI);
             v4i fa[4], fb[4];
@@ -809,6 +806,14 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
     }
 }
 
+// LDS of the triple sweeps: tables EA [0, 4T), EB [4T, 8T), (L, Q) pairs from 8T; three classes:
+// stages from 24T (compile-time offsets), two classes: stages after the N + 1 pairs in use
+size_t m1_stage_off(int T, int N) { return ((size_t)8 * T + 8 * ((size_t)N + 1) + 127) & ~(size_t)127; }
+size_t sweep3m_lds_of(int T, int W, int N)
+{
+    return W == 1 ? m1_stage_off(T, N) + M1_NSTAGE * M1_STAGE + 16 : (size_t)24 * T + M3_NSTAGE * M3_STAGE + 16;
+}
+
 int m3_capacity(const Problem &P)
 {
     const int need = (P.N0 > P.N1 ? P.N0 : P.N1) + 1;
@@ -850,7 +855,8 @@ hipError_t m3_launch(const Problem &P, int r, bool collect)
     a.ovf = P.at<uint32_t>(L.ovf);
     a.w_abs = (float)(2.0 * P.err_bound);
     a.collect = collect ? 1 : 0;
-    const size_t lds = (size_t)24 * T + M3_NSTAGE * (W == 1 ? M1_STAGE : M3_STAGE) + 16;
+    const size_t lds = sweep3m_lds_of(T, W, (int)L.N);
+    a.stage_off = (int)m1_stage_off(T, (int)L.N);
     a.snext_off = (int)(lds - 16);
     auto kern = W == 1 ? k_sweep3m1<T> : k_sweep3m<T>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -861,10 +867,7 @@ hipError_t m3_launch(const Problem &P, int r, bool collect)
 
 }  // namespace
 
-size_t sweep3m_lds_bytes(const Problem &P)
-{
-    return (size_t)24 * m3_capacity(P) + M3_NSTAGE * (P.L.W == 1 ? M1_STAGE : M3_STAGE) + 16;
-}
+size_t sweep3m_lds_bytes(const Problem &P) { return sweep3m_lds_of(m3_capacity(P), P.L.W, (int)P.L.N); }
 
 // Tile list of the triple sweep with JV j variables and LV l variables per tile (W = 2: 32
 // and 64; W = 1: 128 and 128): A blocks (i, jb) with jb >= (i + 1) / JV (some j > i) and
