@@ -13,8 +13,9 @@
 // are read.  The remaining C^3 - W^3 voxels follow exactly from the three pair tables (from
 // the pair sweep of the same discretisation) and the marginals.  Epilogue: F3 = sum_v n_v h(p_v)
 // in float32 from the LDS tables; IG(i|j,l) = F(j,l) - F3 and likewise for j and l (equation
-// IGmax with k = 3), maxima and candidate appends as in the bitset engine.  Three classes
-// (W = 2) only; other widths use the bitset engine.
+// IGmax with k = 3), maxima and candidate appends as in the bitset engine.  `k_sweep3m` is the
+// three-class kernel (W = 2), `k_sweep3m1` the two-class one (W = 1, below); five classes use
+// the bitset engine.
 #include "mdfs_internal.h"
 
 #include <vector>
