@@ -32,7 +32,7 @@ def candidates(n_obj: int, k: int, divisions: int, ones: int) -> list[dict]:
     if k == 2:
         engines = (["mfma_fp4"] if small_classes else []) + ["mfma"]
     else:
-        engines = (["mfma_fp4"] if small_classes and divisions == 2 else []) + ["bitset"]
+        engines = (["mfma_fp4"] if small_classes and divisions in (1, 2) else []) + ["bitset"]
     return [{"engine": e, "workgroups": g} for e in engines for g in GRIDS]
 
 
