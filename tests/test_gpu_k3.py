@@ -100,10 +100,25 @@ def test_k3_full_size_sampled(mdfs_gpu, engine):
     assert_ig_parity(ig[tg], am[tg], ad[tg], ref, "k3 full size")
 
 
-def test_k3_engines_agree_bit_for_bit_on_argmax(mdfs_gpu):
+def test_k3_two_classes_full_size_sampled(mdfs_gpu):
+    # the Madelon-shaped k = 3 workload at d = 2 (N=2000, p=500, 30 discretisations; the shape
+    # of the paper's 3D timing) on the two-class matrix-core engine, sampled against the oracle
+    w = workloads.madelon_like(divisions=1, n_disc=30, k=3)
+    print(f"k3 two classes full size: N={w.n_obj} p={w.n_var} R={w.n_disc}", flush=True)
+    ig, am, ad = run3(mdfs_gpu, w, engine="mfma_fp4")
+    assert np.isfinite(ig).all()
+    g = np.random.default_rng(1)
+    tg = np.array(sorted(set(w.planted["base"][:2] + g.choice(np.arange(w.n_var), 3, replace=False).tolist())),
+                  dtype=np.int64)
+    ref = oracle.max_ig(w.data, w.y, 3, w.divisions, w.n_disc, w.range_, w.xi, w.seed, targets=tg, n_threads=16)
+    assert_ig_parity(ig[tg], am[tg], ad[tg], ref, "k3 two classes full size")
+
+
+@pytest.mark.parametrize("divisions", [1, 2])
+def test_k3_engines_agree_bit_for_bit_on_argmax(mdfs_gpu, divisions):
     # same float32 screen tables, same binary64 re-score: both engines must give identical
     # results (the re-scored maxima do not depend on how the counts were obtained)
-    w = workloads.parity3(seed=34, n_obj=777, n_var=50, n_disc=3)
+    w = workloads.parity3(seed=34, n_obj=777, n_var=50 if divisions == 2 else 150, divisions=divisions, n_disc=3)
     a = run3(mdfs_gpu, w, engine="bitset")
     b = run3(mdfs_gpu, w, engine="mfma_fp4")
     for x, z in zip(a, b):
