@@ -64,7 +64,8 @@ typedef enum {
     MDFS_ENGINE_MFMA = 1,     /* one-hot int8 contraction on the matrix cores */
     MDFS_ENGINE_BITSET = 2,   /* per-class bitsets, AND + popcount */
     MDFS_ENGINE_MFMA_FP4 = 3  /* one-hot E2M1 (fp4) contraction, float32 accumulation (exact
-                                 integers); k=2, each class < 4096 objects, else MDFS_E_LIMIT */
+                                 integers); k=2, or k=3 with divisions 1 or 2; each class < 4096
+                                 objects, else MDFS_E_LIMIT */
 } mdfs_engine;
 
 /* Problem description.  Fields follow the arguments of ComputeMaxInfoGains
