@@ -876,7 +876,11 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
                             : (counts_out ? k_sweep2<W, SWEEP_DEBUG_COUNTS, ENC> : k_sweep2<W, SWEEP_MAX, ENC>);
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    const int grid = P.workgroups > 0 ? P.workgroups : XCDS * WG_PER_XCD;
+    // no more workgroups than tile slots (each loads its tables before it takes a tile), at least
+    // one per XCD; the queue walk hands every tile to some workgroup whatever the grid
+    const int64_t slots = a.n_super * (SB * SB);
+    const int grid = P.workgroups > 0 ? P.workgroups
+                                      : (int)std::min<int64_t>(XCDS * WG_PER_XCD, std::max<int64_t>(XCDS, slots));
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sw_waves(W) * 64), lds, P.stream, a);
     return hipGetLastError();
 }
