@@ -29,6 +29,8 @@ INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
 FP4_PEAK_TFLOPS = 10100.0      # MI355X dense fp4 (and fp6) MFMA, TFLOP/s
 HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 lanes/clk x 2.4 GHz integer VALU = 39.3 Tops/s
+LDS_PEAK_GBS = 256 * 128 * 2.4e9 / 1e9   # 256 CUs x 128 bytes/clk x 2.4 GHz = 78.6 TB/s
+EPILOGUE_OPS_PER_VOXEL = 18               # VALU lane-ops per voxel term of the entropy screen (estimate)
 
 
 def parse():
@@ -92,19 +94,72 @@ def _sweep_source_hash():
     return hashlib.sha256(open(src, "rb").read()).hexdigest()
 
 
-def cpu_baseline(w, n_vars, n_disc):
-    """The FP64 oracle (tuple-sweep form, threads over discretisations) on the first n_vars
-    variables and n_disc discretisations of the same workload."""
+def host_threads() -> int:
+    """Host threads the oracle may use: the machine's CPU share (OMP_NUM_THREADS there), else nproc."""
+    return max(1, min(int(os.environ.get("OMP_NUM_THREADS", str(os.cpu_count() or 1))), os.cpu_count() or 1))
+
+
+def cpu_baseline(w, k, n_vars, n_disc, ig_gpu, argmax_gpu, disc_gpu):
+    """The FP64 oracle timed on the host cores on a bounded sample of the same workload: the
+    tuple-sweep form (threads over discretisations) on the first n_vars variables and n_disc
+    discretisations, on every host thread and on one core.  Also the per-result IG error of the
+    GPU outputs: against the stored oracle values of every variable (tests/golden, when the
+    regenerated inputs hash to the stored digest), else against the per-variable oracle on a
+    sample of variables holding every planted one."""
+    import numpy as np
+
     import oracle
-    threads = max(1, min(n_disc, int(os.environ.get("OMP_NUM_THREADS", "16")), os.cpu_count() or 1))
+    threads = min(host_threads(), n_disc)
     data = w.data[:n_vars]
     t0 = time.perf_counter()
-    oracle.max_ig_all(data, w.y, 2, w.divisions, n_disc, w.range_, w.xi, w.seed, n_threads=threads)
+    oracle.max_ig_all(data, w.y, k, w.divisions, n_disc, w.range_, w.xi, w.seed, n_threads=threads)
     dt = time.perf_counter() - t0
-    tuples = math.comb(n_vars, 2) * n_disc
-    return {"value": tuples / dt, "unit": "k-tuples evaluated/sec", "cores": threads, "kind": "oracle",
-            "sample": f"first {n_vars} of {w.n_var} variables, {n_disc} of {w.n_disc} discretisations, "
-                      f"N={w.n_obj}, k=2, d={w.divisions + 1}: {tuples} pair tables in {dt:.2f} s"}
+    tuples = math.comb(n_vars, k) * n_disc
+    # one core: a quarter of the variables, two discretisations
+    n1v, n1d = max(k + 1, n_vars // 4), min(2, n_disc)
+    t0 = time.perf_counter()
+    oracle.max_ig_all(w.data[:n1v], w.y, k, w.divisions, n1d, w.range_, w.xi, w.seed, n_threads=1)
+    dt1 = time.perf_counter() - t0
+    tuples1 = math.comb(n1v, k) * n1d
+    out = {"value": tuples / dt, "unit": "k-tuples evaluated/sec", "cores": threads, "kind": "oracle",
+           "sample": f"first {n_vars} of {w.n_var} variables, {n_disc} of {w.n_disc} discretisations, "
+                     f"N={w.n_obj}, k={k}, d={w.divisions + 1}: {tuples} tuple tables in {dt:.2f} s",
+           "single_core": {"value": tuples1 / dt1, "cores": 1,
+                           "sample": f"first {n1v} variables, {n1d} discretisations: {tuples1} tuple tables "
+                                     f"in {dt1:.2f} s"}}
+    # per-result IG error of the GPU outputs (outside the timed region)
+    ref, where = None, ""
+    try:
+        sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+        import make_fullsize
+        name = {"headline": "headline", "genomics_like": "genomics_like", "madelon_like": "madelon_like",
+                "parity3": "parity3", "madelon2_d2": "madelon2_d2", "madelon3_d2": "madelon3_d2"}.get(w.name_key)
+        if name and os.path.exists(make_fullsize.path_of(name)):
+            z = make_fullsize.load(name)
+            if str(z["digest"]) == make_fullsize.data_digest(w) and int(z["k"]) == k:
+                tg = np.arange(w.n_var)
+                ref = (z["ig"], z["argmax"].astype(np.int64), z["disc"].astype(np.int64))
+                where = "stored oracle values of every variable (tests/golden)"
+    except Exception as exc:   # the stored values are optional
+        print(f"# stored oracle values unavailable: {exc}", file=sys.stderr)
+    if ref is None:
+        g = np.random.default_rng(0)
+        planted = sorted({int(v) for pr in w.planted.get("pairs", []) for v in pr} |
+                         {int(v) for v in w.planted.get("triple", [])})
+        rest = np.setdiff1d(np.arange(w.n_var), planted)
+        tg = np.array(sorted(planted + g.choice(rest, min(len(rest), 12), replace=False).tolist()))
+        ref = oracle.max_ig(w.data, w.y, k, w.divisions, w.n_disc, w.range_, w.xi, w.seed, targets=tg,
+                            n_threads=host_threads())
+        where = f"per-variable oracle on {len(tg)} variables (every planted one)"
+    ig = np.asarray(ig_gpu, dtype=np.float64)[tg]
+    err = np.abs(ig - ref[0])
+    out["ig_error"] = {"max_rel_floor1": float((err / np.maximum(np.abs(ref[0]), 1.0)).max()),
+                       "max_rel": float((err / np.maximum(np.abs(ref[0]), 1e-300)).max()),
+                       "max_abs": float(err.max()), "tolerance": 1e-4, "vars": int(len(tg)),
+                       "argmax_equal": int(((np.asarray(argmax_gpu)[tg] == ref[1]).all(axis=1) &
+                                            (np.asarray(disc_gpu)[tg] == ref[2])).sum()),
+                       "reference": where}
+    return out
 
 
 def batch_bench(args):
@@ -258,6 +313,7 @@ def main():
         return
     dev = torch.device("cuda:0")
     w = _wl(args.workload)
+    w.name_key = args.workload
     data = torch.from_numpy(w.data).to(dev)
     y = torch.from_numpy(w.y).to(dev)
     k, div, R = w.k, w.divisions, w.n_disc
@@ -352,23 +408,32 @@ def main():
     n0, n1 = int((w.y == 0).sum()), int((w.y == 1).sum())
     fp4 = args.engine == "mfma_fp4" or (args.engine == "auto" and max(n0, n1) < 4096)
     fp4 = fp4 and (k == 2 or (k == 3 and div in (1, 2)))
-    k3_mfma = k == 3 and fp4 and not args.graph   # the asynchronous call runs k = 3 on bitsets
-    if k == 2:
-        ops_per_unit = 2 * w.n_obj * W * W           # MACs x 2 of the one-hot Gram product per pair
-        achieved = tuples * ops_per_unit / (sweep_ms * 1e-3) / 1e12
+    k3_mfma = k == 3 and fp4
+    C = div + 1
+    if k in (2, 3) and (k == 2 or k3_mfma):
+        # algorithmic work: N voxel increments per tuple table, each counted as one multiply-add
+        # (2 ops); the engine executes 2 N (d-1)^k ops (a one-hot contraction over every bin of
+        # the first d-1, the last rebuilt from marginals)
+        alg_per_unit = 2 * w.n_obj
+        exe_per_unit = 2 * w.n_obj * W ** k
+        achieved = tuples * alg_per_unit / (sweep_ms * 1e-3) / 1e12
+        executed = tuples * exe_per_unit / (sweep_ms * 1e-3) / 1e12
         peak = FP4_PEAK_TFLOPS if fp4 else INT8_PEAK_TOPS
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s" if fp4 else "TOP/s",
-                "frac": achieved / peak, "traffic": None,
-                "kernel": f"k_sweep2<{W}, max, {'fp4' if fp4 else 'int8'}>",
-                "per_unit": f"2*N*(d-1)^2 = {ops_per_unit} {'fp4' if fp4 else 'int8'} ops per pair table",
-                "units_per_launch": tuples, "kernel_ms": sweep_ms}
-    elif k3_mfma:
-        ops_per_unit = 2 * w.n_obj * W ** 3          # MACs x 2 of the pair one-hot x one-hot product
-        achieved = tuples * ops_per_unit / (sweep_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": FP4_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP4_PEAK_TFLOPS, "traffic": None,
-                "kernel": f"k_sweep3m{'1' if W == 1 else ''} (+ pair data)",
-                "per_unit": f"2*N*(d-1)^3 = {ops_per_unit} fp4 ops per triple table",
+        unit = "TFLOP/s" if fp4 else "TOP/s"
+        # the float32 entropy screen: C^k voxel terms per tuple table on the vector ALUs
+        epi_rate = ALU_PEAK_TOPS * 1e12 / (C ** k * EPILOGUE_OPS_PER_VOXEL)
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+                "per_unit": f"2*N = {alg_per_unit} ops per {'pair' if k == 2 else 'triple'} table "
+                            f"(N voxel increments, one multiply-add each)",
+                "executed": {"achieved": executed, "frac": executed / peak,
+                             "per_unit": f"2*N*(d-1)^{k} = {exe_per_unit} {'fp4' if fp4 else 'int8'} MFMA ops"},
+                "epilogue_ceiling": {"tuples_per_s": epi_rate,
+                                     "per_unit": f"{C ** k} voxels x {EPILOGUE_OPS_PER_VOXEL} VALU lane-ops "
+                                                 f"on {ALU_PEAK_TOPS:.1f} Tops/s",
+                                     "frac": tuples / (sweep_ms * 1e-3) / epi_rate},
+                "traffic": None,
+                "kernel": (f"k_sweep2<{W}, max, {'fp4' if fp4 else 'int8'}>" if k == 2
+                           else f"k_sweep3m{'1' if W == 1 else ''} (+ pair data)"),
                 "units_per_launch": tuples, "kernel_ms": sweep_ms}
     elif k == 4:
         # AND + popcount-accumulate per (cell, 32-object word), every one of the C^4 cells counted
@@ -393,6 +458,18 @@ def main():
         tr = json.load(open(args.traffic_json))
         if tr.get("sweep2_sha256") == _sweep_source_hash() and tr.get("encoding", "int8") == ("fp4" if fp4 else "int8"):
             roof["traffic"] = tr.get("bytes_per_launch")
+    lds_json = os.path.join(ROOT, "profiles", "sweep2_headline_lds.json")
+    if k == 2 and args.workload == "headline" and fp4 and os.path.exists(lds_json):
+        # the binding resource, from the SQ counters of the same kernel source (profiles/)
+        lc = json.load(open(lds_json))
+        if lc.get("sweep2_sha256") == _sweep_source_hash():
+            roof["binding_resource"] = lc["binding_resource"]
+            roof["lds"] = {"bytes_per_launch": lc["lds_bytes_per_launch"],
+                           "achieved": lc["lds_bytes_per_launch"] / (sweep_ms * 1e-3) / 1e9,
+                           "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                           "frac": lc["lds_bytes_per_launch"] / (sweep_ms * 1e-3) / 1e9 / LDS_PEAK_GBS,
+                           "busy": lc["lds_util"], "bank_conflict_share": lc["bank_conflict_share"],
+                           "mfma_busy": lc["mfma_util"]}
 
     line = {
         "metric": "k-tuples evaluated/sec (k=2, N=2000, p=20k, 30 discretizations); p50/p99 latency",
@@ -418,8 +495,12 @@ def main():
     }
     if k != 2 or args.workload != "headline":
         line["metric"] = f"k-tuples evaluated/sec (k={k} workload, informational)"
-    if not args.no_cpu_baseline and k == 2:
-        line["cpu_baseline"] = cpu_baseline(w, min(args.cpu_vars, w.n_var), min(args.cpu_disc, w.n_disc))
+    if not args.no_cpu_baseline and k in (2, 3):
+        nv = min(args.cpu_vars if k == 2 else 120, w.n_var)
+        cb = cpu_baseline(w, k, nv, min(args.cpu_disc, w.n_disc), ig.cpu().numpy(), am.cpu().numpy(),
+                          out[2].cpu().numpy())
+        line["ig_error"] = cb.pop("ig_error")
+        line["cpu_baseline"] = cb
     print(json.dumps(line))
 
 

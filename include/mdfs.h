@@ -53,8 +53,9 @@ typedef enum {
     MDFS_E_NAN = -5,     /* data holds a NaN */
     MDFS_E_NOMEM = -6,   /* workspace smaller than mdfs_workspace_size() */
     MDFS_E_HIP = -7,     /* a HIP runtime call failed */
-    MDFS_E_LIMIT = -8,   /* a size beyond the supported maximum */
-    MDFS_E_OVERFLOW = -9 /* candidate buffer overflow (pathological mass ties); results invalid */
+    MDFS_E_CANCELLED = -8, /* the caller's cancel word was set while the sweep ran; outputs undefined */
+    MDFS_E_OVERFLOW = -9,  /* candidate buffer overflow (pathological mass ties); results invalid */
+    MDFS_E_LIMIT = -10     /* a size beyond the supported maximum */
 } mdfs_status;
 
 typedef enum {
@@ -87,6 +88,12 @@ typedef struct {
                             8..4096; smaller grids let concurrent calls on other streams share
                             the GPU (results do not depend on it) */
     int32_t reserved;    /* must be 0 */
+    const volatile uint32_t *cancel;
+                         /* nullable: a caller-owned word in host-mapped memory (hipHostMalloc);
+                            while it reads non-zero, the persistent sweep kernels stop taking work
+                            (each checks it every 16 work items and exits normally) and the call
+                            returns MDFS_E_CANCELLED (mdfs_check_status for asynchronous calls).
+                            The library never writes it; the caller clears it. */
 } mdfs_params;
 
 typedef enum {
@@ -140,7 +147,8 @@ int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint8_t *y, flo
  *   other arguments as mdfs_max_ig; outputs are defined once the stream reaches them.
  * Nothing is read back: the candidate-overflow collect pass is always enqueued and exits on the
  * device when not needed; NaN data, bad y and a final overflow are reported by mdfs_check_status.
- * MDFS_FLAG_TIMING is refused; k = 3 runs on the bitset engine (engine mfma_fp4: MDFS_E_LIMIT).
+ * MDFS_FLAG_TIMING is refused.  Every engine runs as in mdfs_max_ig (the k = 3 matrix-core tile
+ * list is built on the device).
  * Argument errors are returned before anything is enqueued, as for the other calls. */
 int mdfs_max_ig_async(const mdfs_params *prm, const float *data, const uint8_t *y, int64_t n1, float *ig_max,
                       int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream);
@@ -181,9 +189,26 @@ int mdfs_max_ig_codes(const mdfs_params *prm, const uint8_t *codes, const uint8_
  *   counts : device int32 [n_var][n_var][2][c][c], c = divisions+1, class-major; entry
  *            [i][j][d][a][b] counts objects of class d with code a in x_i and b in x_j; only
  *            i < j is written (other entries untouched).
- * For tests and inspection: O(p^2 c^2) output.  Synchronises `stream`. */
+ * The directly counted cells come from the maximum pass of mdfs_max_ig itself (the same kernel
+ * body, encoding and table capacity, with a store added); the cells of each variable's dropped
+ * last bin are completed from the marginals.  For tests and inspection: O(p^2 c^2) output.
+ * Synchronises `stream`. */
 int mdfs_pair_counts(const mdfs_params *prm, const float *data, const uint8_t *y, int32_t disc,
                      int32_t *counts, void *ws, size_t ws_bytes, void *stream);
+
+/* Per-class voxel counts of the triples (i_sel, j, l), i_sel < j < l, under one discretisation, as
+ * produced by the k = 3 count engine that `prm` selects (bitset, or the matrix cores for two and
+ * three classes; the counters N^d of section "Algorithm and implementation").  Requires k = 3;
+ * 0 <= disc < n_disc; 0 <= i_sel <= n_var - 3.
+ *   counts : device int32 [n_var][n_var][2][c][c][c], c = divisions+1, class-major; entry
+ *            [j][l][d][a][b][e] counts objects of class d with codes a, b, e in x_i_sel, x_j, x_l;
+ *            only i_sel < j < l is written (other entries untouched).
+ * The directly counted cells come from the very sweep that mdfs_max_ig runs (the same kernel body,
+ * table capacity and encoding, with a store added); the cells of each variable's dropped last bin
+ * are completed from the pair tables and marginals of that discretisation.  For tests and
+ * inspection: O(p^2 c^3) output.  Synchronises `stream`. */
+int mdfs_triple_counts(const mdfs_params *prm, const float *data, const uint8_t *y, int32_t disc, int32_t i_sel,
+                       int32_t *counts, void *ws, size_t ws_bytes, void *stream);
 
 /* ComputeInterestingTuples (section "Canonical package usage": the tuples whose information
  * gain is at least a threshold, with the gain per member): every (variable i, partner tuple m,

@@ -11,25 +11,23 @@
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
-#include <string>
 #include <vector>
 
 using namespace mdfs;
 
-static thread_local std::string g_err;
+// the thread's last error message (a fixed buffer: reporting an error allocates nothing)
+static thread_local char g_err[512];
 
 namespace mdfs {
-void set_error(const std::string &msg) { g_err = msg; }
+void set_error(const char *msg) { snprintf(g_err, sizeof g_err, "%s", msg); }
 }
 
 static int fail(int code, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -38,7 +36,7 @@ static int hip_fail(hipError_t e, const char *what)
     return fail(MDFS_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-extern "C" const char *mdfs_last_error(void) { return g_err.c_str(); }
+extern "C" const char *mdfs_last_error(void) { return g_err; }
 
 // ---- optional per-phase timing with HIP events on the call's stream
 constexpr int N_PHASE = 4;
@@ -127,7 +125,7 @@ static Layout layout_of(const mdfs_params *prm)
 extern "C" size_t mdfs_workspace_size(const mdfs_params *prm)
 {
     if (check_params(prm, false) != MDFS_OK) return 0;
-    g_err.clear();
+    g_err[0] = 0;
     return layout_of(prm).total;
 }
 
@@ -163,6 +161,7 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
     }
     P.disc_offset = prm->disc_offset;
     P.workgroups = prm->workgroups;
+    P.cancel = const_cast<const uint32_t *>(prm->cancel);
     P.range = prm->range;
     P.seed = prm->seed;
     const int64_t N = prm->n_obj;
@@ -221,6 +220,7 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
             return fail(MDFS_E_LIMIT, "k=3 matrix-core engine needs d = 2 or 3 and classes < 4096 objects");
         if (P.k3_mfma && sweep3m_lds_bytes(P) > LDS_MAX)
             return fail(MDFS_E_LIMIT, "k=3 matrix-core sweep: LDS tables too large");
+        if (P.k3_mfma) sweep3m_tile_counts(P.L.p, P.L.W, P.n_ablk3, P.n_tiles3);
     }
     return MDFS_OK;
 }
@@ -236,6 +236,7 @@ static int read_status(const Problem &P, Status &st)
     hipError_t e = hipMemcpyAsync(&st, P.ws + P.L.status, sizeof(Status), hipMemcpyDeviceToHost, P.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(P.stream);
     if (e != hipSuccess) return hip_fail(e, "reading status");
+    if (st.cancelled) return fail(MDFS_E_CANCELLED, "cancelled through the cancel word; outputs undefined");
     if (st.nan_flag) return fail(MDFS_E_NAN, "data holds a NaN");
     if (st.code_flag) return fail(MDFS_E_ARG, "codes hold a value above divisions");
     return MDFS_OK;
@@ -247,60 +248,43 @@ static hipError_t launch_encode(const Problem &P, const float *data)
     return P.codes_in ? launch_encode_codes(P) : launch_discretize(P, data, nullptr, true);
 }
 
-// Pair sweep (k = 2) or, per discretisation, pair data then triple sweep (k = 3).
-static int sweep_pass(const Problem &P, int32_t *counts, int disc_sel, bool collect)
+// Pair sweep (k = 2) or, per discretisation, pair data then triple sweep (k = 3).  counts !=
+// nullptr: the count export of discretisation disc_sel (k = 2: every pair; k = 3: the triples
+// (i_sel, j, l)), completed from the marginals and pair tables of that discretisation.
+static int sweep_pass(const Problem &P, int32_t *counts, int disc_sel, bool collect, int i_sel = -1)
 {
     if (P.L.k == 2) {
         LAUNCH(launch_reset_queue(P));
         LAUNCH(launch_sweep2(P, counts, disc_sel, collect));
+        if (counts) LAUNCH(launch_complete_pairs(P, counts, disc_sel));
     } else if (P.L.k == 4) {
         for (int r = 0; r < P.L.R; ++r) LAUNCH(launch_sweep4(P, r, collect));
     } else {
         for (int r = 0; r < P.L.R; ++r) {
+            int32_t *cr = (counts && r == disc_sel) ? counts : nullptr;
             LAUNCH(launch_reset_queue(P));
             LAUNCH(launch_pairs(P, r, collect));
-            if (P.k3_mfma) LAUNCH(launch_sweep3m(P, r, collect));
-            else LAUNCH(launch_sweep3(P, r, collect));
+            if (P.k3_mfma) LAUNCH(launch_sweep3m(P, r, collect, cr, i_sel));
+            else LAUNCH(launch_sweep3(P, r, collect, cr, i_sel));
+            // before the next discretisation's pair data replace this one's
+            if (cr) LAUNCH(launch_complete_triples(P, cr, r, i_sel));
         }
     }
     return MDFS_OK;
 }
 
-// discretise + encode + sweep, leaving the maxima and candidates in the workspace
-// Tile list of the k = 3 matrix-core sweep, built on the host and copied into the workspace.
-static int upload_k3_tiles(Problem &P)
-{
-    std::vector<int64_t> apref;
-    std::vector<int32_t> ablk;
-    sweep3m_tiles(P.L.p, P.L.W, apref, ablk);
-    P.n_ablk3 = (int64_t)ablk.size();
-    P.n_tiles3 = apref.back();
-    if (ablk.empty()) return MDFS_OK;
-    hipError_t e = hipMemcpyAsync(P.ws + P.L.a3pref, apref.data(), apref.size() * sizeof(int64_t),
-                                  hipMemcpyHostToDevice, P.stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(P.ws + P.L.a3blk, ablk.data(), ablk.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                           P.stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(P.stream);   // the host vectors go out of scope
-    if (e != hipSuccess) return hip_fail(e, "copying the k=3 tile list");
-    return MDFS_OK;
-}
-
 static int run_sweep(Problem &P, const float *data, const uint8_t *y, int32_t *counts, int disc_sel,
-                     PhaseTimer *tm = nullptr)
+                     PhaseTimer *tm = nullptr, int i_sel = -1)
 {
-    if (P.k3_mfma) {
-        const int rc = upload_k3_tiles(P);
-        if (rc) return rc;
-    }
     if (tm) tm->mark(0);
     LAUNCH(launch_init(P));
+    if (P.k3_mfma) LAUNCH(launch_tiles3(P));
     LAUNCH(launch_class_perm(P, y));
     LAUNCH(launch_tables(P));
     if (tm) tm->mark(1);
     LAUNCH(launch_encode(P, data));
     if (tm) tm->mark(2);
-    int rc = sweep_pass(P, counts, disc_sel, false);
+    int rc = sweep_pass(P, counts, disc_sel, false, i_sel);
     if (rc) return rc;
     // If the opportunistic candidate appends overflowed, sweep again with the final float32
     // maxima as fixed thresholds: that pass appends exactly the (tuple, discretisation) pairs
@@ -330,7 +314,7 @@ extern "C" int mdfs_discretize(const mdfs_params *prm, const float *data, uint8_
     LAUNCH(launch_discretize(P, data, codes, false));
     Status st;
     if ((rc = read_status(P, st))) return rc;
-    g_err.clear();
+    g_err[0] = 0;
     return MDFS_OK;
 }
 
@@ -348,7 +332,7 @@ extern "C" int mdfs_add_contrast(const float *data, int64_t n_obj, int64_t n_var
         for (int64_t c = 0; c < n_contrast; ++c) src[c] = (int32_t)contrast_source(seed, c, n_var);
     hipError_t e = launch_contrast(data, n_obj, n_var, n_contrast, seed, out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "contrast variables");
-    g_err.clear();
+    g_err[0] = 0;
     return MDFS_OK;
 }
 
@@ -384,7 +368,7 @@ static int max_ig_impl(const mdfs_params *prm, const float *data, const uint8_t 
         Status st;
         if ((rc = read_status(P, st))) return rc;
         tm.publish();
-        g_err.clear();
+        g_err[0] = 0;
         return MDFS_OK;
     }
     PhaseTimer tm((prm->flags & MDFS_FLAG_TIMING) != 0, P.stream);
@@ -395,7 +379,7 @@ static int max_ig_impl(const mdfs_params *prm, const float *data, const uint8_t 
     if ((rc = read_status(P, st))) return rc;
     tm.publish();
     if (st.overflow) return fail(MDFS_E_OVERFLOW, "candidate buffer overflow (%u appends)", st.n_cand);
-    g_err.clear();
+    g_err[0] = 0;
     return MDFS_OK;
 }
 
@@ -411,21 +395,18 @@ extern "C" int mdfs_max_ig_codes(const mdfs_params *prm, const uint8_t *codes, c
     return max_ig_impl(prm, nullptr, codes, y, ig_max, argmax, argmax_disc, ws, ws_bytes, stream);
 }
 
-extern "C" int mdfs_max_ig_async(const mdfs_params *prm, const float *data, const uint8_t *y, int64_t n1,
-                                 float *ig_max, int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes,
-                                 void *stream)
+static int max_ig_async_impl(const mdfs_params *prm, const float *data, const uint8_t *y, int64_t n1, float *ig_max,
+                             int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream)
 {
     int rc = check_params(prm);
     if (rc) return rc;
     if (!data || !y || !ig_max || !ws) return fail(MDFS_E_ARG, "null pointer");
     if (prm->flags & MDFS_FLAG_TIMING) return fail(MDFS_E_ARG, "timing reads events back: not in the asynchronous call");
     if (n1 < 1 || n1 >= prm->n_obj) return fail(MDFS_E_Y, "n1=%lld: both classes must be non-empty", (long long)n1);
-    if (prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA_FP4)
-        return fail(MDFS_E_LIMIT, "k=3 on the matrix cores prepares its tile list on the host: not asynchronous");
     Problem P;
     if ((rc = setup(prm, y, ws, ws_bytes, stream, P, n1))) return rc;
-    P.k3_mfma = false;   // the bitset engine needs no host-prepared tile list
     LAUNCH(launch_init(P));
+    if (P.k3_mfma) LAUNCH(launch_tiles3(P));
     LAUNCH(launch_class_perm(P, y, n1));
     if (prm->k == 1) {
         LAUNCH(launch_encode(P, data));
@@ -440,8 +421,15 @@ extern "C" int mdfs_max_ig_async(const mdfs_params *prm, const float *data, cons
         if ((rc = sweep_pass(P, nullptr, -1, true))) return rc;
         LAUNCH(launch_finalize(P, ig_max, argmax, argmax_disc));
     }
-    g_err.clear();
+    g_err[0] = 0;
     return MDFS_OK;
+}
+
+extern "C" int mdfs_max_ig_async(const mdfs_params *prm, const float *data, const uint8_t *y, int64_t n1,
+                                 float *ig_max, int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes,
+                                 void *stream)
+{
+    return max_ig_async_impl(prm, data, y, n1, ig_max, argmax, argmax_disc, ws, ws_bytes, stream);
 }
 
 extern "C" size_t mdfs_batch_workspace_size(void) { return 256; }
@@ -495,7 +483,7 @@ extern "C" int mdfs_max_ig_batch(int n, const mdfs_params *prm, const float *con
         if (rc) return rc;
         LAUNCH(launch_finalize(P, ig_max[i], argmax ? argmax[i] : nullptr, argmax_disc ? argmax_disc[i] : nullptr));
     }
-    g_err.clear();
+    g_err[0] = 0;
     return MDFS_OK;
 }
 
@@ -512,10 +500,11 @@ extern "C" int mdfs_check_status(const mdfs_params *prm, const void *ws, size_t 
     if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "reading status");
     if (st.y_flag) return fail(MDFS_E_Y, "y disagrees with n1 or holds a value other than 0 and 1");
+    if (st.cancelled) return fail(MDFS_E_CANCELLED, "cancelled through the cancel word; outputs undefined");
     if (st.nan_flag) return fail(MDFS_E_NAN, "data holds a NaN");
     if (st.code_flag) return fail(MDFS_E_ARG, "codes hold a value above divisions");
     if (st.overflow) return fail(MDFS_E_OVERFLOW, "candidate buffer overflow (%u appends)", st.n_cand);
-    g_err.clear();
+    g_err[0] = 0;
     return MDFS_OK;
 }
 
@@ -533,7 +522,26 @@ extern "C" int mdfs_pair_counts(const mdfs_params *prm, const float *data, const
     if ((rc = run_sweep(P, data, y, counts, disc))) return rc;
     Status st;
     if ((rc = read_status(P, st))) return rc;
-    g_err.clear();
+    g_err[0] = 0;
+    return MDFS_OK;
+}
+
+extern "C" int mdfs_triple_counts(const mdfs_params *prm, const float *data, const uint8_t *y, int32_t disc,
+                                  int32_t i_sel, int32_t *counts, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_params(prm);
+    if (rc) return rc;
+    if (prm->k != 3) return fail(MDFS_E_K, "triple counts need k=3");
+    if (!data || !y || !counts || !ws) return fail(MDFS_E_ARG, "null pointer");
+    if (disc < 0 || disc >= prm->n_disc) return fail(MDFS_E_ARG, "disc=%d outside [0,%d)", disc, prm->n_disc);
+    if (i_sel < 0 || i_sel + 2 >= prm->n_var)
+        return fail(MDFS_E_ARG, "i_sel=%d: needs two larger variables below n_var=%lld", i_sel, (long long)prm->n_var);
+    Problem P;
+    if ((rc = setup(prm, y, ws, ws_bytes, stream, P))) return rc;
+    if ((rc = run_sweep(P, data, y, counts, disc, nullptr, i_sel))) return rc;
+    Status st;
+    if ((rc = read_status(P, st))) return rc;
+    g_err[0] = 0;
     return MDFS_OK;
 }
 
@@ -552,8 +560,8 @@ extern "C" int mdfs_interesting_tuples(const mdfs_params *prm, const float *data
     *n_found = 0;
     Problem P;
     if ((rc = setup(prm, y, ws, ws_bytes, stream, P))) return rc;
-    if (P.k3_mfma && (rc = upload_k3_tiles(P))) return rc;
     LAUNCH(launch_init(P));
+    if (P.k3_mfma) LAUNCH(launch_tiles3(P));
     LAUNCH(launch_class_perm(P, y));
     LAUNCH(launch_tables(P));
     LAUNCH(launch_encode(P, data));
@@ -575,7 +583,7 @@ extern "C" int mdfs_interesting_tuples(const mdfs_params *prm, const float *data
     LAUNCH(launch_emit(P, ig_thr, var, partners, disc, ig, max_out));
     if ((rc = read_status(P, st))) return rc;
     *n_found = st.n_emit;
-    g_err.clear();
+    g_err[0] = 0;
     return MDFS_OK;
 }
 
@@ -593,6 +601,6 @@ extern "C" int mdfs_screen_max(const mdfs_params *prm, const float *data, const 
     Status st;
     if ((rc = read_status(P, st))) return rc;
     if (err_bound) *err_bound = P.err_bound;
-    g_err.clear();
+    g_err[0] = 0;
     return MDFS_OK;
 }

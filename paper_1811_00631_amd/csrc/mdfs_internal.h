@@ -43,7 +43,8 @@ struct Status {
     uint32_t code_flag;   // caller-supplied codes held a value above divisions
     uint32_t collect_go;  // the gated collect pass runs (set on the device before it)
     uint32_t y_flag;      // y disagreed with the class-1 count given to an asynchronous call
-    uint32_t pad0[9];
+    uint32_t cancelled;   // a sweep kernel saw the caller's cancel word set and stopped early
+    uint32_t pad0[8];
     uint32_t next_tile[16];   // per-XCD work counters of the persistent sweep (reset per pass)
     uint32_t pad[32];
 };
@@ -131,6 +132,19 @@ __device__ __forceinline__ uint32_t reserve_slots(uint32_t *counter, uint32_t mi
     return base + incl - mine;
 }
 
+// The caller's cancel word (host-mapped, nullable), read with a system-scope load so that a
+// host write made while the kernel runs is seen.  Persistent sweeps poll it every 16 work items
+// (`taken` counts the items a workgroup or wave has taken) and, when it is set, record it in
+// Status::cancelled and stop taking work.
+__device__ inline bool cancel_poll(const uint32_t *cancel, uint32_t taken, Status *st)
+{
+    if (cancel == nullptr || (taken & 15u) != 0) return false;
+    if (__hip_atomic_load(const_cast<uint32_t *>(cancel), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == 0)
+        return false;
+    atomicOr(&st->cancelled, 1u);
+    return true;
+}
+
 // Everything a launch sequence needs about one problem (sizes, pseudocounts, buffers).
 struct Problem {
     Layout L;
@@ -147,6 +161,7 @@ struct Problem {
     int workgroups;               // persistent sweep grid (0 = the whole GPU)
     int64_t n_ablk3, n_tiles3;    // tile list of the k = 3 matrix-core sweep
     const uint8_t *codes_in = nullptr;   // caller-supplied codes [R][p][N] replace the discretisation
+    const uint32_t *cancel = nullptr;    // caller's host-mapped cancel word (nullable)
     char *ws;
     hipStream_t stream;
     template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -162,6 +177,8 @@ hipError_t launch_discretize(const Problem &P, const float *data, uint8_t *codes
 // the encoding, marginals and F1 from caller-supplied codes (P.codes_in) instead of discretising
 hipError_t launch_encode_codes(const Problem &P);
 hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bool collect = false);
+// the count export: cells of the dropped last bins of every pair from the marginals of disc r
+hipError_t launch_complete_pairs(const Problem &P, int32_t *counts, int r);
 // LDS bytes per workgroup of the pair sweep (max_mode: the maximum sweep, else debug/pair modes)
 size_t sweep2_lds_bytes(const Problem &P, bool max_mode);
 constexpr size_t LDS_MAX = 160 * 1024;
@@ -175,13 +192,17 @@ hipError_t launch_pairs(const Problem &P, int r, bool gated = false);
 hipError_t launch_sweep2_batch(const Problem *const *Ps, int n, Status *queue);
 // Table capacity of the fp4 pair sweep for a problem's class sizes (0 = does not fit).
 int sweep2_fp4_capacity(const Problem &P);
-hipError_t launch_sweep3(const Problem &P, int r, bool collect);
+// k = 3 sweeps of discretisation r; counts_out != nullptr: also the count export of the triples
+// (i_sel, j, l), directly counted cells only (launch_complete_triples fills in the others)
+hipError_t launch_sweep3(const Problem &P, int r, bool collect, int32_t *counts_out = nullptr, int i_sel = -1);
+hipError_t launch_complete_triples(const Problem &P, int32_t *counts, int r, int i_sel);
 // k = 4 bitset sweep of discretisation r (sweep4.hip)
 hipError_t launch_sweep4(const Problem &P, int r, bool collect);
-hipError_t launch_sweep3m(const Problem &P, int r, bool collect);
+hipError_t launch_sweep3m(const Problem &P, int r, bool collect, int32_t *counts_out = nullptr, int i_sel = -1);
 size_t sweep3m_lds_bytes(const Problem &P);
-// host-side tile list of the k = 3 matrix-core sweep (first tile per A block, A blocks)
-void sweep3m_tiles(int64_t p, int W, std::vector<int64_t> &apref, std::vector<int32_t> &ablk);
+// tile list of the k = 3 matrix-core sweep: its size on the host, the list itself on the device
+void sweep3m_tile_counts(int64_t p, int W, int64_t &n_ablk, int64_t &n_tiles);
+hipError_t launch_tiles3(const Problem &P);
 hipError_t launch_reset_queue(const Problem &P);
 hipError_t launch_finalize(const Problem &P, float *ig_max, int32_t *argmax, int32_t *argmax_disc);
 // every variable's threshold key set to `key` (the interesting-tuples collect pass)

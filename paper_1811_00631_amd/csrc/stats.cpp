@@ -35,7 +35,7 @@
 #include <vector>
 
 namespace mdfs {
-void set_error(const std::string &msg);   // api.hip: thread-local message for mdfs_last_error
+void set_error(const char *msg);   // api.hip: thread-local message for mdfs_last_error
 }
 
 namespace {

@@ -50,8 +50,14 @@ __host__ __device__ constexpr int sw_waves(int W) { return W == 2 ? 8 : 4; }
 constexpr int SB = 8;                    // a super-tile is SB x SB tiles
 constexpr int XCDS = 8;                  // workgroup b runs on XCD b % 8
 constexpr int WG_PER_XCD = SB * SB;      // resident workgroups per XCD (2 per CU: LDS)
-constexpr int STAGE_BYTES = 2 * TILE_ROWS * KBLK;   // A and B tiles of one K block
 constexpr int NSTAGE = 3;                           // LDS ring of K blocks
+// direct_b(W): the A operand goes through the LDS ring and each wave loads its own B fragments
+// from global memory (L2) straight into registers, so a stage holds the A tile only and the
+// first pass parks F in a buffer of its own; otherwise (every class count in this build) a stage
+// holds the A and B tiles and F is parked in the stage after the last K block's.
+__host__ __device__ constexpr bool direct_b(int) { return false; }
+__host__ __device__ constexpr int stage_bytes(int W) { return (direct_b(W) ? 1 : 2) * TILE_ROWS * KBLK; }
+__host__ __device__ constexpr int ring_bytes(int W) { return NSTAGE * stage_bytes(W) + (direct_b(W) ? 16 * 1024 : 0); }
 
 struct Sweep2Args {
     const int8_t *onehot;
@@ -80,10 +86,11 @@ struct Sweep2Args {
     int snext_off;           // LDS byte offset of the work-item broadcast slot
     uint32_t *ptab;          // pair mode: packed (W x W) counts [p_pad][p_pad][W*W]
     float *F2out;            // pair mode: float32 F of each pair table [p_pad][p_pad]
+    const uint32_t *cancel;  // caller's cancel word (nullable)
 };
 
 // What one launch of the pair sweep produces.
-enum SweepMode { SWEEP_MAX = 0, SWEEP_DEBUG_COUNTS = 1, SWEEP_PAIRS = 2 };
+enum SweepMode { SWEEP_MAX = 0, SWEEP_PAIRS = 2 };
 
 // Several problems in one persistent launch (maximum pass): their super-tiles are concatenated
 // (pref = prefix of each problem's super-tile count) and drawn from one set of queues.  Passed
@@ -159,7 +166,7 @@ __device__ inline void tri_index(int64_t tt, int &bi, int &bj)
     bi = (int)(tt - j * (j + 1) / 2);
 }
 
-template <int W, int MODE, int ENC, bool BATCH>
+template <int W, int MODE, int ENC, bool BATCH, bool EXPORT = false>
 __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 {
     constexpr bool F4 = ENC != 0;
@@ -170,9 +177,11 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     constexpr int NP = (W == 1) ? 4 : 1; // pairs held per lane per 16x16 block
     constexpr int NWAVE = sw_waves(W), NT = NWAVE * 64;
     constexpr int NN = 16 / NWAVE;       // 16 x 16 column blocks per wave (row blocks: 4)
-    constexpr int LPW = 16 / NWAVE;      // 1 KB operand fetches per wave and K block
+    constexpr bool DB = direct_b(W);     // B fragments straight from L2 into registers
+    constexpr int LPW = (DB ? 8 : 16) / NWAVE;   // 1 KB operand fetches into LDS per wave and K block
+    constexpr int SBYTES = stage_bytes(W);
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    char *stage = smem + stage_base(ENC);   // [NSTAGE buffers][A 8 KB | B 8 KB]
+    char *stage = smem + stage_base(ENC);   // [NSTAGE buffers][A 8 KB | B 8 KB (not with DB)] [F buffer (DB)]
     // int8: tables after the stages, at run-time offsets (per problem)
     float *EA = nullptr, *EB = nullptr;
     float2 *LQ = nullptr;
@@ -185,7 +194,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 
     // the problem's entropy tables into LDS
     auto load_tables = [&]() {
-        EA = reinterpret_cast<float *>(smem + NSTAGE * STAGE_BYTES);
+        EA = reinterpret_cast<float *>(smem + ring_bytes(W));
         EB = EA + (a.N0 + 1);
         LQ = reinterpret_cast<float2 *>(EB + (a.N1 + 1) + ((a.N0 + a.N1) & 1));
         if constexpr (F4) {
@@ -211,12 +220,18 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     // wherever its workgroups run.
     const int xcd = (int)(__builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 7);  // HW_REG_XCC_ID
     int my_q = xcd, q_seen = 0;   // thread 0's position in the queue walk
+    uint32_t taken = 0;           // work items taken by this workgroup (cancel polling)
     for (;;) {
     __syncthreads();   // everyone has read the previous s_next
     if (t == 0) {
         int64_t it = -1;
         const int64_t n_super = BATCH ? bt->pref[bt->nb] : a.n_super;
         Status *qst = BATCH ? bt->queue : a.st;
+        if (cancel_poll(a.cancel, taken++, a.st)) {
+            if constexpr (BATCH)
+                for (int b_ = 0; b_ < bt->nb; ++b_) atomicOr(&bt->p[b_].st->cancelled, 1u);
+            q_seen = XCDS;   // take no more work
+        }
         while (q_seen < XCDS) {
             const int64_t nq = ((n_super - my_q + XCDS - 1) / XCDS) * (SB * SB);
             it = (int64_t)atomicAdd(&qst->next_tile[my_q], 1u);
@@ -272,14 +287,15 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 
     // K blocks in processing order: class 1 first, then class 0
     auto kblock = [&](int s_) { return s_ < n1blk ? a.KB0 + s_ : s_ - n1blk; };
-    auto stage_at = [&](int s_) { return stage + (s_ % NSTAGE) * STAGE_BYTES; };
+    auto stage_at = [&](int s_) { return stage + (s_ % NSTAGE) * SBYTES; };
     // Operands go from global memory straight into LDS (global_load_lds_dwordx4): one
     // instruction fills 1 KB = 16 rows, lane i's 16 bytes landing at offset 16 i.  A stage is
     // 16 such blocks (A rows 0..127, then B rows 0..127); wave w fills blocks LPW w ..
     // LPW w + LPW - 1, so the first half of the waves fetch the A panel and the second half the
     // B panel.  The swizzle of the stage layout is applied on the global side: lane i fetches
     // the chunk that belongs at its slot.
-    const int8_t *pan = wave < NWAVE / 2 ? panA : panB;
+    // With DB every wave fetches one 1 KB block of the A panel (a stage is the A tile only).
+    const int8_t *pan = (DB || wave < NWAVE / 2) ? panA : panB;
     int goff[LPW];
 #pragma unroll
     for (int i = 0; i < LPW; ++i) {
@@ -287,6 +303,14 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         const int j = (lane & 3) ^ ((row >> 1) & 3);
         goff[i] = row * KBLK + j * 16;
     }
+    // DB: lane (q, c16) loads 16 bytes (objects of quarter q) of B row wc 16 NN + 16 n + c16, the
+    // layout of the MFMA operand; one load instruction covers 1 KB contiguous of the panel
+    const int8_t *bsrc = panB + (wc * 16 * NN + c16) * KBLK + q * 16;
+    auto loadB = [&](int s_, v4i (&xb)[NN]) {
+        const int8_t *src = bsrc + (int64_t)kblock(s_) * kstride;
+#pragma unroll
+        for (int n = 0; n < NN; ++n) xb[n] = *reinterpret_cast<const v4i *>(src + n * 16 * KBLK);
+    };
     auto issue = [&](int s_) {
         const int8_t *src = pan + (int64_t)kblock(s_) * kstride;
         char *dst = stage_at(s_) + wave * LPW * 1024;
@@ -300,8 +324,12 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         const char *A = stage_at(s_), *B = A + TILE_ROWS * KBLK;
 #pragma unroll
         for (int m = 0; m < 4; ++m) xa[m] = *reinterpret_cast<const v4i *>(A + fa_off0 + m * 16 * KBLK);
+        if constexpr (DB) {
+            loadB(s_, xb);
+        } else {
 #pragma unroll
-        for (int n = 0; n < NN; ++n) xb[n] = *reinterpret_cast<const v4i *>(B + fb_off0 + n * 16 * KBLK);
+            for (int n = 0; n < NN; ++n) xb[n] = *reinterpret_cast<const v4i *>(B + fb_off0 + n * 16 * KBLK);
+        }
     };
     // Software pipeline over a ring of NSTAGE = 3 LDS stages; blocks are fetched two steps ahead
     // and their fragments read one step ahead.  Step s: the wave waits until its fragment reads
@@ -336,11 +364,16 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                 }
         }
     };
-    // the plain barrier: a fenced one would also drain the fetches still in flight
+    // the plain barrier: a fenced one would also drain the fetches still in flight.  DB: the B
+    // loads of block s+1 are issued (in frags) between the LDS fetches of blocks s+2 and s+3, so
+    // at the top of step s+1 the fetch of block s+2 is complete once at most NN + LPW loads
+    // remain outstanding (NN of them the B loads, whose registers the compiler waits for itself).
+    constexpr int VM_AHEAD = DB ? NN + LPW : LPW;   // loads allowed in flight when block s+2 exists
+    constexpr int VM_LAST = DB ? NN : 0;            // ... when it does not
     auto step = [&](int s_, const v4i (&ca)[4], const v4i (&cb)[NN], v4i (&na)[4], v4i (&nb)[NN]) {
         if (s_ + 1 < a.KB) {
-            if (s_ + 2 < a.KB) __builtin_amdgcn_s_waitcnt(0x0070 | LPW);   // vmcnt(LPW) lgkmcnt(0)
-            else __builtin_amdgcn_s_waitcnt(0x0070);                       // vmcnt(0) lgkmcnt(0)
+            if (s_ + 2 < a.KB) __builtin_amdgcn_s_waitcnt(0x0070 | VM_AHEAD);   // vmcnt(VM_AHEAD) lgkmcnt(0)
+            else __builtin_amdgcn_s_waitcnt(0x0070 | VM_LAST);                  // vmcnt(VM_LAST) lgkmcnt(0)
             __builtin_amdgcn_s_barrier();
             frags(s_ + 1, na, nb);
             if (s_ + 3 < a.KB) issue(s_ + 3);
@@ -350,10 +383,17 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     v4i fa0[4], fb0[NN], fa1[4], fb1[NN];
     issue(0);
     if (a.KB > 1) issue(1);
-    if (a.KB > 1) __builtin_amdgcn_s_waitcnt(0x0F70 | LPW);
-    else __builtin_amdgcn_s_waitcnt(0x0F70);
+    if constexpr (DB) loadB(0, fb0);
+    // the fetch of block 0 complete: block 1's fetch (and the B loads of block 0) may be in flight
+    if (a.KB > 1) __builtin_amdgcn_s_waitcnt(0x0F70 | (LPW + (DB ? NN : 0)));
+    else __builtin_amdgcn_s_waitcnt(0x0F70 | (DB ? NN : 0));
     __builtin_amdgcn_s_barrier();
-    frags(0, fa0, fb0);
+    if constexpr (DB) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) fa0[m] = *reinterpret_cast<const v4i *>(stage_at(0) + fa_off0 + m * 16 * KBLK);
+    } else {
+        frags(0, fa0, fb0);
+    }
     if (a.KB > 2) issue(2);
     int s = 0;
     for (; s + 1 < a.KB; s += 2) {
@@ -368,7 +408,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     // KB - 3 (or nothing): every wave read its fragments and every fetch landed before the last
     // barrier of the K loop, and the next tile's first fetch follows the barriers at the top of
     // the tile loop.
-    float *f2buf = reinterpret_cast<float *>(stage_at(a.KB));
+    float *f2buf = reinterpret_cast<float *>(DB ? stage + NSTAGE * SBYTES : stage_at(a.KB));
     auto put_cand = [&](uint32_t at, int64_t v, int64_t partner, float ig) {
         if (at < a.cap) a.cand[at] = Cand{(int32_t)v, r, (uint32_t)partner, ig};
         else { atomicOr(&a.ovf[v], 1u); atomicOr(&a.st->overflow, 1u); }
@@ -390,6 +430,28 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                 cnt[m][n] = acc[m][n];
             }
         }
+    // Count export (EXPORT: the maximum pass with the same table capacity, encoding and LDS layout,
+    // plus this store): for the selected discretisation every lane stores the W x W directly
+    // counted cells it holds into their places in the caller's [p][p][2][C][C] tables;
+    // launch_complete_pairs then fills in the cells of each variable's dropped last bin.
+    if (EXPORT && r == a.disc_sel) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < NN; ++n)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    // lane (q, c16) holds rows 4q .. 4q + 3 of column c16 of block (m, n)
+                    const int row = wr * 64 + m * 16 + 4 * q + e, col = wc * 16 * NN + n * 16 + c16;
+                    const int64_t rv = (int64_t)bi * TV + row / W, cv = (int64_t)bj * TV + col / W;
+                    if (rv < cv && cv < a.p) {
+                        const uint32_t v = F4 ? (uint32_t)cnt[m][n][e] >> 2 : (uint32_t)cnt[m][n][e];
+                        int32_t *o = a.counts_out + (rv * a.p + cv) * 2 * C * C + (row % W) * C + col % W;
+                        o[0] = (int32_t)(v & 0xffffu);
+                        o[C * C] = (int32_t)(v >> 16);
+                    }
+                }
+    }
 
     if constexpr (W == 4) {
         static_assert(NN == 4, "the five-class epilogue assumes 4 x 4 blocks per wave");
@@ -455,7 +517,6 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 #pragma unroll
         for (int m = 0; m < 4; ++m) rmax[m] = cmax[m] = -INFINITY;
         bool hot = false;
-        const bool emit = MODE == SWEEP_DEBUG_COUNTS && r == a.disc_sel;
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -479,19 +540,6 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                 rmax[m] = fmaxf(rmax[m], igR);
                 cmax[n] = fmaxf(cmax[n], igC);
                 hot |= (igR >= thrR[m]) | (igC >= thrC[n]);
-                if (emit && valid) {
-                    int32_t *o = a.counts_out + ((int64_t)rv * a.p + cv) * 2 * C * C;
-                    auto put = [&](int x, int y, uint32_t P_) {
-                        const uint32_t v_ = dec(P_);
-                        o[x * C + y] = (int32_t)(v_ & 0xffffu);
-                        o[C * C + x * C + y] = (int32_t)(v_ >> 16);
-                    };
-#pragma unroll
-                    for (int x = 0; x < 4; ++x) put(x, b, vx[x]);
-                    put(4, b, vx[4]);
-                    put(b, 4, vx[5]);
-                    if (b == 0) put(4, 4, vx[6]);
-                }
             }
         if constexpr (MODE == SWEEP_PAIRS) continue;
         // wave maxima: a pair's value is replicated on its quad; row variables differ in q,
@@ -641,7 +689,6 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     for (int n = 0; n < NN; ++n) cmax[n] = -INFINITY;
     bool hot = false;
 
-    const bool emit = MODE == SWEEP_DEBUG_COUNTS && r == a.disc_sel;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -671,18 +718,6 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                 rmax[m][s] = fmaxf(rmax[m][s], igR);
                 cmax[n] = fmaxf(cmax[n], igC);
                 hot |= (igR >= thrR[m][s]) | (igC >= thrC[n]);
-
-                if (emit && valid) {
-                    int32_t *o = a.counts_out + ((int64_t)rv * a.p + cv) * 2 * C * C;
-#pragma unroll
-                    for (int x = 0; x < C; ++x)
-#pragma unroll
-                        for (int y = 0; y < C; ++y) {
-                            const uint32_t v = F4 ? tab[x][y] >> 2 : tab[x][y];
-                            o[x * C + y] = (int32_t)(v & 0xffffu);
-                            o[C * C + x * C + y] = (int32_t)(v >> 16);
-                        }
-                }
             }
 
     if constexpr (MODE == SWEEP_PAIRS) continue;
@@ -789,10 +824,10 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     }   // work items
 }
 
-template <int W, int MODE, int ENC>
+template <int W, int MODE, int ENC, bool EXPORT = false>
 __global__ __launch_bounds__(sw_waves(W) * 64, 2) __attribute__((amdgpu_waves_per_eu(sw_waves(W) / 2, sw_waves(W) / 2))) void k_sweep2(Sweep2Args a)
 {
-    sweep2_run<W, MODE, ENC, false>(a, nullptr);
+    sweep2_run<W, MODE, ENC, false, EXPORT>(a, nullptr);
 }
 
 template <int W, int ENC>
@@ -814,10 +849,10 @@ size_t sweep2_lds_bytes(const Problem &P, bool max_mode)
 {
     if (P.fp4) {
         const int T = max_mode ? fp4_capacity(P) : 4096;
-        return (size_t)stage_base(T) + NSTAGE * STAGE_BYTES + 16;
+        return (size_t)stage_base(T) + ring_bytes(P.L.W) + 16;
     }
     size_t tab = sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (P.L.N + 1);
-    return NSTAGE * STAGE_BYTES + ((tab + 15) & ~size_t(15)) + 16;
+    return ring_bytes(P.L.W) + ((tab + 15) & ~size_t(15)) + 16;
 }
 
 int sweep2_fp4_capacity(const Problem &P) { return fp4_capacity(P); }
@@ -861,6 +896,7 @@ static Sweep2Args sweep_args(const Problem &P, int32_t *counts_out, int disc_sel
     a.disc_sel = disc_sel;
     a.collect = collect ? 1 : 0;
     a.gated = gated ? 1 : 0;
+    a.cancel = P.cancel;
     return a;
 }
 
@@ -869,11 +905,10 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
                                bool gated)
 {
     Sweep2Args a = sweep_args<W>(P, counts_out, disc_sel, collect, pair_r, gated);
-    const bool max_mode = pair_r < 0 && !counts_out;
-    const size_t lds = sweep2_lds_bytes(P, max_mode);
+    const size_t lds = sweep2_lds_bytes(P, pair_r < 0);
     a.snext_off = (int)(lds - 16);
     auto kern = pair_r >= 0 ? k_sweep2<W, SWEEP_PAIRS, ENC>
-                            : (counts_out ? k_sweep2<W, SWEEP_DEBUG_COUNTS, ENC> : k_sweep2<W, SWEEP_MAX, ENC>);
+                            : (counts_out ? k_sweep2<W, SWEEP_MAX, ENC, true> : k_sweep2<W, SWEEP_MAX, ENC>);
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     // no more workgroups than tile slots (each loads its tables before it takes a tile), at least
@@ -890,9 +925,9 @@ static hipError_t sweep_dispatch(const Problem &P, int32_t *counts_out, int disc
                                  bool gated)
 {
     if (!P.fp4) return sweep_launch<W, 0>(P, counts_out, disc_sel, collect, pair_r, gated);
-    // the maximum sweep is instantiated per table capacity (occupancy); the debug and pair
-    // modes use the largest
-    if (pair_r >= 0 || counts_out) return sweep_launch<W, 4096>(P, counts_out, disc_sel, collect, pair_r, gated);
+    // the maximum sweep (and with it the count export) is instantiated per table capacity
+    // (occupancy); the pair data of the triple sweeps use the largest
+    if (pair_r >= 0) return sweep_launch<W, 4096>(P, counts_out, disc_sel, collect, pair_r, gated);
     switch (fp4_capacity(P)) {
     case 1024: return sweep_launch<W, 1024>(P, counts_out, disc_sel, collect, pair_r, gated);
     case 2048: return sweep_launch<W, 2048>(P, counts_out, disc_sel, collect, pair_r, gated);
@@ -917,6 +952,56 @@ hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bo
 }
 
 hipError_t launch_pairs(const Problem &P, int r, bool gated) { return sweep_any(P, nullptr, -1, false, r, gated); }
+
+// ---------------------------------------------------------------- count export, completion
+// The maximum pass stored the W x W directly counted cells of every pair i < j of the selected
+// discretisation into counts [p][p][2][C][C]; the cells of the dropped last bin of either variable
+// follow exactly from the per-class marginals: n[a][W] = M_i[a] - sum_b<W n[a][b] and
+// n[W][b] = M_j[b] - sum_a<W n[a][b].  One thread per (i, j).
+template <int C>
+__global__ __launch_bounds__(256) void k_complete_pairs(int32_t *counts, const uint32_t *marg, int r, int64_t p,
+                                                        int64_t p_pad)
+{
+    constexpr int W = C - 1;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p * p) return;
+    const int64_t i = t / p, j = t % p;
+    if (i >= j) return;
+    const uint32_t *Mi = marg + ((int64_t)r * p_pad + i) * C, *Mj = marg + ((int64_t)r * p_pad + j) * C;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        int32_t *o = counts + (t * 2 + d) * C * C;
+        auto part = [d](uint32_t x) { return (int32_t)(d ? x >> 16 : x & 0xffffu); };
+#pragma unroll
+        for (int x = 0; x < W; ++x) {
+            int32_t s = part(Mi[x]);
+#pragma unroll
+            for (int y = 0; y < W; ++y) s -= o[x * C + y];
+            o[x * C + W] = s;
+        }
+#pragma unroll
+        for (int y = 0; y < C; ++y) {
+            int32_t s = part(Mj[y]);
+#pragma unroll
+            for (int x = 0; x < W; ++x) s -= o[x * C + y];
+            o[W * C + y] = s;
+        }
+    }
+}
+
+hipError_t launch_complete_pairs(const Problem &P, int32_t *counts, int r)
+{
+    const int64_t n = P.L.p * P.L.p;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    const uint32_t *marg = P.at<uint32_t>(P.L.marg);
+    switch (P.L.C) {
+    case 2: hipLaunchKernelGGL(k_complete_pairs<2>, grid, dim3(256), 0, P.stream, counts, marg, r, P.L.p, P.L.p_pad); break;
+    case 3: hipLaunchKernelGGL(k_complete_pairs<3>, grid, dim3(256), 0, P.stream, counts, marg, r, P.L.p, P.L.p_pad); break;
+    case 5: hipLaunchKernelGGL(k_complete_pairs<5>, grid, dim3(256), 0, P.stream, counts, marg, r, P.L.p, P.L.p_pad); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 // ---------------------------------------------------------------- several problems, one launch
 template <int W, int ENC>
@@ -950,7 +1035,7 @@ static hipError_t batch_dispatch(const Problem *const *Ps, int n, Status *queue)
         T = std::max(T, fp4_capacity(*Ps[i]));
     }
     if (!Ps[0]->fp4) return batch_launch<W, 0>(Ps, n, queue, lds);
-    lds = (size_t)stage_base(T) + NSTAGE * STAGE_BYTES + 16;
+    lds = (size_t)stage_base(T) + ring_bytes(W) + 16;
     switch (T) {
     case 1024: return batch_launch<W, 1024>(Ps, n, queue, lds);
     case 2048: return batch_launch<W, 2048>(Ps, n, queue, lds);

@@ -38,6 +38,9 @@ struct Sweep3Args {
     uint32_t *ovf;
     float w_abs;
     int collect;
+    int32_t *counts_out;     // count export: [p][p][2][C][C][C], triples (i_sel, j, l)
+    int i_sel;
+    const uint32_t *cancel;  // caller's cancel word (nullable)
 };
 
 // threads per workgroup: 8 waves at two classes (59 VGPRs: 8 waves per SIMD at 4 workgroups per
@@ -96,7 +99,7 @@ __device__ inline void put3(const Sweep3Args &a, uint32_t at, int v, uint32_t pa
     else { atomicOr(&a.ovf[v], 1u); atomicOr(&a.st->overflow, 1u); }
 }
 
-template <int W>
+template <int W, bool EXPORT = false>
 __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3Args a)
 {
     constexpr int C = W + 1;
@@ -116,10 +119,12 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
     const uint32_t *bits1 = a.bits + ((int64_t)a.r * 2 + 1) * a.words_max * plane;
     const uint32_t *bits0 = a.bits + ((int64_t)a.r * 2 + 0) * a.words_max * plane;
 
+    uint32_t taken = 0;   // pairs taken by this wave (cancel polling)
     for (;;) {
         // one pair per wave, taken in order of increasing j (largest amount of work first)
         uint32_t u = 0;
-        if (lane == 0) u = atomicAdd(&a.st->next_tile[0], 1u);
+        if (lane == 0) u = cancel_poll(a.cancel, taken, a.st) ? 0xffffffffu : atomicAdd(&a.st->next_tile[0], 1u);
+        ++taken;
         u = __builtin_amdgcn_readfirstlane(u);
         if ((int64_t)u >= a.n_pairs) break;
         int64_t jj = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
@@ -198,6 +203,21 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
 #pragma unroll
                             for (int z = 0; z < W; ++z) cnt[x][y][z] <<= 16;
                 }
+            }
+
+            // count export (EXPORT: this kernel plus the store): the W^3 directly counted cells of
+            // the triples (i_sel, j, l); launch_complete_triples fills in the others
+            if (EXPORT && i == a.i_sel && act) {
+                int32_t *o = a.counts_out + ((int64_t)j * a.p + l) * 2 * C * C * C;
+#pragma unroll
+                for (int x = 0; x < W; ++x)
+#pragma unroll
+                    for (int y = 0; y < W; ++y)
+#pragma unroll
+                        for (int z = 0; z < W; ++z) {
+                            o[(x * C + y) * C + z] = (int32_t)(cnt[x][y][z] & 0xffffu);
+                            o[C * C * C + (x * C + y) * C + z] = (int32_t)(cnt[x][y][z] >> 16);
+                        }
             }
 
             // ---- full C^3 table from the leading counts, the three pair tables and marginals
@@ -307,7 +327,7 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
 }
 
 template <int W>
-static hipError_t sweep3_launch(const Problem &P, int r, bool collect)
+static hipError_t sweep3_launch(const Problem &P, int r, bool collect, int32_t *counts_out, int i_sel)
 {
     const Layout &L = P.L;
     Sweep3Args a{};
@@ -335,8 +355,11 @@ static hipError_t sweep3_launch(const Problem &P, int r, bool collect)
     a.ovf = P.at<uint32_t>(L.ovf);
     a.w_abs = (float)(2.0 * P.err_bound);
     a.collect = collect ? 1 : 0;
+    a.counts_out = counts_out;
+    a.i_sel = i_sel;
+    a.cancel = P.cancel;
     size_t lds = sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (L.N + 1) + 16;
-    auto kern = k_sweep3<W>;
+    auto kern = counts_out ? k_sweep3<W, true> : k_sweep3<W>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     // resident waves per SIMD: 8 at W = 1 (4 workgroups of 8 waves per CU), 5-6 at W = 2 (6 of
@@ -346,16 +369,110 @@ static hipError_t sweep3_launch(const Problem &P, int r, bool collect)
     return hipGetLastError();
 }
 
-hipError_t launch_sweep3(const Problem &P, int r, bool collect)
+hipError_t launch_sweep3(const Problem &P, int r, bool collect, int32_t *counts_out, int i_sel)
 {
     hipError_t e = launch_reset_queue(P);
     if (e != hipSuccess) return e;
     switch (P.L.W) {
-    case 1: return sweep3_launch<1>(P, r, collect);
-    case 2: return sweep3_launch<2>(P, r, collect);
-    case 4: return sweep3_launch<4>(P, r, collect);
+    case 1: return sweep3_launch<1>(P, r, collect, counts_out, i_sel);
+    case 2: return sweep3_launch<2>(P, r, collect, counts_out, i_sel);
+    case 4: return sweep3_launch<4>(P, r, collect, counts_out, i_sel);
     default: return hipErrorInvalidValue;
     }
+}
+
+// ---------------------------------------------------------------- count export, completion
+// The triple sweep stored the W^3 directly counted cells of the triples (i_sel, j, l) of the
+// selected discretisation into counts [p][p][2][C][C][C] (axes: bins of x_i, x_j, x_l).  Every
+// other cell follows exactly from the three pair tables of the same discretisation (their W x W
+// counts in the workspace, completed from the marginals) by subtracting the cells already known
+// along one axis, the same relations the sweeps use.  One thread per (j, l), i_sel < j < l.
+template <int C>
+__global__ __launch_bounds__(256) void k_complete_triples(int32_t *counts, const uint32_t *ptab, const uint32_t *marg,
+                                                          int r, int i_sel, int64_t p, int64_t p_pad)
+{
+    constexpr int W = C - 1;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p * p) return;
+    const int64_t j = t / p, l = t % p, i = i_sel;
+    if (!(i < j && j < l)) return;
+    const uint32_t *M = marg + (int64_t)r * p_pad * C;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        auto part = [d](uint32_t x) { return (int32_t)(d ? x >> 16 : x & 0xffffu); };
+        // full C x C table of the pair (a, b), a < b
+        auto pair = [&](int64_t a_, int64_t b_, int32_t (&n)[C][C]) {
+            const uint32_t *pw = ptab + (a_ * p_pad + b_) * (W * W);
+            for (int x = 0; x < W; ++x)
+                for (int y = 0; y < W; ++y) n[x][y] = part(pw[x * W + y]);
+            for (int x = 0; x < W; ++x) {
+                int32_t s = part(M[a_ * C + x]);
+                for (int y = 0; y < W; ++y) s -= n[x][y];
+                n[x][W] = s;
+            }
+            for (int y = 0; y < C; ++y) {
+                int32_t s = part(M[b_ * C + y]);
+                for (int x = 0; x < W; ++x) s -= n[x][y];
+                n[W][y] = s;
+            }
+        };
+        int32_t Nij[C][C], Nil[C][C], Njl[C][C];
+        pair(i, j, Nij);
+        pair(i, l, Nil);
+        pair(j, l, Njl);
+        int32_t *o = counts + (t * 2 + d) * C * C * C;
+        auto T = [&](int x, int y, int z) -> int32_t & { return o[(x * C + y) * C + z]; };
+        for (int x = 0; x < W; ++x)
+            for (int y = 0; y < W; ++y) {
+                int32_t s = Nij[x][y];
+                for (int z = 0; z < W; ++z) s -= T(x, y, z);
+                T(x, y, W) = s;
+            }
+        for (int x = 0; x < W; ++x)
+            for (int z = 0; z < W; ++z) {
+                int32_t s = Nil[x][z];
+                for (int y = 0; y < W; ++y) s -= T(x, y, z);
+                T(x, W, z) = s;
+            }
+        for (int y = 0; y < W; ++y)
+            for (int z = 0; z < W; ++z) {
+                int32_t s = Njl[y][z];
+                for (int x = 0; x < W; ++x) s -= T(x, y, z);
+                T(W, y, z) = s;
+            }
+        for (int x = 0; x < W; ++x) {
+            int32_t s = Nil[x][W];
+            for (int y = 0; y < W; ++y) s -= T(x, y, W);
+            T(x, W, W) = s;
+        }
+        for (int y = 0; y < W; ++y) {
+            int32_t s = Njl[y][W];
+            for (int x = 0; x < W; ++x) s -= T(x, y, W);
+            T(W, y, W) = s;
+        }
+        for (int z = 0; z < W; ++z) {
+            int32_t s = Njl[W][z];
+            for (int x = 0; x < W; ++x) s -= T(x, W, z);
+            T(W, W, z) = s;
+        }
+        int32_t s = Njl[W][W];
+        for (int x = 0; x < W; ++x) s -= T(x, W, W);
+        T(W, W, W) = s;
+    }
+}
+
+hipError_t launch_complete_triples(const Problem &P, int32_t *counts, int r, int i_sel)
+{
+    const int64_t n = P.L.p * P.L.p;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    const uint32_t *ptab = P.at<uint32_t>(P.L.ptab), *marg = P.at<uint32_t>(P.L.marg);
+    switch (P.L.C) {
+    case 2: hipLaunchKernelGGL(k_complete_triples<2>, grid, dim3(256), 0, P.stream, counts, ptab, marg, r, i_sel, P.L.p, P.L.p_pad); break;
+    case 3: hipLaunchKernelGGL(k_complete_triples<3>, grid, dim3(256), 0, P.stream, counts, ptab, marg, r, i_sel, P.L.p, P.L.p_pad); break;
+    case 5: hipLaunchKernelGGL(k_complete_triples<5>, grid, dim3(256), 0, P.stream, counts, ptab, marg, r, i_sel, P.L.p, P.L.p_pad); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace mdfs

@@ -58,6 +58,9 @@ struct Sweep3mArgs {
     int collect;
     int snext_off;
     int stage_off;           // two-class kernel: LDS byte offset of the operand stages
+    int32_t *counts_out;     // count export: [p][p][2][C][C][C], triples (i_sel, j, l)
+    int i_sel;
+    const uint32_t *cancel;  // caller's cancel word (nullable)
 };
 
 __device__ inline int lds_sw(int row, int j) { return row * KBLK + ((j ^ ((row >> 1) & 3)) << 4); }
@@ -109,7 +112,7 @@ __device__ inline void put(const Sweep3mArgs &a, uint32_t at, int v, uint32_t pa
     else { atomicOr(&a.ovf[v], 1u); atomicOr(&a.st->overflow, 1u); }
 }
 
-template <int T>
+template <int T, bool EXPORT = false>
 __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
 {
     constexpr int C = 3;
@@ -135,9 +138,10 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
     constexpr int kstride = TILE_ROWS * KBLK;
     const int n1blk = a.KB - a.KB0;
 
+    uint32_t taken = 0;   // tiles taken by this workgroup (cancel polling)
     for (;;) {
         __syncthreads();
-        if (t == 0) *s_next = atomicAdd(&a.st->next_tile[0], 1u);
+        if (t == 0) *s_next = cancel_poll(a.cancel, taken++, a.st) ? a.n_tiles : atomicAdd(&a.st->next_tile[0], 1u);
         __syncthreads();
         const int64_t u = *s_next;
         if (u >= a.n_tiles) break;
@@ -250,6 +254,23 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
                     const uint32_t uu = (uint32_t)acc[m][n][x];
                     cnt[m][n][x] = (int)(__umul24(uu >> 14, 245760u) + uu);
                 }
+        // count export (EXPORT: this kernel plus the store): T[a][b][e] of the triples (i_sel, j, l)
+        if (EXPORT && i == a.i_sel) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    const int j = jb * M3_JV + 16 * wr + 4 * m + q, l = lb * M3_LV + 32 * wc + 8 * n + (c16 >> 1);
+                    if (!(i < j && j < l && l < a.p)) continue;
+                    int32_t *o = a.counts_out + ((int64_t)j * a.p + l) * 2 * 27;
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) {
+                        const uint32_t v = (uint32_t)cnt[m][n][x] >> 2;
+                        o[((x >> 1) * 3 + (x & 1)) * 3 + e] = (int32_t)(v & 0xffffu);
+                        o[27 + ((x >> 1) * 3 + (x & 1)) * 3 + e] = (int32_t)(v >> 16);
+                    }
+                }
+        }
         int jv[4], lv[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) jv[m] = jb * M3_JV + 16 * wr + 4 * m + q;
@@ -485,7 +506,7 @@ constexpr int M1_V = 128;                                   // j and l variables
 constexpr int M1_STAGE = 2 * TILE_ROWS * KBLK + KBLK + 64;  // j rows | l rows | i row | pad
 constexpr int M1_NSTAGE = 2;   // operand stages: fetched one K block ahead (two workgroups per CU)
 
-template <int T>
+template <int T, bool EXPORT = false>
 __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
 {
     constexpr int C = 2;
@@ -513,9 +534,10 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
     const int n1blk = a.KB - a.KB0;
     auto clampv = [&](int v) { return v < a.p ? v : a.p - 1; };
 
+    uint32_t taken = 0;   // tiles taken by this workgroup (cancel polling)
     for (;;) {
         __syncthreads();
-        if (t == 0) *s_next = atomicAdd(&a.st->next_tile[0], 1u);
+        if (t == 0) *s_next = cancel_poll(a.cancel, taken++, a.st) ? a.n_tiles : atomicAdd(&a.st->next_tile[0], 1u);
         __syncthreads();
         const int64_t u = *s_next;
         if (u >= a.n_tiles) break;
@@ -612,6 +634,22 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
                     cnt[m][n][x] = (int)(__umul24(uu >> 14, 245760u) + uu);
                 }
         auto jvar = [&](int m, int x) { return jb * M1_V + 64 * wr + 16 * m + 4 * q + x; };
+        // count export (EXPORT: this kernel plus the store): T[0][0][0] of the triples (i_sel, j, l)
+        if (EXPORT && i == a.i_sel) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) {
+                        const int j = jvar(m, x), l = lb * M1_V + 64 * wc + 16 * n + c16;
+                        if (!(i < j && j < l && l < a.p)) continue;
+                        int32_t *o = a.counts_out + ((int64_t)j * a.p + l) * 2 * 8;
+                        const uint32_t v = (uint32_t)cnt[m][n][x] >> 2;
+                        o[0] = (int32_t)(v & 0xffffu);
+                        o[8] = (int32_t)(v >> 16);
+                    }
+        }
         int lv[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) lv[n] = lb * M1_V + 64 * wc + 16 * n + c16;
@@ -824,7 +862,7 @@ int m3_capacity(const Problem &P)
 }
 
 template <int T, int W>
-hipError_t m3_launch(const Problem &P, int r, bool collect)
+hipError_t m3_launch(const Problem &P, int r, bool collect, int32_t *counts_out, int i_sel)
 {
     const Layout &L = P.L;
     Sweep3mArgs a{};
@@ -856,10 +894,14 @@ hipError_t m3_launch(const Problem &P, int r, bool collect)
     a.ovf = P.at<uint32_t>(L.ovf);
     a.w_abs = (float)(2.0 * P.err_bound);
     a.collect = collect ? 1 : 0;
+    a.counts_out = counts_out;
+    a.i_sel = i_sel;
+    a.cancel = P.cancel;
     const size_t lds = sweep3m_lds_of(T, W, (int)L.N);
     a.stage_off = (int)m1_stage_off(T, (int)L.N);
     a.snext_off = (int)(lds - 16);
-    auto kern = W == 1 ? k_sweep3m1<T> : k_sweep3m<T>;
+    auto kern = W == 1 ? (counts_out ? k_sweep3m1<T, true> : k_sweep3m1<T>)
+                       : (counts_out ? k_sweep3m<T, true> : k_sweep3m<T>);
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(P.workgroups > 0 ? P.workgroups : 512), dim3(M3_THREADS), lds, P.stream, a);
@@ -870,36 +912,88 @@ hipError_t m3_launch(const Problem &P, int r, bool collect)
 
 size_t sweep3m_lds_bytes(const Problem &P) { return sweep3m_lds_of(m3_capacity(P), P.L.W, (int)P.L.N); }
 
-// Tile list of the triple sweep with JV j variables and LV l variables per tile (W = 2: 32
-// and 64; W = 1: 128 and 128): A blocks (i, jb) with jb >= (i + 1) / JV (some j > i) and
-// jb * JV < p - 1, each with l blocks lb = jb * JV / LV .. nLB - 1.  Host-side; apref[k] =
-// first tile of A block k, apref[n_ablk] = number of tiles.
-void sweep3m_tiles(int64_t p, int W, std::vector<int64_t> &apref, std::vector<int32_t> &ablk)
+// Tile list of the triple sweep with JV j variables and LV l variables per tile (W = 2: 32 and
+// 64; W = 1: 128 and 128): A blocks (i, jb) with jb >= (i + 1) / JV (some j > i) and
+// jb * JV < p - 1, in order of i then jb, each with l blocks lb = jb * JV / LV .. nLB - 1.
+// apref[k] = first tile of A block k, ablk[k] = i * 256 + jb, apref[n_ablk] = number of tiles.
+static void m3_geometry(int W, int64_t p, int64_t &JV, int64_t &LV, int64_t &nJB, int64_t &nLB)
 {
-    const int64_t JV = W == 1 ? M1_V : M3_JV, LV = W == 1 ? M1_V : M3_LV;
-    const int64_t nJB = (p + JV - 1) / JV, nLB = (p + LV - 1) / LV;
-    apref.clear();
-    ablk.clear();
-    int64_t at = 0;
-    for (int64_t i = 0; i + 2 < p; ++i)
-        for (int64_t jb = (i + 1) / JV; jb < nJB; ++jb) {
-            if (jb * JV >= p - 1) break;
-            apref.push_back(at);
-            ablk.push_back((int32_t)(i * 256 + jb));
-            at += nLB - jb * JV / LV;
-        }
-    apref.push_back(at);
+    JV = W == 1 ? M1_V : M3_JV;
+    LV = W == 1 ? M1_V : M3_LV;
+    nJB = (p + JV - 1) / JV;
+    nLB = (p + LV - 1) / LV;
 }
 
-hipError_t launch_sweep3m(const Problem &P, int r, bool collect)
+// A blocks and tiles of the list, on the host (the launch needs both before the list exists).
+void sweep3m_tile_counts(int64_t p, int W, int64_t &n_ablk, int64_t &n_tiles)
+{
+    int64_t JV, LV, nJB, nLB;
+    m3_geometry(W, p, JV, LV, nJB, nLB);
+    n_ablk = n_tiles = 0;
+    for (int64_t i = 0; i + 2 < p; ++i)
+        for (int64_t jb = (i + 1) / JV; jb < nJB && jb * JV < p - 1; ++jb) {
+            ++n_ablk;
+            n_tiles += nLB - jb * JV / LV;
+        }
+}
+
+// The list itself, built on the device by one workgroup (so that an asynchronous or captured
+// call needs no host-to-device copy): each thread counts the A blocks and tiles of a contiguous
+// range of i, a block-wide exclusive scan gives every range its first entry and first tile,
+// then each thread writes its entries.
+__global__ __launch_bounds__(1024) void k_tiles3(int64_t p, int64_t JV, int64_t LV, int64_t nJB, int64_t nLB,
+                                                 int64_t *apref, int32_t *ablk)
+{
+    __shared__ int64_t sA[1024], sT[1024];
+    const int t = threadIdx.x;
+    const int64_t ni = p >= 3 ? p - 2 : 0;            // i = 0 .. p - 3
+    const int64_t per = (ni + 1023) / 1024;
+    const int64_t i0 = t * per < ni ? t * per : ni, i1 = i0 + per < ni ? i0 + per : ni;
+    int64_t ca = 0, ct = 0;
+    for (int64_t i = i0; i < i1; ++i)
+        for (int64_t jb = (i + 1) / JV; jb < nJB && jb * JV < p - 1; ++jb) {
+            ++ca;
+            ct += nLB - jb * JV / LV;
+        }
+    sA[t] = ca;
+    sT[t] = ct;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int64_t xa = t >= d ? sA[t - d] : 0, xt = t >= d ? sT[t - d] : 0;
+        __syncthreads();
+        sA[t] += xa;
+        sT[t] += xt;
+        __syncthreads();
+    }
+    int64_t ka = sA[t] - ca, kt = sT[t] - ct;
+    for (int64_t i = i0; i < i1; ++i)
+        for (int64_t jb = (i + 1) / JV; jb < nJB && jb * JV < p - 1; ++jb) {
+            apref[ka] = kt;
+            ablk[ka] = (int32_t)(i * 256 + jb);
+            ++ka;
+            kt += nLB - jb * JV / LV;
+        }
+    if (t == 1023) apref[sA[1023]] = sT[1023];
+}
+
+hipError_t launch_tiles3(const Problem &P)
+{
+    int64_t JV, LV, nJB, nLB;
+    m3_geometry(P.L.W, P.L.p, JV, LV, nJB, nLB);
+    hipLaunchKernelGGL(k_tiles3, dim3(1), dim3(1024), 0, P.stream, P.L.p, JV, LV, nJB, nLB,
+                       P.at<int64_t>(P.L.a3pref), P.at<int32_t>(P.L.a3blk));
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep3m(const Problem &P, int r, bool collect, int32_t *counts_out, int i_sel)
 {
     hipError_t e = launch_reset_queue(P);
     if (e != hipSuccess) return e;
     const bool w1 = P.L.W == 1;
     switch (m3_capacity(P)) {
-    case 1024: return w1 ? m3_launch<1024, 1>(P, r, collect) : m3_launch<1024, 2>(P, r, collect);
-    case 2048: return w1 ? m3_launch<2048, 1>(P, r, collect) : m3_launch<2048, 2>(P, r, collect);
-    case 4096: return w1 ? m3_launch<4096, 1>(P, r, collect) : m3_launch<4096, 2>(P, r, collect);
+    case 1024: return w1 ? m3_launch<1024, 1>(P, r, collect, counts_out, i_sel) : m3_launch<1024, 2>(P, r, collect, counts_out, i_sel);
+    case 2048: return w1 ? m3_launch<2048, 1>(P, r, collect, counts_out, i_sel) : m3_launch<2048, 2>(P, r, collect, counts_out, i_sel);
+    case 4096: return w1 ? m3_launch<4096, 1>(P, r, collect, counts_out, i_sel) : m3_launch<4096, 2>(P, r, collect, counts_out, i_sel);
     default: return hipErrorInvalidValue;
     }
 }

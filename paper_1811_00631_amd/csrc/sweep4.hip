@@ -36,6 +36,7 @@ struct Sweep4Args {
     uint32_t *ovf;
     float w_abs;
     int collect;
+    const uint32_t *cancel;  // caller's cancel word (nullable)
 };
 
 constexpr int S4_THREADS = 256;
@@ -105,9 +106,11 @@ __global__ __launch_bounds__(S4_THREADS) void k_sweep4(Sweep4Args a)
     const uint32_t *bits1 = a.bits + ((int64_t)a.r * 2 + 1) * a.words_max * plane;
     const uint32_t *bits0 = a.bits + ((int64_t)a.r * 2 + 0) * a.words_max * plane;
 
+    uint32_t taken = 0;   // triples taken by this wave (cancel polling)
     for (;;) {
         uint32_t u = 0;
-        if (lane == 0) u = atomicAdd(&a.st->next_tile[0], 1u);
+        if (lane == 0) u = cancel_poll(a.cancel, taken, a.st) ? 0xffffffffu : atomicAdd(&a.st->next_tile[0], 1u);
+        ++taken;
         u = __builtin_amdgcn_readfirstlane(u);
         if ((int64_t)u >= a.n_triples) break;
         int i, j, l;
@@ -279,6 +282,7 @@ hipError_t sweep4_launch(const Problem &P, int r, bool collect)
     a.ovf = P.at<uint32_t>(L.ovf);
     a.w_abs = (float)(2.0 * P.err_bound);
     a.collect = collect ? 1 : 0;
+    a.cancel = P.cancel;
     const size_t lds = sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (L.N + 1) + 16;
     auto kern = k_sweep4<W>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -10,6 +10,8 @@ Functions mirror the C entry points:
     mdfs_max_ig(data, y, ...)           -> (ig_max f32 [n_var], argmax i32 [n_var][k-1],
                                             argmax_disc i32 [n_var])
     mdfs_pair_counts(data, y, disc,...) -> counts i32 [n_var][n_var][2][c][c] (i < j filled)
+    mdfs_triple_counts(data, y, disc, i_sel, ...)
+                                        -> counts i32 [n_var][n_var][2][c][c][c] (i_sel < j < l)
     mdfs_screen_max(data, y, ...)       -> (ig32 f32 [n_var], error bound E)
     mdfs_chi2_df(k, divisions)          -> int
     mdfs_pvalues(ig, k, divisions, ...) -> (p float64 [n], n_eff)       (host arrays)
@@ -30,8 +32,9 @@ LIB_PATH = os.path.join(_HERE, "libmdfs.so")
 
 MDFS_OK = 0
 STATUS = {0: "MDFS_OK", -1: "MDFS_E_ARG", -2: "MDFS_E_Y", -3: "MDFS_E_K", -4: "MDFS_E_DIV",
-          -5: "MDFS_E_NAN", -6: "MDFS_E_NOMEM", -7: "MDFS_E_HIP", -8: "MDFS_E_LIMIT",
-          -9: "MDFS_E_OVERFLOW"}
+          -5: "MDFS_E_NAN", -6: "MDFS_E_NOMEM", -7: "MDFS_E_HIP", -8: "MDFS_E_CANCELLED",
+          -9: "MDFS_E_OVERFLOW", -10: "MDFS_E_LIMIT"}
+E_CANCELLED, E_OVERFLOW, E_LIMIT = -8, -9, -10
 ENGINES = {"auto": 0, "mfma": 1, "bitset": 2, "mfma_fp4": 3}
 ADJUST = {"none": 0, "holm": 1, "BH": 2, "BY": 3}
 
@@ -47,11 +50,11 @@ class Params(ctypes.Structure):
                 ("divisions", ctypes.c_int32), ("n_disc", ctypes.c_int32), ("disc_offset", ctypes.c_int32),
                 ("range", ctypes.c_double), ("pseudocount", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("engine", ctypes.c_int32), ("flags", ctypes.c_int32), ("workgroups", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("cancel", ctypes.c_void_p)]
 
 
 _lib = None
-SYMBOLS = ["mdfs_workspace_size", "mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts",
+SYMBOLS = ["mdfs_workspace_size", "mdfs_discretize", "mdfs_max_ig", "mdfs_pair_counts", "mdfs_triple_counts",
            "mdfs_screen_max", "mdfs_interesting_tuples", "mdfs_phase_times", "mdfs_last_error",
            "mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust", "mdfs_add_contrast",
            "mdfs_max_ig_codes", "mdfs_max_ig_async", "mdfs_check_status", "mdfs_max_ig_batch",
@@ -82,6 +85,7 @@ def load(path: str = LIB_PATH):
     L.mdfs_max_ig_batch.argtypes = [ctypes.c_int, P, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.mdfs_max_ig_batch.restype = ctypes.c_int
     L.mdfs_pair_counts.argtypes = [P, vp, vp, ctypes.c_int32, vp, vp, sz, vp]
+    L.mdfs_triple_counts.argtypes = [P, vp, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, sz, vp]
     L.mdfs_screen_max.argtypes = [P, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
     L.mdfs_interesting_tuples.argtypes = [P, vp, vp, ctypes.c_double, vp, vp, vp, vp, ctypes.c_int64,
                                           ctypes.POINTER(ctypes.c_int64), vp, sz, vp]
@@ -97,17 +101,18 @@ def load(path: str = LIB_PATH):
     for fn in ("mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust", "mdfs_add_contrast"):
         getattr(L, fn).restype = ctypes.c_int
     for fn in ("mdfs_discretize", "mdfs_max_ig", "mdfs_max_ig_codes", "mdfs_max_ig_async", "mdfs_check_status",
-               "mdfs_pair_counts", "mdfs_screen_max", "mdfs_interesting_tuples"):
+               "mdfs_pair_counts", "mdfs_triple_counts", "mdfs_screen_max", "mdfs_interesting_tuples"):
         getattr(L, fn).restype = ctypes.c_int
     _lib = L
     return L
 
 
 def make_params(n_obj, n_var, k=2, divisions=2, n_disc=1, disc_offset=0, range_=0.5, pseudocount=0.25,
-                seed=0, engine="auto", flags=0, workgroups=0) -> Params:
+                seed=0, engine="auto", flags=0, workgroups=0, cancel=None) -> Params:
+    """`cancel`: None, or the address (int) of a caller-owned host-mapped uint32 cancel word."""
     return Params(int(n_obj), int(n_var), int(k), int(divisions), int(n_disc), int(disc_offset),
                   float(range_), float(pseudocount), int(seed) & ((1 << 64) - 1), ENGINES[engine], int(flags),
-                  int(workgroups), 0)
+                  int(workgroups), 0, cancel)
 
 
 def mdfs_phase_times() -> dict:
@@ -187,14 +192,15 @@ def mdfs_discretize(data: torch.Tensor, divisions: int, n_disc: int, range_: flo
 def mdfs_max_ig(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_disc: int,
                 pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0, disc_offset: int = 0,
                 engine: str = "auto", timing: bool = False, workgroups: int = 0, ws: torch.Tensor | None = None,
-                stream=None):
+                stream=None, cancel=None):
     """IG_max, argmax tuple and argmax discretisation of every variable.  `ws` (a caller-owned
     uint8 device workspace of at least mdfs_workspace_size bytes) and `stream` (a torch CUDA
-    stream) default to a per-device cached workspace and the current stream."""
+    stream) default to a per-device cached workspace and the current stream; `cancel` is the
+    address of a caller-owned host-mapped uint32 cancel word, or None."""
     data, y = _dev_inputs(data, y)
     n_var, n_obj = data.shape
     prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed, engine,
-                      FLAG_TIMING if timing else 0, workgroups)
+                      FLAG_TIMING if timing else 0, workgroups, cancel)
     if ws is None:
         ws = workspace_for(prm, data.device)
     strm = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(data.device)
@@ -208,14 +214,15 @@ def mdfs_max_ig(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_d
 
 def mdfs_max_ig_async(data: torch.Tensor, y: torch.Tensor, n1: int, k: int, divisions: int, n_disc: int,
                       pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0, disc_offset: int = 0,
-                      engine: str = "auto", workgroups: int = 0, ws: torch.Tensor | None = None, out=None):
+                      engine: str = "auto", workgroups: int = 0, ws: torch.Tensor | None = None, out=None,
+                      cancel=None):
     """Enqueue mdfs_max_ig on the current stream without any host synchronisation (capturable in
     a CUDA graph).  `out` = (ig, argmax, argmax_disc) preallocated tensors or None; `ws` a
     preallocated workspace or None (the cached one).  Check errors later with mdfs_check_status."""
     data, y = _dev_inputs(data, y)
     n_var, n_obj = data.shape
     prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed, engine, 0,
-                      workgroups)
+                      workgroups, cancel)
     if ws is None:
         ws = workspace_for(prm, data.device)
     if out is None:
@@ -299,12 +306,28 @@ def mdfs_pair_counts(data: torch.Tensor, y: torch.Tensor, disc: int, divisions: 
     return counts
 
 
+def mdfs_triple_counts(data: torch.Tensor, y: torch.Tensor, disc: int, i_sel: int, divisions: int, n_disc: int,
+                       range_: float = 0.5, seed: int = 0, disc_offset: int = 0,
+                       engine: str = "auto") -> torch.Tensor:
+    """Per-class tables [n_var][n_var][2][c][c][c] of the triples (i_sel, j, l), i_sel < j < l, of
+    discretisation `disc`, from the k = 3 count engine `engine` selects."""
+    data, y = _dev_inputs(data, y)
+    n_var, n_obj = data.shape
+    c = divisions + 1
+    prm = make_params(n_obj, n_var, 3, divisions, n_disc, disc_offset, range_, 0.25, seed, engine)
+    ws = workspace_for(prm, data.device)
+    counts = torch.zeros((n_var, n_var, 2, c, c, c), dtype=torch.int32, device=data.device)
+    _check(load().mdfs_triple_counts(ctypes.byref(prm), _ptr(data), _ptr(y), int(disc), int(i_sel), _ptr(counts),
+                                     _ptr(ws), ws.numel(), _stream(data.device)))
+    return counts
+
+
 def mdfs_interesting_tuples(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_disc: int,
                             ig_thr: float, pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0,
                             disc_offset: int = 0, engine: str = "auto", max_out: int = 1 << 20):
     """Every (variable, partner tuple, discretisation) with IG >= ig_thr: device tensors
     (var int32 [n], partners int32 [n][k-1], disc int32 [n], ig float64 [n]) in unspecified order.
-    Raises MdfsError(-8) if more than max_out records exist."""
+    Raises MdfsError(E_LIMIT) if more than max_out records exist."""
     data, y = _dev_inputs(data, y)
     n_var, n_obj = data.shape
     prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed, engine)
@@ -319,7 +342,7 @@ def mdfs_interesting_tuples(data: torch.Tensor, y: torch.Tensor, k: int, divisio
                                           _ptr(part), _ptr(disc), _ptr(ig), int(max_out), ctypes.byref(n), _ptr(ws),
                                           ws.numel(), _stream(dev)))
     if n.value > max_out:
-        raise MdfsError(-8, f"{n.value} interesting tuples exceed max_out={max_out}")
+        raise MdfsError(E_LIMIT, f"{n.value} interesting tuples exceed max_out={max_out}")
     m = n.value
     return var[:m], part[:m], disc[:m], ig[:m]
 

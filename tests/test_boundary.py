@@ -29,10 +29,17 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_struct_matches_header():
     # int64 n_obj, n_var; int32 k, divisions, n_disc, disc_offset; double range, pseudocount;
-    # uint64 seed; int32 engine, flags, workgroups, reserved
-    assert ctypes.sizeof(mdfs.Params) == 72
+    # uint64 seed; int32 engine, flags, workgroups, reserved; pointer cancel
+    assert ctypes.sizeof(mdfs.Params) == 80
     assert mdfs.Params.range.offset == 32 and mdfs.Params.seed.offset == 48 and mdfs.Params.flags.offset == 60
-    assert mdfs.Params.workgroups.offset == 64
+    assert mdfs.Params.workgroups.offset == 64 and mdfs.Params.cancel.offset == 72
+
+
+def test_status_codes_match_header():
+    src = open(HEADER).read()
+    for name, code in [("MDFS_E_CANCELLED", -8), ("MDFS_E_OVERFLOW", -9), ("MDFS_E_LIMIT", -10)]:
+        assert re.search(rf"\b{name}\s*=\s*{code}\b", src), name
+        assert mdfs.STATUS[code] == name
 
 
 def test_workspace_size_valid_and_monotone():
@@ -45,11 +52,11 @@ def test_workspace_size_valid_and_monotone():
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(k=5), -3), (dict(k=0), -3), (dict(k=4, divisions=4), -8), (dict(k=4, engine="mfma"), -8), (dict(divisions=3), -4), (dict(divisions=0), -4),
-    (dict(n_obj=2, divisions=2), -1), (dict(n_obj=20000), -8), (dict(range_=1.5), -1),
+    (dict(k=5), -3), (dict(k=0), -3), (dict(k=4, divisions=4), -10), (dict(k=4, engine="mfma"), -10), (dict(divisions=3), -4), (dict(divisions=0), -4),
+    (dict(n_obj=2, divisions=2), -1), (dict(n_obj=20000), -10), (dict(range_=1.5), -1),
     (dict(range_=-0.1), -1), (dict(pseudocount=-1.0), -1), (dict(n_disc=0), -1),
-    (dict(disc_offset=-1), -1), (dict(n_var=1), -1), (dict(workgroups=4), -1), (dict(workgroups=5000), -1), (dict(k=3, engine="mfma_fp4", divisions=4), -8),
-    (dict(k=3, engine="mfma"), -8), (dict(engine="bitset"), -8),
+    (dict(disc_offset=-1), -1), (dict(n_var=1), -1), (dict(workgroups=4), -1), (dict(workgroups=5000), -1), (dict(k=3, engine="mfma_fp4", divisions=4), -10),
+    (dict(k=3, engine="mfma"), -10), (dict(engine="bitset"), -10),
 ])
 def test_invalid_params_rejected_on_host(kw, code):
     base = dict(n_obj=100, n_var=10, k=2, divisions=2, n_disc=1, disc_offset=0, range_=0.5,
@@ -57,7 +64,7 @@ def test_invalid_params_rejected_on_host(kw, code):
     base.update(kw)
     prm = mdfs.make_params(**base)
     lib = mdfs.load()
-    if code != -8:   # size limits of the sweep do not affect the workspace query
+    if code != -10:   # size limits of the sweep do not affect the workspace query
         assert lib.mdfs_workspace_size(ctypes.byref(prm)) == 0
         assert lib.mdfs_last_error().decode() != ""
     null = ctypes.c_void_p(0)

@@ -22,14 +22,19 @@ def async_call(X, y, k, div, R, ws=None, out=None):
     return mdfs.mdfs_max_ig_async(X, y, n1, k, div, R, 0.25, 0.5, 7, ws=ws, out=out)
 
 
-@pytest.mark.parametrize("k,div,p", [(1, 2, 50), (2, 2, 130), (2, 4, 70), (2, 1, 90), (3, 2, 40), (4, 1, 18)])
-def test_async_equals_sync(k, div, p):
+@pytest.mark.parametrize("k,div,p,engine", [(1, 2, 50, "auto"), (2, 2, 130, "auto"), (2, 4, 70, "auto"),
+                                            (2, 1, 90, "auto"), (3, 2, 40, "bitset"), (3, 2, 70, "mfma_fp4"),
+                                            (3, 1, 150, "mfma_fp4"), (4, 1, 18, "auto")])
+def test_async_equals_sync(k, div, p, engine):
+    # the k = 3 matrix-core engine builds its tile list on the device, so the asynchronous call
+    # runs it as the synchronous one does
     w = workloads.xor_small(seed=81, n_obj=600, n_var=p, divisions=div, n_disc=3)
     X, y = dev(w)
-    print(f"async k={k} div={div} p={p}", flush=True)
-    ref = sync_call(X, y, k, div, 3, engine="bitset" if k == 3 else "auto")
-    got = async_call(X, y, k, div, 3)
-    mdfs.mdfs_check_status(X.shape, k, div, 3)
+    print(f"async k={k} div={div} p={p} {engine}", flush=True)
+    ref = sync_call(X, y, k, div, 3, engine=engine)
+    n1 = int(y.sum().item())
+    got = mdfs.mdfs_max_ig_async(X, y, n1, k, div, 3, 0.25, 0.5, 7, engine=engine)
+    mdfs.mdfs_check_status(X.shape, k, div, 3, engine=engine)
     for a, b in zip(ref, got):
         assert torch.equal(a, b)
 
@@ -114,6 +119,6 @@ def test_graph_capture_replays_match_eager(k):
         g.replay()
         torch.cuda.synchronize()
         mdfs.mdfs_check_status(X.shape, k, 2, 3, ws=ws)
-        ref = mdfs.mdfs_max_ig(X.clone(), y, k, 2, 3, 0.25, 0.5, 7, engine="bitset" if k == 3 else "auto")
+        ref = mdfs.mdfs_max_ig(X.clone(), y, k, 2, 3, 0.25, 0.5, 7)
         for a, b in zip(out, ref):
             assert torch.equal(a, b), f"replay {rep}"

@@ -77,7 +77,7 @@ def test_batch_rejections():
         big = workloads.xor_small(seed=171, n_obj=4500, n_var=20)
         yb = torch.from_numpy(_force_ones(big.y, 4200, 3)).to(DEV)
         mdfs.mdfs_max_ig_batch(d + [torch.from_numpy(big.data).to(DEV)], y + [yb], n1 + [4200], 2, 2, [1, 1, 1])
-    assert e.value.code == -8
+    assert e.value.code == -10
     with pytest.raises(mdfs.MdfsError) as e:
         mdfs.mdfs_max_ig_batch(d * 7, y * 7, n1 * 7, 2, 2, [1] * 14)   # 14 > 12
     assert e.value.code == -1

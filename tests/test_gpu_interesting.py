@@ -51,7 +51,7 @@ def test_interesting_none_above_the_maximum(mdfs_gpu):
 def test_interesting_capacity_errors(mdfs_gpu, monkeypatch):
     # threshold -inf at p=100, R=3: 29700 records, more than a candidate buffer held to 5000
     # records -> -9; a small max_out with a feasible threshold -> the binding refuses to
-    # truncate silently (-8)
+    # truncate silently (-10)
     w = workloads.xor_small(seed=63, n_obj=200, n_var=100, n_disc=3)
     data, y = torch.from_numpy(w.data).cuda(), torch.from_numpy(w.y).cuda()
     monkeypatch.setenv("MDFS_TEST_CAP", "5000")
@@ -65,6 +65,6 @@ def test_interesting_capacity_errors(mdfs_gpu, monkeypatch):
     thr = midpoint_threshold(ref[3], 20)
     with pytest.raises(mdfs_gpu.MdfsError) as e:
         mdfs_gpu.mdfs_interesting_tuples(data, y, 2, 2, 3, thr, w.xi, w.range_, w.seed, max_out=5)
-    assert e.value.code == -8
+    assert e.value.code == -10
     got = mdfs_gpu.mdfs_interesting_tuples(data, y, 2, 2, 3, thr, w.xi, w.range_, w.seed)
     assert got[0].numel() == int((ref[3] >= thr).sum())

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import torch
 
+import fullsize_ref
 import oracle
 from paper_1811_00631_amd import workloads
 
@@ -53,6 +54,40 @@ def test_k3_matches_oracle(mdfs_gpu, name, engine):
     assert_ig_parity(*got, ref, name)
 
 
+def _triple_ref(codes_r, y, c, i, n_var):
+    """The oracle's tables of every triple (i, j, l), i < j < l, indexed [j][l]."""
+    ref = {}
+    for j in range(i + 1, n_var):
+        for l in range(j + 1, n_var):
+            ref[(j, l)] = oracle.table(codes_r, y, c, [i, j, l])
+    return ref
+
+
+# n_obj, n_var, divisions, class-1 objects, i_sel: ragged tiles of both matrix-core kernels (32 j x
+# 64 l and 128 x 128 variables), several K blocks per class, the largest class the fp4 encoding
+# takes (4095 objects), imbalanced classes, five classes on the bitset engine, the last i_sel
+COUNT3 = [(300, 70, 2, None, 0), (257, 140, 1, 40, 0), (333, 45, 2, 60, 7), (4095 + 70, 12, 2, 4095, 0),
+          (500, 29, 4, None, 0), (199, 37, 1, None, 34), (1000, 67, 2, 300, 1)]
+
+
+@pytest.mark.parametrize("engine", ENGINES3)
+@pytest.mark.parametrize("n_obj,n_var,div,ones,i_sel", COUNT3)
+def test_k3_counts_bit_exact(mdfs_gpu, engine, n_obj, n_var, div, ones, i_sel):
+    # the tables of every triple (i_sel, j, l) of one discretisation, from the count engine the
+    # maximum sweep runs, equal the oracle's brute-force tables cell by cell
+    if engine == "mfma_fp4" and div not in (1, 2):
+        pytest.skip("the matrix-core k=3 engine is built for two or three classes")
+    w = workloads.null_data(70 + n_var, n_obj, n_var, ones=ones)
+    data, y = to_dev(w)
+    R, disc, c = 3, 2, div + 1
+    print(f"k3 counts {engine} N={n_obj} p={n_var} d={c} i={i_sel}", flush=True)
+    got = mdfs_gpu.mdfs_triple_counts(data, y, disc, i_sel, div, R, 0.5, 19, engine=engine).cpu().numpy()
+    codes = oracle.discretize(w.data, div, R, 0.5, 19)[disc]
+    for (j, l), ref in _triple_ref(codes, w.y, c, i_sel, n_var).items():
+        if not np.array_equal(got[j, l], ref):
+            pytest.fail(f"triple ({i_sel},{j},{l}): gpu {got[j, l].tolist()} oracle {ref.tolist()}")
+
+
 @pytest.mark.parametrize("engine", ENGINES3)
 def test_k3_parity_triple_found(mdfs_gpu, engine):
     w = workloads.parity3(seed=31, n_obj=1000, n_var=40, n_disc=2)
@@ -85,33 +120,23 @@ def test_k3_deterministic_and_fused_equals_separate(mdfs_gpu, engine):
     assert np.array_equal(a[0], np.stack([s[0] for s in sep]).max(axis=0))
 
 
-@pytest.mark.parametrize("engine", ENGINES3)
-def test_k3_full_size_sampled(mdfs_gpu, engine):
-    # the parity-triple workload at its full size: N=2000, p=500, 30 discretisations
-    w = workloads.parity3(seed=3)
-    print(f"k3 full size {engine}: N={w.n_obj} p={w.n_var} R={w.n_disc}", flush=True)
+@pytest.mark.parametrize("which,engine", [("parity3", "mfma_fp4"), ("parity3", "bitset"),
+                                          ("madelon3_d2", "mfma_fp4"), ("madelon3_d2", "bitset")])
+def test_k3_full_size_every_variable(mdfs_gpu, which, engine):
+    # the k = 3 workloads at full size (N=2000, p=500, 30 discretisations; three classes with the
+    # planted parity triple, and two classes in the shape of the paper's 3D timing), every variable
+    # against the FP64 oracle stored by tests/golden/make_fullsize.py
+    w, k = fullsize_ref.workload(which)
+    print(f"k3 full size {which} {engine}: N={w.n_obj} p={w.n_var} R={w.n_disc} d={w.divisions + 1}", flush=True)
     ig, am, ad = run3(mdfs_gpu, w, engine=engine)
     assert np.isfinite(ig).all()
-    for v, others in [(0, [1, 2]), (1, [0, 2]), (2, [0, 1])]:
-        assert am[v].tolist() == others
-    g = np.random.default_rng(0)
-    tg = np.array([0, 1] + sorted(g.choice(np.arange(3, w.n_var), 3, replace=False).tolist()), dtype=np.int64)
-    ref = oracle.max_ig(w.data, w.y, 3, w.divisions, w.n_disc, w.range_, w.xi, w.seed, targets=tg, n_threads=16)
-    assert_ig_parity(ig[tg], am[tg], ad[tg], ref, "k3 full size")
-
-
-def test_k3_two_classes_full_size_sampled(mdfs_gpu):
-    # the Madelon-shaped k = 3 workload at d = 2 (N=2000, p=500, 30 discretisations; the shape
-    # of the paper's 3D timing) on the two-class matrix-core engine, sampled against the oracle
-    w = workloads.madelon_like(divisions=1, n_disc=30, k=3)
-    print(f"k3 two classes full size: N={w.n_obj} p={w.n_var} R={w.n_disc}", flush=True)
-    ig, am, ad = run3(mdfs_gpu, w, engine="mfma_fp4")
-    assert np.isfinite(ig).all()
-    g = np.random.default_rng(1)
-    tg = np.array(sorted(set(w.planted["base"][:2] + g.choice(np.arange(w.n_var), 3, replace=False).tolist())),
-                  dtype=np.int64)
-    ref = oracle.max_ig(w.data, w.y, 3, w.divisions, w.n_disc, w.range_, w.xi, w.seed, targets=tg, n_threads=16)
-    assert_ig_parity(ig[tg], am[tg], ad[tg], ref, "k3 two classes full size")
+    if "triple" in w.planted:
+        for v, others in [(0, [1, 2]), (1, [0, 2]), (2, [0, 1])]:
+            assert am[v].tolist() == others
+    tg, ref, complete = fullsize_ref.reference(which, w, k)
+    print(f"  compared {len(tg)} of {w.n_var} variables ({'all, stored' if complete else 'live sample'})",
+          flush=True)
+    assert_ig_parity(ig[tg], am[tg], ad[tg], ref, which)
 
 
 @pytest.mark.parametrize("divisions", [1, 2])
@@ -129,7 +154,7 @@ def test_k3_mfma_engine_limits(mdfs_gpu):
     w = workloads.parity3(seed=35, n_obj=200, n_var=12, divisions=4, n_disc=1)
     with pytest.raises(mdfs_gpu.MdfsError) as e:
         run3(mdfs_gpu, w, engine="mfma_fp4")
-    assert e.value.code == -8
+    assert e.value.code == -10
     with pytest.raises(mdfs_gpu.MdfsError) as e:
         run3(mdfs_gpu, workloads.parity3(seed=35, n_obj=200, n_var=12, n_disc=1), engine="mfma")
-    assert e.value.code == -8
+    assert e.value.code == -10

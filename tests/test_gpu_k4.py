@@ -71,8 +71,8 @@ def test_k4_limits(mdfs_gpu):
     import ctypes
     lib = mdfs_gpu.load()
     null = ctypes.c_void_p(0)
-    for kw, code in ((dict(divisions=4), -8), (dict(engine="mfma"), -8), (dict(engine="mfma_fp4"), -8),
-                     (dict(n_var=1025), -8)):
+    for kw, code in ((dict(divisions=4), -10), (dict(engine="mfma"), -10), (dict(engine="mfma_fp4"), -10),
+                     (dict(n_var=1025), -10)):
         base = dict(n_obj=100, n_var=8, k=4, divisions=2, n_disc=1)
         base.update(kw)
         prm = mdfs_gpu.make_params(**base)

@@ -56,6 +56,45 @@ def test_cuts_valid_random_range():
             assert np.all(np.diff(t) >= 1) and t[0] >= 1 and t[-1] <= n - 1
 
 
+def _ratio_cdf(z, rng):
+    # CDF of s0 / (s0 + s1) for independent s0, s1 ~ U(1 - range, 1 + range): P(s0 <= k s1) with
+    # k = z / (1 - z), integrated over s1 (each share's law is what the paper states)
+    from scipy import integrate
+    a, b = 1.0 - rng, 1.0 + rng
+    k = z / (1.0 - z)
+    f = lambda s1: min(max((k * s1 - a) / (b - a), 0.0), 1.0) / (b - a)   # noqa: E731
+    pts = [p for p in (a / k if k > 0 else a, b / k if k > 0 else b) if a < p < b]
+    return integrate.quad(f, a, b, points=pts or None, limit=200)[0]
+
+
+@pytest.mark.parametrize("rng", [0.25, 0.5, 1.0])
+def test_share_spread_is_uniform_on_one_plus_minus_range(rng):
+    # Two classes: the single cut sits at floor(N s0 / (s0 + s1)).  With N = 2^40 the cut fraction
+    # is s0 / (s0 + s1) to 1e-12, whose law is fixed by shares ~ U(1 - range, 1 + range) ("Algorithm
+    # and implementation", range/shares paragraph).  Reading the spread as U(1 - range, 1) or
+    # U(1 - range/2, 1 + range/2) gives a narrower law and fails the KS test.
+    n = 1 << 40
+    z = np.array([oracle.cuts(n, 1, rng, s, r, v)[0] / n for s in range(4) for r in range(25) for v in range(20)])
+    lo, hi = (1 - rng) / 2.0, (1 + rng) / 2.0       # support of s0 / (s0 + s1)
+    assert z.min() >= lo - 1e-9 and z.max() <= hi + 1e-9
+    assert z.min() < lo + 0.05 * (hi - lo) and z.max() > hi - 0.05 * (hi - lo)
+    cdf = np.vectorize(lambda t: _ratio_cdf(t, rng))
+    assert stats.kstest(z, cdf).pvalue > 1e-3
+    # and symmetric about one half, as two exchangeable shares must be
+    assert abs(np.mean(z) - 0.5) < 4 * np.std(z) / np.sqrt(len(z))
+
+
+def test_range_one_cuts_span_the_variable():
+    # range = 1: shares ~ U(0, 2), so cut positions reach from near the first to near the last
+    # object; with five classes every cut still leaves each class non-empty
+    n = 1000
+    t1 = np.array([oracle.cuts(n, 1, 1.0, 3, r, v)[0] for r in range(40) for v in range(50)])
+    assert t1.min() < 0.03 * n and t1.max() > 0.97 * n
+    t4 = np.array([oracle.cuts(n, 4, 1.0, 3, r, v) for r in range(20) for v in range(50)])
+    assert (np.diff(t4, axis=1) >= 1).all() and t4[:, 0].min() >= 1 and t4[:, -1].max() <= n - 1
+    assert t4[:, 0].min() < 0.02 * n and t4[:, -1].max() > 0.98 * n
+
+
 def test_codes_are_thresholds_of_sorted_values():
     g = np.random.default_rng(0)
     X = g.standard_normal((6, 301)).astype(np.float32)
@@ -174,6 +213,58 @@ def test_k2_xi0_is_conditional_mi():
     assert am[0, 0] == 1 and am[1, 0] == 0
 
 
+@pytest.mark.parametrize("k,div", [(3, 2), (4, 1), (4, 2), (5, 1)])
+def test_higher_k_xi0_is_conditional_mi(k, div):
+    # xi = 0: IG(i | m) = N [MI(y; (x_i, m)) - MI(y; m)] with the joint codes of the tuple as one
+    # label (scikit-learn's plug-in mutual information, natural log), for tuples up to k = 5
+    w = workloads.parity3(seed=40 + k, n_obj=240, n_var=6)
+    c = div + 1
+    codes = oracle.discretize(w.data, div, 1, 0.5, 40 + k)[0]
+
+    def joint(vs):
+        lab = np.zeros(w.n_obj, dtype=np.int64)
+        for v in vs:
+            lab = lab * c + codes[v]
+        return lab
+    for T in itertools.combinations(range(6), k):
+        for pos, i in enumerate(T):
+            rest = [v for v in T if v != i]
+            ref = w.n_obj * (mutual_info_score(w.y, joint(T)) - mutual_info_score(w.y, joint(rest)))
+            got = oracle.ig_member(codes, w.y, c, list(T), pos, 0.0, 0.0)
+            assert got == pytest.approx(ref, rel=1e-9, abs=1e-9)
+
+
+@pytest.mark.parametrize("k,div,xi,ones", [(1, 2, 0.25, None), (2, 2, 0.25, 7), (2, 4, 1.0, None),
+                                           (3, 1, 0.25, 11), (3, 2, 0.5, None), (4, 1, 0.25, None),
+                                           (4, 2, 2.0, 9), (5, 1, 0.25, 13)])
+def test_oracle_equals_pure_python_brute_force(k, div, xi, ones):
+    # the C oracle against an independent pure-Python brute force of every step (oracle/brute.py),
+    # at xi > 0 with balanced and imbalanced decisions, ties in the data and several
+    # discretisations: IG to 1e-12, argmax tuple and discretisation exact
+    from oracle import brute
+    n_obj, n_var, R = 37, 7, 2
+    w = workloads.null_data(60 + k, n_obj, n_var, ones=ones)
+    X = w.data.copy()
+    X[1] = np.round(X[1])                              # heavy ties
+    X[2] = (w.y * 2.0 - 1.0) + 0.5 * X[2]                # an informative variable
+    ig, am, ad = oracle.max_ig_all(X, w.y, k, div, R, 0.6, xi, 5, disc_offset=1)
+    bi, bam, bad = brute.max_ig(X.tolist(), w.y.tolist(), k, div, R, 0.6, xi, 5, disc_offset=1)
+    assert np.allclose(ig, bi, rtol=1e-12, atol=1e-12)
+    if k > 1:
+        assert am.tolist() == bam
+    assert ad.tolist() == bad
+
+
+def test_brute_force_discretisation_equals_oracle():
+    from oracle import brute
+    X = np.random.default_rng(3).standard_normal((5, 61)).astype(np.float32)
+    X[0, ::4] = X[0, 1]
+    codes = oracle.discretize(X, 4, 3, 0.8, 21, disc_offset=2)
+    for r in range(3):
+        for v in range(5):
+            assert codes[r, v].tolist() == brute.codes_of(X[v].tolist(), 5, 0.8, 21, 2 + r, v)
+
+
 # ------------------------------------------------------------------ identities
 def test_root_entropy_unchanged_by_pseudocount():
     # beta^d proportional to N^d leaves the root probabilities at N^d/N exactly.
@@ -231,7 +322,7 @@ def test_max_over_discretisations_is_max_of_separate_runs():
         assert sep[r][0][v] == fused[0][v] and np.array_equal(sep[r][1][v], fused[1][v])
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
 def test_tuple_sweep_equals_per_variable_definition(k):
     w = workloads.xor_small(seed=11, n_obj=150, n_var=7)
     a = oracle.max_ig(w.data, w.y, k, 2, 2, 0.5, 0.25, 11)
