@@ -153,6 +153,22 @@ int mdfs_max_ig(const mdfs_params *prm, const float *data, const uint8_t *y, flo
 int mdfs_max_ig_async(const mdfs_params *prm, const float *data, const uint8_t *y, int64_t n1, float *ig_max,
                       int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream);
 
+/* mdfs_max_ig_async for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same computation and outputs, with the
+ * workspace taken from a device array inside the library (128 MiB per GPU, held from the first
+ * use until the process ends) instead of a caller buffer.  No device or host memory is allocated
+ * by the call.
+ *   prm, data, y, n1, ig_max, argmax, argmax_disc, stream : as mdfs_max_ig_async
+ *   status_out : device int32 [1] (nullable): written on `stream` after the outputs with the code
+ *                mdfs_check_status would return (MDFS_OK, MDFS_E_Y, MDFS_E_NAN, MDFS_E_OVERFLOW)
+ * Returns MDFS_E_NOMEM when mdfs_workspace_size(prm) exceeds 128 MiB (e.g. N = 2000, p = 500,
+ * three classes and 30 discretisations need 92 MiB at k = 2, 112 MiB at k = 3), other argument
+ * errors as mdfs_max_ig_async, before anything is enqueued.  Every call on one GPU uses that GPU's
+ * one array: calls that overlap in time on one GPU (other streams, other host threads) race and
+ * must be serialised by the caller; each call starts by clearing what it needs cleared. */
+int mdfs_max_ig_noalloc(const mdfs_params *prm, const float *data, const uint8_t *y, int64_t n1, float *ig_max,
+                        int32_t *argmax, int32_t *argmax_disc, int32_t *status_out, void *stream);
+
 /* Several k = 2 problems (datasets of uneven N and p, their own discretisation counts) in one
  * asynchronous call whose maximum pass is ONE persistent launch over the concatenated tiles of all
  * problems, so small problems share the GPU instead of leaving it idle between launches.

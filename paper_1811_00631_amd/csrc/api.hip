@@ -11,6 +11,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <mutex>
 #include <vector>
 
 using namespace mdfs;
@@ -430,6 +431,69 @@ extern "C" int mdfs_max_ig_async(const mdfs_params *prm, const float *data, cons
                                  void *stream)
 {
     return max_ig_async_impl(prm, data, y, n1, ig_max, argmax, argmax_disc, ws, ws_bytes, stream);
+}
+
+// ---- the entry point that allocates nothing
+// Its workspace is a file-scope device array of fixed size; every GPU that loads the library holds
+// its own copy until the process ends.  In host code `scratch` names a host-side stand-in, not a
+// device address: its device address is taken once per device with hipGetSymbolAddress (with that
+// device current) and only that address is passed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// Device address of this device's scratch array (nullptr and an error message on failure).
+static void *scratch_on(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            fail(MDFS_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// The device status word of the last call on `st`, as mdfs_check_status reports it.
+__global__ void k_status_code(const Status *st, int32_t *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    out[0] = st->y_flag ? MDFS_E_Y : st->cancelled ? MDFS_E_CANCELLED : st->nan_flag ? MDFS_E_NAN
+           : st->code_flag ? MDFS_E_ARG : st->overflow ? MDFS_E_OVERFLOW : MDFS_OK;
+}
+
+extern "C" int mdfs_max_ig_noalloc(const mdfs_params *prm, const float *data, const uint8_t *y, int64_t n1,
+                                   float *ig_max, int32_t *argmax, int32_t *argmax_disc, int32_t *status_out,
+                                   void *stream)
+{
+    int rc = check_params(prm);
+    if (rc) return rc;
+    const size_t need = layout_of(prm).total;
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(MDFS_E_NOMEM, "this problem needs %zu bytes of workspace; the allocation-free call holds %zu per GPU",
+                    need, NOALLOC_SCRATCH_BYTES);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(MDFS_E_LIMIT, "device %d >= %d", dev, NOALLOC_MAX_DEVICES);
+    void *ws = scratch_on(dev);
+    if (!ws) return MDFS_E_HIP;
+    if ((rc = max_ig_async_impl(prm, data, y, n1, ig_max, argmax, argmax_disc, ws, NOALLOC_SCRATCH_BYTES, stream)))
+        return rc;
+    if (status_out) {
+        const Layout L = layout_of(prm);
+        hipLaunchKernelGGL(k_status_code, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream),
+                           reinterpret_cast<const Status *>(static_cast<char *>(ws) + L.status), status_out);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "status kernel");
+    }
+    g_err[0] = 0;
+    return MDFS_OK;
 }
 
 extern "C" size_t mdfs_batch_workspace_size(void) { return 256; }

@@ -58,7 +58,7 @@ SYMBOLS = ["mdfs_workspace_size", "mdfs_discretize", "mdfs_max_ig", "mdfs_pair_c
            "mdfs_screen_max", "mdfs_interesting_tuples", "mdfs_phase_times", "mdfs_last_error",
            "mdfs_chi2_df", "mdfs_pvalues", "mdfs_ig_lim", "mdfs_p_adjust", "mdfs_add_contrast",
            "mdfs_max_ig_codes", "mdfs_max_ig_async", "mdfs_check_status", "mdfs_max_ig_batch",
-           "mdfs_batch_workspace_size"]
+           "mdfs_batch_workspace_size", "mdfs_max_ig_noalloc"]
 FLAG_TIMING = 1
 PHASES = ["setup", "discretize", "sweep", "finalize"]
 
@@ -80,6 +80,8 @@ def load(path: str = LIB_PATH):
     L.mdfs_max_ig_codes.argtypes = [P, vp, vp, vp, vp, vp, vp, sz, vp]
     L.mdfs_max_ig_async.argtypes = [P, vp, vp, ctypes.c_int64, vp, vp, vp, vp, sz, vp]
     L.mdfs_check_status.argtypes = [P, vp, sz, vp]
+    L.mdfs_max_ig_noalloc.argtypes = [P, vp, vp, ctypes.c_int64, vp, vp, vp, vp, vp]
+    L.mdfs_max_ig_noalloc.restype = ctypes.c_int
     L.mdfs_batch_workspace_size.argtypes = []
     L.mdfs_batch_workspace_size.restype = sz
     L.mdfs_max_ig_batch.argtypes = [ctypes.c_int, P, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -232,6 +234,26 @@ def mdfs_max_ig_async(data: torch.Tensor, y: torch.Tensor, n1: int, k: int, divi
     ig, am, ad = out
     _check(load().mdfs_max_ig_async(ctypes.byref(prm), _ptr(data), _ptr(y), int(n1), _ptr(ig), _ptr(am), _ptr(ad),
                                     _ptr(ws), ws.numel(), _stream(data.device)))
+    return ig, am, ad
+
+
+def mdfs_max_ig_noalloc(data: torch.Tensor, y: torch.Tensor, n1: int, k: int, divisions: int, n_disc: int,
+                        pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0, disc_offset: int = 0,
+                        engine: str = "auto", workgroups: int = 0, out=None, status=None):
+    """mdfs_max_ig_async with the library's own fixed device workspace: nothing is allocated by the
+    call (`out` = preallocated (ig, argmax, argmax_disc) or None; `status` = a preallocated int32
+    device tensor of one element that receives the device status code, or None)."""
+    data, y = _dev_inputs(data, y)
+    n_var, n_obj = data.shape
+    prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed, engine, 0,
+                      workgroups)
+    if out is None:
+        out = (torch.empty(n_var, dtype=torch.float32, device=data.device),
+               torch.empty((n_var, k - 1), dtype=torch.int32, device=data.device),
+               torch.empty(n_var, dtype=torch.int32, device=data.device))
+    ig, am, ad = out
+    _check(load().mdfs_max_ig_noalloc(ctypes.byref(prm), _ptr(data), _ptr(y), int(n1), _ptr(ig), _ptr(am), _ptr(ad),
+                                      _ptr(status), _stream(data.device)))
     return ig, am, ad
 
 
