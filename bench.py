@@ -62,12 +62,14 @@ def _wl(name):
             "madelon_like": workloads.madelon_like, "parity3": workloads.parity3,
             "genomics_like": workloads.genomics_like,
             "madelon4": lambda: workloads.madelon_like(divisions=1, n_disc=1, k=4),
+            "madelon5": lambda: workloads.madelon_like(divisions=1, n_disc=1, k=5),
+            "madelon4_d5": lambda: workloads.madelon_like(divisions=4, n_disc=1, k=4, n_noise=180),
             "madelon2_d2": lambda: workloads.madelon_like(divisions=1, n_disc=30, k=2),
             "madelon3_d2": lambda: workloads.madelon_like(divisions=1, n_disc=30, k=3)}[name]()
 
 
-WORKLOADS = ["headline", "xor_small", "madelon_like", "parity3", "genomics_like", "madelon4", "madelon2_d2",
-             "madelon3_d2", "batch12", "serving"]
+WORKLOADS = ["headline", "xor_small", "madelon_like", "parity3", "genomics_like", "madelon4", "madelon5",
+             "madelon4_d5", "madelon2_d2", "madelon3_d2", "batch12", "serving"]
 WORKLOAD_TEXT = {
     "headline": "genomics-shaped k=2: N=2000, p=20000 log-normal, 10 planted XOR pairs, balanced y, d=3, "
                 "30 random discretisations (range 0.5, xi 0.25)",
@@ -78,6 +80,10 @@ WORKLOAD_TEXT = {
                      "30 discretisations",
     "madelon4": "Madelon-shaped k=4: N=2000, p=500 (5 base + 15 combinations + 480 noise), d=2, 1 discretisation "
                 "(the shape of the paper's 4D timing)",
+    "madelon5": "Madelon-shaped k=5: N=2000, p=500 (5 base + 15 combinations + 480 noise), d=2, 1 discretisation "
+                "(the shape of the paper's 5D timing), histogram engine",
+    "madelon4_d5": "Madelon-shaped k=4 with five classes: N=2000, p=200 (5 base + 15 combinations + 180 noise), "
+                   "1 discretisation, histogram engine",
     "madelon2_d2": "Madelon-shaped k=2: N=2000, p=500, d=2, 30 discretisations (the shape of the paper's 2D timing)",
     "madelon3_d2": "Madelon-shaped k=3: N=2000, p=500, d=2, 30 discretisations (the shape of the paper's 3D timing)",
     "batch12": "12 Madelon-shaped k=2 datasets of uneven size (N 500-2000, p 200-600), d=3, 30 discretisations each: "
@@ -435,6 +441,15 @@ def main():
                 "kernel": (f"k_sweep2<{W}, max, {'fp4' if fp4 else 'int8'}>" if k == 2
                            else f"k_sweep3m{'1' if W == 1 else ''} (+ pair data)"),
                 "units_per_launch": tuples, "kernel_ms": sweep_ms}
+    elif k == 5 or (k == 4 and (div == 4 or args.engine == "hist")):
+        # per-tuple histogram: N voxel increments (one LDS add each, the algorithmic work), then
+        # C^k + k C^(k-1) voxel terms of the float32 screen
+        ops_per_unit = 2 * w.n_obj
+        achieved = tuples * ops_per_unit / (sweep_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "Tops/s (32-bit integer VALU)",
+                "frac": achieved / ALU_PEAK_TOPS, "traffic": None, "kernel": f"k_sweep_hist<{C}, {k}>",
+                "per_unit": f"2*N = {ops_per_unit} ops per tuple table (N voxel increments)",
+                "units_per_launch": tuples, "kernel_ms": sweep_ms}
     elif k == 4:
         # AND + popcount-accumulate per (cell, 32-object word), every one of the C^4 cells counted
         words = (int((w.y == 0).sum()) + 31) // 32 + (int((w.y == 1).sum()) + 31) // 32
@@ -477,7 +492,9 @@ def main():
         "unit": "k-tuples evaluated/sec",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp4 (E2M1 one-hot), f32 accumulate" if fp4 else ("i8" if k == 2 else "u32 bitsets"),
+        "dtype": "fp4 (E2M1 one-hot), f32 accumulate" if fp4 else ("i8" if k == 2 else (
+            "u8 codes, u32 histograms" if (k == 5 or (k == 4 and (div == 4 or args.engine == "hist")))
+            else "u32 bitsets")),
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "k": k, "n_obj": w.n_obj, "n_var": w.n_var, "classes": div + 1, "n_disc": R,
@@ -485,7 +502,8 @@ def main():
                    "engine": args.engine, "workgroups": workgroups or "whole GPU",
                    "autotuned": bool(tuned), "graph_replay": bool(args.graph),
                    "counts": ("fp4 MFMA, exact f32 accumulate" if fp4 else "int8 MFMA, int32 accumulate")
-                   if (k == 2 or k3_mfma) else "bitset AND + popcount, int32",
+                   if (k == 2 or k3_mfma) else ("per-tuple LDS histograms" if k >= 4 and "hist" in roof["kernel"]
+                                                else "bitset AND + popcount, int32"),
                    "entropy": "float32 screen + binary64 re-score"},
         "p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
         "p99_ms": float(np.percentile(np.array(lat) * 1e3, 99)),

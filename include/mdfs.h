@@ -30,9 +30,11 @@
  *     size the launch) and once at exit (to check the device status word); all kernels run
  *     on `stream`.
  *   * Supported sizes: 2 <= n_obj <= 16384 and n_obj >= divisions+1; each class < 32768
- *     objects; k in {1, 2, 3, 4}; divisions in {1, 2, 4} (2, 3 or 5 classes); n_disc >= 1;
- *     disc_offset >= 0; for k = 3, n_var <= 4096; for k = 4, divisions in {1, 2},
- *     n_var <= 1024 and the bitset engine.  Beyond these, MDFS_E_LIMIT.
+ *     objects; k in {1, 2, 3, 4, 5} (the paper's limit); divisions in {1, 2, 4} (2, 3 or 5
+ *     classes); n_disc >= 1; disc_offset >= 0; for k = 3, n_var <= 4096; for k = 4,
+ *     n_var <= 2048; for k = 5, n_var <= 512 (the partner tuple of a k >= 4 candidate travels
+ *     as its 32-bit lexicographic rank); the k >= 4 engines keep the entropy tables (16 bytes per
+ *     object) in LDS, which bounds n_obj near 8000 there.  Beyond these, MDFS_E_LIMIT.
  */
 #ifndef MDFS_H
 #define MDFS_H
@@ -61,12 +63,16 @@ typedef enum {
 typedef enum {
     MDFS_ENGINE_AUTO = 0,     /* k=2: fp4 MFMA if both classes < 4096 objects, else int8 MFMA;
                                  k=3: fp4 MFMA for 2 or 3 classes under the same condition, else
-                                 bitset; k=4: bitset */
+                                 bitset; k=4: bitset for 2 or 3 classes, else histogram; k=5:
+                                 histogram */
     MDFS_ENGINE_MFMA = 1,     /* one-hot int8 contraction on the matrix cores */
     MDFS_ENGINE_BITSET = 2,   /* per-class bitsets, AND + popcount */
-    MDFS_ENGINE_MFMA_FP4 = 3  /* one-hot E2M1 (fp4) contraction, float32 accumulation (exact
+    MDFS_ENGINE_MFMA_FP4 = 3, /* one-hot E2M1 (fp4) contraction, float32 accumulation (exact
                                  integers); k=2, or k=3 with divisions 1 or 2; each class < 4096
                                  objects, else MDFS_E_LIMIT */
+    MDFS_ENGINE_HIST = 4      /* per-tuple histogram of the class-sorted codes, every cell counted
+                                 directly; k = 4 or 5, any class count ("auto" for k = 5 and for
+                                 k = 4 with five classes) */
 } mdfs_engine;
 
 /* Problem description.  Fields follow the arguments of ComputeMaxInfoGains
@@ -75,7 +81,7 @@ typedef enum {
 typedef struct {
     int64_t n_obj;       /* N, objects */
     int64_t n_var;       /* p, variables */
-    int32_t k;           /* dimensions: tuple size 1 to 4 (k = 1: each variable alone) */
+    int32_t k;           /* dimensions: tuple size 1 to 5 (k = 1: each variable alone) */
     int32_t divisions;   /* classes per variable = divisions + 1 */
     int32_t n_disc;      /* number of random discretisations */
     int32_t disc_offset; /* index of the first discretisation (run r uses index disc_offset+r) */

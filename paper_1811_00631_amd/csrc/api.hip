@@ -85,7 +85,7 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
 {
     if (!prm) return fail(MDFS_E_ARG, "params is NULL");
     if (prm->flags & ~MDFS_FLAG_TIMING) return fail(MDFS_E_ARG, "unknown flag bits 0x%x", prm->flags);
-    if (prm->k < 1 || prm->k > 4) return fail(MDFS_E_K, "k=%d: supported tuple sizes are 1 to 4", prm->k);
+    if (prm->k < 1 || prm->k > 5) return fail(MDFS_E_K, "k=%d: supported tuple sizes are 1 to 5", prm->k);
     if (prm->divisions != 1 && prm->divisions != 2 && prm->divisions != 4)
         return fail(MDFS_E_DIV, "divisions=%d: supported are 1, 2, 4", prm->divisions);
     if (prm->n_obj < 2 || prm->n_obj < prm->divisions + 1)
@@ -94,12 +94,17 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
     if (prm->n_var < prm->k) return fail(MDFS_E_ARG, "n_var=%lld < k", (long long)prm->n_var);
     if (prm->k == 3 && prm->n_var > MAX_K3_VARS)
         return fail(MDFS_E_LIMIT, "k=3 with n_var=%lld > %d", (long long)prm->n_var, MAX_K3_VARS);
-    if (prm->k == 4 && prm->divisions > 2)
-        return fail(MDFS_E_LIMIT, "k=4 is built for divisions 1 and 2 (2 or 3 classes)");
     if (prm->k == 4 && prm->n_var > MAX_K4_VARS)
         return fail(MDFS_E_LIMIT, "k=4 with n_var=%lld > %d", (long long)prm->n_var, MAX_K4_VARS);
-    if (sweep && prm->k == 4 && prm->engine != MDFS_ENGINE_AUTO && prm->engine != MDFS_ENGINE_BITSET)
-        return fail(MDFS_E_LIMIT, "k=4 runs on the bitset engine");
+    if (prm->k == 5 && prm->n_var > MAX_K5_VARS)
+        return fail(MDFS_E_LIMIT, "k=5 with n_var=%lld > %d", (long long)prm->n_var, MAX_K5_VARS);
+    if (sweep && prm->k == 4 && prm->engine != MDFS_ENGINE_AUTO && prm->engine != MDFS_ENGINE_HIST &&
+        !(prm->engine == MDFS_ENGINE_BITSET && prm->divisions <= 2))
+        return fail(MDFS_E_LIMIT, "k=4 runs on the bitset engine (2 or 3 classes) or the histogram engine");
+    if (sweep && prm->k == 5 && prm->engine != MDFS_ENGINE_AUTO && prm->engine != MDFS_ENGINE_HIST)
+        return fail(MDFS_E_LIMIT, "k=5 runs on the histogram engine");
+    if (sweep && prm->k <= 3 && prm->engine == MDFS_ENGINE_HIST)
+        return fail(MDFS_E_LIMIT, "the histogram engine is built for k = 4 and 5");
     if (sweep && prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA)
         return fail(MDFS_E_LIMIT, "k=3 on the matrix cores uses the fp4 encoding (engine mfma_fp4)");
     if (sweep && prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA_FP4 && prm->divisions != 1 && prm->divisions != 2)
@@ -111,7 +116,7 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
     if (!(prm->range >= 0.0 && prm->range <= 1.0)) return fail(MDFS_E_ARG, "range=%g outside [0,1]", prm->range);
     if (!(prm->pseudocount >= 0.0) || !isfinite(prm->pseudocount))
         return fail(MDFS_E_ARG, "pseudocount=%g must be finite and >= 0", prm->pseudocount);
-    if (prm->engine < 0 || prm->engine > 3) return fail(MDFS_E_ARG, "engine=%d", prm->engine);
+    if (prm->engine < 0 || prm->engine > 4) return fail(MDFS_E_ARG, "engine=%d", prm->engine);
     if (prm->workgroups != 0 && (prm->workgroups < 8 || prm->workgroups > 4096))
         return fail(MDFS_E_ARG, "workgroups=%d: 0 (whole GPU) or 8..4096", prm->workgroups);
     if (prm->reserved != 0) return fail(MDFS_E_ARG, "reserved field must be 0");
@@ -210,10 +215,17 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
         P.err_bound = screen_err_bound(N, P.beta0, P.beta1, C * C);
         // k = 3: the triple's own F (C^3 voxels) plus the float32 F of the parent pair
         if (prm->k == 3) P.err_bound += screen_err_bound(N, P.beta0, P.beta1, C * C * C);
-        // k = 4: the quadruple's F (C^4 voxels) and a sub-triple's float32 F (C^3 voxels)
-        if (prm->k == 4)
-            P.err_bound = screen_err_bound(N, P.beta0, P.beta1, C * C * C * C) +
-                          screen_err_bound(N, P.beta0, P.beta1, C * C * C);
+        // k = 4, 5: the tuple's F (C^k voxels) and a parent's float32 F (C^(k-1) voxels)
+        if (prm->k >= 4) {
+            const int V = prm->k == 4 ? C * C * C * C : C * C * C * C * C;
+            P.err_bound = screen_err_bound(N, P.beta0, P.beta1, V) + screen_err_bound(N, P.beta0, P.beta1, V / C);
+        }
+        // k >= 4 engine: bitsets for k = 4 with two or three classes unless the histogram engine
+        // is asked for; the histogram engine otherwise
+        P.hist = prm->k == 5 || (prm->k == 4 && (C == 5 || prm->engine == MDFS_ENGINE_HIST));
+        if (P.hist && sweep_hist_lds_bytes(P) > LDS_MAX)
+            return fail(MDFS_E_LIMIT, "histogram engine: LDS tables and histograms need %zu bytes > %zu",
+                        sweep_hist_lds_bytes(P), LDS_MAX);
         // k = 3 engine: matrix cores for two or three classes in the fp4 encoding (auto or asked for)
         P.k3_mfma = prm->k == 3 && (prm->divisions == 1 || prm->divisions == 2) && P.fp4 &&
                     (prm->engine == MDFS_ENGINE_AUTO || prm->engine == MDFS_ENGINE_MFMA_FP4);
@@ -258,8 +270,11 @@ static int sweep_pass(const Problem &P, int32_t *counts, int disc_sel, bool coll
         LAUNCH(launch_reset_queue(P));
         LAUNCH(launch_sweep2(P, counts, disc_sel, collect));
         if (counts) LAUNCH(launch_complete_pairs(P, counts, disc_sel));
-    } else if (P.L.k == 4) {
-        for (int r = 0; r < P.L.R; ++r) LAUNCH(launch_sweep4(P, r, collect));
+    } else if (P.L.k >= 4) {
+        for (int r = 0; r < P.L.R; ++r) {
+            if (P.hist) LAUNCH(launch_sweep_hist(P, r, collect));
+            else LAUNCH(launch_sweep4(P, r, collect));
+        }
     } else {
         for (int r = 0; r < P.L.R; ++r) {
             int32_t *cr = (counts && r == disc_sel) ? counts : nullptr;
@@ -616,7 +631,7 @@ extern "C" int mdfs_interesting_tuples(const mdfs_params *prm, const float *data
     int rc = check_params(prm);
     if (rc) return rc;
     if (prm->k == 1) return fail(MDFS_E_K, "k=1 has no tuples (mdfs_max_ig covers it)");
-    if (prm->k == 4) return fail(MDFS_E_K, "k=4 interesting tuples are not built (mdfs_max_ig covers k=4)");
+    if (prm->k >= 4) return fail(MDFS_E_K, "k=%d interesting tuples are not built (mdfs_max_ig covers k=4, 5)", prm->k);
     if (!data || !y || !ws || !n_found) return fail(MDFS_E_ARG, "null pointer");
     if (max_out < 0 || (max_out > 0 && (!var || !partners || !disc || !ig)))
         return fail(MDFS_E_ARG, "max_out=%lld with a null output array", (long long)max_out);

@@ -66,11 +66,13 @@ struct RescoreArgs {
 };
 
 // One wave per candidate (grid-stride).  k = 2: table of (v, m); k = 3: table of (v, m1, m2).
+// (k >= 4: k_rescore_hist, which recounts from the class-sorted codes into an LDS histogram.)
 template <int C, int K>
 __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a)
 {
     constexpr int W = C - 1;
-    constexpr int NC = (K == 2) ? C * C : (K == 3) ? C * C * C : C * C * C * C;
+    static_assert(K == 2 || K == 3, "k >= 4 is re-scored by k_rescore_hist");
+    constexpr int NC = (K == 2) ? C * C : C * C * C;
     const int lane = threadIdx.x & 63;
     const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -82,10 +84,9 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a)
             if (lane == 0) a.ig64[ci] = -INFINITY;
             continue;
         }
-        int64_t m1, m2 = 0, m3 = 0;
+        int64_t m1, m2 = 0;
         if (K == 2) m1 = x.partner;
-        else if (K == 3) { m1 = x.partner >> 16; m2 = x.partner & 0xffff; }
-        else { m1 = x.partner >> 20; m2 = (x.partner >> 10) & 1023; m3 = x.partner & 1023; }
+        else { m1 = x.partner >> 16; m2 = x.partner & 0xffff; }
         int cnt[2][NC];
 #pragma unroll
         for (int d = 0; d < 2; ++d)
@@ -98,7 +99,6 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a)
             int cell = code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, x.v, e, a.fp4) * C +
                        code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, m1, e, a.fp4);
             if (K >= 3) cell = cell * C + code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, m2, e, a.fp4);
-            if (K == 4) cell = cell * C + code_from_onehot<W>(a.onehot, x.r, kb, a.KB, a.rows_pad, m3, e, a.fp4);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 cnt[0][c] += (valid && c0 && cell == c) ? 1 : 0;
@@ -153,10 +153,11 @@ __global__ void k_output(int64_t p, int k, int disc_offset, const uint64_t *max6
     if (argmax) {
         const uint32_t pt = (uint32_t)key;
         if (k == 2) argmax[v] = bad ? -1 : (int32_t)pt;
-        else if (k == 4) {
-            argmax[3 * v] = bad ? -1 : (int32_t)(pt >> 20);
-            argmax[3 * v + 1] = bad ? -1 : (int32_t)((pt >> 10) & 1023);
-            argmax[3 * v + 2] = bad ? -1 : (int32_t)(pt & 1023);
+        else if (k >= 4) {
+            // the lexicographic rank of the partner tuple among the (k-1)-subsets of p variables
+            int part[4] = {-1, -1, -1, -1};
+            if (!bad) lex_unrank(pt, k - 1, p, part);
+            for (int q = 0; q < k - 1; ++q) argmax[(int64_t)(k - 1) * v + q] = bad ? -1 : part[q];
         } else {
             argmax[2 * v] = bad ? -1 : (int32_t)(pt >> 16);
             argmax[2 * v + 1] = bad ? -1 : (int32_t)(pt & 0xffff);
@@ -206,12 +207,8 @@ static hipError_t rescore_all(const Problem &P, const RescoreArgs &a)
         case 5: rescore_launch<5, 2>(P, a); break;
         default: return hipErrorInvalidValue;
         }
-    } else if (L.k == 4) {
-        switch (L.C) {
-        case 2: rescore_launch<2, 4>(P, a); break;
-        case 3: rescore_launch<3, 4>(P, a); break;
-        default: return hipErrorInvalidValue;
-        }
+    } else if (L.k >= 4) {
+        return launch_rescore_hist(P);   // from the class-sorted codes, any class count
     } else {
         switch (L.C) {
         case 2: rescore_launch<2, 3>(P, a); break;

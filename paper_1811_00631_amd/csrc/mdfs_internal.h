@@ -31,7 +31,10 @@ constexpr int VAR_PAD = 128;
 constexpr int MAX_NOBJ = 16384;
 constexpr int MAX_CLASS_OBJ = 32767;
 constexpr int MAX_K3_VARS = 4096;
-constexpr int MAX_K4_VARS = 1024;      // k = 4: three partners packed 10 bits each
+// k >= 4 candidates carry the lexicographic rank of their partner tuple in 32 bits:
+// C(2048, 3) and C(512, 4) are below 2^32
+constexpr int MAX_K4_VARS = 2048;
+constexpr int MAX_K5_VARS = 512;
 constexpr int MAX_BATCH = 12;          // problems fused in one persistent pair-sweep launch
 
 // Status words at the start of the workspace.
@@ -70,7 +73,7 @@ struct Layout {
     int64_t words_max;    // bitset words (32 objects) per class, worst case (k=3)
     // offsets
     size_t status, pos, perm, tabEA, tabEB, tabLQ, marg, F1, onehot, G32, max64, keyw, ovf,
-        cand, ig64, bits, ptab, F2, a3pref, a3blk, F1d, total;
+        cand, ig64, bits, ptab, F2, a3pref, a3blk, F1d, ccodes, total;
 };
 
 Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R);
@@ -105,6 +108,40 @@ __host__ __device__ inline double key_f64(uint64_t k)
 {
     uint64_t b = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
     return __builtin_bit_cast(double, b);
+}
+
+// Partner tuples of k >= 4 candidates: the lexicographic rank of the ascending tuple among the
+// m-subsets of {0 .. n-1} (so that comparing ranks compares tuples as the tie rule does).  The
+// subsets whose first element is below x, given the earlier elements end before a, number
+// C(n - a, m) - C(n - x, m) (hockey-stick identity).
+__host__ __device__ inline uint64_t binom_u64(int64_t n, int k)
+{
+    if (k < 0 || n < k) return 0;
+    uint64_t r = 1;
+    for (int i = 0; i < k; ++i) r = r * (uint64_t)(n - i) / (uint64_t)(i + 1);   // C(n, i + 1), exact
+    return r;
+}
+__host__ __device__ inline uint32_t lex_rank(const int *c, int m, int64_t n)
+{
+    uint64_t r = 0;
+    int64_t a = 0;
+    for (int i = 0; i < m; ++i) {
+        r += binom_u64(n - a, m - i) - binom_u64(n - c[i], m - i);
+        a = c[i] + 1;
+    }
+    return (uint32_t)r;
+}
+__host__ __device__ inline void lex_unrank(uint64_t r, int m, int64_t n, int *c)
+{
+    int64_t a = 0;
+    for (int i = 0; i < m; ++i) {
+        const uint64_t top = binom_u64(n - a, m - i);
+        int64_t x = a;
+        while (top - binom_u64(n - x - 1, m - i) <= r) ++x;   // subsets with first element <= x
+        r -= top - binom_u64(n - x, m - i);
+        c[i] = (int)x;
+        a = x + 1;
+    }
 }
 
 // Tie tolerance of the argmax: candidates within tau of the maximum are tied.
@@ -158,6 +195,7 @@ struct Problem {
     uint64_t seed;
     double err_bound;             // float32 screen error bound E (per IG)
     bool k3_mfma;                 // k = 3 on the matrix cores (else bitsets)
+    bool hist;                    // k >= 4 on the per-tuple histogram engine (else bitsets, k = 4)
     int workgroups;               // persistent sweep grid (0 = the whole GPU)
     int64_t n_ablk3, n_tiles3;    // tile list of the k = 3 matrix-core sweep
     const uint8_t *codes_in = nullptr;   // caller-supplied codes [R][p][N] replace the discretisation
@@ -198,6 +236,12 @@ hipError_t launch_sweep3(const Problem &P, int r, bool collect, int32_t *counts_
 hipError_t launch_complete_triples(const Problem &P, int32_t *counts, int r, int i_sel);
 // k = 4 bitset sweep of discretisation r (sweep4.hip)
 hipError_t launch_sweep4(const Problem &P, int r, bool collect);
+// k = 4 or 5 per-tuple histogram sweep of discretisation r, any class count (sweep_hist.hip)
+hipError_t launch_sweep_hist(const Problem &P, int r, bool collect);
+// binary64 re-score of k >= 4 candidates from the class-sorted codes (sweep_hist.hip)
+hipError_t launch_rescore_hist(const Problem &P);
+// LDS bytes per workgroup of the histogram sweep (0 = not built for these sizes)
+size_t sweep_hist_lds_bytes(const Problem &P);
 hipError_t launch_sweep3m(const Problem &P, int r, bool collect, int32_t *counts_out = nullptr, int i_sel = -1);
 size_t sweep3m_lds_bytes(const Problem &P);
 // tile list of the k = 3 matrix-core sweep: its size on the host, the list itself on the device

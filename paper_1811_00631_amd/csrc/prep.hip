@@ -40,7 +40,7 @@ Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
     L.marg = take(sizeof(uint32_t) * (size_t)R * L.p_pad * L.C);
     L.F1 = take(sizeof(float) * (size_t)R * L.p_pad);
     // >= one byte per position; k = 1 needs no tuple encoding, only binary64 F of each variable
-    L.onehot = take(k == 1 ? 0 : (size_t)R * L.Kpad_max * L.rows_pad);
+    L.onehot = take((k == 1 || k >= 4) ? 0 : (size_t)R * L.Kpad_max * L.rows_pad);
     L.F1d = take(k == 1 ? sizeof(double) * (size_t)R * L.p_pad : 0);
     L.G32 = take(sizeof(uint32_t) * L.p_pad);
     L.max64 = take(sizeof(uint64_t) * L.p_pad);
@@ -48,9 +48,11 @@ Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
     L.ovf = take(sizeof(uint32_t) * L.p_pad);
     L.cand = take(sizeof(Cand) * L.cap);
     L.ig64 = take(sizeof(double) * L.cap);
-    if (k == 4) {
-        // bitsets only: the quadruple sweep counts every cell directly
-        L.bits = take(sizeof(uint32_t) * (size_t)R * 2 * L.words_max * L.p_pad * L.W);
+    if (k >= 4) {
+        // bitsets (the k = 4 bitset sweep counts every cell directly) and class-sorted codes
+        // [R][p][N] (the histogram sweep and the binary64 re-score of k >= 4)
+        L.bits = take(k == 4 ? sizeof(uint32_t) * (size_t)R * 2 * L.words_max * L.p_pad * L.W : 0);
+        L.ccodes = take((size_t)R * p * N);
         L.ptab = L.F2 = L.a3pref = L.a3blk = o;
     } else if (k == 3) {
         L.bits = take(sizeof(uint32_t) * (size_t)R * 2 * L.words_max * L.p_pad * L.W);
@@ -62,6 +64,7 @@ Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
     } else {
         L.bits = L.ptab = L.F2 = L.a3pref = L.a3blk = o;
     }
+    if (k < 4) L.ccodes = o;
     L.total = o;
     return L;
 }
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
     int64_t rows_pad, uint8_t *__restrict__ codes, int8_t *__restrict__ onehot,
     uint32_t *__restrict__ marg, float *__restrict__ F1, double *__restrict__ F1d, int64_t p_pad, double b0,
     double b1, Status *st,
-    uint32_t *__restrict__ bits, int64_t words_max)
+    uint32_t *__restrict__ bits, int64_t words_max, uint8_t *__restrict__ ccodes)
 {
     constexpr int W = C - 1;
     extern __shared__ float lds[];
@@ -486,6 +489,15 @@ __global__ __launch_bounds__(DISC_THREADS) void k_discretize(
                 }
             }
         }
+        if (ccodes) {
+            // class-sorted codes without padding: class 0's objects, then class 1's
+            for (int rr = 0; rr < nr; ++rr) {
+                const float *th = thr + rr * (C - 1);
+                uint8_t *out = ccodes + ((int64_t)(rb + rr) * p + v) * N;
+                for (int ps = t; ps < N0 + N1; ps += DISC_THREADS)
+                    out[ps] = (uint8_t)code_of<C>(xcs[ps < N0 ? ps : K0pad + ps - N0], th);
+            }
+        }
         if (marg || F1) {
             // bin a of class d holds G_d(a) - G_d(a+1) values, G_d(a) = count >= threshold a
             // (G_d(0) = n_d, G_d(C) = 0); packed marginals and the F terms of every (r, bin)
@@ -529,10 +541,12 @@ static hipError_t disc_launch(const Problem &P, const float *data, uint8_t *code
     const int64_t nblk = encode ? L.p_pad : L.p;   // encode: also zero the padding variables' rows
     hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(DISC_THREADS), lds, P.stream, data, N, (int)L.p,
                        L.R, P.disc_offset, P.range, P.seed, encode ? P.at<int32_t>(L.perm) : nullptr, P.K0pad, P.N0, P.N1, P.KB,
-                       P.Kpad, P.fp4 ? 1 : 0, L.rows_pad, codes, (encode && L.k != 1) ? P.at<int8_t>(L.onehot) : nullptr,
+                       P.Kpad, P.fp4 ? 1 : 0, L.rows_pad, codes,
+                       (encode && (L.k == 2 || L.k == 3)) ? P.at<int8_t>(L.onehot) : nullptr,
                        encode ? P.at<uint32_t>(L.marg) : nullptr, encode ? P.at<float>(L.F1) : nullptr,
                        (encode && L.k == 1) ? P.at<double>(L.F1d) : nullptr, L.p_pad, P.beta0, P.beta1, P.at<Status>(L.status),
-                       (encode && L.k >= 3) ? P.at<uint32_t>(L.bits) : nullptr, L.words_max);
+                       (encode && (L.k == 3 || L.k == 4)) ? P.at<uint32_t>(L.bits) : nullptr, L.words_max,
+                       (encode && L.k >= 4) ? P.at<uint8_t>(L.ccodes) : nullptr);
     return hipGetLastError();
 }
 
@@ -545,7 +559,7 @@ __global__ __launch_bounds__(DISC_THREADS) void k_encode_codes(
     const uint8_t *__restrict__ codes, int N, int p, int R, const int32_t *__restrict__ perm, int K0pad, int N0,
     int N1, int KB, int Kpad, int fp4, int64_t rows_pad, int8_t *__restrict__ onehot, uint32_t *__restrict__ marg,
     float *__restrict__ F1, double *__restrict__ F1d, int64_t p_pad, double b0, double b1, Status *st,
-    uint32_t *__restrict__ bits, int64_t words_max)
+    uint32_t *__restrict__ bits, int64_t words_max, uint8_t *__restrict__ ccodes)
 {
     constexpr int W = C - 1;
     extern __shared__ uint8_t cls[];        // [Kpad] codes in class-sorted order; C at padding
@@ -610,6 +624,15 @@ __global__ __launch_bounds__(DISC_THREADS) void k_encode_codes(
                 bits[((((int64_t)r * 2 + y) * words_max + w) * p_pad + v) * W + a] = word;
             }
         }
+        if (ccodes) {
+            uint8_t *out = ccodes + ((int64_t)r * p + v) * N;
+            // a code above divisions fails the call (code_flag); it is clamped so that no kernel
+            // indexes past its C^k cells meanwhile
+            for (int ps = t; ps < N0 + N1; ps += DISC_THREADS) {
+                const uint8_t c = cls[ps < N0 ? ps : K0pad + ps - N0];
+                out[ps] = c < C ? c : (uint8_t)(C - 1);
+            }
+        }
         if (marg || F1) {
             int loc[2][C];
 #pragma unroll
@@ -658,10 +681,10 @@ static hipError_t encode_codes_launch(const Problem &P)
     auto kern = k_encode_codes<C>;
     hipLaunchKernelGGL(kern, dim3((unsigned)L.p_pad), dim3(DISC_THREADS), (size_t)P.Kpad, P.stream, P.codes_in,
                        (int)L.N, (int)L.p, L.R, P.at<int32_t>(L.perm), P.K0pad, P.N0, P.N1, P.KB, P.Kpad,
-                       P.fp4 ? 1 : 0, L.rows_pad, L.k != 1 ? P.at<int8_t>(L.onehot) : nullptr,
+                       P.fp4 ? 1 : 0, L.rows_pad, (L.k == 2 || L.k == 3) ? P.at<int8_t>(L.onehot) : nullptr,
                        P.at<uint32_t>(L.marg), P.at<float>(L.F1), L.k == 1 ? P.at<double>(L.F1d) : nullptr, L.p_pad,
-                       P.beta0, P.beta1, P.at<Status>(L.status), L.k >= 3 ? P.at<uint32_t>(L.bits) : nullptr,
-                       L.words_max);
+                       P.beta0, P.beta1, P.at<Status>(L.status), (L.k == 3 || L.k == 4) ? P.at<uint32_t>(L.bits) : nullptr,
+                       L.words_max, L.k >= 4 ? P.at<uint8_t>(L.ccodes) : nullptr);
     return hipGetLastError();
 }
 

@@ -50,14 +50,8 @@ __host__ __device__ constexpr int sw_waves(int W) { return W == 2 ? 8 : 4; }
 constexpr int SB = 8;                    // a super-tile is SB x SB tiles
 constexpr int XCDS = 8;                  // workgroup b runs on XCD b % 8
 constexpr int WG_PER_XCD = SB * SB;      // resident workgroups per XCD (2 per CU: LDS)
+constexpr int STAGE_BYTES = 2 * TILE_ROWS * KBLK;   // A and B tiles of one K block
 constexpr int NSTAGE = 3;                           // LDS ring of K blocks
-// direct_b(W): the A operand goes through the LDS ring and each wave loads its own B fragments
-// from global memory (L2) straight into registers, so a stage holds the A tile only and the
-// first pass parks F in a buffer of its own; otherwise (every class count in this build) a stage
-// holds the A and B tiles and F is parked in the stage after the last K block's.
-__host__ __device__ constexpr bool direct_b(int) { return false; }
-__host__ __device__ constexpr int stage_bytes(int W) { return (direct_b(W) ? 1 : 2) * TILE_ROWS * KBLK; }
-__host__ __device__ constexpr int ring_bytes(int W) { return NSTAGE * stage_bytes(W) + (direct_b(W) ? 16 * 1024 : 0); }
 
 struct Sweep2Args {
     const int8_t *onehot;
@@ -177,11 +171,9 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     constexpr int NP = (W == 1) ? 4 : 1; // pairs held per lane per 16x16 block
     constexpr int NWAVE = sw_waves(W), NT = NWAVE * 64;
     constexpr int NN = 16 / NWAVE;       // 16 x 16 column blocks per wave (row blocks: 4)
-    constexpr bool DB = direct_b(W);     // B fragments straight from L2 into registers
-    constexpr int LPW = (DB ? 8 : 16) / NWAVE;   // 1 KB operand fetches into LDS per wave and K block
-    constexpr int SBYTES = stage_bytes(W);
+    constexpr int LPW = 16 / NWAVE;      // 1 KB operand fetches per wave and K block
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    char *stage = smem + stage_base(ENC);   // [NSTAGE buffers][A 8 KB | B 8 KB (not with DB)] [F buffer (DB)]
+    char *stage = smem + stage_base(ENC);   // [NSTAGE buffers][A 8 KB | B 8 KB]
     // int8: tables after the stages, at run-time offsets (per problem)
     float *EA = nullptr, *EB = nullptr;
     float2 *LQ = nullptr;
@@ -194,7 +186,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 
     // the problem's entropy tables into LDS
     auto load_tables = [&]() {
-        EA = reinterpret_cast<float *>(smem + ring_bytes(W));
+        EA = reinterpret_cast<float *>(smem + NSTAGE * STAGE_BYTES);
         EB = EA + (a.N0 + 1);
         LQ = reinterpret_cast<float2 *>(EB + (a.N1 + 1) + ((a.N0 + a.N1) & 1));
         if constexpr (F4) {
@@ -287,15 +279,14 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 
     // K blocks in processing order: class 1 first, then class 0
     auto kblock = [&](int s_) { return s_ < n1blk ? a.KB0 + s_ : s_ - n1blk; };
-    auto stage_at = [&](int s_) { return stage + (s_ % NSTAGE) * SBYTES; };
+    auto stage_at = [&](int s_) { return stage + (s_ % NSTAGE) * STAGE_BYTES; };
     // Operands go from global memory straight into LDS (global_load_lds_dwordx4): one
     // instruction fills 1 KB = 16 rows, lane i's 16 bytes landing at offset 16 i.  A stage is
     // 16 such blocks (A rows 0..127, then B rows 0..127); wave w fills blocks LPW w ..
     // LPW w + LPW - 1, so the first half of the waves fetch the A panel and the second half the
     // B panel.  The swizzle of the stage layout is applied on the global side: lane i fetches
     // the chunk that belongs at its slot.
-    // With DB every wave fetches one 1 KB block of the A panel (a stage is the A tile only).
-    const int8_t *pan = (DB || wave < NWAVE / 2) ? panA : panB;
+    const int8_t *pan = wave < NWAVE / 2 ? panA : panB;
     int goff[LPW];
 #pragma unroll
     for (int i = 0; i < LPW; ++i) {
@@ -303,14 +294,6 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         const int j = (lane & 3) ^ ((row >> 1) & 3);
         goff[i] = row * KBLK + j * 16;
     }
-    // DB: lane (q, c16) loads 16 bytes (objects of quarter q) of B row wc 16 NN + 16 n + c16, the
-    // layout of the MFMA operand; one load instruction covers 1 KB contiguous of the panel
-    const int8_t *bsrc = panB + (wc * 16 * NN + c16) * KBLK + q * 16;
-    auto loadB = [&](int s_, v4i (&xb)[NN]) {
-        const int8_t *src = bsrc + (int64_t)kblock(s_) * kstride;
-#pragma unroll
-        for (int n = 0; n < NN; ++n) xb[n] = *reinterpret_cast<const v4i *>(src + n * 16 * KBLK);
-    };
     auto issue = [&](int s_) {
         const int8_t *src = pan + (int64_t)kblock(s_) * kstride;
         char *dst = stage_at(s_) + wave * LPW * 1024;
@@ -324,12 +307,8 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         const char *A = stage_at(s_), *B = A + TILE_ROWS * KBLK;
 #pragma unroll
         for (int m = 0; m < 4; ++m) xa[m] = *reinterpret_cast<const v4i *>(A + fa_off0 + m * 16 * KBLK);
-        if constexpr (DB) {
-            loadB(s_, xb);
-        } else {
 #pragma unroll
-            for (int n = 0; n < NN; ++n) xb[n] = *reinterpret_cast<const v4i *>(B + fb_off0 + n * 16 * KBLK);
-        }
+        for (int n = 0; n < NN; ++n) xb[n] = *reinterpret_cast<const v4i *>(B + fb_off0 + n * 16 * KBLK);
     };
     // Software pipeline over a ring of NSTAGE = 3 LDS stages; blocks are fetched two steps ahead
     // and their fragments read one step ahead.  Step s: the wave waits until its fragment reads
@@ -364,16 +343,11 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                 }
         }
     };
-    // the plain barrier: a fenced one would also drain the fetches still in flight.  DB: the B
-    // loads of block s+1 are issued (in frags) between the LDS fetches of blocks s+2 and s+3, so
-    // at the top of step s+1 the fetch of block s+2 is complete once at most NN + LPW loads
-    // remain outstanding (NN of them the B loads, whose registers the compiler waits for itself).
-    constexpr int VM_AHEAD = DB ? NN + LPW : LPW;   // loads allowed in flight when block s+2 exists
-    constexpr int VM_LAST = DB ? NN : 0;            // ... when it does not
+    // the plain barrier: a fenced one would also drain the fetches still in flight
     auto step = [&](int s_, const v4i (&ca)[4], const v4i (&cb)[NN], v4i (&na)[4], v4i (&nb)[NN]) {
         if (s_ + 1 < a.KB) {
-            if (s_ + 2 < a.KB) __builtin_amdgcn_s_waitcnt(0x0070 | VM_AHEAD);   // vmcnt(VM_AHEAD) lgkmcnt(0)
-            else __builtin_amdgcn_s_waitcnt(0x0070 | VM_LAST);                  // vmcnt(VM_LAST) lgkmcnt(0)
+            if (s_ + 2 < a.KB) __builtin_amdgcn_s_waitcnt(0x0070 | LPW);   // vmcnt(LPW) lgkmcnt(0)
+            else __builtin_amdgcn_s_waitcnt(0x0070);                       // vmcnt(0) lgkmcnt(0)
             __builtin_amdgcn_s_barrier();
             frags(s_ + 1, na, nb);
             if (s_ + 3 < a.KB) issue(s_ + 3);
@@ -383,17 +357,10 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     v4i fa0[4], fb0[NN], fa1[4], fb1[NN];
     issue(0);
     if (a.KB > 1) issue(1);
-    if constexpr (DB) loadB(0, fb0);
-    // the fetch of block 0 complete: block 1's fetch (and the B loads of block 0) may be in flight
-    if (a.KB > 1) __builtin_amdgcn_s_waitcnt(0x0F70 | (LPW + (DB ? NN : 0)));
-    else __builtin_amdgcn_s_waitcnt(0x0F70 | (DB ? NN : 0));
+    if (a.KB > 1) __builtin_amdgcn_s_waitcnt(0x0F70 | LPW);
+    else __builtin_amdgcn_s_waitcnt(0x0F70);
     __builtin_amdgcn_s_barrier();
-    if constexpr (DB) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) fa0[m] = *reinterpret_cast<const v4i *>(stage_at(0) + fa_off0 + m * 16 * KBLK);
-    } else {
-        frags(0, fa0, fb0);
-    }
+    frags(0, fa0, fb0);
     if (a.KB > 2) issue(2);
     int s = 0;
     for (; s + 1 < a.KB; s += 2) {
@@ -408,7 +375,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     // KB - 3 (or nothing): every wave read its fragments and every fetch landed before the last
     // barrier of the K loop, and the next tile's first fetch follows the barriers at the top of
     // the tile loop.
-    float *f2buf = reinterpret_cast<float *>(DB ? stage + NSTAGE * SBYTES : stage_at(a.KB));
+    float *f2buf = reinterpret_cast<float *>(stage_at(a.KB));
     auto put_cand = [&](uint32_t at, int64_t v, int64_t partner, float ig) {
         if (at < a.cap) a.cand[at] = Cand{(int32_t)v, r, (uint32_t)partner, ig};
         else { atomicOr(&a.ovf[v], 1u); atomicOr(&a.st->overflow, 1u); }
@@ -849,10 +816,10 @@ size_t sweep2_lds_bytes(const Problem &P, bool max_mode)
 {
     if (P.fp4) {
         const int T = max_mode ? fp4_capacity(P) : 4096;
-        return (size_t)stage_base(T) + ring_bytes(P.L.W) + 16;
+        return (size_t)stage_base(T) + NSTAGE * STAGE_BYTES + 16;
     }
     size_t tab = sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (P.L.N + 1);
-    return ring_bytes(P.L.W) + ((tab + 15) & ~size_t(15)) + 16;
+    return NSTAGE * STAGE_BYTES + ((tab + 15) & ~size_t(15)) + 16;
 }
 
 int sweep2_fp4_capacity(const Problem &P) { return fp4_capacity(P); }
@@ -1035,7 +1002,7 @@ static hipError_t batch_dispatch(const Problem *const *Ps, int n, Status *queue)
         T = std::max(T, fp4_capacity(*Ps[i]));
     }
     if (!Ps[0]->fp4) return batch_launch<W, 0>(Ps, n, queue, lds);
-    lds = (size_t)stage_base(T) + ring_bytes(W) + 16;
+    lds = (size_t)stage_base(T) + NSTAGE * STAGE_BYTES + 16;
     switch (T) {
     case 1024: return batch_launch<W, 1024>(Ps, n, queue, lds);
     case 2048: return batch_launch<W, 2048>(Ps, n, queue, lds);

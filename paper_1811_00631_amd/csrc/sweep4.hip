@@ -61,7 +61,12 @@ __device__ inline float wave_max4(float x)
     return x;
 }
 
-__device__ inline uint32_t pack3(int a, int b, int c) { return ((uint32_t)a << 20) | ((uint32_t)b << 10) | (uint32_t)c; }
+// partner triple a < b < c as its lexicographic rank among the 3-subsets of the p variables
+__device__ inline uint32_t pack3(int a, int b, int c, int p)
+{
+    const int t[3] = {a, b, c};
+    return lex_rank(t, 3, p);
+}
 
 // candidate record at a reserved slot, or the overflow marks when the buffer is full
 __device__ inline void put4(const Sweep4Args &a, uint32_t at, int v, uint32_t partner, float ig)
@@ -235,10 +240,10 @@ __global__ __launch_bounds__(S4_THREADS) void k_sweep4(Sweep4Args a)
             const bool al = act && igl >= topl - window4(a.w_abs, topl);
             // one slot reservation per chunk for the wave's records
             uint32_t at = reserve_slots(&a.st->n_cand, (uint32_t)am + (uint32_t)ai + (uint32_t)aj + (uint32_t)al, lane);
-            if (am) put4(a, at++, m, pack3(i, j, l), igm);
-            if (ai) put4(a, at++, i, pack3(j, l, m), igi);
-            if (aj) put4(a, at++, j, pack3(i, l, m), igj);
-            if (al) put4(a, at++, l, pack3(i, j, m), igl);
+            if (am) put4(a, at++, m, pack3(i, j, l, a.p), igm);
+            if (ai) put4(a, at++, i, pack3(j, l, m, a.p), igi);
+            if (aj) put4(a, at++, j, pack3(i, l, m, a.p), igj);
+            if (al) put4(a, at++, l, pack3(i, j, m, a.p), igl);
             runi = fmaxf(runi, mi);
             runj = fmaxf(runj, mj);
             runl = fmaxf(runl, ml);

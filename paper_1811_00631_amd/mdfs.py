@@ -35,7 +35,7 @@ STATUS = {0: "MDFS_OK", -1: "MDFS_E_ARG", -2: "MDFS_E_Y", -3: "MDFS_E_K", -4: "M
           -5: "MDFS_E_NAN", -6: "MDFS_E_NOMEM", -7: "MDFS_E_HIP", -8: "MDFS_E_CANCELLED",
           -9: "MDFS_E_OVERFLOW", -10: "MDFS_E_LIMIT"}
 E_CANCELLED, E_OVERFLOW, E_LIMIT = -8, -9, -10
-ENGINES = {"auto": 0, "mfma": 1, "bitset": 2, "mfma_fp4": 3}
+ENGINES = {"auto": 0, "mfma": 1, "bitset": 2, "mfma_fp4": 3, "hist": 4}
 ADJUST = {"none": 0, "holm": 1, "BH": 2, "BY": 3}
 
 

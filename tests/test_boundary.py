@@ -52,7 +52,9 @@ def test_workspace_size_valid_and_monotone():
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(k=5), -3), (dict(k=0), -3), (dict(k=4, divisions=4), -10), (dict(k=4, engine="mfma"), -10), (dict(divisions=3), -4), (dict(divisions=0), -4),
+    (dict(k=6), -3), (dict(k=0), -3), (dict(k=4, divisions=4, engine="bitset"), -10), (dict(k=4, engine="mfma"), -10),
+    (dict(k=5, engine="bitset"), -10), (dict(k=5, n_var=513), -10), (dict(k=4, n_var=2049), -10),
+    (dict(k=3, engine="hist"), -10), (dict(divisions=3), -4), (dict(divisions=0), -4),
     (dict(n_obj=2, divisions=2), -1), (dict(n_obj=20000), -10), (dict(range_=1.5), -1),
     (dict(range_=-0.1), -1), (dict(pseudocount=-1.0), -1), (dict(n_disc=0), -1),
     (dict(disc_offset=-1), -1), (dict(n_var=1), -1), (dict(workgroups=4), -1), (dict(workgroups=5000), -1), (dict(k=3, engine="mfma_fp4", divisions=4), -10),
@@ -92,7 +94,7 @@ def test_small_workspace_rejected_on_host():
 def test_unknown_engine_rejected_on_host():
     lib = mdfs.load()
     prm = mdfs.make_params(100, 10, 2, 2, 1)
-    prm.engine = 4
+    prm.engine = 5
     null = ctypes.c_void_p(0)
     assert lib.mdfs_workspace_size(ctypes.byref(prm)) == 0
     assert lib.mdfs_max_ig(ctypes.byref(prm), null, null, null, null, null, null, 0, null) == -1

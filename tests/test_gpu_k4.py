@@ -1,5 +1,5 @@
-"""k = 4 sweep (bitset engine, two or three classes) on the GPU through the C ABI, against the
-FP64 oracle."""
+"""k = 4 and k = 5 sweeps on the GPU through the C ABI, against the FP64 oracle: the bitset engine
+(k = 4, two or three classes) and the per-tuple histogram engine (k = 4 and 5, any class count)."""
 import dataclasses
 
 import numpy as np
@@ -14,9 +14,9 @@ from test_gpu_k2 import assert_ig_parity, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def run4(mdfs, w, n_disc=None, divisions=None, disc_offset=0, engine="auto"):
+def run4(mdfs, w, n_disc=None, divisions=None, disc_offset=0, engine="auto", k=4):
     data, y = to_dev(w)
-    out = mdfs.mdfs_max_ig(data, y, 4, w.divisions if divisions is None else divisions,
+    out = mdfs.mdfs_max_ig(data, y, k, w.divisions if divisions is None else divisions,
                            w.n_disc if n_disc is None else n_disc, w.xi, w.range_, w.seed, disc_offset,
                            engine=engine)
     torch.cuda.synchronize()
@@ -71,8 +71,8 @@ def test_k4_limits(mdfs_gpu):
     import ctypes
     lib = mdfs_gpu.load()
     null = ctypes.c_void_p(0)
-    for kw, code in ((dict(divisions=4), -10), (dict(engine="mfma"), -10), (dict(engine="mfma_fp4"), -10),
-                     (dict(n_var=1025), -10)):
+    for kw, code in ((dict(divisions=4, engine="bitset"), -10), (dict(engine="mfma"), -10),
+                     (dict(engine="mfma_fp4"), -10), (dict(n_var=2049), -10)):
         base = dict(n_obj=100, n_var=8, k=4, divisions=2, n_disc=1)
         base.update(kw)
         prm = mdfs_gpu.make_params(**base)
@@ -83,3 +83,69 @@ def test_k4_limits(mdfs_gpu):
     with pytest.raises(mdfs_gpu.MdfsError) as e:
         mdfs_gpu.mdfs_interesting_tuples(data, y, 4, 2, 1, 0.0)
     assert e.value.code == -3
+
+
+# ------------------------------------------------------------------ the histogram engine (k = 4, 5)
+CASES_H = {
+    # k, workload
+    "k4_d5": (4, lambda: dataclasses.replace(workloads.xor_small(seed=71, n_obj=500, n_var=17, n_disc=2), divisions=4)),
+    "k4_d5_imbalanced": (4, lambda: dataclasses.replace(workloads.null_data(72, 333, 15, ones=70), divisions=4,
+                                                        n_disc=2)),
+    "k5_d2": (5, lambda: dataclasses.replace(workloads.xor_small(seed=73, n_obj=600, n_var=16, n_disc=2), divisions=1)),
+    "k5_d3": (5, lambda: workloads.xor_small(seed=74, n_obj=450, n_var=13, n_disc=2)),
+    "k5_d5": (5, lambda: dataclasses.replace(workloads.null_data(75, 700, 9, ones=300), divisions=4, n_disc=1)),
+    "k5_five_vars": (5, lambda: workloads.xor_small(seed=76, n_obj=120, n_var=5, n_disc=3)),
+    "k5_tiny_n": (5, lambda: dataclasses.replace(workloads.xor_small(seed=77, n_obj=9, n_var=8, n_disc=2), divisions=1)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES_H))
+def test_hist_engine_matches_oracle(mdfs_gpu, name):
+    k, make = CASES_H[name]
+    w = make()
+    print(f"hist {name} k={k} N={w.n_obj} p={w.n_var} d={w.divisions + 1} R={w.n_disc}", flush=True)
+    got = run4(mdfs_gpu, w, k=k)
+    ref = oracle.max_ig_all(w.data, w.y, k, w.divisions, w.n_disc, w.range_, w.xi, w.seed, n_threads=8)
+    assert_ig_parity(*got, ref, name)
+
+
+@pytest.mark.parametrize("divisions", [1, 2])
+def test_hist_engine_equals_bitset_engine_k4(mdfs_gpu, divisions):
+    # two count engines of k = 4: identical outputs (the re-scored maxima do not depend on how the
+    # counts were obtained)
+    w = dataclasses.replace(workloads.xor_small(seed=78, n_obj=800, n_var=30, n_disc=2), divisions=divisions)
+    print(f"hist vs bitset k=4 d={divisions + 1}", flush=True)
+    a = run4(mdfs_gpu, w, engine="bitset")
+    b = run4(mdfs_gpu, w, engine="hist")
+    for x, z in zip(a, b):
+        assert np.array_equal(x, z)
+
+
+def test_hist_engine_finds_a_planted_parity_quintuple(mdfs_gpu):
+    # y = xor of the signs of x0..x4: invisible to every quadruple, found by the k = 5 sweep
+    g = np.random.default_rng(79)
+    n, p = 2000, 14
+    X = g.standard_normal((p, n)).astype(np.float32)
+    y = ((X[0] > 0) ^ (X[1] > 0) ^ (X[2] > 0) ^ (X[3] > 0) ^ (X[4] > 0)).astype(np.uint8)
+    w = workloads.Workload("parity5", X, y, 5, 1, 1, 0.0, 0.25, 3, {})
+    print("k5 planted", flush=True)
+    ig, am, ad = run4(mdfs_gpu, w, k=5, divisions=1)
+    assert set(np.argsort(-ig)[:5].tolist()) == {0, 1, 2, 3, 4}
+    assert am[0].tolist() == [1, 2, 3, 4]
+    assert ig[:5].min() > 10 * np.median(ig[5:])
+
+
+def test_hist_engine_collect_pass_and_async(mdfs_gpu, monkeypatch):
+    w = dataclasses.replace(workloads.xor_small(seed=80, n_obj=300, n_var=12, n_disc=2), divisions=4)
+    monkeypatch.setenv("MDFS_TEST_CAP", str(3 * w.n_var))
+    print("hist collect pass", flush=True)
+    got = run4(mdfs_gpu, w)
+    monkeypatch.delenv("MDFS_TEST_CAP")
+    ref = oracle.max_ig_all(w.data, w.y, 4, w.divisions, w.n_disc, w.range_, w.xi, w.seed, n_threads=8)
+    assert_ig_parity(*got, ref, "hist collect pass")
+    data, y = to_dev(w)
+    a = mdfs_gpu.mdfs_max_ig_async(data, y, int(w.y.sum()), 5, 4, 2, w.xi, w.range_, w.seed)
+    mdfs_gpu.mdfs_check_status((w.n_var, w.n_obj), 5, 4, 2)
+    b = mdfs_gpu.mdfs_max_ig(data, y, 5, 4, 2, w.xi, w.range_, w.seed)
+    for x, z in zip(a, b):
+        assert torch.equal(x, z)
