@@ -81,7 +81,7 @@ WORKLOAD_TEXT = {
     "madelon4": "Madelon-shaped k=4: N=2000, p=500 (5 base + 15 combinations + 480 noise), d=2, 1 discretisation "
                 "(the shape of the paper's 4D timing)",
     "madelon5": "Madelon-shaped k=5: N=2000, p=500 (5 base + 15 combinations + 480 noise), d=2, 1 discretisation "
-                "(the shape of the paper's 5D timing), histogram engine",
+                "(the shape of the paper's 5D timing)",
     "madelon4_d5": "Madelon-shaped k=4 with five classes: N=2000, p=200 (5 base + 15 combinations + 180 noise), "
                    "1 discretisation, histogram engine",
     "madelon2_d2": "Madelon-shaped k=2: N=2000, p=500, d=2, 30 discretisations (the shape of the paper's 2D timing)",
@@ -325,22 +325,24 @@ def main():
     k, div, R = w.k, w.divisions, w.n_disc
     tuples = math.comb(w.n_var, k) * R
 
-    workgroups, tuned = 0, None
+    workgroups, tile, tuned = 0, 0, None
     if args.autotune:
         from paper_1811_00631_amd import autotune
         tuned = autotune.Tuner(os.path.join(ROOT, "gpurun_out", "autotune.json")).best(w.n_obj, w.n_var, k, div, R)
-        args.engine, workgroups = tuned["engine"], tuned["workgroups"]
-        print(f"# autotune: {tuned['engine']} x {workgroups} workgroups", file=sys.stderr, flush=True)
+        args.engine, workgroups, tile = tuned["engine"], tuned["workgroups"], tuned.get("tile", 0)
+        print(f"# autotune: {tuned['engine']} x {workgroups} workgroups, tile 0x{tile:x}", file=sys.stderr,
+              flush=True)
 
     def step():
         return mdfs.mdfs_max_ig(data, y, k, div, R, w.xi, w.range_, w.seed, engine=args.engine, timing=True,
-                                workgroups=workgroups)
+                                workgroups=workgroups, tile=tile)
 
     graph = None
     if args.graph:
         # one asynchronous call captured once; a step is one replay (inputs stay in HBM)
         n1 = int(w.y.sum())
-        prm = mdfs.make_params(w.n_obj, w.n_var, k, div, R, 0, w.range_, w.xi, w.seed, args.engine, 0, workgroups)
+        prm = mdfs.make_params(w.n_obj, w.n_var, k, div, R, 0, w.range_, w.xi, w.seed, args.engine, 0, workgroups,
+                               tile=tile)
         gws = torch.empty(mdfs.mdfs_workspace_size(prm), dtype=torch.uint8, device=dev)
         gout = (torch.empty(w.n_var, dtype=torch.float32, device=dev),
                 torch.empty((w.n_var, k - 1), dtype=torch.int32, device=dev),
@@ -349,13 +351,13 @@ def main():
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
             mdfs.mdfs_max_ig_async(data, y, n1, k, div, R, w.xi, w.range_, w.seed, engine=args.engine,
-                                   workgroups=workgroups, ws=gws, out=gout)
+                                   workgroups=workgroups, ws=gws, out=gout, tile=tile)
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             mdfs.mdfs_max_ig_async(data, y, n1, k, div, R, w.xi, w.range_, w.seed, engine=args.engine,
-                                   workgroups=workgroups, ws=gws, out=gout)
+                                   workgroups=workgroups, ws=gws, out=gout, tile=tile)
         ref = step()
 
         def step():   # noqa: F811
@@ -385,7 +387,7 @@ def main():
             raise RuntimeError("graph replay differs from the synchronous call")
         # phase times come from the synchronous call (same kernels)
         step_sync = lambda: mdfs.mdfs_max_ig(data, y, k, div, R, w.xi, w.range_, w.seed, engine=args.engine,  # noqa: E731
-                                             timing=True, workgroups=workgroups)
+                                             timing=True, workgroups=workgroups, tile=tile)
         step_sync()
         phases.append(mdfs.mdfs_phase_times())
 
@@ -441,7 +443,7 @@ def main():
                 "kernel": (f"k_sweep2<{W}, max, {'fp4' if fp4 else 'int8'}>" if k == 2
                            else f"k_sweep3m{'1' if W == 1 else ''} (+ pair data)"),
                 "units_per_launch": tuples, "kernel_ms": sweep_ms}
-    elif k == 5 or (k == 4 and (div == 4 or args.engine == "hist")):
+    elif k >= 4 and (args.engine == "hist" or C > (3 if k == 4 else 2)):
         # per-tuple histogram: N voxel increments (one LDS add each, the algorithmic work), then
         # C^k + k C^(k-1) voxel terms of the float32 screen
         ops_per_unit = 2 * w.n_obj
@@ -449,6 +451,16 @@ def main():
         roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "Tops/s (32-bit integer VALU)",
                 "frac": achieved / ALU_PEAK_TOPS, "traffic": None, "kernel": f"k_sweep_hist<{C}, {k}>",
                 "per_unit": f"2*N = {ops_per_unit} ops per tuple table (N voxel increments)",
+                "units_per_launch": tuples, "kernel_ms": sweep_ms}
+    elif k >= 4 and C == 2:
+        # two classes: AND + popcount-accumulate per (subset holding m or n, 32-object word), the
+        # 3 * 2^(k-2) per-lane subset counts of the prefix-wave / pair-lane engine
+        words = (int((w.y == 0).sum()) + 31) // 32 + (int((w.y == 1).sum()) + 31) // 32
+        ops_per_unit = 2 * 3 * 2 ** (k - 2) * words
+        achieved = tuples * ops_per_unit / (sweep_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "Tops/s (32-bit integer VALU)",
+                "frac": achieved / ALU_PEAK_TOPS, "traffic": None, "kernel": f"k_sweep45<{k}>",
+                "per_unit": f"2*3*2^(k-2)*words = {ops_per_unit} VALU lane-ops per {k}-tuple",
                 "units_per_launch": tuples, "kernel_ms": sweep_ms}
     elif k == 4:
         # AND + popcount-accumulate per (cell, 32-object word), every one of the C^4 cells counted
@@ -493,13 +505,15 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "fp4 (E2M1 one-hot), f32 accumulate" if fp4 else ("i8" if k == 2 else (
-            "u8 codes, u32 histograms" if (k == 5 or (k == 4 and (div == 4 or args.engine == "hist")))
+            "u8 codes, u32 histograms" if "hist" in roof["kernel"]
             else "u32 bitsets")),
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "k": k, "n_obj": w.n_obj, "n_var": w.n_var, "classes": div + 1, "n_disc": R,
                    "tuples_per_step": tuples,
                    "engine": args.engine, "workgroups": workgroups or "whole GPU",
+                   "tile": ({"supertile": (tile & 0xff) or 8, "waves": ((tile >> 8) & 0xf) or (8 if div == 2 else 4)}
+                            if k == 2 else None),
                    "autotuned": bool(tuned), "graph_replay": bool(args.graph),
                    "counts": ("fp4 MFMA, exact f32 accumulate" if fp4 else "int8 MFMA, int32 accumulate")
                    if (k == 2 or k3_mfma) else ("per-tuple LDS histograms" if k >= 4 and "hist" in roof["kernel"]

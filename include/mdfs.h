@@ -64,15 +64,18 @@ typedef enum {
     MDFS_ENGINE_AUTO = 0,     /* k=2: fp4 MFMA if both classes < 4096 objects, else int8 MFMA;
                                  k=3: fp4 MFMA for 2 or 3 classes under the same condition, else
                                  bitset; k=4: bitset for 2 or 3 classes, else histogram; k=5:
-                                 histogram */
+                                 bitset for 2 classes, else histogram */
     MDFS_ENGINE_MFMA = 1,     /* one-hot int8 contraction on the matrix cores */
-    MDFS_ENGINE_BITSET = 2,   /* per-class bitsets, AND + popcount */
+    MDFS_ENGINE_BITSET = 2,   /* per-class bitsets, AND + popcount; k=3, k=4 with 2 or 3 classes,
+                                 k=5 with 2 classes (there every cell follows from the counts of
+                                 the objects in the first bin of each subset of the tuple, by
+                                 inclusion-exclusion) */
     MDFS_ENGINE_MFMA_FP4 = 3, /* one-hot E2M1 (fp4) contraction, float32 accumulation (exact
                                  integers); k=2, or k=3 with divisions 1 or 2; each class < 4096
                                  objects, else MDFS_E_LIMIT */
     MDFS_ENGINE_HIST = 4      /* per-tuple histogram of the class-sorted codes, every cell counted
-                                 directly; k = 4 or 5, any class count ("auto" for k = 5 and for
-                                 k = 4 with five classes) */
+                                 directly; k = 4 or 5, any class count ("auto" for k = 5 with 3
+                                 or 5 classes and for k = 4 with five classes) */
 } mdfs_engine;
 
 /* Problem description.  Fields follow the arguments of ComputeMaxInfoGains
@@ -93,7 +96,11 @@ typedef struct {
     int32_t workgroups;  /* workgroups of the persistent sweep kernels: 0 = the whole GPU, else
                             8..4096; smaller grids let concurrent calls on other streams share
                             the GPU (results do not depend on it) */
-    int32_t reserved;    /* must be 0 */
+    int32_t tile;        /* launch shape of the pair sweep, 0 = default (results do not depend on
+                            it; the autotuner picks it): bits 0-7 the super-tile side in tiles
+                            (2, 4, 8 or 16: the tiles whose operand panels share an XCD's L2),
+                            bits 8-11 the waves per workgroup with three classes (4 or 8);
+                            other bits must be 0 */
     const volatile uint32_t *cancel;
                          /* nullable: a caller-owned word in host-mapped memory (hipHostMalloc);
                             while it reads non-zero, the persistent sweep kernels stop taking work
@@ -178,13 +185,14 @@ int mdfs_max_ig_noalloc(const mdfs_params *prm, const float *data, const uint8_t
 /* Several k = 2 problems (datasets of uneven N and p, their own discretisation counts) in one
  * asynchronous call whose maximum pass is ONE persistent launch over the concatenated tiles of all
  * problems, so small problems share the GPU instead of leaving it idle between launches.
- *   n               : 1 <= n <= 12 problems; all with k = 2, the same divisions and the same
- *                     encoding (every class < 4096 objects for fp4, or engine mfma for int8)
+ *   n               : 1 <= n <= 12 problems; all with k = 2, the same divisions, the same
+ *                     encoding (every class < 4096 objects for fp4, or engine mfma for int8) and
+ *                     the same super-tile side (tile bits 0-7; the wave bits are not used here)
  *   prm[i], data[i], y[i], n1[i], ig_max[i], argmax[i], argmax_disc[i], ws[i], ws_bytes[i]:
  *                     problem i, as for mdfs_max_ig_async (its own workspace)
  *   batch_ws        : device memory of mdfs_batch_workspace_size() bytes (the work counters)
  * Per-problem status: mdfs_check_status(&prm[i], ws[i], ...).  Returns MDFS_E_LIMIT for mixed
- * divisions or encodings; other argument errors as mdfs_max_ig_async, before anything is
+ * divisions, encodings or super-tiles; other argument errors as mdfs_max_ig_async, before anything is
  * enqueued.  Enqueued on `stream` with no host synchronisation (capturable). */
 size_t mdfs_batch_workspace_size(void);
 int mdfs_max_ig_batch(int n, const mdfs_params *prm, const float *const *data, const uint8_t *const *y,

@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "libmdfs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["prep.hip", "sweep2.hip", "sweep3.hip", "sweep3m.hip", "sweep4.hip", "sweep_hist.hip", "finalize.hip",
+SOURCES = ["prep.hip", "sweep2.hip", "sweep3.hip", "sweep3m.hip", "sweep4.hip", "sweep45.hip", "sweep_hist.hip",
+           "finalize.hip",
            "contrast.hip", "api.hip", "stats.cpp"]
 
 # Packed fp32 instructions are disabled for every device pass (hipcc's host pass warns that it

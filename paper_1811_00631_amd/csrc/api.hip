@@ -101,8 +101,9 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
     if (sweep && prm->k == 4 && prm->engine != MDFS_ENGINE_AUTO && prm->engine != MDFS_ENGINE_HIST &&
         !(prm->engine == MDFS_ENGINE_BITSET && prm->divisions <= 2))
         return fail(MDFS_E_LIMIT, "k=4 runs on the bitset engine (2 or 3 classes) or the histogram engine");
-    if (sweep && prm->k == 5 && prm->engine != MDFS_ENGINE_AUTO && prm->engine != MDFS_ENGINE_HIST)
-        return fail(MDFS_E_LIMIT, "k=5 runs on the histogram engine");
+    if (sweep && prm->k == 5 && prm->engine != MDFS_ENGINE_AUTO && prm->engine != MDFS_ENGINE_HIST &&
+        !(prm->engine == MDFS_ENGINE_BITSET && prm->divisions == 1))
+        return fail(MDFS_E_LIMIT, "k=5 runs on the bitset engine (2 classes) or the histogram engine");
     if (sweep && prm->k <= 3 && prm->engine == MDFS_ENGINE_HIST)
         return fail(MDFS_E_LIMIT, "the histogram engine is built for k = 4 and 5");
     if (sweep && prm->k == 3 && prm->engine == MDFS_ENGINE_MFMA)
@@ -119,7 +120,13 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
     if (prm->engine < 0 || prm->engine > 4) return fail(MDFS_E_ARG, "engine=%d", prm->engine);
     if (prm->workgroups != 0 && (prm->workgroups < 8 || prm->workgroups > 4096))
         return fail(MDFS_E_ARG, "workgroups=%d: 0 (whole GPU) or 8..4096", prm->workgroups);
-    if (prm->reserved != 0) return fail(MDFS_E_ARG, "reserved field must be 0");
+    {
+        const int sb = prm->tile & 0xff, nw = (prm->tile >> 8) & 0xf;
+        if ((prm->tile & ~0xfff) || !(sb == 0 || sb == 2 || sb == 4 || sb == 8 || sb == 16) ||
+            !(nw == 0 || nw == 4 || nw == 8))
+            return fail(MDFS_E_ARG, "tile=0x%x: super-tile 2, 4, 8 or 16 (bits 0-7), waves 4 or 8 (bits 8-11)",
+                        prm->tile);
+    }
     return MDFS_OK;
 }
 
@@ -167,6 +174,8 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
     }
     P.disc_offset = prm->disc_offset;
     P.workgroups = prm->workgroups;
+    P.supertile = prm->tile & 0xff;
+    P.sweep_waves = (prm->tile >> 8) & 0xf;
     P.cancel = const_cast<const uint32_t *>(prm->cancel);
     P.range = prm->range;
     P.seed = prm->seed;
@@ -220,9 +229,13 @@ static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_b
             const int V = prm->k == 4 ? C * C * C * C : C * C * C * C * C;
             P.err_bound = screen_err_bound(N, P.beta0, P.beta1, V) + screen_err_bound(N, P.beta0, P.beta1, V / C);
         }
-        // k >= 4 engine: bitsets for k = 4 with two or three classes unless the histogram engine
-        // is asked for; the histogram engine otherwise
-        P.hist = prm->k == 5 || (prm->k == 4 && (C == 5 || prm->engine == MDFS_ENGINE_HIST));
+        // k >= 4 engine: bitsets for k = 4 with two or three classes and for k = 5 with two,
+        // unless the histogram engine is asked for; the histogram engine otherwise
+        P.hist = prm->k >= 4 && (C > (prm->k == 4 ? 3 : 2) || prm->engine == MDFS_ENGINE_HIST);
+        P.sweep45 = prm->k >= 4 && !P.hist && C == 2;
+        if (P.sweep45 && sweep45_lds_bytes(P) > LDS_MAX)
+            return fail(MDFS_E_LIMIT, "k=%d bitset sweep: LDS tables and prefix words need %zu bytes > %zu", prm->k,
+                        sweep45_lds_bytes(P), LDS_MAX);
         if (P.hist && sweep_hist_lds_bytes(P) > LDS_MAX)
             return fail(MDFS_E_LIMIT, "histogram engine: LDS tables and histograms need %zu bytes > %zu",
                         sweep_hist_lds_bytes(P), LDS_MAX);
@@ -273,17 +286,21 @@ static int sweep_pass(const Problem &P, int32_t *counts, int disc_sel, bool coll
     } else if (P.L.k >= 4) {
         for (int r = 0; r < P.L.R; ++r) {
             if (P.hist) LAUNCH(launch_sweep_hist(P, r, collect));
+            else if (P.sweep45) LAUNCH(launch_sweep45(P, r, collect));
             else LAUNCH(launch_sweep4(P, r, collect));
         }
     } else {
-        for (int r = 0; r < P.L.R; ++r) {
-            int32_t *cr = (counts && r == disc_sel) ? counts : nullptr;
+        // per chunk of up to RC discretisations: one launch of the pair sweep for all their pair
+        // data, one of the triple sweep over all their tiles
+        for (int r0 = 0; r0 < P.L.R; r0 += P.L.RC) {
+            const int nr = P.L.R - r0 < P.L.RC ? P.L.R - r0 : P.L.RC;
+            int32_t *cr = (counts && disc_sel >= r0 && disc_sel < r0 + nr) ? counts : nullptr;
             LAUNCH(launch_reset_queue(P));
-            LAUNCH(launch_pairs(P, r, collect));
-            if (P.k3_mfma) LAUNCH(launch_sweep3m(P, r, collect, cr, i_sel));
-            else LAUNCH(launch_sweep3(P, r, collect, cr, i_sel));
-            // before the next discretisation's pair data replace this one's
-            if (cr) LAUNCH(launch_complete_triples(P, cr, r, i_sel));
+            LAUNCH(launch_pairs(P, r0, nr, collect));
+            if (P.k3_mfma) LAUNCH(launch_sweep3m(P, r0, nr, collect, cr, i_sel, disc_sel));
+            else LAUNCH(launch_sweep3(P, r0, nr, collect, cr, i_sel, disc_sel));
+            // before the next chunk's pair data replace this one's
+            if (cr) LAUNCH(launch_complete_triples(P, cr, disc_sel, r0, i_sel));
         }
     }
     return MDFS_OK;
@@ -530,6 +547,8 @@ extern "C" int mdfs_max_ig_batch(int n, const mdfs_params *prm, const float *con
         if (rc) return rc;
         if (prm[i].k != 2) return fail(MDFS_E_K, "problem %d: batches are built for k=2", i);
         if (prm[i].divisions != prm[0].divisions) return fail(MDFS_E_LIMIT, "problem %d: one divisions per batch", i);
+        if ((prm[i].tile & 0xff) != (prm[0].tile & 0xff))
+            return fail(MDFS_E_LIMIT, "problem %d: one super-tile side per batch (the shared queue's unit)", i);
         if (prm[i].flags & MDFS_FLAG_TIMING) return fail(MDFS_E_ARG, "timing is not available in a batch");
         if (!data[i] || !y[i] || !ig_max[i] || !ws[i]) return fail(MDFS_E_ARG, "problem %d: null pointer", i);
         if (n1[i] < 1 || n1[i] >= prm[i].n_obj)

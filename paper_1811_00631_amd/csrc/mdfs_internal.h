@@ -67,6 +67,7 @@ struct Layout {
     int64_t N, p, p_pad;
     int k, C, W;          // classes C = divisions+1, one-hot width W = C-1
     int R;
+    int RC;               // k = 3: discretisations whose pair data are held at once (one launch pair)
     int64_t Kpad_max;     // class-sorted positions reserved: worst-case padding of either encoding
     int64_t rows_pad;     // p_pad * W
     int64_t cap;          // candidate capacity
@@ -77,6 +78,8 @@ struct Layout {
 };
 
 Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R);
+// per-class bitsets are built for k = 3, k = 4 and, with two classes, k = 5
+inline bool uses_bits(const Layout &L) { return L.k == 3 || L.k == 4 || (L.k == 5 && L.C == 2); }
 
 // Byte offset of (discretisation r, one-hot row, K block kb, byte) in the panel-major one-hot
 // encoding [r][row / TILE_ROWS][kb][row % TILE_ROWS][KBLK]: the rows of one sweep panel are
@@ -195,8 +198,11 @@ struct Problem {
     uint64_t seed;
     double err_bound;             // float32 screen error bound E (per IG)
     bool k3_mfma;                 // k = 3 on the matrix cores (else bitsets)
-    bool hist;                    // k >= 4 on the per-tuple histogram engine (else bitsets, k = 4)
+    bool hist;                    // k >= 4 on the per-tuple histogram engine (else bitsets)
+    bool sweep45;                 // k >= 4 on bitsets with two classes (prefix waves, pair lanes)
     int workgroups;               // persistent sweep grid (0 = the whole GPU)
+    int supertile;                // pair sweep: super-tile side in tiles (0 = default)
+    int sweep_waves;              // pair sweep, three classes: waves per workgroup (0 = default)
     int64_t n_ablk3, n_tiles3;    // tile list of the k = 3 matrix-core sweep
     const uint8_t *codes_in = nullptr;   // caller-supplied codes [R][p][N] replace the discretisation
     const uint32_t *cancel = nullptr;    // caller's host-mapped cancel word (nullable)
@@ -224,7 +230,8 @@ constexpr size_t LDS_MAX = 160 * 1024;
 hipError_t launch_reset_candidates(const Problem &P, bool gated = false);
 // Status::collect_go = force ? 1 : (a candidate append overflowed)
 hipError_t launch_collect_decide(const Problem &P, bool force);
-hipError_t launch_pairs(const Problem &P, int r, bool gated = false);
+// pair data (W x W counts and float32 F of every pair) of discretisations r0 .. r0 + nr - 1
+hipError_t launch_pairs(const Problem &P, int r0, int nr, bool gated = false);
 // The maximum pass of several k = 2 problems in one persistent launch (same d and encoding);
 // `queue` holds the batch's work counters (a Status in device memory).
 hipError_t launch_sweep2_batch(const Problem *const *Ps, int n, Status *queue);
@@ -232,17 +239,25 @@ hipError_t launch_sweep2_batch(const Problem *const *Ps, int n, Status *queue);
 int sweep2_fp4_capacity(const Problem &P);
 // k = 3 sweeps of discretisation r; counts_out != nullptr: also the count export of the triples
 // (i_sel, j, l), directly counted cells only (launch_complete_triples fills in the others)
-hipError_t launch_sweep3(const Problem &P, int r, bool collect, int32_t *counts_out = nullptr, int i_sel = -1);
-hipError_t launch_complete_triples(const Problem &P, int32_t *counts, int r, int i_sel);
-// k = 4 bitset sweep of discretisation r (sweep4.hip)
+hipError_t launch_sweep3(const Problem &P, int r0, int nr, bool collect, int32_t *counts_out = nullptr,
+                         int i_sel = -1, int disc_sel = -1);
+// cells of the dropped last bins of the exported triples, from the pair data of discretisation
+// r (held in the chunk that starts at r0)
+hipError_t launch_complete_triples(const Problem &P, int32_t *counts, int r, int r0, int i_sel);
+// k = 4 bitset sweep of discretisation r, three classes (sweep4.hip)
 hipError_t launch_sweep4(const Problem &P, int r, bool collect);
+// k = 4 or 5 bitset sweep of discretisation r, two classes (sweep45.hip)
+hipError_t launch_sweep45(const Problem &P, int r, bool collect);
+// LDS bytes per workgroup of that sweep (tables and the waves' prefix words)
+size_t sweep45_lds_bytes(const Problem &P);
 // k = 4 or 5 per-tuple histogram sweep of discretisation r, any class count (sweep_hist.hip)
 hipError_t launch_sweep_hist(const Problem &P, int r, bool collect);
 // binary64 re-score of k >= 4 candidates from the class-sorted codes (sweep_hist.hip)
 hipError_t launch_rescore_hist(const Problem &P);
 // LDS bytes per workgroup of the histogram sweep (0 = not built for these sizes)
 size_t sweep_hist_lds_bytes(const Problem &P);
-hipError_t launch_sweep3m(const Problem &P, int r, bool collect, int32_t *counts_out = nullptr, int i_sel = -1);
+hipError_t launch_sweep3m(const Problem &P, int r0, int nr, bool collect, int32_t *counts_out = nullptr,
+                          int i_sel = -1, int disc_sel = -1);
 size_t sweep3m_lds_bytes(const Problem &P);
 // tile list of the k = 3 matrix-core sweep: its size on the host, the list itself on the device
 void sweep3m_tile_counts(int64_t p, int W, int64_t &n_ablk, int64_t &n_tiles);

@@ -9,6 +9,8 @@
 // discretisation is reproducible bit for bit.
 #include "mdfs_internal.h"
 
+#include <algorithm>
+
 #include <math.h>
 
 namespace mdfs {
@@ -49,15 +51,19 @@ Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
     L.cand = take(sizeof(Cand) * L.cap);
     L.ig64 = take(sizeof(double) * L.cap);
     if (k >= 4) {
-        // bitsets (the k = 4 bitset sweep counts every cell directly) and class-sorted codes
-        // [R][p][N] (the histogram sweep and the binary64 re-score of k >= 4)
-        L.bits = take(k == 4 ? sizeof(uint32_t) * (size_t)R * 2 * L.words_max * L.p_pad * L.W : 0);
+        // bitsets (the bitset sweeps of k = 4 and of k = 5 with two classes) and class-sorted
+        // codes [R][p][N] (the histogram sweep and the binary64 re-score of k >= 4)
+        L.bits = take(uses_bits(L) ? sizeof(uint32_t) * (size_t)R * 2 * L.words_max * L.p_pad * L.W : 0);
         L.ccodes = take((size_t)R * p * N);
         L.ptab = L.F2 = L.a3pref = L.a3blk = o;
     } else if (k == 3) {
         L.bits = take(sizeof(uint32_t) * (size_t)R * 2 * L.words_max * L.p_pad * L.W);
-        L.ptab = take(sizeof(uint32_t) * (size_t)L.p_pad * L.p_pad * L.W * L.W);
-        L.F2 = take(sizeof(float) * (size_t)L.p_pad * L.p_pad);
+        // the pair data of up to RC discretisations (at most 512 MiB, at least one): one launch of
+        // the pair sweep and one of the triple sweep per chunk of discretisations
+        const size_t per_r = (size_t)L.p_pad * L.p_pad * (sizeof(uint32_t) * L.W * L.W + sizeof(float));
+        L.RC = (int)std::min<size_t>((size_t)R, std::max<size_t>(1, (size_t(512) << 20) / per_r));
+        L.ptab = take(sizeof(uint32_t) * (size_t)L.RC * L.p_pad * L.p_pad * L.W * L.W);
+        L.F2 = take(sizeof(float) * (size_t)L.RC * L.p_pad * L.p_pad);
         const int64_t n_ablk_max = L.p_pad * ((L.p_pad + 31) / 32);
         L.a3pref = take(sizeof(int64_t) * (size_t)(n_ablk_max + 1));
         L.a3blk = take(sizeof(int32_t) * (size_t)n_ablk_max);
@@ -545,7 +551,7 @@ static hipError_t disc_launch(const Problem &P, const float *data, uint8_t *code
                        (encode && (L.k == 2 || L.k == 3)) ? P.at<int8_t>(L.onehot) : nullptr,
                        encode ? P.at<uint32_t>(L.marg) : nullptr, encode ? P.at<float>(L.F1) : nullptr,
                        (encode && L.k == 1) ? P.at<double>(L.F1d) : nullptr, L.p_pad, P.beta0, P.beta1, P.at<Status>(L.status),
-                       (encode && (L.k == 3 || L.k == 4)) ? P.at<uint32_t>(L.bits) : nullptr, L.words_max,
+                       (encode && uses_bits(L)) ? P.at<uint32_t>(L.bits) : nullptr, L.words_max,
                        (encode && L.k >= 4) ? P.at<uint8_t>(L.ccodes) : nullptr);
     return hipGetLastError();
 }
@@ -683,7 +689,7 @@ static hipError_t encode_codes_launch(const Problem &P)
                        (int)L.N, (int)L.p, L.R, P.at<int32_t>(L.perm), P.K0pad, P.N0, P.N1, P.KB, P.Kpad,
                        P.fp4 ? 1 : 0, L.rows_pad, (L.k == 2 || L.k == 3) ? P.at<int8_t>(L.onehot) : nullptr,
                        P.at<uint32_t>(L.marg), P.at<float>(L.F1), L.k == 1 ? P.at<double>(L.F1d) : nullptr, L.p_pad,
-                       P.beta0, P.beta1, P.at<Status>(L.status), (L.k == 3 || L.k == 4) ? P.at<uint32_t>(L.bits) : nullptr,
+                       P.beta0, P.beta1, P.at<Status>(L.status), uses_bits(L) ? P.at<uint32_t>(L.bits) : nullptr,
                        L.words_max, L.k >= 4 ? P.at<uint8_t>(L.ccodes) : nullptr);
     return hipGetLastError();
 }

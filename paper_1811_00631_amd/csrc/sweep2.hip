@@ -46,10 +46,11 @@ __host__ __device__ constexpr int stage_base(int ENC) { return ENC ? 24 * ENC : 
 // Waves per workgroup: 8 for three classes (2 x 4 wave grid, 64 x 32 outputs per wave; at most
 // 128 VGPRs, so 4 waves per SIMD), else 4 (2 x 2 grid, 64 x 64 outputs per wave, 2 per SIMD; the
 // two- and five-class epilogues hold more per lane).  The tile and its LDS are the same.
+// Three classes may also run 4 waves (2 x 2 grid, 64 x 64 outputs per wave), a tuning choice.
 __host__ __device__ constexpr int sw_waves(int W) { return W == 2 ? 8 : 4; }
-constexpr int SB = 8;                    // a super-tile is SB x SB tiles
+constexpr int SB_DEFAULT = 8;            // a super-tile is sb x sb tiles (sb 2 .. 16, a tuning choice)
 constexpr int XCDS = 8;                  // workgroup b runs on XCD b % 8
-constexpr int WG_PER_XCD = SB * SB;      // resident workgroups per XCD (2 per CU: LDS)
+constexpr int WG_PER_XCD = 64;           // resident workgroups per XCD (2 per CU: LDS)
 constexpr int STAGE_BYTES = 2 * TILE_ROWS * KBLK;   // A and B tiles of one K block
 constexpr int NSTAGE = 3;                           // LDS ring of K blocks
 
@@ -64,7 +65,8 @@ struct Sweep2Args {
     int64_t p_pad, rows_pad;
     int R, KB, KB0;
     int nbv;                 // variable blocks of TV = TILE_ROWS / W variables
-    int nsb;                 // super-blocks of SB variable blocks
+    int sb;                  // super-tile side in tiles
+    int nsb;                 // super-blocks of sb variable blocks
     int64_t super_per_r, n_super;
     uint32_t *G32;
     Cand *cand;
@@ -78,8 +80,8 @@ struct Sweep2Args {
     int gated;               // run only if Status::collect_go is set (the collect pass)
     int r_base;              // first discretisation of this launch
     int snext_off;           // LDS byte offset of the work-item broadcast slot
-    uint32_t *ptab;          // pair mode: packed (W x W) counts [p_pad][p_pad][W*W]
-    float *F2out;            // pair mode: float32 F of each pair table [p_pad][p_pad]
+    uint32_t *ptab;          // pair mode: packed (W x W) counts [r - r_base][p_pad][p_pad][W*W]
+    float *F2out;            // pair mode: float32 F of each pair table [r - r_base][p_pad][p_pad]
     const uint32_t *cancel;  // caller's cancel word (nullable)
 };
 
@@ -160,7 +162,7 @@ __device__ inline void tri_index(int64_t tt, int &bi, int &bj)
     bi = (int)(tt - j * (j + 1) / 2);
 }
 
-template <int W, int MODE, int ENC, bool BATCH, bool EXPORT = false>
+template <int W, int MODE, int ENC, bool BATCH, bool EXPORT = false, int NWV = sw_waves(W)>
 __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 {
     constexpr bool F4 = ENC != 0;
@@ -169,7 +171,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     typedef typename AccOf<F4>::type Acc;
     constexpr int TV = TILE_ROWS / W;    // variables per tile side
     constexpr int NP = (W == 1) ? 4 : 1; // pairs held per lane per 16x16 block
-    constexpr int NWAVE = sw_waves(W), NT = NWAVE * 64;
+    constexpr int NWAVE = NWV, NT = NWAVE * 64;
     constexpr int NN = 16 / NWAVE;       // 16 x 16 column blocks per wave (row blocks: 4)
     constexpr int LPW = 16 / NWAVE;      // 1 KB operand fetches per wave and K block
     extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -225,7 +227,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
             q_seen = XCDS;   // take no more work
         }
         while (q_seen < XCDS) {
-            const int64_t nq = ((n_super - my_q + XCDS - 1) / XCDS) * (SB * SB);
+            const int64_t nq = ((n_super - my_q + XCDS - 1) / XCDS) * (a.sb * a.sb);
             it = (int64_t)atomicAdd(&qst->next_tile[my_q], 1u);
             if (it < nq) break;
             it = -1;
@@ -238,7 +240,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     __syncthreads();
     const int64_t item = s_next_p[0];
     if (item < 0) break;
-    int64_t sup = s_next_p[1] + XCDS * (item / (SB * SB));
+    int64_t sup = s_next_p[1] + XCDS * (item / (a.sb * a.sb));
     if constexpr (BATCH) {
         // the problem owning this super-tile; arguments and tables follow it (workgroup-uniform;
         // every wave finished the previous tile before the barriers of the fetch)
@@ -256,11 +258,11 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         }
         sup -= bt->pref[lo];
     }
-    const int slot = (int)(item % (SB * SB));
+    const int slot = (int)(item % (a.sb * a.sb));
     const int r = a.r_base + (int)(sup / a.super_per_r);
     int SI, SJ;
     tri_index(sup % a.super_per_r, SI, SJ);
-    const int bi = SI * SB + slot / SB, bj = SJ * SB + slot % SB;
+    const int bi = SI * a.sb + slot / a.sb, bj = SJ * a.sb + slot % a.sb;
     if (bi > bj || bj >= a.nbv) continue;   // workgroup-uniform
 
     // ---------------------------------------------------------------- K loop
@@ -495,10 +497,11 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                 const bool valid = rv < cv && cv < a.p;
                 if constexpr (MODE == SWEEP_PAIRS) {
                     if (valid) {
-                        uint32_t *o = a.ptab + (rv * a.p_pad + cv) * (W * W);
+                        const int64_t pc = (int64_t)(r - a.r_base) * a.p_pad * a.p_pad + rv * a.p_pad + cv;
+                        uint32_t *o = a.ptab + pc * (W * W);
 #pragma unroll
                         for (int x = 0; x < 4; ++x) o[x * W + b] = dec(vx[x]);
-                        if (b == 0) a.F2out[rv * a.p_pad + cv] = F2;
+                        if (b == 0) a.F2out[pc] = F2;
                     }
                     continue;
                 }
@@ -671,12 +674,13 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                 if constexpr (MODE == SWEEP_PAIRS) {
                     // parent data of the k = 3 sweep: the W x W packed counts and F of the pair
                     if (valid) {
-                        uint32_t *o = a.ptab + (rv * a.p_pad + cv) * (W * W);
+                        const int64_t pc = (int64_t)(r - a.r_base) * a.p_pad * a.p_pad + rv * a.p_pad + cv;
+                        uint32_t *o = a.ptab + pc * (W * W);
 #pragma unroll
                         for (int x = 0; x < W; ++x)
 #pragma unroll
                             for (int y = 0; y < W; ++y) o[x * W + y] = F4 ? tab[x][y] >> 2 : tab[x][y];
-                        a.F2out[rv * a.p_pad + cv] = F2;
+                        a.F2out[pc] = F2;
                     }
                     continue;
                 }
@@ -791,10 +795,10 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
     }   // work items
 }
 
-template <int W, int MODE, int ENC, bool EXPORT = false>
-__global__ __launch_bounds__(sw_waves(W) * 64, 2) __attribute__((amdgpu_waves_per_eu(sw_waves(W) / 2, sw_waves(W) / 2))) void k_sweep2(Sweep2Args a)
+template <int W, int MODE, int ENC, bool EXPORT = false, int NWV = sw_waves(W)>
+__global__ __launch_bounds__(NWV * 64, 2) __attribute__((amdgpu_waves_per_eu(NWV / 2, NWV / 2))) void k_sweep2(Sweep2Args a)
 {
-    sweep2_run<W, MODE, ENC, false, EXPORT>(a, nullptr);
+    sweep2_run<W, MODE, ENC, false, EXPORT, NWV>(a, nullptr);
 }
 
 template <int W, int ENC>
@@ -826,7 +830,8 @@ int sweep2_fp4_capacity(const Problem &P) { return fp4_capacity(P); }
 
 // Arguments of one problem's pair sweep.
 template <int W>
-static Sweep2Args sweep_args(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r, bool gated)
+static Sweep2Args sweep_args(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r, bool gated,
+                             int pair_nr = 1)
 {
     const Layout &L = P.L;
     Sweep2Args a{};
@@ -847,9 +852,10 @@ static Sweep2Args sweep_args(const Problem &P, int32_t *counts_out, int disc_sel
     a.KB0 = P.KB0;
     constexpr int TV = TILE_ROWS / W;
     a.nbv = (int)((L.p + TV - 1) / TV);
-    a.nsb = (a.nbv + SB - 1) / SB;
+    a.sb = P.supertile > 0 ? P.supertile : SB_DEFAULT;
+    a.nsb = (a.nbv + a.sb - 1) / a.sb;
     a.super_per_r = (int64_t)a.nsb * (a.nsb + 1) / 2;
-    a.n_super = a.super_per_r * (pair_r >= 0 ? 1 : L.R);
+    a.n_super = a.super_per_r * (pair_r >= 0 ? pair_nr : L.R);
     a.r_base = pair_r >= 0 ? pair_r : 0;
     a.ptab = pair_r >= 0 ? P.at<uint32_t>(L.ptab) : nullptr;
     a.F2out = pair_r >= 0 ? P.at<float>(L.F2) : nullptr;
@@ -869,46 +875,50 @@ static Sweep2Args sweep_args(const Problem &P, int32_t *counts_out, int disc_sel
 
 template <int W, int ENC>
 static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r,
-                               bool gated)
+                               bool gated, int pair_nr)
 {
-    Sweep2Args a = sweep_args<W>(P, counts_out, disc_sel, collect, pair_r, gated);
+    Sweep2Args a = sweep_args<W>(P, counts_out, disc_sel, collect, pair_r, gated, pair_nr);
     const size_t lds = sweep2_lds_bytes(P, pair_r < 0);
     a.snext_off = (int)(lds - 16);
+    // three classes, maximum pass: 4-wave workgroups when asked for (a tuning choice)
+    const bool four = W == 2 && pair_r < 0 && !counts_out && P.sweep_waves == 4;
     auto kern = pair_r >= 0 ? k_sweep2<W, SWEEP_PAIRS, ENC>
-                            : (counts_out ? k_sweep2<W, SWEEP_MAX, ENC, true> : k_sweep2<W, SWEEP_MAX, ENC>);
+                            : (counts_out ? k_sweep2<W, SWEEP_MAX, ENC, true>
+                                          : (four ? k_sweep2<W, SWEEP_MAX, ENC, false, 4> : k_sweep2<W, SWEEP_MAX, ENC>));
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     // no more workgroups than tile slots (each loads its tables before it takes a tile), at least
     // one per XCD; the queue walk hands every tile to some workgroup whatever the grid
-    const int64_t slots = a.n_super * (SB * SB);
+    const int64_t slots = a.n_super * (a.sb * a.sb);
     const int grid = P.workgroups > 0 ? P.workgroups
                                       : (int)std::min<int64_t>(XCDS * WG_PER_XCD, std::max<int64_t>(XCDS, slots));
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sw_waves(W) * 64), lds, P.stream, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3((four ? 4 : sw_waves(W)) * 64), lds, P.stream, a);
     return hipGetLastError();
 }
 
 template <int W>
 static hipError_t sweep_dispatch(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r,
-                                 bool gated)
+                                 bool gated, int pair_nr)
 {
-    if (!P.fp4) return sweep_launch<W, 0>(P, counts_out, disc_sel, collect, pair_r, gated);
+    if (!P.fp4) return sweep_launch<W, 0>(P, counts_out, disc_sel, collect, pair_r, gated, pair_nr);
     // the maximum sweep (and with it the count export) is instantiated per table capacity
     // (occupancy); the pair data of the triple sweeps use the largest
-    if (pair_r >= 0) return sweep_launch<W, 4096>(P, counts_out, disc_sel, collect, pair_r, gated);
+    if (pair_r >= 0) return sweep_launch<W, 4096>(P, counts_out, disc_sel, collect, pair_r, gated, pair_nr);
     switch (fp4_capacity(P)) {
-    case 1024: return sweep_launch<W, 1024>(P, counts_out, disc_sel, collect, pair_r, gated);
-    case 2048: return sweep_launch<W, 2048>(P, counts_out, disc_sel, collect, pair_r, gated);
-    case 4096: return sweep_launch<W, 4096>(P, counts_out, disc_sel, collect, pair_r, gated);
+    case 1024: return sweep_launch<W, 1024>(P, counts_out, disc_sel, collect, pair_r, gated, pair_nr);
+    case 2048: return sweep_launch<W, 2048>(P, counts_out, disc_sel, collect, pair_r, gated, pair_nr);
+    case 4096: return sweep_launch<W, 4096>(P, counts_out, disc_sel, collect, pair_r, gated, pair_nr);
     default: return hipErrorInvalidValue;
     }
 }
 
-static hipError_t sweep_any(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r, bool gated)
+static hipError_t sweep_any(const Problem &P, int32_t *counts_out, int disc_sel, bool collect, int pair_r, bool gated,
+                            int pair_nr = 1)
 {
     switch (P.L.W) {
-    case 1: return sweep_dispatch<1>(P, counts_out, disc_sel, collect, pair_r, gated);
-    case 2: return sweep_dispatch<2>(P, counts_out, disc_sel, collect, pair_r, gated);
-    case 4: return sweep_dispatch<4>(P, counts_out, disc_sel, collect, pair_r, gated);
+    case 1: return sweep_dispatch<1>(P, counts_out, disc_sel, collect, pair_r, gated, pair_nr);
+    case 2: return sweep_dispatch<2>(P, counts_out, disc_sel, collect, pair_r, gated, pair_nr);
+    case 4: return sweep_dispatch<4>(P, counts_out, disc_sel, collect, pair_r, gated, pair_nr);
     default: return hipErrorInvalidValue;
     }
 }
@@ -918,7 +928,10 @@ hipError_t launch_sweep2(const Problem &P, int32_t *counts_out, int disc_sel, bo
     return sweep_any(P, counts_out, disc_sel, collect, -1, collect);
 }
 
-hipError_t launch_pairs(const Problem &P, int r, bool gated) { return sweep_any(P, nullptr, -1, false, r, gated); }
+hipError_t launch_pairs(const Problem &P, int r0, int nr, bool gated)
+{
+    return sweep_any(P, nullptr, -1, false, r0, gated, nr);
+}
 
 // ---------------------------------------------------------------- count export, completion
 // The maximum pass stored the W x W directly counted cells of every pair i < j of the selected

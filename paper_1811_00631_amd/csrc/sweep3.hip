@@ -20,8 +20,9 @@ namespace mdfs {
 
 struct Sweep3Args {
     const uint32_t *bits;    // [R][2][words_max][p_pad][W]
-    const uint32_t *ptab;    // [p_pad][p_pad][W*W] packed counts of pairs i < j (this r)
-    const float *F2;         // [p_pad][p_pad] float32 F of pairs i < j (this r)
+    const uint32_t *ptab;    // [nr][p_pad][p_pad][W*W] packed counts of pairs i < j
+    const float *F2;         // [nr][p_pad][p_pad] float32 F of pairs i < j
+    int64_t ptab_stride, f2_stride;   // elements per discretisation of ptab and F2
     const uint32_t *marg;    // [R][p_pad][C] packed per-class marginals
     const float *EA, *EB;
     const float2 *LQ;
@@ -29,7 +30,7 @@ struct Sweep3Args {
     int p;
     int64_t p_pad, words_max;
     int w0, w1;              // bitset words of class 0 / class 1
-    int r;
+    int r0, nr;              // discretisations r0 .. r0 + nr - 1 in this launch
     int64_t n_pairs;         // C(p, 2)
     uint32_t *G32;
     Cand *cand;
@@ -38,8 +39,8 @@ struct Sweep3Args {
     uint32_t *ovf;
     float w_abs;
     int collect;
-    int32_t *counts_out;     // count export: [p][p][2][C][C][C], triples (i_sel, j, l)
-    int i_sel;
+    int32_t *counts_out;     // count export: [p][p][2][C][C][C], triples (i_sel, j, l) of disc_sel
+    int i_sel, disc_sel;
     const uint32_t *cancel;  // caller's cancel word (nullable)
 };
 
@@ -93,9 +94,9 @@ __device__ inline void full_pair(const uint32_t *pw, const uint32_t *Mx, const u
 }
 
 // candidate record at a reserved slot, or the overflow marks when the buffer is full
-__device__ inline void put3(const Sweep3Args &a, uint32_t at, int v, uint32_t partner, float ig)
+__device__ inline void put3(const Sweep3Args &a, int r, uint32_t at, int v, uint32_t partner, float ig)
 {
-    if (at < a.cap) a.cand[at] = Cand{v, a.r, partner, ig};
+    if (at < a.cap) a.cand[at] = Cand{v, r, partner, ig};
     else { atomicOr(&a.ovf[v], 1u); atomicOr(&a.st->overflow, 1u); }
 }
 
@@ -114,10 +115,7 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
     for (int i = t; i <= a.N; i += s3_threads(W)) LQ[i] = a.LQ[i];
     __syncthreads();
 
-    const uint32_t *margr = a.marg + (int64_t)a.r * a.p_pad * C;
     const int64_t plane = a.p_pad * W;                 // u32 per bitset word plane
-    const uint32_t *bits1 = a.bits + ((int64_t)a.r * 2 + 1) * a.words_max * plane;
-    const uint32_t *bits0 = a.bits + ((int64_t)a.r * 2 + 0) * a.words_max * plane;
 
     uint32_t taken = 0;   // pairs taken by this wave (cancel polling)
     for (;;) {
@@ -126,7 +124,16 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
         if (lane == 0) u = cancel_poll(a.cancel, taken, a.st) ? 0xffffffffu : atomicAdd(&a.st->next_tile[0], 1u);
         ++taken;
         u = __builtin_amdgcn_readfirstlane(u);
-        if ((int64_t)u >= a.n_pairs) break;
+        if ((int64_t)u >= a.n_pairs * a.nr) break;
+        // pair u of discretisation r = r0 + rr of the launch
+        const int rr = (int)(u / (uint32_t)a.n_pairs);
+        u -= (uint32_t)rr * (uint32_t)a.n_pairs;
+        const int r = a.r0 + rr;
+        const uint32_t *margr = a.marg + (int64_t)r * a.p_pad * C;
+        const uint32_t *bits1 = a.bits + ((int64_t)r * 2 + 1) * a.words_max * plane;
+        const uint32_t *bits0 = a.bits + ((int64_t)r * 2 + 0) * a.words_max * plane;
+        const uint32_t *ptab = a.ptab + (int64_t)rr * a.ptab_stride;
+        const float *F2 = a.F2 + (int64_t)rr * a.f2_stride;
         int64_t jj = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
         while ((jj + 1) * (jj + 2) / 2 <= (int64_t)u) ++jj;
         while (jj * (jj + 1) / 2 > (int64_t)u) --jj;
@@ -138,8 +145,8 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
 #pragma unroll
         for (int c = 0; c < C; ++c) { Mi[c] = margr[(int64_t)i * C + c]; Mj[c] = margr[(int64_t)j * C + c]; }
         uint32_t Nij[C][C];
-        full_pair<W>(a.ptab + ((int64_t)i * a.p_pad + j) * (W * W), Mi, Mj, Nij);
-        const float F2ij = a.F2[(int64_t)i * a.p_pad + j];
+        full_pair<W>(ptab + ((int64_t)i * a.p_pad + j) * (W * W), Mi, Mj, Nij);
+        const float F2ij = F2[(int64_t)i * a.p_pad + j];
         float Gi = key_f32(a.G32[i]), Gj = key_f32(a.G32[j]);
         float runi = -INFINITY, runj = -INFINITY;
 
@@ -207,7 +214,7 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
 
             // count export (EXPORT: this kernel plus the store): the W^3 directly counted cells of
             // the triples (i_sel, j, l); launch_complete_triples fills in the others
-            if (EXPORT && i == a.i_sel && act) {
+            if (EXPORT && i == a.i_sel && r == a.disc_sel && act) {
                 int32_t *o = a.counts_out + ((int64_t)j * a.p + l) * 2 * C * C * C;
 #pragma unroll
                 for (int x = 0; x < W; ++x)
@@ -225,8 +232,8 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
 #pragma unroll
             for (int c = 0; c < C; ++c) Ml[c] = margr[(int64_t)lc * C + c];
             uint32_t Nil[C][C], Njl[C][C];
-            full_pair<W>(a.ptab + ((int64_t)i * a.p_pad + lc) * (W * W), Mi, Ml, Nil);
-            full_pair<W>(a.ptab + ((int64_t)j * a.p_pad + lc) * (W * W), Mj, Ml, Njl);
+            full_pair<W>(ptab + ((int64_t)i * a.p_pad + lc) * (W * W), Mi, Ml, Nil);
+            full_pair<W>(ptab + ((int64_t)j * a.p_pad + lc) * (W * W), Mj, Ml, Njl);
             uint32_t T[C][C][C];
 #pragma unroll
             for (int x = 0; x < W; ++x)
@@ -296,7 +303,7 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
 #pragma unroll
                     for (int z = 0; z < C; ++z) F3 += vox3(T[x][y][z], EA, EB, LQ);
 
-            const float Fjl = a.F2[(int64_t)j * a.p_pad + lc], Fil = a.F2[(int64_t)i * a.p_pad + lc];
+            const float Fjl = F2[(int64_t)j * a.p_pad + lc], Fil = F2[(int64_t)i * a.p_pad + lc];
             const float igi = act ? Fjl - F3 : -INFINITY;    // gain of x_i given (x_j, x_l)
             const float igj = act ? Fil - F3 : -INFINITY;    // gain of x_j given (x_i, x_l)
             const float igl = act ? F2ij - F3 : -INFINITY;   // gain of x_l given (x_i, x_j)
@@ -312,9 +319,9 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
             const bool aj = act && igj >= topj - window3(a.w_abs, topj);
             // one slot reservation per chunk for the wave's records
             uint32_t at = reserve_slots(&a.st->n_cand, (uint32_t)al + (uint32_t)ai + (uint32_t)aj, lane);
-            if (al) put3(a, at++, l, ((uint32_t)i << 16) | (uint32_t)j, igl);
-            if (ai) put3(a, at++, i, ((uint32_t)j << 16) | (uint32_t)l, igi);
-            if (aj) put3(a, at++, j, ((uint32_t)i << 16) | (uint32_t)l, igj);
+            if (al) put3(a, r, at++, l, ((uint32_t)i << 16) | (uint32_t)j, igl);
+            if (ai) put3(a, r, at++, i, ((uint32_t)j << 16) | (uint32_t)l, igi);
+            if (aj) put3(a, r, at++, j, ((uint32_t)i << 16) | (uint32_t)l, igj);
             runi = fmaxf(runi, mi);
             runj = fmaxf(runj, mj);
             if (!a.collect) { Gi = fmaxf(Gi, mi); Gj = fmaxf(Gj, mj); }
@@ -327,7 +334,8 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
 }
 
 template <int W>
-static hipError_t sweep3_launch(const Problem &P, int r, bool collect, int32_t *counts_out, int i_sel)
+static hipError_t sweep3_launch(const Problem &P, int r0, int nr, bool collect, int32_t *counts_out, int i_sel,
+                                int disc_sel)
 {
     const Layout &L = P.L;
     Sweep3Args a{};
@@ -346,7 +354,10 @@ static hipError_t sweep3_launch(const Problem &P, int r, bool collect, int32_t *
     a.words_max = L.words_max;
     a.w0 = (P.N0 + 31) / 32;
     a.w1 = (P.N1 + 31) / 32;
-    a.r = r;
+    a.r0 = r0;
+    a.nr = nr;
+    a.ptab_stride = L.p_pad * L.p_pad * W * W;
+    a.f2_stride = L.p_pad * L.p_pad;
     a.n_pairs = L.p * (L.p - 1) / 2;
     a.G32 = P.at<uint32_t>(L.G32);
     a.cand = P.at<Cand>(L.cand);
@@ -357,6 +368,7 @@ static hipError_t sweep3_launch(const Problem &P, int r, bool collect, int32_t *
     a.collect = collect ? 1 : 0;
     a.counts_out = counts_out;
     a.i_sel = i_sel;
+    a.disc_sel = disc_sel;
     a.cancel = P.cancel;
     size_t lds = sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (L.N + 1) + 16;
     auto kern = counts_out ? k_sweep3<W, true> : k_sweep3<W>;
@@ -369,14 +381,14 @@ static hipError_t sweep3_launch(const Problem &P, int r, bool collect, int32_t *
     return hipGetLastError();
 }
 
-hipError_t launch_sweep3(const Problem &P, int r, bool collect, int32_t *counts_out, int i_sel)
+hipError_t launch_sweep3(const Problem &P, int r0, int nr, bool collect, int32_t *counts_out, int i_sel, int disc_sel)
 {
     hipError_t e = launch_reset_queue(P);
     if (e != hipSuccess) return e;
     switch (P.L.W) {
-    case 1: return sweep3_launch<1>(P, r, collect, counts_out, i_sel);
-    case 2: return sweep3_launch<2>(P, r, collect, counts_out, i_sel);
-    case 4: return sweep3_launch<4>(P, r, collect, counts_out, i_sel);
+    case 1: return sweep3_launch<1>(P, r0, nr, collect, counts_out, i_sel, disc_sel);
+    case 2: return sweep3_launch<2>(P, r0, nr, collect, counts_out, i_sel, disc_sel);
+    case 4: return sweep3_launch<4>(P, r0, nr, collect, counts_out, i_sel, disc_sel);
     default: return hipErrorInvalidValue;
     }
 }
@@ -461,11 +473,12 @@ __global__ __launch_bounds__(256) void k_complete_triples(int32_t *counts, const
     }
 }
 
-hipError_t launch_complete_triples(const Problem &P, int32_t *counts, int r, int i_sel)
+hipError_t launch_complete_triples(const Problem &P, int32_t *counts, int r, int r0, int i_sel)
 {
     const int64_t n = P.L.p * P.L.p;
     const dim3 grid((unsigned)((n + 255) / 256));
-    const uint32_t *ptab = P.at<uint32_t>(P.L.ptab), *marg = P.at<uint32_t>(P.L.marg);
+    const uint32_t *ptab = P.at<uint32_t>(P.L.ptab) + (int64_t)(r - r0) * P.L.p_pad * P.L.p_pad * P.L.W * P.L.W;
+    const uint32_t *marg = P.at<uint32_t>(P.L.marg);
     switch (P.L.C) {
     case 2: hipLaunchKernelGGL(k_complete_triples<2>, grid, dim3(256), 0, P.stream, counts, ptab, marg, r, i_sel, P.L.p, P.L.p_pad); break;
     case 3: hipLaunchKernelGGL(k_complete_triples<3>, grid, dim3(256), 0, P.stream, counts, ptab, marg, r, i_sel, P.L.p, P.L.p_pad); break;

@@ -37,8 +37,9 @@ constexpr int M3_NSTAGE = 3;
 
 struct Sweep3mArgs {
     const int8_t *onehot;
-    const uint32_t *ptab;    // [p_pad][p_pad][4] packed (n1 << 16 | n0) 2 x 2 counts of pairs (this r)
-    const float *F2;         // [p_pad][p_pad] float32 F of pairs (this r)
+    const uint32_t *ptab;    // [nr][p_pad][p_pad][W*W] packed (n1 << 16 | n0) W x W counts of pairs
+    const float *F2;         // [nr][p_pad][p_pad] float32 F of pairs
+    int64_t ptab_stride, f2_stride;   // elements per discretisation of ptab and F2
     const uint32_t *marg;    // [R][p_pad][3]
     const float *EA, *EB;
     const float2 *LQ;
@@ -48,7 +49,7 @@ struct Sweep3mArgs {
     int N0, N1, N;
     int p;
     int64_t p_pad, rows_pad;
-    int KB, KB0, r, nLB;
+    int KB, KB0, r0, nr, nLB;   // discretisations r0 .. r0 + nr - 1 in this launch
     uint32_t *G32;
     Cand *cand;
     int64_t cap;
@@ -58,8 +59,8 @@ struct Sweep3mArgs {
     int collect;
     int snext_off;
     int stage_off;           // two-class kernel: LDS byte offset of the operand stages
-    int32_t *counts_out;     // count export: [p][p][2][C][C][C], triples (i_sel, j, l)
-    int i_sel;
+    int32_t *counts_out;     // count export: [p][p][2][C][C][C], triples (i_sel, j, l) of disc_sel
+    int i_sel, disc_sel;
     const uint32_t *cancel;  // caller's cancel word (nullable)
 };
 
@@ -106,9 +107,9 @@ __device__ inline void full3(const uint32_t (&d)[4], const uint32_t (&Mx)[3], co
 }
 
 // candidate record at a reserved slot, or the overflow marks when the buffer is full
-__device__ inline void put(const Sweep3mArgs &a, uint32_t at, int v, uint32_t partner, float ig)
+__device__ inline void put(const Sweep3mArgs &a, int r, uint32_t at, int v, uint32_t partner, float ig)
 {
-    if (at < a.cap) a.cand[at] = Cand{v, a.r, partner, ig};
+    if (at < a.cap) a.cand[at] = Cand{v, r, partner, ig};
     else { atomicOr(&a.ovf[v], 1u); atomicOr(&a.st->overflow, 1u); }
 }
 
@@ -133,7 +134,6 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
         for (int i = t; i <= a.N; i += M3_THREADS) lq[i] = a.LQ[i];
     }
     auto repack = [](uint32_t x) -> uint32_t { return x << 2; };   // n1 << 16 | n0 -> fp4 packing
-    const uint32_t *margr = a.marg + (int64_t)a.r * a.p_pad * C;
     const int64_t nrb = a.rows_pad / TILE_ROWS;
     constexpr int kstride = TILE_ROWS * KBLK;
     const int n1blk = a.KB - a.KB0;
@@ -141,10 +141,17 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
     uint32_t taken = 0;   // tiles taken by this workgroup (cancel polling)
     for (;;) {
         __syncthreads();
-        if (t == 0) *s_next = cancel_poll(a.cancel, taken++, a.st) ? a.n_tiles : atomicAdd(&a.st->next_tile[0], 1u);
+        if (t == 0) *s_next = cancel_poll(a.cancel, taken++, a.st) ? a.n_tiles * a.nr : atomicAdd(&a.st->next_tile[0], 1u);
         __syncthreads();
-        const int64_t u = *s_next;
-        if (u >= a.n_tiles) break;
+        const int64_t u_all = *s_next;
+        if (u_all >= a.n_tiles * a.nr) break;
+        // tile u of the list, under discretisation r = r0 + rr of the launch
+        const int rr = (int)(u_all / a.n_tiles);
+        const int64_t u = u_all - (int64_t)rr * a.n_tiles;
+        const int r = a.r0 + rr;
+        const uint32_t *margr = a.marg + (int64_t)r * a.p_pad * C;
+        const uint32_t *ptab = a.ptab + (int64_t)rr * a.ptab_stride;
+        const float *F2 = a.F2 + (int64_t)rr * a.f2_stride;
         // A block: last k with apref[k] <= u
         int64_t lo = 0, hi = a.n_ablk - 1;
         while (lo < hi) {
@@ -157,9 +164,9 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
 
         // ---------------------------------------------------------------- K loop
         // operand sources in the panel-major one-hot encoding
-        const int8_t *panJ = a.onehot + ((int64_t)a.r * nrb + jb / 2) * a.KB * kstride + (jb & 1) * M3_JROWS * KBLK;
-        const int8_t *panL = a.onehot + ((int64_t)a.r * nrb + lb) * a.KB * kstride;
-        const int8_t *panI = a.onehot + ((int64_t)a.r * nrb + (2 * i) / TILE_ROWS) * a.KB * kstride +
+        const int8_t *panJ = a.onehot + ((int64_t)r * nrb + jb / 2) * a.KB * kstride + (jb & 1) * M3_JROWS * KBLK;
+        const int8_t *panL = a.onehot + ((int64_t)r * nrb + lb) * a.KB * kstride;
+        const int8_t *panI = a.onehot + ((int64_t)r * nrb + (2 * i) / TILE_ROWS) * a.KB * kstride +
                              ((2 * i) % TILE_ROWS) * KBLK;
         auto kblock = [&](int s_) { return s_ < n1blk ? a.KB0 + s_ : s_ - n1blk; };
         auto stage_at = [&](int s_) { return stage + (s_ % M3_NSTAGE) * M3_STAGE; };
@@ -255,7 +262,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
                     cnt[m][n][x] = (int)(__umul24(uu >> 14, 245760u) + uu);
                 }
         // count export (EXPORT: this kernel plus the store): T[a][b][e] of the triples (i_sel, j, l)
-        if (EXPORT && i == a.i_sel) {
+        if (EXPORT && i == a.i_sel && r == a.disc_sel) {
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -293,10 +300,10 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) d.M[c] = repack(margr[(int64_t)j * C + c]);
             const int ii = i < j ? i : j, jj = i < j ? j : i;
-            const v4i pw = *reinterpret_cast<const v4i *>(a.ptab + ((int64_t)ii * a.p_pad + jj) * 4);
+            const v4i pw = *reinterpret_cast<const v4i *>(ptab + ((int64_t)ii * a.p_pad + jj) * 4);
 #pragma unroll
             for (int x = 0; x < 4; ++x) d.P[x] = repack((uint32_t)pw[x]);
-            d.F = a.F2[(int64_t)ii * a.p_pad + jj];
+            d.F = F2[(int64_t)ii * a.p_pad + jj];
         };
 #pragma unroll
         for (int m = 0; m < 4; ++m) gJ[m] = key_f32(a.G32[clampv(jv[m])]);
@@ -306,10 +313,10 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) Ml[n][c] = repack(margr[(int64_t)l * C + c]);
             const int ii = i < l ? i : l, ll = i < l ? l : i;
-            const v4i pw = *reinterpret_cast<const v4i *>(a.ptab + ((int64_t)ii * a.p_pad + ll) * 4);
+            const v4i pw = *reinterpret_cast<const v4i *>(ptab + ((int64_t)ii * a.p_pad + ll) * 4);
 #pragma unroll
             for (int x = 0; x < 4; ++x) Pil[n][x] = repack((uint32_t)pw[x]);
-            Fil[n] = a.F2[(int64_t)ii * a.p_pad + ll];
+            Fil[n] = F2[(int64_t)ii * a.p_pad + ll];
             const float g = key_f32(a.G32[l]);
             gL[n] = g;
             thrL[n] = g - win3(a.w_abs, g);
@@ -322,8 +329,8 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
             const bool valid = i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;
             const int j = clampv(jv[m]), l = clampv(lv[n]);
             const int jj = j < l ? j : l, ll = j < l ? l : j;
-            const v4i pw = *reinterpret_cast<const v4i *>(a.ptab + ((int64_t)jj * a.p_pad + ll) * 4);
-            Fjl = a.F2[(int64_t)jj * a.p_pad + ll];
+            const v4i pw = *reinterpret_cast<const v4i *>(ptab + ((int64_t)jj * a.p_pad + ll) * 4);
+            Fjl = F2[(int64_t)jj * a.p_pad + ll];
             uint32_t dj[4];
 #pragma unroll
             for (int x = 0; x < 4; ++x) dj[x] = repack((uint32_t)pw[x]);
@@ -472,9 +479,9 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
 #pragma unroll
                     for (int n = 0; n < 4; ++n) {
                         const int l = lv[n];
-                        if (sel & (1u << (3 * n))) put(a, at++, i, ((uint32_t)j << 16) | (uint32_t)l, gI[n]);
-                        if (sel & (2u << (3 * n))) put(a, at++, j, ((uint32_t)i << 16) | (uint32_t)l, gJ[n]);
-                        if (sel & (4u << (3 * n))) put(a, at++, l, ((uint32_t)i << 16) | (uint32_t)j, gL[n]);
+                        if (sel & (1u << (3 * n))) put(a, r, at++, i, ((uint32_t)j << 16) | (uint32_t)l, gI[n]);
+                        if (sel & (2u << (3 * n))) put(a, r, at++, j, ((uint32_t)i << 16) | (uint32_t)l, gJ[n]);
+                        if (sel & (4u << (3 * n))) put(a, r, at++, l, ((uint32_t)i << 16) | (uint32_t)j, gL[n]);
                     }
                 }
             }
@@ -527,7 +534,6 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
         for (int i = t; i <= a.N; i += M3_THREADS) lq[i] = a.LQ[i];
     }
     auto repack = [](uint32_t x) -> uint32_t { return x << 2; };   // n1 << 16 | n0 -> fp4 packing
-    const uint32_t *margr = a.marg + (int64_t)a.r * a.p_pad * C;
     const uint32_t Ntot = ((uint32_t)a.N1 << 18) | ((uint32_t)a.N0 << 2);
     const int64_t nrb = a.rows_pad / TILE_ROWS;
     constexpr int kstride = TILE_ROWS * KBLK;
@@ -537,10 +543,17 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
     uint32_t taken = 0;   // tiles taken by this workgroup (cancel polling)
     for (;;) {
         __syncthreads();
-        if (t == 0) *s_next = cancel_poll(a.cancel, taken++, a.st) ? a.n_tiles : atomicAdd(&a.st->next_tile[0], 1u);
+        if (t == 0) *s_next = cancel_poll(a.cancel, taken++, a.st) ? a.n_tiles * a.nr : atomicAdd(&a.st->next_tile[0], 1u);
         __syncthreads();
-        const int64_t u = *s_next;
-        if (u >= a.n_tiles) break;
+        const int64_t u_all = *s_next;
+        if (u_all >= a.n_tiles * a.nr) break;
+        // tile u of the list, under discretisation r = r0 + rr of the launch
+        const int rr = (int)(u_all / a.n_tiles);
+        const int64_t u = u_all - (int64_t)rr * a.n_tiles;
+        const int r = a.r0 + rr;
+        const uint32_t *margr = a.marg + (int64_t)r * a.p_pad * C;
+        const uint32_t *ptab = a.ptab + (int64_t)rr * a.ptab_stride;
+        const float *F2 = a.F2 + (int64_t)rr * a.f2_stride;
         int64_t lo = 0, hi = a.n_ablk - 1;
         while (lo < hi) {
             const int64_t mid = (lo + hi + 1) >> 1;
@@ -551,9 +564,9 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
         const int lb = jb + (int)(u - a.apref[lo]);
 
         // ---------------------------------------------------------------- K loop
-        const int8_t *panJ = a.onehot + ((int64_t)a.r * nrb + jb) * a.KB * kstride;
-        const int8_t *panL = a.onehot + ((int64_t)a.r * nrb + lb) * a.KB * kstride;
-        const int8_t *panI = a.onehot + ((int64_t)a.r * nrb + i / TILE_ROWS) * a.KB * kstride + (i % TILE_ROWS) * KBLK;
+        const int8_t *panJ = a.onehot + ((int64_t)r * nrb + jb) * a.KB * kstride;
+        const int8_t *panL = a.onehot + ((int64_t)r * nrb + lb) * a.KB * kstride;
+        const int8_t *panI = a.onehot + ((int64_t)r * nrb + i / TILE_ROWS) * a.KB * kstride + (i % TILE_ROWS) * KBLK;
         auto kblock = [&](int s_) { return s_ < n1blk ? a.KB0 + s_ : s_ - n1blk; };
         auto stage_at = [&](int s_) { return stage + (s_ % M1_NSTAGE) * M1_STAGE; };
         // 17 fetches per K block: 8 of 1 KB for the j rows, 8 for the l rows (stage rows
@@ -635,7 +648,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
                 }
         auto jvar = [&](int m, int x) { return jb * M1_V + 64 * wr + 16 * m + 4 * q + x; };
         // count export (EXPORT: this kernel plus the store): T[0][0][0] of the triples (i_sel, j, l)
-        if (EXPORT && i == a.i_sel) {
+        if (EXPORT && i == a.i_sel && r == a.disc_sel) {
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -662,9 +675,9 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
             const int l = clampv(lv[n]);
             Ml[n] = repack(margr[(int64_t)l * C]);
             const int ii = i < l ? i : l, ll = i < l ? l : i;
-            Nil[n] = repack(a.ptab[(int64_t)ii * a.p_pad + ll]);
+            Nil[n] = repack(ptab[(int64_t)ii * a.p_pad + ll]);
             Ail[n] = Ml[n] - Nil[n];                        // x_i = 1, x_l = 0
-            Fil[n] = a.F2[(int64_t)ii * a.p_pad + ll];
+            Fil[n] = F2[(int64_t)ii * a.p_pad + ll];
             const float g = key_f32(a.G32[l]);
             gL[n] = g;
             thrL[n] = g - win3(a.w_abs, g);
@@ -681,11 +694,11 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
                 const int j = clampv(jvar(m, x));
                 const uint32_t Mj = repack(margr[(int64_t)j * C]);
                 const int ii = i < j ? i : j, jj = i < j ? j : i;
-                const uint32_t nij = repack(a.ptab[(int64_t)ii * a.p_pad + jj]);
+                const uint32_t nij = repack(ptab[(int64_t)ii * a.p_pad + jj]);
                 d.Nij[x] = nij;
                 d.Aij[x] = Mi - nij;
                 d.Cij[x] = Ni1 - (Mj - nij);
-                d.F[x] = a.F2[(int64_t)ii * a.p_pad + jj];
+                d.F[x] = F2[(int64_t)ii * a.p_pad + jj];
                 d.g[x] = key_f32(a.G32[j]);
             }
         };
@@ -695,8 +708,8 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
             const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
             const int j = clampv(jraw), l = clampv(lv[n]);
             const int jj = j < l ? j : l, ll = j < l ? l : j;
-            const uint32_t Njl = repack(a.ptab[(int64_t)jj * a.p_pad + ll]);
-            Fjl = a.F2[(int64_t)jj * a.p_pad + ll];
+            const uint32_t Njl = repack(ptab[(int64_t)jj * a.p_pad + ll]);
+            Fjl = F2[(int64_t)jj * a.p_pad + ll];
             const uint32_t D = (uint32_t)cnt[m][n][x];
             uint32_t V[8];
             V[0] = D;                                   // T000
@@ -818,9 +831,9 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
 #pragma unroll
                         for (int x = 0; x < 4; ++x) {
                             const int j = jvar(m, x);
-                            if (sel & (1u << (3 * x))) put(a, at++, i, ((uint32_t)j << 16) | (uint32_t)l, gI[x]);
-                            if (sel & (2u << (3 * x))) put(a, at++, j, ((uint32_t)i << 16) | (uint32_t)l, gJ[x]);
-                            if (sel & (4u << (3 * x))) put(a, at++, l, ((uint32_t)i << 16) | (uint32_t)j, gL[x]);
+                            if (sel & (1u << (3 * x))) put(a, r, at++, i, ((uint32_t)j << 16) | (uint32_t)l, gI[x]);
+                            if (sel & (2u << (3 * x))) put(a, r, at++, j, ((uint32_t)i << 16) | (uint32_t)l, gJ[x]);
+                            if (sel & (4u << (3 * x))) put(a, r, at++, l, ((uint32_t)i << 16) | (uint32_t)j, gL[x]);
                         }
                     }
                 }
@@ -862,7 +875,7 @@ int m3_capacity(const Problem &P)
 }
 
 template <int T, int W>
-hipError_t m3_launch(const Problem &P, int r, bool collect, int32_t *counts_out, int i_sel)
+hipError_t m3_launch(const Problem &P, int r0, int nr, bool collect, int32_t *counts_out, int i_sel, int disc_sel)
 {
     const Layout &L = P.L;
     Sweep3mArgs a{};
@@ -885,7 +898,10 @@ hipError_t m3_launch(const Problem &P, int r, bool collect, int32_t *counts_out,
     a.rows_pad = L.rows_pad;
     a.KB = P.KB;
     a.KB0 = P.KB0;
-    a.r = r;
+    a.r0 = r0;
+    a.nr = nr;
+    a.ptab_stride = L.p_pad * L.p_pad * W * W;
+    a.f2_stride = L.p_pad * L.p_pad;
     a.nLB = (int)((L.p + (W == 1 ? M1_V : M3_LV) - 1) / (W == 1 ? M1_V : M3_LV));
     a.G32 = P.at<uint32_t>(L.G32);
     a.cand = P.at<Cand>(L.cand);
@@ -896,6 +912,7 @@ hipError_t m3_launch(const Problem &P, int r, bool collect, int32_t *counts_out,
     a.collect = collect ? 1 : 0;
     a.counts_out = counts_out;
     a.i_sel = i_sel;
+    a.disc_sel = disc_sel;
     a.cancel = P.cancel;
     const size_t lds = sweep3m_lds_of(T, W, (int)L.N);
     a.stage_off = (int)m1_stage_off(T, (int)L.N);
@@ -985,15 +1002,18 @@ hipError_t launch_tiles3(const Problem &P)
     return hipGetLastError();
 }
 
-hipError_t launch_sweep3m(const Problem &P, int r, bool collect, int32_t *counts_out, int i_sel)
+hipError_t launch_sweep3m(const Problem &P, int r0, int nr, bool collect, int32_t *counts_out, int i_sel, int disc_sel)
 {
     hipError_t e = launch_reset_queue(P);
     if (e != hipSuccess) return e;
     const bool w1 = P.L.W == 1;
     switch (m3_capacity(P)) {
-    case 1024: return w1 ? m3_launch<1024, 1>(P, r, collect, counts_out, i_sel) : m3_launch<1024, 2>(P, r, collect, counts_out, i_sel);
-    case 2048: return w1 ? m3_launch<2048, 1>(P, r, collect, counts_out, i_sel) : m3_launch<2048, 2>(P, r, collect, counts_out, i_sel);
-    case 4096: return w1 ? m3_launch<4096, 1>(P, r, collect, counts_out, i_sel) : m3_launch<4096, 2>(P, r, collect, counts_out, i_sel);
+    case 1024: return w1 ? m3_launch<1024, 1>(P, r0, nr, collect, counts_out, i_sel, disc_sel)
+                         : m3_launch<1024, 2>(P, r0, nr, collect, counts_out, i_sel, disc_sel);
+    case 2048: return w1 ? m3_launch<2048, 1>(P, r0, nr, collect, counts_out, i_sel, disc_sel)
+                         : m3_launch<2048, 2>(P, r0, nr, collect, counts_out, i_sel, disc_sel);
+    case 4096: return w1 ? m3_launch<4096, 1>(P, r0, nr, collect, counts_out, i_sel, disc_sel)
+                         : m3_launch<4096, 2>(P, r0, nr, collect, counts_out, i_sel, disc_sel);
     default: return hipErrorInvalidValue;
     }
 }

@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
                 ("divisions", ctypes.c_int32), ("n_disc", ctypes.c_int32), ("disc_offset", ctypes.c_int32),
                 ("range", ctypes.c_double), ("pseudocount", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("engine", ctypes.c_int32), ("flags", ctypes.c_int32), ("workgroups", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("cancel", ctypes.c_void_p)]
+                ("tile", ctypes.c_int32), ("cancel", ctypes.c_void_p)]
 
 
 _lib = None
@@ -109,12 +109,19 @@ def load(path: str = LIB_PATH):
     return L
 
 
+def tile_code(supertile: int = 0, waves: int = 0) -> int:
+    """The `tile` field: super-tile side (2, 4, 8, 16; 0 default) and waves per workgroup of the
+    three-class pair sweep (4, 8; 0 default)."""
+    return (int(supertile) & 0xff) | ((int(waves) & 0xf) << 8)
+
+
 def make_params(n_obj, n_var, k=2, divisions=2, n_disc=1, disc_offset=0, range_=0.5, pseudocount=0.25,
-                seed=0, engine="auto", flags=0, workgroups=0, cancel=None) -> Params:
-    """`cancel`: None, or the address (int) of a caller-owned host-mapped uint32 cancel word."""
+                seed=0, engine="auto", flags=0, workgroups=0, cancel=None, tile=0) -> Params:
+    """`cancel`: None, or the address (int) of a caller-owned host-mapped uint32 cancel word;
+    `tile`: see tile_code."""
     return Params(int(n_obj), int(n_var), int(k), int(divisions), int(n_disc), int(disc_offset),
                   float(range_), float(pseudocount), int(seed) & ((1 << 64) - 1), ENGINES[engine], int(flags),
-                  int(workgroups), 0, cancel)
+                  int(workgroups), int(tile), cancel)
 
 
 def mdfs_phase_times() -> dict:
@@ -180,21 +187,22 @@ def workspace_for(prm: Params, device) -> torch.Tensor:
 
 
 def mdfs_discretize(data: torch.Tensor, divisions: int, n_disc: int, range_: float = 0.5, seed: int = 0,
-                    disc_offset: int = 0, k: int = 2) -> torch.Tensor:
+                    disc_offset: int = 0, k: int = 2, ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     data, _ = _dev_inputs(data)
     n_var, n_obj = data.shape
     prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, 0.25, seed)
-    ws = workspace_for(prm, data.device)
+    if ws is None:
+        ws = workspace_for(prm, data.device)
+    strm = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(data.device)
     codes = torch.empty((n_disc, n_var, n_obj), dtype=torch.uint8, device=data.device)
-    _check(load().mdfs_discretize(ctypes.byref(prm), _ptr(data), _ptr(codes), _ptr(ws), ws.numel(),
-                                  _stream(data.device)))
+    _check(load().mdfs_discretize(ctypes.byref(prm), _ptr(data), _ptr(codes), _ptr(ws), ws.numel(), strm))
     return codes
 
 
 def mdfs_max_ig(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_disc: int,
                 pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0, disc_offset: int = 0,
                 engine: str = "auto", timing: bool = False, workgroups: int = 0, ws: torch.Tensor | None = None,
-                stream=None, cancel=None):
+                stream=None, cancel=None, tile: int = 0):
     """IG_max, argmax tuple and argmax discretisation of every variable.  `ws` (a caller-owned
     uint8 device workspace of at least mdfs_workspace_size bytes) and `stream` (a torch CUDA
     stream) default to a per-device cached workspace and the current stream; `cancel` is the
@@ -202,7 +210,7 @@ def mdfs_max_ig(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_d
     data, y = _dev_inputs(data, y)
     n_var, n_obj = data.shape
     prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed, engine,
-                      FLAG_TIMING if timing else 0, workgroups, cancel)
+                      FLAG_TIMING if timing else 0, workgroups, cancel, tile)
     if ws is None:
         ws = workspace_for(prm, data.device)
     strm = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(data.device)
@@ -217,14 +225,14 @@ def mdfs_max_ig(data: torch.Tensor, y: torch.Tensor, k: int, divisions: int, n_d
 def mdfs_max_ig_async(data: torch.Tensor, y: torch.Tensor, n1: int, k: int, divisions: int, n_disc: int,
                       pseudocount: float = 0.25, range_: float = 0.5, seed: int = 0, disc_offset: int = 0,
                       engine: str = "auto", workgroups: int = 0, ws: torch.Tensor | None = None, out=None,
-                      cancel=None):
+                      cancel=None, tile: int = 0):
     """Enqueue mdfs_max_ig on the current stream without any host synchronisation (capturable in
     a CUDA graph).  `out` = (ig, argmax, argmax_disc) preallocated tensors or None; `ws` a
     preallocated workspace or None (the cached one).  Check errors later with mdfs_check_status."""
     data, y = _dev_inputs(data, y)
     n_var, n_obj = data.shape
     prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, range_, pseudocount, seed, engine, 0,
-                      workgroups, cancel)
+                      workgroups, cancel, tile)
     if ws is None:
         ws = workspace_for(prm, data.device)
     if out is None:
@@ -296,7 +304,8 @@ def mdfs_max_ig_batch(datas, ys, n1s, k: int, divisions: int, n_discs, pseudocou
 
 
 def mdfs_max_ig_codes(codes: torch.Tensor, y: torch.Tensor, k: int, divisions: int, pseudocount: float = 0.25,
-                      disc_offset: int = 0, engine: str = "auto", workgroups: int = 0):
+                      disc_offset: int = 0, engine: str = "auto", workgroups: int = 0, ws: torch.Tensor | None = None,
+                      stream=None):
     """mdfs_max_ig from device codes uint8 [n_disc][n_var][n_obj] (values 0..divisions)."""
     if not (isinstance(codes, torch.Tensor) and codes.is_cuda and codes.dtype == torch.uint8 and codes.dim() == 3):
         raise ValueError("codes must be a CUDA uint8 tensor [n_disc][n_var][n_obj]")
@@ -306,12 +315,14 @@ def mdfs_max_ig_codes(codes: torch.Tensor, y: torch.Tensor, k: int, divisions: i
         raise ValueError("y must be a CUDA uint8 tensor [n_obj]")
     y = y.contiguous()
     prm = make_params(n_obj, n_var, k, divisions, n_disc, disc_offset, 0.0, pseudocount, 0, engine, 0, workgroups)
-    ws = workspace_for(prm, codes.device)
+    if ws is None:
+        ws = workspace_for(prm, codes.device)
+    strm = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(codes.device)
     ig = torch.empty(n_var, dtype=torch.float32, device=codes.device)
     am = torch.empty((n_var, k - 1), dtype=torch.int32, device=codes.device)
     ad = torch.empty(n_var, dtype=torch.int32, device=codes.device)
     _check(load().mdfs_max_ig_codes(ctypes.byref(prm), _ptr(codes), _ptr(y), _ptr(ig), _ptr(am), _ptr(ad), _ptr(ws),
-                                    ws.numel(), _stream(codes.device)))
+                                    ws.numel(), strm))
     return ig, am, ad
 
 

@@ -5,13 +5,23 @@ parameters (k, divisions, discretisations, pseudocount, seed).  The server admit
 requests into free slots while their HBM footprint (the library's workspace plus the outputs)
 fits the memory budget, first fit in arrival order (a request passed over too often blocks
 later ones until it fits).  Each slot is a host thread with its own HIP stream; the C-ABI call
-releases the GIL, so the sweeps of admitted requests run concurrently on the device, each
-with a bounded persistent grid so that small requests are not stuck behind large ones.  Small
-k = 2 requests waiting behind an admitted small one (same divisions, encoding and engine, up to
-12, memory permitting) are fused with it into one mdfs_max_ig_batch call: one persistent sweep
-launch over all their tiles.
-Results do not depend on the mix: every call is deterministic and the persistent grids take
-all of their tiles whatever their size.
+releases the GIL, so the sweeps of admitted requests run concurrently on the device.
+* Persistent grids follow the request's size: a large request (at least `big_tuples` tuples)
+  takes three quarters of the GPU's resident sweep workgroups, a smaller one an eighth to a
+  quarter, so the large request that sets the tail latency is not slowed to a slot's share while
+  small ones still find room beside it.
+* `express` of the slots take only small requests (at most `fuse_tuples` tuples), so small
+  requests never wait behind large ones that occupy the other slots.
+* Small k = 2 requests waiting behind an admitted small one (same divisions, encoding and engine,
+  up to 12, memory permitting) are fused with it into one mdfs_max_ig_batch call: one persistent
+  sweep launch over all their tiles.
+* Encoded datasets stay resident when discretisation parameters repeat: the second request
+  with the same (dataset, divisions, range, seed) has its codes computed once (mdfs_discretize)
+  and kept in an LRU cache within `code_cache_bytes`; that and every later such request with at
+  most as many discretisations runs mdfs_max_ig_codes on them, skipping the discretisation.
+Results do not depend on the mix: every call is deterministic, the persistent grids take all of
+their tiles whatever their size, and a sweep from cached codes is bit-identical to the sweep
+that discretises.
 
 Host orchestration only: every step of every sweep runs in the library's kernels.
 """
@@ -75,7 +85,8 @@ def tuples_of(ds: Dataset, req: Request) -> int:
 class Server:
     def __init__(self, device: str = "cuda:0", slots: int = 4, hbm_budget: int | None = None,
                  workgroups: int | None = None, max_bypass: int = 8, fuse: bool = True,
-                 fuse_tuples: float = 5e8):
+                 fuse_tuples: float = 5e8, express: int | None = None, big_tuples: float = 1e9,
+                 code_cache_bytes: int = 2 << 30):
         mdfs.load()
         self.device = torch.device(device)
         self.slots = slots
@@ -83,12 +94,19 @@ class Server:
             free, _ = torch.cuda.mem_get_info(self.device)
             hbm_budget = int(0.8 * free)
         self.budget = hbm_budget
-        # persistent grid per call: the GPU's 512 resident sweep workgroups shared by the slots
-        self.workgroups = workgroups if workgroups is not None else max(64, (512 // slots) // 8 * 8)
+        # persistent grid per call (None: by request size, see grid_of), out of the GPU's 512
+        # resident pair-sweep workgroups
+        self.workgroups = workgroups
         self.max_bypass = max_bypass
         self.fuse = fuse
-        self.fuse_tuples = fuse_tuples   # requests up to this many tuples may be fused
+        self.fuse_tuples = fuse_tuples   # requests up to this many tuples may be fused (and are small)
+        self.big_tuples = big_tuples     # requests from this many tuples take most of the GPU
+        self.express = express if express is not None else (1 if slots >= 3 else 0)
         self.n_fused = 0                 # requests that ran inside a fused batch
+        self.code_cache_bytes = code_cache_bytes
+        self._codes: collections.OrderedDict = collections.OrderedDict()   # key -> codes (LRU)
+        self._code_seen: dict = {}       # discretisation key -> requests seen
+        self.code_hits = 0               # requests served from cached codes
         self.datasets: dict[int, Dataset] = {}
         self.resident = 0
         self._lock = threading.Condition()
@@ -124,10 +142,21 @@ class Server:
             self.resident -= ds.data.numel() * 4 + ds.y.numel()
 
     # -------------------------------------------------------------- requests
+    def grid_of(self, req: Request) -> int:
+        """Persistent workgroups of the request's sweep."""
+        if self.workgroups is not None:
+            return self.workgroups
+        if self.slots == 1:
+            return 0                      # one request at a time: the whole GPU
+        t = tuples_of(self.datasets[req.dataset], req)
+        if t >= self.big_tuples:
+            return 384
+        return 128 if t > self.fuse_tuples else 64
+
     def footprint(self, req: Request) -> int:
         ds = self.datasets[req.dataset]
         prm = mdfs.make_params(ds.n_obj, ds.n_var, req.k, req.divisions, req.n_disc, 0, req.range_,
-                               req.pseudocount, req.seed, req.engine, 0, self.workgroups)
+                               req.pseudocount, req.seed, req.engine, 0, self.grid_of(req))
         ws = mdfs.mdfs_workspace_size(prm)
         return ws + ds.n_var * 4 * (req.k + 1) + 4096
 
@@ -158,11 +187,16 @@ class Server:
         fp4 = max(ds.n1, ds.n_obj - ds.n1) < 4096 and req.engine != "mfma"
         return (req.divisions, fp4, req.engine)
 
-    def _take(self) -> list[Request]:
-        """First queued request whose footprint fits, and the fusable ones queued behind it that
-        also fit (called with the lock held)."""
+    def _small(self, req: Request) -> bool:
+        return tuples_of(self.datasets[req.dataset], req) <= self.fuse_tuples
+
+    def _take(self, express: bool = False) -> list[Request]:
+        """First queued request whose footprint fits (an express slot: first small one), and the
+        fusable ones queued behind it that also fit (called with the lock held)."""
         free = self.budget - self.resident - self._in_use
         for idx, req in enumerate(self._queue):
+            if express and not self._small(req):
+                continue
             if req.footprint <= free:
                 for earlier in list(self._queue)[:idx]:
                     self._bypassed[earlier.id] = self._bypassed.get(earlier.id, 0) + 1
@@ -187,13 +221,14 @@ class Server:
 
     def _worker(self, slot: int):
         stream = self._streams[slot]
+        express = slot < self.express
         while True:
             with self._lock:
                 group = []
                 while not group:
                     if self._closing and not self._queue:
                         return
-                    group = self._take()
+                    group = self._take(express)
                     if not group:
                         self._lock.wait()
                 now = self.now()
@@ -217,15 +252,47 @@ class Server:
                     self.n_fused += len(group)
                 self._lock.notify_all()
 
+    def _cached_codes(self, req: Request, ws: torch.Tensor, stream: torch.cuda.Stream):
+        """Resident codes for the request's discretisations, or None.  A discretisation key seen
+        for the second time is encoded once (mdfs_discretize) and kept, LRU, within the budget."""
+        ds = self.datasets[req.dataset]
+        key = (req.dataset, req.divisions, req.range_, req.seed)
+        with self._lock:
+            hit = self._codes.get(key)
+            if hit is not None and hit.shape[0] >= req.n_disc:
+                self._codes.move_to_end(key)
+                self.code_hits += 1
+                return hit[:req.n_disc]
+            self._code_seen[key] = self._code_seen.get(key, 0) + 1
+            if self._code_seen[key] < 2:
+                return None
+        nbytes = req.n_disc * ds.n_var * ds.n_obj
+        if nbytes > self.code_cache_bytes:
+            return None
+        codes = mdfs.mdfs_discretize(ds.data, req.divisions, req.n_disc, req.range_, req.seed, k=req.k, ws=ws,
+                                     stream=stream)
+        with self._lock:
+            self._codes[key] = codes
+            while sum(c.numel() for c in self._codes.values()) > self.code_cache_bytes:
+                self._codes.popitem(last=False)
+            self.code_hits += 1
+        return codes
+
     def _run(self, req: Request, stream: torch.cuda.Stream):
         ds = self.datasets[req.dataset]
+        grid = self.grid_of(req)
         with torch.cuda.stream(stream):
             prm = mdfs.make_params(ds.n_obj, ds.n_var, req.k, req.divisions, req.n_disc, 0, req.range_,
-                                   req.pseudocount, req.seed, req.engine, 0, self.workgroups)
+                                   req.pseudocount, req.seed, req.engine, 0, grid)
             ws = torch.empty(mdfs.mdfs_workspace_size(prm), dtype=torch.uint8, device=self.device)
-            ig, am, ad = mdfs.mdfs_max_ig(ds.data, ds.y, req.k, req.divisions, req.n_disc, req.pseudocount,
-                                          req.range_, req.seed, 0, engine=req.engine,
-                                          workgroups=self.workgroups, ws=ws, stream=stream)
+            codes = self._cached_codes(req, ws, stream) if req.k >= 2 else None
+            if codes is not None:
+                ig, am, ad = mdfs.mdfs_max_ig_codes(codes, ds.y, req.k, req.divisions, req.pseudocount, 0,
+                                                    engine=req.engine, workgroups=grid, ws=ws, stream=stream)
+            else:
+                ig, am, ad = mdfs.mdfs_max_ig(ds.data, ds.y, req.k, req.divisions, req.n_disc, req.pseudocount,
+                                              req.range_, req.seed, 0, engine=req.engine, workgroups=grid, ws=ws,
+                                              stream=stream)
             req.result = (ig.cpu().numpy(), am.cpu().numpy(), ad.cpu().numpy())
             del ws
 
@@ -237,7 +304,8 @@ class Server:
                 outs, wss = mdfs.mdfs_max_ig_batch(
                     [d.data for d in dss], [d.y for d in dss], [d.n1 for d in dss], 2, group[0].divisions,
                     [r.n_disc for r in group], [r.pseudocount for r in group], [r.range_ for r in group],
-                    [r.seed for r in group], engine=group[0].engine, workgroups=self.workgroups)
+                    [r.seed for r in group], engine=group[0].engine,
+                    workgroups=self.workgroups if self.workgroups is not None else 128)
                 for r, d, (ig, am, ad), ws in zip(group, dss, outs, wss):
                     try:
                         mdfs.mdfs_check_status((d.n_var, d.n_obj), 2, r.divisions, r.n_disc, ws=ws, engine=r.engine)

@@ -29,10 +29,11 @@ def test_library_exports_every_declared_symbol():
 
 def test_params_struct_matches_header():
     # int64 n_obj, n_var; int32 k, divisions, n_disc, disc_offset; double range, pseudocount;
-    # uint64 seed; int32 engine, flags, workgroups, reserved; pointer cancel
+    # uint64 seed; int32 engine, flags, workgroups, tile; pointer cancel
     assert ctypes.sizeof(mdfs.Params) == 80
     assert mdfs.Params.range.offset == 32 and mdfs.Params.seed.offset == 48 and mdfs.Params.flags.offset == 60
-    assert mdfs.Params.workgroups.offset == 64 and mdfs.Params.cancel.offset == 72
+    assert mdfs.Params.workgroups.offset == 64 and mdfs.Params.tile.offset == 68
+    assert mdfs.Params.cancel.offset == 72
 
 
 def test_status_codes_match_header():
@@ -59,6 +60,7 @@ def test_workspace_size_valid_and_monotone():
     (dict(range_=-0.1), -1), (dict(pseudocount=-1.0), -1), (dict(n_disc=0), -1),
     (dict(disc_offset=-1), -1), (dict(n_var=1), -1), (dict(workgroups=4), -1), (dict(workgroups=5000), -1), (dict(k=3, engine="mfma_fp4", divisions=4), -10),
     (dict(k=3, engine="mfma"), -10), (dict(engine="bitset"), -10),
+    (dict(tile=3), -1), (dict(tile=32), -1), (dict(tile=0x508), -1), (dict(tile=0x1008), -1),
 ])
 def test_invalid_params_rejected_on_host(kw, code):
     base = dict(n_obj=100, n_var=10, k=2, divisions=2, n_disc=1, disc_offset=0, range_=0.5,

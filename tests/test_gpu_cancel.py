@@ -32,25 +32,26 @@ def cancel_word(mdfs_gpu):
     hip.hipHostFree(ptr)
 
 
-@pytest.mark.parametrize("k,engine", [(2, "auto"), (3, "mfma_fp4"), (3, "bitset"), (4, "bitset")])
-def test_cancel_before_the_call_then_a_clean_call(cancel_word, k, engine):
+@pytest.mark.parametrize("k,engine,div", [(2, "auto", 2), (3, "mfma_fp4", 2), (3, "bitset", 2), (4, "bitset", 2),
+                                          (4, "bitset", 1), (5, "bitset", 1), (5, "hist", 2)])
+def test_cancel_before_the_call_then_a_clean_call(cancel_word, k, engine, div):
     addr, word = cancel_word
-    w = workloads.xor_small(seed=90 + k, n_obj=400, n_var={2: 300, 3: 60, 4: 20}[k], n_disc=3)
+    w = workloads.xor_small(seed=90 + k, n_obj=400, n_var={2: 300, 3: 60, 4: 20, 5: 11}[k], n_disc=3)
     X, y = torch.from_numpy(w.data).to(DEV), torch.from_numpy(w.y).to(DEV)
-    print(f"cancel before k={k} {engine}", flush=True)
-    ref = mdfs.mdfs_max_ig(X, y, k, 2, 3, engine=engine)
+    print(f"cancel before k={k} {engine} d={div + 1}", flush=True)
+    ref = mdfs.mdfs_max_ig(X, y, k, div, 3, engine=engine)
     word[0] = 1
     with pytest.raises(mdfs.MdfsError) as e:
-        mdfs.mdfs_max_ig(X, y, k, 2, 3, engine=engine, cancel=addr)
+        mdfs.mdfs_max_ig(X, y, k, div, 3, engine=engine, cancel=addr)
     assert e.value.code == mdfs.E_CANCELLED
     # asynchronous call: reported by mdfs_check_status
-    mdfs.mdfs_max_ig_async(X, y, int(w.y.sum()), k, 2, 3, engine=engine, cancel=addr)
+    mdfs.mdfs_max_ig_async(X, y, int(w.y.sum()), k, div, 3, engine=engine, cancel=addr)
     with pytest.raises(mdfs.MdfsError) as e:
-        mdfs.mdfs_check_status(X.shape, k, 2, 3, engine=engine)
+        mdfs.mdfs_check_status(X.shape, k, div, 3, engine=engine)
     assert e.value.code == mdfs.E_CANCELLED
     # cleared: the same workspace gives the complete result
     word[0] = 0
-    got = mdfs.mdfs_max_ig(X, y, k, 2, 3, engine=engine, cancel=addr)
+    got = mdfs.mdfs_max_ig(X, y, k, div, 3, engine=engine, cancel=addr)
     for a, b in zip(ref, got):
         assert torch.equal(a, b)
 

@@ -152,6 +152,32 @@ def test_deterministic_and_fused_equals_separate(mdfs_gpu):
         assert np.array_equal(sep[r][1][v], a[1][v]) and sep[r][2][v] == r
 
 
+@pytest.mark.parametrize("div,n_var,engine", [(2, 1500, "mfma_fp4"), (2, 700, "mfma"), (1, 1100, "mfma_fp4"),
+                                               (4, 900, "mfma_fp4")])
+def test_launch_shapes_give_identical_results(mdfs_gpu, div, n_var, engine):
+    # every super-tile side and wave count (and grid) takes every tile once: the outputs are
+    # bit-identical to the default launch; the variable counts leave ragged super-tiles
+    w = workloads.xor_small(seed=12, n_obj=700, n_var=n_var, divisions=div, n_disc=2)
+    X, y = to_dev(w)
+    print(f"launch shapes div={div} p={n_var} {engine}", flush=True)
+    ref = [t.cpu() for t in mdfs_gpu.mdfs_max_ig(X, y, 2, div, 2, 0.25, 0.5, 3, engine=engine)]
+    waves = (0, 4, 8) if div == 2 else (0,)
+    for sb in (2, 4, 16):
+        for nw in waves:
+            for g in (0, 96):
+                got = mdfs_gpu.mdfs_max_ig(X, y, 2, div, 2, 0.25, 0.5, 3, engine=engine, workgroups=g,
+                                           tile=mdfs_gpu.tile_code(sb, nw))
+                for a_, b_ in zip(ref, got):
+                    assert torch.equal(a_, b_.cpu()), (sb, nw, g)
+    if div in (1, 2):   # k = 3: the pair tables come from the pair sweep at the chosen shape
+        w3 = workloads.xor_small(seed=13, n_obj=700, n_var=150, divisions=div, n_disc=2)
+        X3, y3 = to_dev(w3)
+        ref3 = [t.cpu() for t in mdfs_gpu.mdfs_max_ig(X3, y3, 3, div, 2, engine="mfma_fp4")]
+        got3 = mdfs_gpu.mdfs_max_ig(X3, y3, 3, div, 2, engine="mfma_fp4", tile=mdfs_gpu.tile_code(2, 4))
+        for a_, b_ in zip(ref3, got3):
+            assert torch.equal(a_, b_.cpu())
+
+
 def test_decision_errors(mdfs_gpu):
     w = workloads.xor_small(seed=11, n_obj=50, n_var=4)
     data, y = to_dev(w)

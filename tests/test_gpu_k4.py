@@ -1,5 +1,7 @@
-"""k = 4 and k = 5 sweeps on the GPU through the C ABI, against the FP64 oracle: the bitset engine
-(k = 4, two or three classes) and the per-tuple histogram engine (k = 4 and 5, any class count)."""
+"""k = 4 and k = 5 sweeps on the GPU through the C ABI, against the FP64 oracle: the bitset engines
+(k = 4 with three classes: every cell counted directly; k = 4 and 5 with two classes: subset
+counts and inclusion-exclusion) and the per-tuple histogram engine (k = 4 and 5, any class
+count)."""
 import dataclasses
 
 import numpy as np
@@ -29,6 +31,8 @@ CASES4 = {
     "d3_wide_words": lambda: workloads.xor_small(seed=63, n_obj=1100, n_var=17, n_disc=1),
     "four_vars": lambda: workloads.xor_small(seed=64, n_obj=200, n_var=4, n_disc=3),
     "tiny_n": lambda: workloads.xor_small(seed=65, n_obj=7, n_var=9, n_disc=2),
+    "d2": lambda: dataclasses.replace(workloads.xor_small(seed=69, n_obj=700, n_var=31, n_disc=2), divisions=1),
+    "d2_tiny_n": lambda: dataclasses.replace(workloads.xor_small(seed=60, n_obj=9, n_var=8, n_disc=2), divisions=1),
 }
 
 
@@ -109,16 +113,50 @@ def test_hist_engine_matches_oracle(mdfs_gpu, name):
     assert_ig_parity(*got, ref, name)
 
 
-@pytest.mark.parametrize("divisions", [1, 2])
-def test_hist_engine_equals_bitset_engine_k4(mdfs_gpu, divisions):
-    # two count engines of k = 4: identical outputs (the re-scored maxima do not depend on how the
-    # counts were obtained)
-    w = dataclasses.replace(workloads.xor_small(seed=78, n_obj=800, n_var=30, n_disc=2), divisions=divisions)
-    print(f"hist vs bitset k=4 d={divisions + 1}", flush=True)
-    a = run4(mdfs_gpu, w, engine="bitset")
-    b = run4(mdfs_gpu, w, engine="hist")
+@pytest.mark.parametrize("k,divisions", [(4, 1), (4, 2), (5, 1)])
+def test_hist_engine_equals_bitset_engine(mdfs_gpu, k, divisions):
+    # two count engines: identical outputs (the re-scored maxima do not depend on how the counts
+    # were obtained); p spans several 64-pair chunks above the early prefixes
+    w = dataclasses.replace(workloads.xor_small(seed=78, n_obj=800, n_var=30 if k == 4 else 24, n_disc=2),
+                            divisions=divisions)
+    print(f"hist vs bitset k={k} d={divisions + 1}", flush=True)
+    a = run4(mdfs_gpu, w, engine="bitset", k=k)
+    b = run4(mdfs_gpu, w, engine="hist", k=k)
     for x, z in zip(a, b):
         assert np.array_equal(x, z)
+
+
+# ------------------------------------------------------------------ k = 5, two classes, bitsets
+CASES_B5 = {
+    "k5_d2": lambda: dataclasses.replace(workloads.xor_small(seed=81, n_obj=600, n_var=16, n_disc=2), divisions=1),
+    "k5_d2_imbalanced": lambda: dataclasses.replace(workloads.null_data(82, 333, 12, ones=90), divisions=1,
+                                                    n_disc=2),
+    "k5_d2_wide_words": lambda: dataclasses.replace(workloads.xor_small(seed=83, n_obj=2100, n_var=9, n_disc=1),
+                                                    divisions=1),
+    "k5_d2_five_vars": lambda: dataclasses.replace(workloads.xor_small(seed=84, n_obj=120, n_var=5, n_disc=3),
+                                                   divisions=1),
+    "k5_d2_tiny_n": lambda: dataclasses.replace(workloads.xor_small(seed=85, n_obj=9, n_var=8, n_disc=2),
+                                                divisions=1),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES_B5))
+def test_k5_bitset_engine_matches_oracle(mdfs_gpu, name):
+    w = CASES_B5[name]()
+    print(f"k5 bitset {name} N={w.n_obj} p={w.n_var} R={w.n_disc}", flush=True)
+    got = run4(mdfs_gpu, w, k=5, engine="bitset")
+    ref = oracle.max_ig_all(w.data, w.y, 5, w.divisions, w.n_disc, w.range_, w.xi, w.seed, n_threads=8)
+    assert_ig_parity(*got, ref, name)
+
+
+def test_k5_bitset_engine_collect_pass(mdfs_gpu, monkeypatch):
+    w = dataclasses.replace(workloads.xor_small(seed=86, n_obj=500, n_var=13, n_disc=2), divisions=1)
+    monkeypatch.setenv("MDFS_TEST_CAP", str(3 * w.n_var))
+    print("k5 bitset collect pass", flush=True)
+    got = run4(mdfs_gpu, w, k=5, engine="bitset")
+    monkeypatch.delenv("MDFS_TEST_CAP")
+    ref = oracle.max_ig_all(w.data, w.y, 5, w.divisions, w.n_disc, w.range_, w.xi, w.seed, n_threads=8)
+    assert_ig_parity(*got, ref, "k5 bitset collect pass")
 
 
 def test_hist_engine_finds_a_planted_parity_quintuple(mdfs_gpu):
@@ -128,11 +166,12 @@ def test_hist_engine_finds_a_planted_parity_quintuple(mdfs_gpu):
     X = g.standard_normal((p, n)).astype(np.float32)
     y = ((X[0] > 0) ^ (X[1] > 0) ^ (X[2] > 0) ^ (X[3] > 0) ^ (X[4] > 0)).astype(np.uint8)
     w = workloads.Workload("parity5", X, y, 5, 1, 1, 0.0, 0.25, 3, {})
-    print("k5 planted", flush=True)
-    ig, am, ad = run4(mdfs_gpu, w, k=5, divisions=1)
-    assert set(np.argsort(-ig)[:5].tolist()) == {0, 1, 2, 3, 4}
-    assert am[0].tolist() == [1, 2, 3, 4]
-    assert ig[:5].min() > 10 * np.median(ig[5:])
+    for engine in ("auto", "hist"):   # two classes: "auto" is the bitset engine
+        print(f"k5 planted {engine}", flush=True)
+        ig, am, ad = run4(mdfs_gpu, w, k=5, divisions=1, engine=engine)
+        assert set(np.argsort(-ig)[:5].tolist()) == {0, 1, 2, 3, 4}
+        assert am[0].tolist() == [1, 2, 3, 4]
+        assert ig[:5].min() > 10 * np.median(ig[5:])
 
 
 def test_hist_engine_collect_pass_and_async(mdfs_gpu, monkeypatch):

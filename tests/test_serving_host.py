@@ -83,6 +83,16 @@ def test_autotune_candidates_and_buckets():
     assert {c["engine"] for c in autotune.candidates(9000, 2, 2, 4500)} == {"mfma"}   # classes >= 4096
     assert {c["engine"] for c in autotune.candidates(2000, 3, 2, 1000)} == {"mfma_fp4", "bitset"}
     assert {c["engine"] for c in autotune.candidates(2000, 3, 4, 1000)} == {"bitset"}
+    # k = 4: bitsets (two or three classes) or histograms; k = 5: bitsets (two classes) or histograms
+    assert {c["engine"] for c in autotune.candidates(2000, 4, 2, 1000)} == {"bitset", "hist"}
+    assert {c["engine"] for c in autotune.candidates(2000, 4, 4, 1000)} == {"hist"}
+    assert {c["engine"] for c in autotune.candidates(2000, 5, 1, 1000)} == {"bitset", "hist"}
+    assert {c["engine"] for c in autotune.candidates(2000, 5, 2, 1000)} == {"hist"}
+    # k = 2 launch shapes: super-tiles 4, 8, 16; with three classes 8 or 4 waves too
+    shapes = {(c["tile"] & 0xff, c["tile"] >> 8) for c in c2}
+    assert shapes == {(sb, nw) for sb in (4, 8, 16) for nw in (8, 4)}
+    assert {c["tile"] >> 8 for c in autotune.candidates(2000, 2, 1, 1000)} == {0}
+    assert all(c["tile"] == 0 for c in autotune.candidates(2000, 3, 2, 1000))
     assert all(c["workgroups"] % 8 == 0 and 8 <= c["workgroups"] <= 4096 for c in c2)
     assert autotune.bucket(2000, 20000, 2, 2, 30) == (2048, 32768, 2, 2, 4)
     assert autotune.bucket(1025, 100, 3, 1, 1) == (2048, 128, 3, 1, 1)
