@@ -105,20 +105,22 @@ def host_threads() -> int:
     return max(1, min(int(os.environ.get("OMP_NUM_THREADS", str(os.cpu_count() or 1))), os.cpu_count() or 1))
 
 
-def cpu_baseline(w, k, n_vars, n_disc, ig_gpu, argmax_gpu, disc_gpu):
+def cpu_baseline(w, k, n_vars, n_disc, ig_gpu, argmax_gpu, disc_gpu, gpu_on_sample=None):
     """The FP64 oracle timed on the host cores on a bounded sample of the same workload: the
     tuple-sweep form (threads over discretisations) on the first n_vars variables and n_disc
     discretisations, on every host thread and on one core.  Also the per-result IG error of the
     GPU outputs: against the stored oracle values of every variable (tests/golden, when the
     regenerated inputs hash to the stored digest), else against the per-variable oracle on a
-    sample of variables holding every planted one."""
+    sample of variables holding every planted one; for k >= 4 (where the per-variable oracle over
+    all p variables is out of reach) against the timed oracle run itself, with the GPU run on the
+    same sample (`gpu_on_sample`)."""
     import numpy as np
 
     import oracle
     threads = min(host_threads(), n_disc)
     data = w.data[:n_vars]
     t0 = time.perf_counter()
-    oracle.max_ig_all(data, w.y, k, w.divisions, n_disc, w.range_, w.xi, w.seed, n_threads=threads)
+    sample_ref = oracle.max_ig_all(data, w.y, k, w.divisions, n_disc, w.range_, w.xi, w.seed, n_threads=threads)
     dt = time.perf_counter() - t0
     tuples = math.comb(n_vars, k) * n_disc
     # one core: a quarter of the variables, two discretisations
@@ -148,6 +150,11 @@ def cpu_baseline(w, k, n_vars, n_disc, ig_gpu, argmax_gpu, disc_gpu):
                 where = "stored oracle values of every variable (tests/golden)"
     except Exception as exc:   # the stored values are optional
         print(f"# stored oracle values unavailable: {exc}", file=sys.stderr)
+    if ref is None and gpu_on_sample is not None:
+        ig_gpu, argmax_gpu, disc_gpu = gpu_on_sample(n_vars, n_disc)
+        tg = np.arange(n_vars)
+        ref = tuple(np.asarray(x) for x in sample_ref)
+        where = f"the timed oracle run (first {n_vars} variables, {n_disc} discretisations) against the GPU on the same"
     if ref is None:
         g = np.random.default_rng(0)
         planted = sorted({int(v) for pr in w.planted.get("pairs", []) for v in pr} |
@@ -527,10 +534,16 @@ def main():
     }
     if k != 2 or args.workload != "headline":
         line["metric"] = f"k-tuples evaluated/sec (k={k} workload, informational)"
-    if not args.no_cpu_baseline and k in (2, 3):
-        nv = min(args.cpu_vars if k == 2 else 120, w.n_var)
+    if not args.no_cpu_baseline:
+        nv = min({2: args.cpu_vars, 3: 120, 4: 60, 5: 36}[k], w.n_var)
+
+        def gpu_on_sample(n_vars, n_disc):
+            o = mdfs.mdfs_max_ig(data[:n_vars].contiguous(), y, k, div, n_disc, w.xi, w.range_, w.seed,
+                                 engine=args.engine)
+            return [t.cpu().numpy() for t in o]
+
         cb = cpu_baseline(w, k, nv, min(args.cpu_disc, w.n_disc), ig.cpu().numpy(), am.cpu().numpy(),
-                          out[2].cpu().numpy())
+                          out[2].cpu().numpy(), gpu_on_sample if k >= 4 else None)
         line["ig_error"] = cb.pop("ig_error")
         line["cpu_baseline"] = cb
     print(json.dumps(line))

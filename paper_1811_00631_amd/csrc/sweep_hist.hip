@@ -8,8 +8,8 @@
 // that class (class 0 occupies the first N0 positions).  Every cell is counted directly, so the
 // class count only sets the histogram size (C^K = 32 .. 3125 cells), and each parent table
 // T \ {t_m} is the histogram summed over axis m: the entropy of a parent needs no stored data
-// of lower order.  This is the engine for the cases the bitset sweep does not cover (k = 5, and
-// k = 4 with five classes); k = 4 with two or three classes can be asked for too.
+// of lower order.  This is the engine for the cases the bitset sweeps do not cover (k = 5 with
+// three or five classes, k = 4 with five); the others can be asked for too.
 //
 // Epilogue: F = sum_v n_v h(p_v) in float32 from the lookup tables (the screen of the other
 // sweeps, error bound E for C^K and C^(K-1) voxels), IG(t_m | T \ {t_m}) = F(T \ {t_m}) - F(T) for
