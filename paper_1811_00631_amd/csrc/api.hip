@@ -130,9 +130,9 @@ static int check_params(const mdfs_params *prm, bool sweep = true)
     return MDFS_OK;
 }
 
-static Layout layout_of(const mdfs_params *prm)
+static Layout layout_of(const mdfs_params *prm, size_t pair_budget = PAIR_BUDGET_DEFAULT)
 {
-    return make_layout(prm->n_obj, prm->n_var, prm->k, prm->divisions, prm->n_disc);
+    return make_layout(prm->n_obj, prm->n_var, prm->k, prm->divisions, prm->n_disc, pair_budget);
 }
 
 extern "C" size_t mdfs_workspace_size(const mdfs_params *prm)
@@ -159,10 +159,10 @@ static double screen_err_bound(int64_t N, double b0, double b1, int V)
 
 // Read and validate the decision, then fill in everything the launches need.
 static int setup(const mdfs_params *prm, const uint8_t *y, void *ws, size_t ws_bytes, void *stream,
-                 Problem &P, int64_t n1_given = -1)
+                 Problem &P, int64_t n1_given = -1, size_t pair_budget = PAIR_BUDGET_DEFAULT)
 {
     P = Problem{};
-    P.L = layout_of(prm);
+    P.L = layout_of(prm, pair_budget);
     if (ws_bytes < P.L.total)
         return fail(MDFS_E_NOMEM, "workspace %zu bytes < required %zu", ws_bytes, P.L.total);
     P.ws = static_cast<char *>(ws);
@@ -429,7 +429,8 @@ extern "C" int mdfs_max_ig_codes(const mdfs_params *prm, const uint8_t *codes, c
 }
 
 static int max_ig_async_impl(const mdfs_params *prm, const float *data, const uint8_t *y, int64_t n1, float *ig_max,
-                             int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream)
+                             int32_t *argmax, int32_t *argmax_disc, void *ws, size_t ws_bytes, void *stream,
+                             size_t pair_budget = PAIR_BUDGET_DEFAULT)
 {
     int rc = check_params(prm);
     if (rc) return rc;
@@ -437,7 +438,7 @@ static int max_ig_async_impl(const mdfs_params *prm, const float *data, const ui
     if (prm->flags & MDFS_FLAG_TIMING) return fail(MDFS_E_ARG, "timing reads events back: not in the asynchronous call");
     if (n1 < 1 || n1 >= prm->n_obj) return fail(MDFS_E_Y, "n1=%lld: both classes must be non-empty", (long long)n1);
     Problem P;
-    if ((rc = setup(prm, y, ws, ws_bytes, stream, P, n1))) return rc;
+    if ((rc = setup(prm, y, ws, ws_bytes, stream, P, n1, pair_budget))) return rc;
     LAUNCH(launch_init(P));
     if (P.k3_mfma) LAUNCH(launch_tiles3(P));
     LAUNCH(launch_class_perm(P, y, n1));
@@ -506,7 +507,12 @@ extern "C" int mdfs_max_ig_noalloc(const mdfs_params *prm, const float *data, co
 {
     int rc = check_params(prm);
     if (rc) return rc;
-    const size_t need = layout_of(prm).total;
+    // k = 3: fewer discretisations' pair data at once (more launches, the same results) where the
+    // default would not fit the array
+    size_t pair_budget = PAIR_BUDGET_DEFAULT;
+    while (layout_of(prm, pair_budget).total > NOALLOC_SCRATCH_BYTES && layout_of(prm, pair_budget).RC > 1)
+        pair_budget /= 2;
+    const size_t need = layout_of(prm, pair_budget).total;
     if (need > NOALLOC_SCRATCH_BYTES)
         return fail(MDFS_E_NOMEM, "this problem needs %zu bytes of workspace; the allocation-free call holds %zu per GPU",
                     need, NOALLOC_SCRATCH_BYTES);
@@ -516,10 +522,11 @@ extern "C" int mdfs_max_ig_noalloc(const mdfs_params *prm, const float *data, co
     if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(MDFS_E_LIMIT, "device %d >= %d", dev, NOALLOC_MAX_DEVICES);
     void *ws = scratch_on(dev);
     if (!ws) return MDFS_E_HIP;
-    if ((rc = max_ig_async_impl(prm, data, y, n1, ig_max, argmax, argmax_disc, ws, NOALLOC_SCRATCH_BYTES, stream)))
+    if ((rc = max_ig_async_impl(prm, data, y, n1, ig_max, argmax, argmax_disc, ws, NOALLOC_SCRATCH_BYTES, stream,
+                                pair_budget)))
         return rc;
     if (status_out) {
-        const Layout L = layout_of(prm);
+        const Layout L = layout_of(prm, pair_budget);
         hipLaunchKernelGGL(k_status_code, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream),
                            reinterpret_cast<const Status *>(static_cast<char *>(ws) + L.status), status_out);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "status kernel");

@@ -77,7 +77,9 @@ struct Layout {
         cand, ig64, bits, ptab, F2, a3pref, a3blk, F1d, ccodes, total;
 };
 
-Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R);
+// k = 3 holds the pair data of as many discretisations as fit in pair_budget bytes (at least one)
+constexpr size_t PAIR_BUDGET_DEFAULT = size_t(64) << 20;
+Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R, size_t pair_budget = PAIR_BUDGET_DEFAULT);
 // per-class bitsets are built for k = 3, k = 4 and, with two classes, k = 5
 inline bool uses_bits(const Layout &L) { return L.k == 3 || L.k == 4 || (L.k == 5 && L.C == 2); }
 

@@ -17,7 +17,7 @@ namespace mdfs {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
+Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R, size_t pair_budget)
 {
     Layout L{};
     L.N = N;
@@ -58,10 +58,10 @@ Layout make_layout(int64_t N, int64_t p, int k, int divisions, int R)
         L.ptab = L.F2 = L.a3pref = L.a3blk = o;
     } else if (k == 3) {
         L.bits = take(sizeof(uint32_t) * (size_t)R * 2 * L.words_max * L.p_pad * L.W);
-        // the pair data of up to RC discretisations (at most 512 MiB, at least one): one launch of
-        // the pair sweep and one of the triple sweep per chunk of discretisations
+        // the pair data of up to RC discretisations (at most pair_budget bytes, at least one): one
+        // launch of the pair sweep and one of the triple sweep per chunk of discretisations
         const size_t per_r = (size_t)L.p_pad * L.p_pad * (sizeof(uint32_t) * L.W * L.W + sizeof(float));
-        L.RC = (int)std::min<size_t>((size_t)R, std::max<size_t>(1, (size_t(512) << 20) / per_r));
+        L.RC = (int)std::min<size_t>((size_t)R, std::max<size_t>(1, pair_budget / per_r));
         L.ptab = take(sizeof(uint32_t) * (size_t)L.RC * L.p_pad * L.p_pad * L.W * L.W);
         L.F2 = take(sizeof(float) * (size_t)L.RC * L.p_pad * L.p_pad);
         const int64_t n_ablk_max = L.p_pad * ((L.p_pad + 31) / 32);

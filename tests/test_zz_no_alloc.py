@@ -47,6 +47,28 @@ def test_noalloc_equals_async_twice_then_smaller(mdfs_gpu, k):
             assert am[0, 0] == 1 and am[1, 0] == 0
 
 
+def test_noalloc_k3_holds_fewer_discretisations_of_pair_data(mdfs_gpu):
+    # N = 2000, p = 500, R = 30 at k = 3: the default chunk of pair data (12 discretisations) does
+    # not fit the array, so the allocation-free call takes fewer per launch; same results
+    lib = mdfs.load()
+    w = workloads.parity3(seed=3)
+    prm = mdfs.make_params(w.n_obj, w.n_var, 3, w.divisions, w.n_disc, 0, w.range_, w.xi, w.seed)
+    assert lib.mdfs_workspace_size(ctypes.byref(prm)) > 128 << 20
+    data, y = torch.from_numpy(w.data).to(DEV), torch.from_numpy(w.y).to(DEV)
+    n1 = int(w.y.sum())
+    print("noalloc k=3 C3 size", flush=True)
+    ref = mdfs.mdfs_max_ig_async(data, y, n1, 3, w.divisions, w.n_disc, w.xi, w.range_, w.seed)
+    mdfs.mdfs_check_status((w.n_var, w.n_obj), 3, w.divisions, w.n_disc)
+    out = (torch.empty(w.n_var, device=DEV), torch.empty((w.n_var, 2), dtype=torch.int32, device=DEV),
+           torch.empty(w.n_var, dtype=torch.int32, device=DEV))
+    status = torch.full((1,), 123, dtype=torch.int32, device=DEV)
+    assert _noalloc(lib, prm, data, y, n1, out, status) == 0, lib.mdfs_last_error().decode()
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    for a, b in zip(out, ref):
+        assert torch.equal(a, b)
+
+
 def test_noalloc_reports_device_status_and_rejects_oversize(mdfs_gpu):
     lib = mdfs.load()
     w = workloads.xor_small(seed=83, n_obj=200, n_var=20, n_disc=1)
