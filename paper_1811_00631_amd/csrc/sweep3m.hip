@@ -513,25 +513,31 @@ constexpr int M1_V = 128;                                   // j and l variables
 constexpr int M1_STAGE = 2 * TILE_ROWS * KBLK + KBLK + 64;  // j rows | l rows | i row | pad
 constexpr int M1_NSTAGE = 2;   // operand stages: fetched one K block ahead (two workgroups per CU)
 
-template <int T, bool EXPORT = false>
-__global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
+// NWV waves per workgroup: 4 (a 2 x 2 wave grid, 4 x 4 blocks of 16 x 16 triples per wave) or 8
+// (2 x 4, 4 x 2 blocks per wave).  The launch uses 4: with 8 the epilogue needs 211 VGPRs (one
+// workgroup per CU, 8.4 ms against 7.4 on the Madelon-shaped d = 2 call) or spills at 128.
+template <int T, bool EXPORT = false, int NWV = 4>
+__global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
 {
     constexpr int C = 2;
+    constexpr int NT = NWV * 64;
+    constexpr int NN = 16 / NWV;          // 16 x 16 column (l) blocks per wave; row (j) blocks: 4
+    constexpr int LSPAN = 16 * NN;        // l variables per wave
     if (a.collect && a.st->collect_go == 0) return;   // collect pass not needed (uniform)
     extern __shared__ __attribute__((aligned(16))) char smem[];
     char *stage = smem + a.stage_off;   // after the (L, Q) pairs of n = 0 .. N
     int64_t *s_next = reinterpret_cast<int64_t *>(smem + a.snext_off);
 
     const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave / (NWV / 2), wc = wave % (NWV / 2);
     const int q = lane >> 4, c16 = lane & 15;
 
     {
         float *tf = reinterpret_cast<float *>(smem);
-        for (int i = t; i <= a.N0; i += M3_THREADS) tf[i] = a.EA[i];
-        for (int i = t; i <= a.N1; i += M3_THREADS) tf[T + i] = a.EB[i];
+        for (int i = t; i <= a.N0; i += NT) tf[i] = a.EA[i];
+        for (int i = t; i <= a.N1; i += NT) tf[T + i] = a.EB[i];
         float2 *lq = reinterpret_cast<float2 *>(smem + 8 * T);
-        for (int i = t; i <= a.N; i += M3_THREADS) lq[i] = a.LQ[i];
+        for (int i = t; i <= a.N; i += NT) lq[i] = a.LQ[i];
     }
     auto repack = [](uint32_t x) -> uint32_t { return x << 2; };   // n1 << 16 | n0 -> fp4 packing
     const uint32_t Ntot = ((uint32_t)a.N1 << 18) | ((uint32_t)a.N0 << 2);
@@ -570,14 +576,14 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
         auto kblock = [&](int s_) { return s_ < n1blk ? a.KB0 + s_ : s_ - n1blk; };
         auto stage_at = [&](int s_) { return stage + (s_ % M1_NSTAGE) * M1_STAGE; };
         // 17 fetches per K block: 8 of 1 KB for the j rows, 8 for the l rows (stage rows
-        // 128..255), one of 64 bytes for the row of i (lanes 0..3).  Wave w takes fetches w, w+4,
-        // w+8, w+12, and wave 0 also the row of i.
+        // 128..255), one of 64 bytes for the row of i (lanes 0..3).  Wave w takes fetches w,
+        // w + NWV, ..., and wave 0 also the row of i.
         auto issue = [&](int s_) {
             const int64_t kb_off = (int64_t)kblock(s_) * kstride;
             char *st_ = stage_at(s_);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int f = wave + 4 * k;
+            for (int k = 0; k < 16 / NWV; ++k) {
+                const int f = wave + NWV * k;
                 const int srow = 16 * f + (lane >> 2);
                 const int j = (lane & 3) ^ ((srow >> 1) & 3);
                 const int8_t *src = f < 8 ? panJ + kb_off + srow * KBLK + j * 16
@@ -591,16 +597,16 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
                                                  (__attribute__((address_space(3))) void *)(st_ + 16 * 1024), 16, 0, 0);
             }
         };
-        v4f acc[4][4];
+        v4f acc[4][NN];
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] = v4f{0.f, 0.f, 0.f, 0.f};
-        int offJ[4], offL[4];
+            for (int n = 0; n < NN; ++n) acc[m][n] = v4f{0.f, 0.f, 0.f, 0.f};
+        int offJ[4], offL[NN];
 #pragma unroll
         for (int m = 0; m < 4; ++m) offJ[m] = lds_sw(64 * wr + 16 * m + c16, q);
 #pragma unroll
-        for (int n = 0; n < 4; ++n) offL[n] = TILE_ROWS * KBLK + lds_sw(64 * wc + 16 * n + c16, q);
+        for (int n = 0; n < NN; ++n) offL[n] = TILE_ROWS * KBLK + lds_sw(LSPAN * wc + 16 * n + c16, q);
         const int offI = 2 * TILE_ROWS * KBLK + 16 * q;
 
         // Two stages: step s waits for its own fetches of block s (the only ones outstanding),
@@ -614,15 +620,15 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
             if (s + 1 < a.KB) issue(s + 1);
             const char *st_ = stage_at(s);
             const v4i fi = *reinterpret_cast<const v4i *>(st_ + offI);
-            v4i fa[4], fb[4];
+            v4i fa[4], fb[NN];
 #pragma unroll
             for (int m = 0; m < 4; ++m) fa[m] = *reinterpret_cast<const v4i *>(st_ + offJ[m]) & fi;
 #pragma unroll
-            for (int n = 0; n < 4; ++n) fb[n] = *reinterpret_cast<const v4i *>(st_ + offL[n]);
+            for (int n = 0; n < NN; ++n) fb[n] = *reinterpret_cast<const v4i *>(st_ + offL[n]);
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int n = 0; n < 4; ++n) {
+                for (int n = 0; n < NN; ++n) {
                     const v8i a8{fa[m][0], fa[m][1], fa[m][2], fa[m][3], 0, 0, 0, 0};
                     const v8i b8{fb[n][0], fb[n][1], fb[n][2], fb[n][3], 0, 0, 0, 0};
                     acc[m][n] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, b8, acc[m][n], 4, 4, 0, 0, 0, 0);
@@ -631,16 +637,16 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
 #pragma unroll
-                    for (int n = 0; n < 4; ++n) acc[m][n] = acc[m][n] * 4096.0f;
+                    for (int n = 0; n < NN; ++n) acc[m][n] = acc[m][n] * 4096.0f;
             }
         }
 
         // ---------------------------------------------------------------- epilogue
-        v4i cnt[4][4];
+        v4i cnt[4][NN];
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n)
+            for (int n = 0; n < NN; ++n)
 #pragma unroll
                 for (int x = 0; x < 4; ++x) {
                     const uint32_t uu = (uint32_t)acc[m][n][x];
@@ -652,10 +658,10 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int n = 0; n < 4; ++n)
+                for (int n = 0; n < NN; ++n)
 #pragma unroll
                     for (int x = 0; x < 4; ++x) {
-                        const int j = jvar(m, x), l = lb * M1_V + 64 * wc + 16 * n + c16;
+                        const int j = jvar(m, x), l = lb * M1_V + LSPAN * wc + 16 * n + c16;
                         if (!(i < j && j < l && l < a.p)) continue;
                         int32_t *o = a.counts_out + ((int64_t)j * a.p + l) * 2 * 8;
                         const uint32_t v = (uint32_t)cnt[m][n][x] >> 2;
@@ -663,41 +669,34 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
                         o[8] = (int32_t)(v >> 16);
                     }
         }
-        int lv[4];
+        int lv[NN];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) lv[n] = lb * M1_V + 64 * wc + 16 * n + c16;
+        for (int n = 0; n < NN; ++n) lv[n] = lb * M1_V + LSPAN * wc + 16 * n + c16;
         const uint32_t Mi = repack(margr[(int64_t)i * C]);
         const uint32_t Ni1 = Ntot - Mi;                     // class sizes of x_i = 1
-        uint32_t Ml[4], Nil[4], Ail[4];
-        float Fil[4], gL[4], thrL[4];
+        uint32_t Ml[NN], Nil[NN];
+        float Fil[NN], gL_read[NN];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
+        for (int n = 0; n < NN; ++n) {
             const int l = clampv(lv[n]);
             Ml[n] = repack(margr[(int64_t)l * C]);
             const int ii = i < l ? i : l, ll = i < l ? l : i;
             Nil[n] = repack(ptab[(int64_t)ii * a.p_pad + ll]);
-            Ail[n] = Ml[n] - Nil[n];                        // x_i = 1, x_l = 0
             Fil[n] = F2[(int64_t)ii * a.p_pad + ll];
-            const float g = key_f32(a.G32[l]);
-            gL[n] = g;
-            thrL[n] = g - win3(a.w_abs, g);
+            gL_read[n] = key_f32(a.G32[l]);
         }
         const float Gi = key_f32(a.G32[i]);
-        float thrI = Gi - win3(a.w_abs, Gi);
         struct JData {
-            uint32_t Nij[4], Aij[4], Cij[4];   // N(0,0); x_i = 0, x_j = 1; x_i = 1, x_j = 1
+            uint32_t Nij[4], Mj[4];   // N(0,0) of (i, j); bin-0 count of j
             float F[4], g[4];
         };
         auto load_j = [&](int m, JData &d) {
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
                 const int j = clampv(jvar(m, x));
-                const uint32_t Mj = repack(margr[(int64_t)j * C]);
+                d.Mj[x] = repack(margr[(int64_t)j * C]);
                 const int ii = i < j ? i : j, jj = i < j ? j : i;
-                const uint32_t nij = repack(ptab[(int64_t)ii * a.p_pad + jj]);
-                d.Nij[x] = nij;
-                d.Aij[x] = Mi - nij;
-                d.Cij[x] = Ni1 - (Mj - nij);
+                d.Nij[x] = repack(ptab[(int64_t)ii * a.p_pad + jj]);
                 d.F[x] = F2[(int64_t)ii * a.p_pad + jj];
                 d.g[x] = key_f32(a.G32[j]);
             }
@@ -716,145 +715,128 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m1(Sweep3mArgs a)
             V[1] = jd.Nij[x] - D;                       // T001
             V[2] = Nil[n] - D;                          // T010
             V[3] = Njl - D;                             // T100
-            V[4] = jd.Aij[x] - V[2];                    // T011
-            V[5] = (Ni1 - jd.Cij[x]) - V[3];            // T101: Mj - Nij = Ni1 - Cij (x_i = 1, x_j = 0)
-            V[6] = Ail[n] - V[3];                       // T110
-            V[7] = jd.Cij[x] - V[6];                    // T111
+            const uint32_t Bj = jd.Mj[x] - jd.Nij[x];   // x_i = 1, x_j = 0
+            V[4] = (Mi - jd.Nij[x]) - V[2];             // T011
+            V[5] = Bj - V[3];                           // T101
+            V[6] = (Ml[n] - Nil[n]) - V[3];             // T110
+            V[7] = (Ni1 - Bj) - V[6];                   // T111
             // an invalid triple may combine unrelated tables: its counts are not counts
 #pragma unroll
             for (int k = 0; k < 8; ++k) V[k] = valid ? V[k] : 0u;
             return vox_sum<T, 8>(V, smem);
         };
 
-        float mi = -INFINITY, mj[4][4], ml[4];
+        // One pass, row by row (block row m: the j(m, x) of the lane's q): the F of the row's
+        // triples are kept, the maxima of the row's members reduced over the wave, and the row's
+        // appends decided against thresholds that are the larger of the maximum read before the
+        // tile and the wave's maximum so far (both below the final maximum, so every triple
+        // within the window of the final maximum is appended); one slot reservation per row.
+        float mi = -INFINITY, ml[NN];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) ml[n] = -INFINITY;
-        bool hot = false;
+        for (int n = 0; n < NN; ++n) ml[n] = -INFINITY;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             JData jd;
             load_j(m, jd);
-            float mjx[4], thrJ[4];
+            float F3r[NN][4], Fjlr[NN][4], mjx[4];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                mjx[x] = -INFINITY;
-                thrJ[x] = jd.g[x] - win3(a.w_abs, jd.g[x]);
-            }
+            for (int x = 0; x < 4; ++x) mjx[x] = -INFINITY;
 #pragma unroll
-            for (int n = 0; n < 4; ++n) {
+            for (int n = 0; n < NN; ++n) {
+#pragma unroll
+                for (int x = 0; x < 4; ++x) F3r[n][x] = Fjlr[n][x] = 0.f;
                 // wave-uniform skip of a block without any valid triple
                 if (!__any(i < jvar(m, 3) && jvar(m, 0) < lv[n] && lv[n] < a.p)) continue;
 #pragma unroll
                 for (int x = 0; x < 4; ++x) {
                     const int jraw = jvar(m, x);
                     const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
-                    float Fjl;
-                    const float F3 = triple(m, n, x, jd, Fjl);
-                    const float gi = valid ? Fjl - F3 : -INFINITY;       // gain of x_i given (x_j, x_l)
-                    const float gj = valid ? Fil[n] - F3 : -INFINITY;    // gain of x_j given (x_i, x_l)
-                    const float gl = valid ? jd.F[x] - F3 : -INFINITY;   // gain of x_l given (x_i, x_j)
-                    mi = fmaxf(mi, gi);
-                    mjx[x] = fmaxf(mjx[x], gj);
-                    ml[n] = fmaxf(ml[n], gl);
-                    hot |= (gi >= thrI) | (gj >= thrJ[x]) | (gl >= thrL[n]);
+                    const float F3 = triple(m, n, x, jd, Fjlr[n][x]);
+                    F3r[n][x] = F3;
+                    mi = fmaxf(mi, valid ? Fjlr[n][x] - F3 : -INFINITY);   // gain of x_i given (x_j, x_l)
+                    mjx[x] = fmaxf(mjx[x], valid ? Fil[n] - F3 : -INFINITY);  // gain of x_j given (x_i, x_l)
+                    ml[n] = fmaxf(ml[n], valid ? jd.F[x] - F3 : -INFINITY);  // gain of x_l given (x_i, x_j)
                 }
             }
-            // j(m, x) is shared by the 16 lanes of one q
+            // wave maxima so far: i over all lanes, j(m, x) over the 16 lanes of one q, l_n over
+            // the lanes of one c16
+            float wi = mi, wj[4], wl[NN];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) wi = fmaxf(wi, __shfl_xor(wi, o));
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
                 float y = mjx[x];
                 y = fmaxf(y, __shfl_xor(y, 1));
                 y = fmaxf(y, __shfl_xor(y, 2));
                 y = fmaxf(y, __shfl_xor(y, 4));
-                mj[m][x] = fmaxf(y, __shfl_xor(y, 8));
+                wj[x] = fmaxf(y, __shfl_xor(y, 8));
+            }
+#pragma unroll
+            for (int n = 0; n < NN; ++n) {
+                float y = ml[n];
+                y = fmaxf(y, __shfl_xor(y, 16));
+                wl[n] = fmaxf(y, __shfl_xor(y, 32));
+            }
+            const float tI = a.collect ? Gi : fmaxf(Gi, wi);
+            const float thI = tI - win3(a.w_abs, tI);
+            float thJ[4], thL[NN];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                const float tJ = a.collect ? jd.g[x] : fmaxf(jd.g[x], wj[x]);
+                thJ[x] = tJ - win3(a.w_abs, tJ);
+            }
+#pragma unroll
+            for (int n = 0; n < NN; ++n) {
+                const float tL = a.collect ? gL_read[n] : fmaxf(gL_read[n], wl[n]);
+                thL[n] = tL - win3(a.w_abs, tL);
+            }
+            uint64_t sel = 0;   // bit 3 (4 n + x) + member
+#pragma unroll
+            for (int n = 0; n < NN; ++n)
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    const int jraw = jvar(m, x);
+                    const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
+                    const int b = 3 * (4 * n + x);
+                    if (valid && Fjlr[n][x] - F3r[n][x] >= thI) sel |= 1ull << b;
+                    if (valid && Fil[n] - F3r[n][x] >= thJ[x]) sel |= 2ull << b;
+                    if (valid && jd.F[x] - F3r[n][x] >= thL[n]) sel |= 4ull << b;
+                }
+            uint32_t at = reserve_slots(&a.st->n_cand, (uint32_t)__popcll(sel), lane);
+            if (sel) {
+#pragma unroll
+                for (int n = 0; n < NN; ++n)
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) {
+                        const int j = jvar(m, x), l = lv[n], b = 3 * (4 * n + x);
+                        const float F3 = F3r[n][x];
+                        if (sel & (1ull << b)) put(a, r, at++, i, ((uint32_t)j << 16) | (uint32_t)l, Fjlr[n][x] - F3);
+                        if (sel & (2ull << b)) put(a, r, at++, j, ((uint32_t)i << 16) | (uint32_t)l, Fil[n] - F3);
+                        if (sel & (4ull << b)) put(a, r, at++, l, ((uint32_t)i << 16) | (uint32_t)j, jd.F[x] - F3);
+                    }
+            }
+            // j(m, x) appears in this row only: its maximum goes out now
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                const int j = jvar(m, x);
+                if (!a.collect && c16 == 0 && j < a.p && wj[x] > jd.g[x]) atomicMax(&a.G32[j], f32_key(wj[x]));
             }
         }
         // i is the tile's; l_n is shared by the lanes of one c16
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) mi = fmaxf(mi, __shfl_xor(mi, o));
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
+        for (int n = 0; n < NN; ++n) {
             float y = ml[n];
             y = fmaxf(y, __shfl_xor(y, 16));
             ml[n] = fmaxf(y, __shfl_xor(y, 32));
-        }
-        if (__any(hot)) {
-            {
-                const float g = key_f32(a.G32[i]);
-                const float top = a.collect ? g : fmaxf(g, mi);
-                thrI = top - win3(a.w_abs, top);
-            }
-#pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                const float g = key_f32(a.G32[clampv(lv[n])]);
-                const float top = a.collect ? g : fmaxf(g, ml[n]);
-                thrL[n] = top - win3(a.w_abs, top);
-            }
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-#pragma unroll
-                for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(cnt[m][n]) : : "memory");
-            // per block (m, n): the four triples' gains, which members append (bit 3 x + member),
-            // one slot reservation for the wave, then the records
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                JData jd;
-                load_j(m, jd);
-                float thrJ[4];
-#pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    const float g = key_f32(a.G32[clampv(jvar(m, x))]);
-                    const float top = a.collect ? g : fmaxf(g, mj[m][x]);
-                    thrJ[x] = top - win3(a.w_abs, top);
-                }
-#pragma unroll
-                for (int n = 0; n < 4; ++n) {
-                    if (!__any(i < jvar(m, 3) && jvar(m, 0) < lv[n] && lv[n] < a.p)) continue;   // as in the first pass
-                    uint32_t sel = 0;
-                    float gI[4], gJ[4], gL[4];
-#pragma unroll
-                    for (int x = 0; x < 4; ++x) {
-                        const int jraw = jvar(m, x);
-                        const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
-                        float Fjl;
-                        const float F3 = triple(m, n, x, jd, Fjl);
-                        gI[x] = Fjl - F3;
-                        gJ[x] = Fil[n] - F3;
-                        gL[x] = jd.F[x] - F3;
-                        if (valid && gI[x] >= thrI) sel |= 1u << (3 * x);
-                        if (valid && gJ[x] >= thrJ[x]) sel |= 2u << (3 * x);
-                        if (valid && gL[x] >= thrL[n]) sel |= 4u << (3 * x);
-                    }
-                    uint32_t at = reserve_slots(&a.st->n_cand, __popc(sel), lane);
-                    if (sel) {
-                        const int l = lv[n];
-#pragma unroll
-                        for (int x = 0; x < 4; ++x) {
-                            const int j = jvar(m, x);
-                            if (sel & (1u << (3 * x))) put(a, r, at++, i, ((uint32_t)j << 16) | (uint32_t)l, gI[x]);
-                            if (sel & (2u << (3 * x))) put(a, r, at++, j, ((uint32_t)i << 16) | (uint32_t)l, gJ[x]);
-                            if (sel & (4u << (3 * x))) put(a, r, at++, l, ((uint32_t)i << 16) | (uint32_t)j, gL[x]);
-                        }
-                    }
-                }
-            }
         }
         if (a.collect) continue;
         // only where the tile raised the maximum read before (maxima only grow)
         if (lane == 0 && mi > Gi) atomicMax(&a.G32[i], f32_key(mi));
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                const int j = jvar(m, x);
-                if (c16 == 0 && j < a.p && mj[m][x] > -INFINITY) {
-                    const float g = key_f32(a.G32[j]);
-                    if (mj[m][x] > g) atomicMax(&a.G32[j], f32_key(mj[m][x]));
-                }
-            }
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-            if (q == 0 && ml[n] > gL[n]) atomicMax(&a.G32[lv[n]], f32_key(ml[n]));
+        for (int n = 0; n < NN; ++n)
+            if (q == 0 && ml[n] > gL_read[n]) atomicMax(&a.G32[lv[n]], f32_key(ml[n]));
     }
 }
 
@@ -917,11 +899,12 @@ hipError_t m3_launch(const Problem &P, int r0, int nr, bool collect, int32_t *co
     const size_t lds = sweep3m_lds_of(T, W, (int)L.N);
     a.stage_off = (int)m1_stage_off(T, (int)L.N);
     a.snext_off = (int)(lds - 16);
-    auto kern = W == 1 ? (counts_out ? k_sweep3m1<T, true> : k_sweep3m1<T>)
+    constexpr int nwv = 4;
+    auto kern = W == 1 ? (counts_out ? k_sweep3m1<T, true, nwv> : k_sweep3m1<T, false, nwv>)
                        : (counts_out ? k_sweep3m<T, true> : k_sweep3m<T>);
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(P.workgroups > 0 ? P.workgroups : 512), dim3(M3_THREADS), lds, P.stream, a);
+    hipLaunchKernelGGL(kern, dim3(P.workgroups > 0 ? P.workgroups : 512), dim3(nwv * 64), lds, P.stream, a);
     return hipGetLastError();
 }
 
