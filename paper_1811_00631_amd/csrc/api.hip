@@ -537,6 +537,67 @@ extern "C" int mdfs_max_ig_noalloc(const mdfs_params *prm, const float *data, co
 
 extern "C" size_t mdfs_batch_workspace_size(void) { return 256; }
 
+// Side streams of the batched call: the per-problem kernels around the fused sweep (the encoding
+// before it; the collect pass, re-score and outputs after it) of different problems run on up to
+// four streams (the caller's and three side streams), so that their small launches overlap
+// instead of queueing one after another on the caller's stream.  One pool per host thread and
+// device, so that calls from several threads share no stream or event; created on the first call
+// that is not under stream capture (a call under capture with no pool yet runs on the caller's
+// stream alone); default priority; destroyed when the thread ends.
+constexpr int N_SIDE = 3;
+struct SidePool {
+    bool ok = false;
+    hipStream_t s[N_SIDE] = {};
+    hipEvent_t fork = nullptr, join[N_SIDE] = {};
+    ~SidePool()
+    {
+        if (!ok) return;
+        for (int i = 0; i < N_SIDE; ++i) {
+            (void)hipEventDestroy(join[i]);
+            (void)hipStreamDestroy(s[i]);
+        }
+        (void)hipEventDestroy(fork);
+    }
+};
+constexpr int SIDE_MAX_DEVICES = 64;
+static thread_local SidePool g_side[SIDE_MAX_DEVICES];
+
+static SidePool *side_pool(hipStream_t stream)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SIDE_MAX_DEVICES) return nullptr;
+    SidePool &sp = g_side[dev];
+    if (sp.ok) return &sp;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    bool good = hipEventCreateWithFlags(&sp.fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < N_SIDE && good; ++i)
+        good = hipStreamCreateWithFlags(&sp.s[i], hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&sp.join[i], hipEventDisableTiming) == hipSuccess;
+    if (!good) return nullptr;   // a partial pool is kept unused (not marked ok)
+    sp.ok = true;
+    return &sp;
+}
+
+// The side streams wait for the work enqueued so far on `stream` / `stream` waits for theirs.
+static hipError_t side_fork(const SidePool *sp, hipStream_t stream)
+{
+    if (!sp) return hipSuccess;
+    hipError_t e = hipEventRecord(sp->fork, stream);
+    for (int i = 0; i < N_SIDE && e == hipSuccess; ++i) e = hipStreamWaitEvent(sp->s[i], sp->fork, 0);
+    return e;
+}
+static hipError_t side_join(const SidePool *sp, hipStream_t stream)
+{
+    if (!sp) return hipSuccess;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < N_SIDE && e == hipSuccess; ++i) {
+        e = hipEventRecord(sp->join[i], sp->s[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(stream, sp->join[i], 0);
+    }
+    return e;
+}
+
 extern "C" int mdfs_max_ig_batch(int n, const mdfs_params *prm, const float *const *data, const uint8_t *const *y,
                                  const int64_t *n1, float *const *ig_max, int32_t *const *argmax,
                                  int32_t *const *argmax_disc, void *const *ws, const size_t *ws_bytes, void *batch_ws,
@@ -565,14 +626,24 @@ extern "C" int mdfs_max_ig_batch(int n, const mdfs_params *prm, const float *con
         if (Ps[(size_t)i].fp4 != Ps[0].fp4)
             return fail(MDFS_E_LIMIT, "problem %d: one encoding per batch (fp4 needs classes < 4096 objects)", i);
     }
+    // problem i's own kernels run on stream i mod 4 (0: the caller's)
+    const hipStream_t main_stream = static_cast<hipStream_t>(stream);
+    const SidePool *sp = n > 1 ? side_pool(main_stream) : nullptr;
+    auto on_stream = [&](int i) {
+        Problem P = Ps[(size_t)i];
+        if (sp && i % (N_SIDE + 1) != 0) P.stream = sp->s[i % (N_SIDE + 1) - 1];
+        return P;
+    };
     // per problem: status, class order (checked against n1 on the device), tables, encoding
+    LAUNCH(side_fork(sp, main_stream));
     for (int i = 0; i < n; ++i) {
-        const Problem &P = Ps[(size_t)i];
+        const Problem P = on_stream(i);
         LAUNCH(launch_init(P));
         LAUNCH(launch_class_perm(P, y[i], n1[i]));
         LAUNCH(launch_tables(P));
         LAUNCH(launch_encode(P, data[i]));
     }
+    LAUNCH(side_join(sp, main_stream));
     // the maximum pass of every problem in one persistent launch
     Problem Q = Ps[0];
     Q.ws = static_cast<char *>(batch_ws);
@@ -580,14 +651,16 @@ extern "C" int mdfs_max_ig_batch(int n, const mdfs_params *prm, const float *con
     LAUNCH(launch_reset_queue(Q));
     LAUNCH(launch_sweep2_batch(pp.data(), n, static_cast<Status *>(batch_ws)));
     // per problem: the gated collect pass, then re-score and outputs
+    LAUNCH(side_fork(sp, main_stream));
     for (int i = 0; i < n; ++i) {
-        const Problem &P = Ps[(size_t)i];
+        const Problem P = on_stream(i);
         LAUNCH(launch_collect_decide(P, false));
         LAUNCH(launch_reset_candidates(P, true));
         int rc = sweep_pass(P, nullptr, -1, true);
         if (rc) return rc;
         LAUNCH(launch_finalize(P, ig_max[i], argmax ? argmax[i] : nullptr, argmax_disc ? argmax_disc[i] : nullptr));
     }
+    LAUNCH(side_join(sp, main_stream));
     g_err[0] = 0;
     return MDFS_OK;
 }
