@@ -535,7 +535,8 @@ def main():
     if k != 2 or args.workload != "headline":
         line["metric"] = f"k-tuples evaluated/sec (k={k} workload, informational)"
     if not args.no_cpu_baseline:
-        nv = min({2: args.cpu_vars, 3: 120, 4: 60, 5: 36}[k], w.n_var)
+        # samples of about 10 s of oracle work on the host
+        nv = min({2: args.cpu_vars, 3: 200, 4: 90, 5: 48}[k], w.n_var)
 
         def gpu_on_sample(n_vars, n_disc):
             o = mdfs.mdfs_max_ig(data[:n_vars].contiguous(), y, k, div, n_disc, w.xi, w.range_, w.seed,
