@@ -290,7 +290,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
         for (int c = 0; c < 3; ++c) Mi[c] = repack(margr[(int64_t)i * C + c]);
         // per-l data for the whole tile; per-j data (one m block at a time) loaded in the loops
         uint32_t Ml[4][3], Pil[4][4];
-        float Fil[4], thrL[4], gL[4], gJ[4];
+        float Fil[4], gL[4], gJ[4];
         struct JData {
             uint32_t M[3], P[4];
             float F;
@@ -319,10 +319,8 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
             Fil[n] = F2[(int64_t)ii * a.p_pad + ll];
             const float g = key_f32(a.G32[l]);
             gL[n] = g;
-            thrL[n] = g - win3(a.w_abs, g);
         }
         const float Gi = key_f32(a.G32[i]);
-        float thrI = Gi - win3(a.w_abs, Gi);
 
         // F3 of triple (i, j_m, l_n) on the lane pair (e = 0, 1) and the parents' F
         auto triple = [&](int m, int n, const JData &jd, float &Fjl) -> float {
@@ -384,114 +382,81 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
             return f + swap1f(f);
         };
 
-        float mi = -INFINITY, mj[4], ml[4];
+        // One pass, row by row (block row m: the j_m of the lane's q): the row's triples are
+        // evaluated and their F kept, the maxima of the row's members reduced over the wave, and
+        // the row's appends decided against thresholds that are the larger of the maximum read
+        // before the tile and the wave's maximum so far (both below the final maximum, so every
+        // triple within the window of the final maximum is appended); one slot reservation per
+        // row; the j_m maximum goes out with its row.
+        float mi = -INFINITY, ml[4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) mj[m] = ml[m] = -INFINITY;
-        bool hot = false;
+        for (int n = 0; n < 4; ++n) ml[n] = -INFINITY;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             JData jd;
             load_j(m, jd);
-            const float thrJ = gJ[m] - win3(a.w_abs, gJ[m]);
+            float F3r[4], Fjlr[4], mjm = -INFINITY;
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
+                F3r[n] = Fjlr[n] = 0.f;
                 const bool valid = i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;
                 // wave-uniform skip of a block without any valid triple (near the diagonal of
                 // the (j, l) blocks and past p): its maxima would stay -inf
                 if (!__any(valid)) continue;
-                float Fjl;
-                const float F3 = triple(m, n, jd, Fjl);
-                const float gi = valid ? Fjl - F3 : -INFINITY;       // gain of x_i given (x_j, x_l)
-                const float gj = valid ? Fil[n] - F3 : -INFINITY;    // gain of x_j given (x_i, x_l)
-                const float gl = valid ? jd.F - F3 : -INFINITY;      // gain of x_l given (x_i, x_j)
-                mi = fmaxf(mi, gi);
-                mj[m] = fmaxf(mj[m], gj);
-                ml[n] = fmaxf(ml[n], gl);
-                hot |= (gi >= thrI) | (gj >= thrJ) | (gl >= thrL[n]);
+                F3r[n] = triple(m, n, jd, Fjlr[n]);
+                mi = fmaxf(mi, valid ? Fjlr[n] - F3r[n] : -INFINITY);     // gain of x_i given (x_j, x_l)
+                mjm = fmaxf(mjm, valid ? Fil[n] - F3r[n] : -INFINITY);    // gain of x_j given (x_i, x_l)
+                ml[n] = fmaxf(ml[n], valid ? jd.F - F3r[n] : -INFINITY);  // gain of x_l given (x_i, x_j)
             }
+            // wave maxima so far: i over all lanes; j_m over the lanes of one q; l_n over the
+            // lanes of one c16 / 2 (the two lanes of a pair hold the same values)
+            float wi = mi, wj = mjm, wl[4];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) wi = fmaxf(wi, __shfl_xor(wi, o));
+            wj = fmaxf(wj, __shfl_xor(wj, 2));
+            wj = fmaxf(wj, __shfl_xor(wj, 4));
+            wj = fmaxf(wj, __shfl_xor(wj, 8));
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                float x = ml[n];
+                x = fmaxf(x, __shfl_xor(x, 16));
+                wl[n] = fmaxf(x, __shfl_xor(x, 32));
+            }
+            const float tI = a.collect ? Gi : fmaxf(Gi, wi), thI = tI - win3(a.w_abs, tI);
+            const float tJ = a.collect ? gJ[m] : fmaxf(gJ[m], wj), thJ = tJ - win3(a.w_abs, tJ);
+            uint32_t sel = 0;   // bit 3 n + member
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const bool valid = e == 0 && i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;   // one lane per triple
+                const float tL = a.collect ? gL[n] : fmaxf(gL[n], wl[n]), thL = tL - win3(a.w_abs, tL);
+                if (valid && Fjlr[n] - F3r[n] >= thI) sel |= 1u << (3 * n);
+                if (valid && Fil[n] - F3r[n] >= thJ) sel |= 2u << (3 * n);
+                if (valid && jd.F - F3r[n] >= thL) sel |= 4u << (3 * n);
+            }
+            uint32_t at = reserve_slots(&a.st->n_cand, __popc(sel), lane);
+            if (sel) {
+                const int j = jv[m];
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    const int l = lv[n];
+                    if (sel & (1u << (3 * n))) put(a, r, at++, i, ((uint32_t)j << 16) | (uint32_t)l, Fjlr[n] - F3r[n]);
+                    if (sel & (2u << (3 * n))) put(a, r, at++, j, ((uint32_t)i << 16) | (uint32_t)l, Fil[n] - F3r[n]);
+                    if (sel & (4u << (3 * n))) put(a, r, at++, l, ((uint32_t)i << 16) | (uint32_t)j, jd.F - F3r[n]);
+                }
+            }
+            if (!a.collect && c16 == 0 && jv[m] < a.p && wj > gJ[m]) atomicMax(&a.G32[jv[m]], f32_key(wj));
         }
-        // wave maxima: i is the tile's; j_m is shared by the lanes of one q; l_n by the lanes of
-        // one c16 / 2 (the two lanes of a pair hold the same values)
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) mi = fmaxf(mi, __shfl_xor(mi, o));
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            float x = mj[m];
-            x = fmaxf(x, __shfl_xor(x, 2));
-            x = fmaxf(x, __shfl_xor(x, 4));
-            mj[m] = fmaxf(x, __shfl_xor(x, 8));
-        }
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             float x = ml[n];
             x = fmaxf(x, __shfl_xor(x, 16));
             ml[n] = fmaxf(x, __shfl_xor(x, 32));
         }
-        if (__any(hot)) {
-            {
-                const float g = key_f32(a.G32[i]);
-                const float top = a.collect ? g : fmaxf(g, mi);
-                thrI = top - win3(a.w_abs, top);
-            }
-            float thrJ[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const float g = key_f32(a.G32[clampv(jv[m])]);
-                const float top = a.collect ? g : fmaxf(g, mj[m]);
-                thrJ[m] = top - win3(a.w_abs, top);
-            }
-#pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                const float g = key_f32(a.G32[clampv(lv[n])]);
-                const float top = a.collect ? g : fmaxf(g, ml[n]);
-                thrL[n] = top - win3(a.w_abs, top);
-            }
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-#pragma unroll
-                for (int n = 0; n < 4; ++n) asm volatile("" : "+v"(cnt[m][n]) : : "memory");
-            // per m: the four triples' gains, which members append (bit 3 n + member), one slot
-            // reservation for the wave, then the records
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                JData jd;
-                load_j(m, jd);
-                float gI[4], gJ[4], gL[4];
-                uint32_t sel = 0;
-#pragma unroll
-                for (int n = 0; n < 4; ++n) {
-                    gI[n] = gJ[n] = gL[n] = 0.f;
-                    const int j = jv[m], l = lv[n];
-                    if (!__any(i < j && j < l && l < a.p)) continue;   // as in the first pass
-                    float Fjl;
-                    const float F3 = triple(m, n, jd, Fjl);
-                    const bool valid = e == 0 && i < j && j < l && l < a.p;   // one lane per triple
-                    gI[n] = Fjl - F3;
-                    gJ[n] = Fil[n] - F3;
-                    gL[n] = jd.F - F3;
-                    if (valid && gI[n] >= thrI) sel |= 1u << (3 * n);
-                    if (valid && gJ[n] >= thrJ[m]) sel |= 2u << (3 * n);
-                    if (valid && gL[n] >= thrL[n]) sel |= 4u << (3 * n);
-                }
-                uint32_t at = reserve_slots(&a.st->n_cand, __popc(sel), lane);
-                if (sel) {
-                    const int j = jv[m];
-#pragma unroll
-                    for (int n = 0; n < 4; ++n) {
-                        const int l = lv[n];
-                        if (sel & (1u << (3 * n))) put(a, r, at++, i, ((uint32_t)j << 16) | (uint32_t)l, gI[n]);
-                        if (sel & (2u << (3 * n))) put(a, r, at++, j, ((uint32_t)i << 16) | (uint32_t)l, gJ[n]);
-                        if (sel & (4u << (3 * n))) put(a, r, at++, l, ((uint32_t)i << 16) | (uint32_t)j, gL[n]);
-                    }
-                }
-            }
-        }
         if (a.collect) continue;
         // only where the tile raised the maximum read before (maxima only grow)
         if (lane == 0 && mi > Gi) atomicMax(&a.G32[i], f32_key(mi));
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            if (c16 == 0 && mj[m] > gJ[m]) atomicMax(&a.G32[jv[m]], f32_key(mj[m]));
 #pragma unroll
         for (int n = 0; n < 4; ++n)
             if (q == 0 && e == 0 && ml[n] > gL[n]) atomicMax(&a.G32[lv[n]], f32_key(ml[n]));
@@ -672,17 +637,20 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
         int lv[NN];
 #pragma unroll
         for (int n = 0; n < NN; ++n) lv[n] = lb * M1_V + LSPAN * wc + 16 * n + c16;
-        const uint32_t Mi = repack(margr[(int64_t)i * C]);
+        // pair-table offsets fit 32 bits (p_pad^2 <= 2^24): uniform base + 32-bit lane offset
+        const uint32_t pp32 = (uint32_t)a.p_pad;
+        auto pidx = [pp32](int u, int v) -> uint32_t { return (uint32_t)u * pp32 + (uint32_t)v; };
+        const uint32_t Mi = repack(margr[(uint32_t)i * C]);
         const uint32_t Ni1 = Ntot - Mi;                     // class sizes of x_i = 1
         uint32_t Ml[NN], Nil[NN];
         float Fil[NN], gL_read[NN];
 #pragma unroll
         for (int n = 0; n < NN; ++n) {
             const int l = clampv(lv[n]);
-            Ml[n] = repack(margr[(int64_t)l * C]);
+            Ml[n] = repack(margr[(uint32_t)l * C]);
             const int ii = i < l ? i : l, ll = i < l ? l : i;
-            Nil[n] = repack(ptab[(int64_t)ii * a.p_pad + ll]);
-            Fil[n] = F2[(int64_t)ii * a.p_pad + ll];
+            Nil[n] = repack(ptab[pidx(ii, ll)]);
+            Fil[n] = F2[pidx(ii, ll)];
             gL_read[n] = key_f32(a.G32[l]);
         }
         const float Gi = key_f32(a.G32[i]);
@@ -694,10 +662,10 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
                 const int j = clampv(jvar(m, x));
-                d.Mj[x] = repack(margr[(int64_t)j * C]);
+                d.Mj[x] = repack(margr[(uint32_t)j * C]);
                 const int ii = i < j ? i : j, jj = i < j ? j : i;
-                d.Nij[x] = repack(ptab[(int64_t)ii * a.p_pad + jj]);
-                d.F[x] = F2[(int64_t)ii * a.p_pad + jj];
+                d.Nij[x] = repack(ptab[pidx(ii, jj)]);
+                d.F[x] = F2[pidx(ii, jj)];
                 d.g[x] = key_f32(a.G32[j]);
             }
         };
@@ -707,8 +675,8 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
             const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
             const int j = clampv(jraw), l = clampv(lv[n]);
             const int jj = j < l ? j : l, ll = j < l ? l : j;
-            const uint32_t Njl = repack(ptab[(int64_t)jj * a.p_pad + ll]);
-            Fjl = F2[(int64_t)jj * a.p_pad + ll];
+            const uint32_t Njl = repack(ptab[pidx(jj, ll)]);
+            Fjl = F2[pidx(jj, ll)];
             const uint32_t D = (uint32_t)cnt[m][n][x];
             uint32_t V[8];
             V[0] = D;                                   // T000
