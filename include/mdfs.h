@@ -31,7 +31,7 @@
  *     on `stream`.
  *   * Supported sizes: 2 <= n_obj <= 16384 and n_obj >= divisions+1; each class < 32768
  *     objects; k in {1, 2, 3, 4, 5} (the paper's limit); divisions in {1, 2, 4} (2, 3 or 5
- *     classes); n_disc >= 1; disc_offset >= 0; for k = 3, n_var <= 4096; for k = 4,
+ *     classes); n_disc >= 1; disc_offset >= 0; for k = 3, n_var <= 8192; for k = 4,
  *     n_var <= 2048; for k = 5, n_var <= 512 (the partner tuple of a k >= 4 candidate travels
  *     as its 32-bit lexicographic rank); the k >= 4 engines keep the entropy tables (16 bytes per
  *     object) in LDS, which bounds n_obj near 8000 there.  Beyond these, MDFS_E_LIMIT.

@@ -30,7 +30,8 @@ constexpr int TILE_ROWS = 128;
 constexpr int VAR_PAD = 128;
 constexpr int MAX_NOBJ = 16384;
 constexpr int MAX_CLASS_OBJ = 32767;
-constexpr int MAX_K3_VARS = 4096;
+// k = 3: the matrix-core tile list holds j blocks of 32 variables below 256 (p <= 8192)
+constexpr int MAX_K3_VARS = 8192;
 // k >= 4 candidates carry the lexicographic rank of their partner tuple in 32 bits:
 // C(2048, 3) and C(512, 4) are below 2^32
 constexpr int MAX_K4_VARS = 2048;

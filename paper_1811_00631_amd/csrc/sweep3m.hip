@@ -637,7 +637,7 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
         int lv[NN];
 #pragma unroll
         for (int n = 0; n < NN; ++n) lv[n] = lb * M1_V + LSPAN * wc + 16 * n + c16;
-        // pair-table offsets fit 32 bits (p_pad^2 <= 2^24): uniform base + 32-bit lane offset
+        // pair-table offsets fit 32 bits (p_pad^2 <= 2^26): uniform base + 32-bit lane offset
         const uint32_t pp32 = (uint32_t)a.p_pad;
         auto pidx = [pp32](int u, int v) -> uint32_t { return (uint32_t)u * pp32 + (uint32_t)v; };
         const uint32_t Mi = repack(margr[(uint32_t)i * C]);

@@ -150,6 +150,24 @@ def test_k3_engines_agree_bit_for_bit_on_argmax(mdfs_gpu, divisions):
         assert np.array_equal(x, z)
 
 
+def test_k3_at_the_largest_variable_count(mdfs_gpu):
+    # p = 8192, the limit: the last j block of the matrix-core tile list and pair tables of
+    # 2^26 entries; both engines agree on every variable and the planted triple is found
+    p = 8192
+    w = workloads.parity3(seed=36, n_obj=256, n_var=p, divisions=1, n_disc=1)
+    print(f"k3 p={p}", flush=True)
+    a = run3(mdfs_gpu, w, engine="mfma_fp4")
+    b = run3(mdfs_gpu, w, engine="bitset")
+    for x, z in zip(a, b):
+        assert np.array_equal(x, z)
+    assert set(np.argsort(-a[0])[:3].tolist()) == {0, 1, 2}
+    assert a[1][0].tolist() == [1, 2]
+    import ctypes
+    prm = mdfs_gpu.make_params(256, p + 1, 3, 1, 1)
+    null = ctypes.c_void_p(0)
+    assert mdfs_gpu.load().mdfs_max_ig(ctypes.byref(prm), null, null, null, null, null, null, 0, null) == -10
+
+
 def test_k3_mfma_engine_limits(mdfs_gpu):
     w = workloads.parity3(seed=35, n_obj=200, n_var=12, divisions=4, n_disc=1)
     with pytest.raises(mdfs_gpu.MdfsError) as e:
