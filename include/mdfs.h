@@ -182,18 +182,25 @@ int mdfs_max_ig_async(const mdfs_params *prm, const float *data, const uint8_t *
 int mdfs_max_ig_noalloc(const mdfs_params *prm, const float *data, const uint8_t *y, int64_t n1, float *ig_max,
                         int32_t *argmax, int32_t *argmax_disc, int32_t *status_out, void *stream);
 
-/* Several k = 2 problems (datasets of uneven N and p, their own discretisation counts) in one
- * asynchronous call whose maximum pass is ONE persistent launch over the concatenated tiles of all
- * problems, so small problems share the GPU instead of leaving it idle between launches.
- *   n               : 1 <= n <= 12 problems; all with k = 2, the same divisions, the same
- *                     encoding (every class < 4096 objects for fp4, or engine mfma for int8) and
- *                     the same super-tile side (tile bits 0-7; the wave bits are not used here)
+/* Several problems (datasets of uneven N and p, their own discretisation counts) in one
+ * asynchronous call.  k = 2: the maximum pass is ONE persistent launch over the concatenated
+ * tiles of all problems, so small problems share the GPU instead of leaving it idle between
+ * launches, and each problem's own kernels (encoding, collect pass, re-score) run on one of four
+ * streams.  Other k: each problem's calls run on one of four streams (the caller's and three
+ * side streams of a per-thread pool, forked from and joined back into `stream`), so problems that
+ * do not fill the GPU run concurrently.
+ *   n               : 1 <= n <= 12 problems, all with the same k; for k = 2 also the same
+ *                     divisions, the same encoding (every class < 4096 objects for fp4, or
+ *                     engine mfma for int8) and the same super-tile side (tile bits 0-7; the
+ *                     wave bits are not used here)
  *   prm[i], data[i], y[i], n1[i], ig_max[i], argmax[i], argmax_disc[i], ws[i], ws_bytes[i]:
  *                     problem i, as for mdfs_max_ig_async (its own workspace)
- *   batch_ws        : device memory of mdfs_batch_workspace_size() bytes (the work counters)
- * Per-problem status: mdfs_check_status(&prm[i], ws[i], ...).  Returns MDFS_E_LIMIT for mixed
- * divisions, encodings or super-tiles; other argument errors as mdfs_max_ig_async, before anything is
- * enqueued.  Enqueued on `stream` with no host synchronisation (capturable). */
+ *   batch_ws        : device memory of mdfs_batch_workspace_size() bytes (the work counters of
+ *                     the k = 2 fused launch)
+ * Per-problem status: mdfs_check_status(&prm[i], ws[i], ...).  Returns MDFS_E_K for mixed k,
+ * MDFS_E_LIMIT for mixed divisions, encodings or super-tiles at k = 2; other argument errors as
+ * mdfs_max_ig_async, before anything is enqueued.  Enqueued on `stream` with no host
+ * synchronisation (capturable once a call outside capture has created the thread's streams). */
 size_t mdfs_batch_workspace_size(void);
 int mdfs_max_ig_batch(int n, const mdfs_params *prm, const float *const *data, const uint8_t *const *y,
                       const int64_t *n1, float *const *ig_max, int32_t *const *argmax, int32_t *const *argmax_disc,

@@ -598,6 +598,42 @@ static hipError_t side_join(const SidePool *sp, hipStream_t stream)
     return e;
 }
 
+// A batch of k >= 3 problems: every problem is validated first (so that an argument error
+// leaves nothing enqueued), then each runs the asynchronous call's launches on stream i mod 4,
+// forked from and joined back into the caller's stream: small problems that do not fill the
+// GPU run concurrently.
+static int batch_streams(int n, const mdfs_params *prm, const float *const *data, const uint8_t *const *y,
+                         const int64_t *n1, float *const *ig_max, int32_t *const *argmax,
+                         int32_t *const *argmax_disc, void *const *ws, const size_t *ws_bytes, void *stream)
+{
+    for (int i = 0; i < n; ++i) {
+        int rc = check_params(&prm[i]);
+        if (rc) return rc;
+        if (prm[i].k != prm[0].k) return fail(MDFS_E_K, "problem %d: one k per batch", i);
+    }
+    for (int i = 0; i < n; ++i) {
+        if (prm[i].flags & MDFS_FLAG_TIMING) return fail(MDFS_E_ARG, "timing is not available in a batch");
+        if (!data[i] || !y[i] || !ig_max[i] || !ws[i]) return fail(MDFS_E_ARG, "problem %d: null pointer", i);
+        if (n1[i] < 1 || n1[i] >= prm[i].n_obj)
+            return fail(MDFS_E_Y, "problem %d: n1=%lld: both classes must be non-empty", i, (long long)n1[i]);
+        if (ws_bytes[i] < layout_of(&prm[i]).total)
+            return fail(MDFS_E_NOMEM, "problem %d: workspace %zu bytes < required %zu", i, ws_bytes[i],
+                        layout_of(&prm[i]).total);
+    }
+    const hipStream_t main_stream = static_cast<hipStream_t>(stream);
+    const SidePool *sp = n > 1 ? side_pool(main_stream) : nullptr;
+    LAUNCH(side_fork(sp, main_stream));
+    for (int i = 0; i < n; ++i) {
+        const hipStream_t st = (sp && i % (N_SIDE + 1) != 0) ? sp->s[i % (N_SIDE + 1) - 1] : main_stream;
+        const int rc = max_ig_async_impl(&prm[i], data[i], y[i], n1[i], ig_max[i], argmax ? argmax[i] : nullptr,
+                                         argmax_disc ? argmax_disc[i] : nullptr, ws[i], ws_bytes[i], st);
+        if (rc) return rc;
+    }
+    LAUNCH(side_join(sp, main_stream));
+    g_err[0] = 0;
+    return MDFS_OK;
+}
+
 extern "C" int mdfs_max_ig_batch(int n, const mdfs_params *prm, const float *const *data, const uint8_t *const *y,
                                  const int64_t *n1, float *const *ig_max, int32_t *const *argmax,
                                  int32_t *const *argmax_disc, void *const *ws, const size_t *ws_bytes, void *batch_ws,
@@ -608,12 +644,13 @@ extern "C" int mdfs_max_ig_batch(int n, const mdfs_params *prm, const float *con
         return fail(MDFS_E_ARG, "null pointer");
     if (batch_ws_bytes < sizeof(Status)) return fail(MDFS_E_NOMEM, "batch workspace %zu bytes < %zu", batch_ws_bytes,
                                                      sizeof(Status));
+    if (prm[0].k != 2) return batch_streams(n, prm, data, y, n1, ig_max, argmax, argmax_disc, ws, ws_bytes, stream);
     std::vector<Problem> Ps((size_t)n);
     std::vector<const Problem *> pp((size_t)n);
     for (int i = 0; i < n; ++i) {
         int rc = check_params(&prm[i]);
         if (rc) return rc;
-        if (prm[i].k != 2) return fail(MDFS_E_K, "problem %d: batches are built for k=2", i);
+        if (prm[i].k != 2) return fail(MDFS_E_K, "problem %d: k=%d in a batch of k=2 problems", i, prm[i].k);
         if (prm[i].divisions != prm[0].divisions) return fail(MDFS_E_LIMIT, "problem %d: one divisions per batch", i);
         if ((prm[i].tile & 0xff) != (prm[0].tile & 0xff))
             return fail(MDFS_E_LIMIT, "problem %d: one super-tile side per batch (the shared queue's unit)", i);

@@ -277,8 +277,9 @@ def mdfs_check_status(data_shape, k: int, divisions: int, n_disc: int, ws: torch
 
 def mdfs_max_ig_batch(datas, ys, n1s, k: int, divisions: int, n_discs, pseudocount: float = 0.25,
                       range_: float = 0.5, seeds=None, engine: str = "auto", workgroups: int = 0):
-    """Several k = 2 problems, one fused persistent sweep launch (no host synchronisation);
-    pseudocount and range_ may be one value or one per problem.  Returns
+    """Several problems with one k in one asynchronous call (no host synchronisation): for k = 2
+    one fused persistent sweep launch, for other k the problems' calls on four concurrent
+    streams; pseudocount and range_ may be one value or one per problem.  Returns
     [(ig, argmax, argmax_disc)] and the workspaces (for mdfs_check_status)."""
     n = len(datas)
     seeds = seeds if seeds is not None else [0] * n
