@@ -9,7 +9,7 @@
 //
 // Tile: one i; A rows (j, a, b) for 32 consecutive j (128 rows), B rows (l, e) for 64
 // consecutive l (128 rows).  The j rows and the two rows of i are staged in LDS (fetched
-// straight into LDS two K blocks ahead, as in the pair sweep) and ANDed when the A fragments
+// straight into LDS one K block ahead into a 2-stage ring) and ANDed when the A fragments
 // are read.  The remaining C^3 - W^3 voxels follow exactly from the three pair tables (from
 // the pair sweep of the same discretisation) and the marginals.  Epilogue: F3 = sum_v n_v h(p_v)
 // in float32 from the LDS tables; IG(i|j,l) = F(j,l) - F3 and likewise for j and l (equation
@@ -33,7 +33,7 @@ constexpr int M3_JV = 32;                        // j variables per A tile (4 ro
 constexpr int M3_LV = 64;                        // l variables per B tile (2 rows each)
 constexpr int M3_JROWS = 2 * M3_JV;              // one-hot rows of the j block
 constexpr int M3_STAGE = (M3_JROWS + TILE_ROWS) * KBLK + 2 * KBLK + 128;   // j rows | l rows | i rows | pad
-constexpr int M3_NSTAGE = 3;
+constexpr int M3_NSTAGE = 2;   // operand stages, fetched one K block ahead (3 stages: 2.4% slower)
 
 struct Sweep3mArgs {
     const int8_t *onehot;
@@ -173,7 +173,6 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
         // 13 fetches of 1 KB per K block: 4 for the 64 j rows, 8 for the 128 l rows (stage
         // rows 64..191), 1 for the two rows of i (lanes 0..7).  Wave w takes fetches w, w+4,
         // w+8, w+12 (wave 0 four, the others three).
-        const int nfetch = wave == 0 ? 4 : 3;
         auto issue = [&](int s_) {
             const int64_t kb_off = (int64_t)kblock(s_) * kstride;
             char *st_ = stage_at(s_);
@@ -212,19 +211,15 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
         for (int n = 0; n < 4; ++n) offL[n] = M3_JROWS * KBLK + lds_sw(wc * 64 + 16 * n + c16, q);
         const int offI = (M3_JROWS + TILE_ROWS) * KBLK + lds_sw(ia, q);
 
+        // Two stages: step s waits for its own fetches of block s (the only ones outstanding),
+        // passes a barrier (block s is complete, and every wave has finished reading block s-1,
+        // whose stage the fetch of block s+1 then takes) and fetches block s+1 before reading
+        // the fragments of block s.
         issue(0);
-        if (a.KB > 1) issue(1);
         for (int s = 0; s < a.KB; ++s) {
-            // this wave's fetches of block s complete (loads return in order); then a plain
-            // barrier (a fenced one would also drain the fetches of block s+1)
-            if (s + 1 < a.KB) {
-                if (nfetch == 4) __builtin_amdgcn_s_waitcnt(0x0F74);   // vmcnt(4)
-                else __builtin_amdgcn_s_waitcnt(0x0F73);               // vmcnt(3)
-            } else {
-                __builtin_amdgcn_s_waitcnt(0x0F70);
-            }
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
             __builtin_amdgcn_s_barrier();
-            if (s + 2 < a.KB) issue(s + 2);
+            if (s + 1 < a.KB) issue(s + 1);
             const char *st_ = stage_at(s);
             const v4i fi = *reinterpret_cast<const v4i *>(st_ + offI);
             v4i fa[4], fb[4];
