@@ -75,6 +75,29 @@ __device__ inline float win3(float w_abs, float g)
 __device__ inline uint32_t swap1(uint32_t x) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false); }
 __device__ inline float swap1f(float x) { return __builtin_bit_cast(float, swap1(__builtin_bit_cast(uint32_t, x))); }
 
+// Loads at 32-bit byte offsets from a wave-uniform base: a buffer resource over `bytes` bytes
+// (word 3: the 32-bit data format that raw loads take); a read past the end returns 0.  The
+// pair tables of one discretisation stay below 2^31 bytes (p_pad <= 8192).
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline uint32_t ld32(__amdgpu_buffer_rsrc_t rs, uint32_t off) { return __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0); }
+__device__ inline float ldf(__amdgpu_buffer_rsrc_t rs, uint32_t off) { return __builtin_bit_cast(float, ld32(rs, off)); }
+__device__ inline v4i ld128(__amdgpu_buffer_rsrc_t rs, uint32_t off)
+{
+    return __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+}
+
+// A value that every lane holds, made visibly uniform (scalar registers and loads downstream).
+__device__ inline int64_t uniform64(int64_t x)
+{
+    const uint64_t u = (uint64_t)x;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Sum of n h(p) over NV packed counts (4 n1) << 16 | 4 n0 with the fixed LDS table layout of
 // capacity T (EA at 0, EB at 4T, (L, Q) pairs at 8T); a packed 0 contributes exactly 0.
 template <int T, int NV>
@@ -143,7 +166,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
         __syncthreads();
         if (t == 0) *s_next = cancel_poll(a.cancel, taken++, a.st) ? a.n_tiles * a.nr : atomicAdd(&a.st->next_tile[0], 1u);
         __syncthreads();
-        const int64_t u_all = *s_next;
+        const int64_t u_all = uniform64(*s_next);
         if (u_all >= a.n_tiles * a.nr) break;
         // tile u of the list, under discretisation r = r0 + rr of the launch
         const int rr = (int)(u_all / a.n_tiles);
@@ -280,53 +303,54 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
         for (int n = 0; n < 4; ++n) lv[n] = lb * M3_LV + 32 * wc + 8 * n + (c16 >> 1);
         // indices past p are clamped for the loads; such triples are invalid and masked
         auto clampv = [&](int v) { return v < a.p ? v : a.p - 1; };
+        // pair data of (u, v): 2 x 2 counts at byte offset 16 (u p_pad + v), F at 4 (u p_pad + v);
+        // u < v for every valid triple (an invalid one may read the unwritten lower triangle,
+        // and its counts are masked); bases re-read as uniform (a resource sits in scalar registers)
+        const uint32_t pp = (uint32_t)a.p_pad;
+        const __amdgpu_buffer_rsrc_t rsP = rsrc(reinterpret_cast<const void *>(uniform64((int64_t)ptab)), 16u * pp * pp);
+        const __amdgpu_buffer_rsrc_t rsF = rsrc(reinterpret_cast<const void *>(uniform64((int64_t)F2)), 4u * pp * pp);
+        auto pair4 = [&](uint32_t uv, uint32_t (&d)[4]) {
+            const v4i pw = ld128(rsP, 16u * uv);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) d[x] = repack((uint32_t)pw[x]);
+        };
         uint32_t Mi[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) Mi[c] = repack(margr[(int64_t)i * C + c]);
         // per-l data for the whole tile; per-j data (one m block at a time) loaded in the loops
-        uint32_t Ml[4][3], Pil[4][4];
+        uint32_t Ml[4][3], Pil[4][4], lc[4];
         float Fil[4], gL[4], gJ[4];
         struct JData {
-            uint32_t M[3], P[4];
+            uint32_t M[3], P[4], jrow;
             float F;
         };
         auto load_j = [&](int m, JData &d) {
             const int j = clampv(jv[m]);
 #pragma unroll
             for (int c = 0; c < 3; ++c) d.M[c] = repack(margr[(int64_t)j * C + c]);
-            const int ii = i < j ? i : j, jj = i < j ? j : i;
-            const v4i pw = *reinterpret_cast<const v4i *>(ptab + ((int64_t)ii * a.p_pad + jj) * 4);
-#pragma unroll
-            for (int x = 0; x < 4; ++x) d.P[x] = repack((uint32_t)pw[x]);
-            d.F = F2[(int64_t)ii * a.p_pad + jj];
+            d.jrow = (uint32_t)j * pp;
+            pair4((uint32_t)i * pp + (uint32_t)j, d.P);
+            d.F = ldf(rsF, 4u * ((uint32_t)i * pp + (uint32_t)j));
         };
 #pragma unroll
         for (int m = 0; m < 4; ++m) gJ[m] = key_f32(a.G32[clampv(jv[m])]);
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             const int l = clampv(lv[n]);
+            lc[n] = (uint32_t)l;
 #pragma unroll
             for (int c = 0; c < 3; ++c) Ml[n][c] = repack(margr[(int64_t)l * C + c]);
-            const int ii = i < l ? i : l, ll = i < l ? l : i;
-            const v4i pw = *reinterpret_cast<const v4i *>(ptab + ((int64_t)ii * a.p_pad + ll) * 4);
-#pragma unroll
-            for (int x = 0; x < 4; ++x) Pil[n][x] = repack((uint32_t)pw[x]);
-            Fil[n] = F2[(int64_t)ii * a.p_pad + ll];
+            pair4((uint32_t)i * pp + lc[n], Pil[n]);
+            Fil[n] = ldf(rsF, 4u * ((uint32_t)i * pp + lc[n]));
             const float g = key_f32(a.G32[l]);
             gL[n] = g;
         }
         const float Gi = key_f32(a.G32[i]);
 
-        // F3 of triple (i, j_m, l_n) on the lane pair (e = 0, 1) and the parents' F
-        auto triple = [&](int m, int n, const JData &jd, float &Fjl) -> float {
+        // F3 of triple (i, j_m, l_n) on the lane pair (e = 0, 1) from the 2 x 2 direct counts dj
+        // of (j_m, l_n)
+        auto triple = [&](int m, int n, const JData &jd, const uint32_t (&dj)[4]) -> float {
             const bool valid = i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;
-            const int j = clampv(jv[m]), l = clampv(lv[n]);
-            const int jj = j < l ? j : l, ll = j < l ? l : j;
-            const v4i pw = *reinterpret_cast<const v4i *>(ptab + ((int64_t)jj * a.p_pad + ll) * 4);
-            Fjl = F2[(int64_t)jj * a.p_pad + ll];
-            uint32_t dj[4];
-#pragma unroll
-            for (int x = 0; x < 4; ++x) dj[x] = repack((uint32_t)pw[x]);
             uint32_t Nij[3][3], Nil[3][3], Njl[3][3];
             full3(jd.P, Mi, jd.M, Nij);
             full3(Pil[n], Mi, Ml[n], Nil);
@@ -377,12 +401,14 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
             return f + swap1f(f);
         };
 
-        // One pass, row by row (block row m: the j_m of the lane's q): the row's triples are
-        // evaluated and their F kept, the maxima of the row's members reduced over the wave, and
-        // the row's appends decided against thresholds that are the larger of the maximum read
-        // before the tile and the wave's maximum so far (both below the final maximum, so every
-        // triple within the window of the final maximum is appended); one slot reservation per
-        // row; the j_m maximum goes out with its row.
+        // One pass, row by row (block row m: the j_m of the lane's q): the row's (j, l) pair data
+        // are loaded first, all loads in flight together; the row's triples are evaluated and
+        // their F kept, the maxima of the row's members reduced over the wave, and the row's
+        // appends decided against thresholds that are the larger of the maximum read before the
+        // tile and the wave's maximum so far (both below the final maximum, so every triple
+        // within the window of the final maximum is appended); a row whose wave maxima all stay
+        // below their thresholds appends nothing and skips the selection; one slot reservation
+        // per row; the j_m maximum goes out with its row.
         float mi = -INFINITY, ml[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) ml[n] = -INFINITY;
@@ -390,15 +416,21 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
         for (int m = 0; m < 4; ++m) {
             JData jd;
             load_j(m, jd);
+            uint32_t Pjl[4][4];
             float F3r[4], Fjlr[4], mjm = -INFINITY;
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
-                F3r[n] = Fjlr[n] = 0.f;
+                pair4(jd.jrow + lc[n], Pjl[n]);
+                Fjlr[n] = ldf(rsF, 4u * (jd.jrow + lc[n]));
+            }
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                F3r[n] = 0.f;
                 const bool valid = i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;
                 // wave-uniform skip of a block without any valid triple (near the diagonal of
                 // the (j, l) blocks and past p): its maxima would stay -inf
                 if (!__any(valid)) continue;
-                F3r[n] = triple(m, n, jd, Fjlr[n]);
+                F3r[n] = triple(m, n, jd, Pjl[n]);
                 mi = fmaxf(mi, valid ? Fjlr[n] - F3r[n] : -INFINITY);     // gain of x_i given (x_j, x_l)
                 mjm = fmaxf(mjm, valid ? Fil[n] - F3r[n] : -INFINITY);    // gain of x_j given (x_i, x_l)
                 ml[n] = fmaxf(ml[n], valid ? jd.F - F3r[n] : -INFINITY);  // gain of x_l given (x_i, x_j)
@@ -419,24 +451,33 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
             }
             const float tI = a.collect ? Gi : fmaxf(Gi, wi), thI = tI - win3(a.w_abs, tI);
             const float tJ = a.collect ? gJ[m] : fmaxf(gJ[m], wj), thJ = tJ - win3(a.w_abs, tJ);
-            uint32_t sel = 0;   // bit 3 n + member
+            float thL[4];
+            bool hot = wi >= thI || wj >= thJ;
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
-                const bool valid = e == 0 && i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;   // one lane per triple
-                const float tL = a.collect ? gL[n] : fmaxf(gL[n], wl[n]), thL = tL - win3(a.w_abs, tL);
-                if (valid && Fjlr[n] - F3r[n] >= thI) sel |= 1u << (3 * n);
-                if (valid && Fil[n] - F3r[n] >= thJ) sel |= 2u << (3 * n);
-                if (valid && jd.F - F3r[n] >= thL) sel |= 4u << (3 * n);
+                const float tL = a.collect ? gL[n] : fmaxf(gL[n], wl[n]);
+                thL[n] = tL - win3(a.w_abs, tL);
+                hot |= wl[n] >= thL[n];
             }
-            uint32_t at = reserve_slots(&a.st->n_cand, __popc(sel), lane);
-            if (sel) {
-                const int j = jv[m];
+            if (__any(hot)) {
+                uint32_t sel = 0;   // bit 3 n + member
 #pragma unroll
                 for (int n = 0; n < 4; ++n) {
-                    const int l = lv[n];
-                    if (sel & (1u << (3 * n))) put(a, r, at++, i, ((uint32_t)j << 16) | (uint32_t)l, Fjlr[n] - F3r[n]);
-                    if (sel & (2u << (3 * n))) put(a, r, at++, j, ((uint32_t)i << 16) | (uint32_t)l, Fil[n] - F3r[n]);
-                    if (sel & (4u << (3 * n))) put(a, r, at++, l, ((uint32_t)i << 16) | (uint32_t)j, jd.F - F3r[n]);
+                    const bool valid = e == 0 && i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;   // one lane per triple
+                    if (valid && Fjlr[n] - F3r[n] >= thI) sel |= 1u << (3 * n);
+                    if (valid && Fil[n] - F3r[n] >= thJ) sel |= 2u << (3 * n);
+                    if (valid && jd.F - F3r[n] >= thL[n]) sel |= 4u << (3 * n);
+                }
+                uint32_t at = reserve_slots(&a.st->n_cand, __popc(sel), lane);
+                if (sel) {
+                    const int j = jv[m];
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) {
+                        const int l = lv[n];
+                        if (sel & (1u << (3 * n))) put(a, r, at++, i, ((uint32_t)j << 16) | (uint32_t)l, Fjlr[n] - F3r[n]);
+                        if (sel & (2u << (3 * n))) put(a, r, at++, j, ((uint32_t)i << 16) | (uint32_t)l, Fil[n] - F3r[n]);
+                        if (sel & (4u << (3 * n))) put(a, r, at++, l, ((uint32_t)i << 16) | (uint32_t)j, jd.F - F3r[n]);
+                    }
                 }
             }
             if (!a.collect && c16 == 0 && jv[m] < a.p && wj > gJ[m]) atomicMax(&a.G32[jv[m]], f32_key(wj));
@@ -511,7 +552,7 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
         __syncthreads();
         if (t == 0) *s_next = cancel_poll(a.cancel, taken++, a.st) ? a.n_tiles * a.nr : atomicAdd(&a.st->next_tile[0], 1u);
         __syncthreads();
-        const int64_t u_all = *s_next;
+        const int64_t u_all = uniform64(*s_next);
         if (u_all >= a.n_tiles * a.nr) break;
         // tile u of the list, under discretisation r = r0 + rr of the launch
         const int rr = (int)(u_all / a.n_tiles);
@@ -632,9 +673,17 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
         int lv[NN];
 #pragma unroll
         for (int n = 0; n < NN; ++n) lv[n] = lb * M1_V + LSPAN * wc + 16 * n + c16;
-        // pair-table offsets fit 32 bits (p_pad^2 <= 2^26): uniform base + 32-bit lane offset
-        const uint32_t pp32 = (uint32_t)a.p_pad;
-        auto pidx = [pp32](int u, int v) -> uint32_t { return (uint32_t)u * pp32 + (uint32_t)v; };
+        // pair data of (u, v) at byte offset 4 (u p_pad + v), u < v for every valid triple (an
+        // invalid one may read the unwritten lower triangle; its counts are masked below)
+        const uint32_t pp4 = 4u * (uint32_t)a.p_pad;
+        const uint32_t pbytes = pp4 * (uint32_t)a.p_pad;
+        // (bases re-read as uniform: a resource must sit in scalar registers)
+        const __amdgpu_buffer_rsrc_t rsP = rsrc(reinterpret_cast<const void *>(uniform64((int64_t)ptab)), pbytes);
+        const __amdgpu_buffer_rsrc_t rsF = rsrc(reinterpret_cast<const void *>(uniform64((int64_t)F2)), pbytes);
+        const uint32_t io = (uint32_t)i * pp4;
+        uint32_t lo4[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) lo4[n] = 4u * (uint32_t)clampv(lv[n]);
         const uint32_t Mi = repack(margr[(uint32_t)i * C]);
         const uint32_t Ni1 = Ntot - Mi;                     // class sizes of x_i = 1
         uint32_t Ml[NN], Nil[NN];
@@ -643,36 +692,30 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
         for (int n = 0; n < NN; ++n) {
             const int l = clampv(lv[n]);
             Ml[n] = repack(margr[(uint32_t)l * C]);
-            const int ii = i < l ? i : l, ll = i < l ? l : i;
-            Nil[n] = repack(ptab[pidx(ii, ll)]);
-            Fil[n] = F2[pidx(ii, ll)];
+            Nil[n] = repack(ld32(rsP, io + lo4[n]));
+            Fil[n] = ldf(rsF, io + lo4[n]);
             gL_read[n] = key_f32(a.G32[l]);
         }
         const float Gi = key_f32(a.G32[i]);
         struct JData {
-            uint32_t Nij[4], Mj[4];   // N(0,0) of (i, j); bin-0 count of j
+            uint32_t Nij[4], Mj[4], jo[4];   // N(0,0) of (i, j); bin-0 count of j; row offset of j
             float F[4], g[4];
         };
         auto load_j = [&](int m, JData &d) {
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
                 const int j = clampv(jvar(m, x));
+                d.jo[x] = (uint32_t)j * pp4;
                 d.Mj[x] = repack(margr[(uint32_t)j * C]);
-                const int ii = i < j ? i : j, jj = i < j ? j : i;
-                d.Nij[x] = repack(ptab[pidx(ii, jj)]);
-                d.F[x] = F2[pidx(ii, jj)];
+                d.Nij[x] = repack(ld32(rsP, io + 4u * (uint32_t)j));
+                d.F[x] = ldf(rsF, io + 4u * (uint32_t)j);
                 d.g[x] = key_f32(a.G32[j]);
             }
         };
-        // F3 of triple (i, j(m, x), l_n) and the F of the pair (j, l)
-        auto triple = [&](int m, int n, int x, const JData &jd, float &Fjl) -> float {
+        // F3 of triple (i, j(m, x), l_n) from its direct count D and the pair count Njl of (j, l_n)
+        auto triple = [&](int m, int n, int x, const JData &jd, uint32_t D, uint32_t Njl) -> float {
             const int jraw = jvar(m, x);
             const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
-            const int j = clampv(jraw), l = clampv(lv[n]);
-            const int jj = j < l ? j : l, ll = j < l ? l : j;
-            const uint32_t Njl = repack(ptab[pidx(jj, ll)]);
-            Fjl = F2[pidx(jj, ll)];
-            const uint32_t D = (uint32_t)cnt[m][n][x];
             uint32_t V[8];
             V[0] = D;                                   // T000
             V[1] = jd.Nij[x] - D;                       // T001
@@ -689,32 +732,48 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
             return vox_sum<T, 8>(V, smem);
         };
 
-        // One pass, row by row (block row m: the j(m, x) of the lane's q): the F of the row's
-        // triples are kept, the maxima of the row's members reduced over the wave, and the row's
-        // appends decided against thresholds that are the larger of the maximum read before the
-        // tile and the wave's maximum so far (both below the final maximum, so every triple
-        // within the window of the final maximum is appended); one slot reservation per row.
+        // One pass, row by row (block row m: the j(m, x) of the lane's q): the row's (j, l) pair
+        // data are loaded first, all loads in flight together; the F of the row's triples are
+        // kept, the maxima of the row's members reduced over the wave, and the row's appends
+        // decided against thresholds that are the larger of the maximum read before the tile and
+        // the wave's maximum so far (both below the final maximum, so every triple within the
+        // window of the final maximum is appended); a row whose wave maxima all stay below their
+        // thresholds appends nothing and skips the selection; one slot reservation per row.
         float mi = -INFINITY, ml[NN];
 #pragma unroll
         for (int n = 0; n < NN; ++n) ml[n] = -INFINITY;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
+            // the row's direct counts first (the row index is not a constant: the tile may live
+            // in scratch memory), then the pair data, so that one wait covers every load
+            v4i crow[NN];
+#pragma unroll
+            for (int n = 0; n < NN; ++n) crow[n] = cnt[m][n];
             JData jd;
             load_j(m, jd);
+            uint32_t Njl[NN][4];
             float F3r[NN][4], Fjlr[NN][4], mjx[4];
+#pragma unroll
+            for (int n = 0; n < NN; ++n)
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    const uint32_t o = jd.jo[x] + lo4[n];
+                    Njl[n][x] = repack(ld32(rsP, o));
+                    Fjlr[n][x] = ldf(rsF, o);
+                }
 #pragma unroll
             for (int x = 0; x < 4; ++x) mjx[x] = -INFINITY;
 #pragma unroll
             for (int n = 0; n < NN; ++n) {
 #pragma unroll
-                for (int x = 0; x < 4; ++x) F3r[n][x] = Fjlr[n][x] = 0.f;
+                for (int x = 0; x < 4; ++x) F3r[n][x] = 0.f;
                 // wave-uniform skip of a block without any valid triple
                 if (!__any(i < jvar(m, 3) && jvar(m, 0) < lv[n] && lv[n] < a.p)) continue;
 #pragma unroll
                 for (int x = 0; x < 4; ++x) {
                     const int jraw = jvar(m, x);
                     const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
-                    const float F3 = triple(m, n, x, jd, Fjlr[n][x]);
+                    const float F3 = triple(m, n, x, jd, (uint32_t)crow[n][x], Njl[n][x]);
                     F3r[n][x] = F3;
                     mi = fmaxf(mi, valid ? Fjlr[n][x] - F3 : -INFINITY);   // gain of x_i given (x_j, x_l)
                     mjx[x] = fmaxf(mjx[x], valid ? Fil[n] - F3 : -INFINITY);  // gain of x_j given (x_i, x_l)
@@ -743,40 +802,45 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
             const float tI = a.collect ? Gi : fmaxf(Gi, wi);
             const float thI = tI - win3(a.w_abs, tI);
             float thJ[4], thL[NN];
+            bool hot = wi >= thI;
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
                 const float tJ = a.collect ? jd.g[x] : fmaxf(jd.g[x], wj[x]);
                 thJ[x] = tJ - win3(a.w_abs, tJ);
+                hot |= wj[x] >= thJ[x];
             }
 #pragma unroll
             for (int n = 0; n < NN; ++n) {
                 const float tL = a.collect ? gL_read[n] : fmaxf(gL_read[n], wl[n]);
                 thL[n] = tL - win3(a.w_abs, tL);
+                hot |= wl[n] >= thL[n];
             }
-            uint64_t sel = 0;   // bit 3 (4 n + x) + member
-#pragma unroll
-            for (int n = 0; n < NN; ++n)
-#pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    const int jraw = jvar(m, x);
-                    const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
-                    const int b = 3 * (4 * n + x);
-                    if (valid && Fjlr[n][x] - F3r[n][x] >= thI) sel |= 1ull << b;
-                    if (valid && Fil[n] - F3r[n][x] >= thJ[x]) sel |= 2ull << b;
-                    if (valid && jd.F[x] - F3r[n][x] >= thL[n]) sel |= 4ull << b;
-                }
-            uint32_t at = reserve_slots(&a.st->n_cand, (uint32_t)__popcll(sel), lane);
-            if (sel) {
+            if (__any(hot)) {
+                uint64_t sel = 0;   // bit 3 (4 n + x) + member
 #pragma unroll
                 for (int n = 0; n < NN; ++n)
 #pragma unroll
                     for (int x = 0; x < 4; ++x) {
-                        const int j = jvar(m, x), l = lv[n], b = 3 * (4 * n + x);
-                        const float F3 = F3r[n][x];
-                        if (sel & (1ull << b)) put(a, r, at++, i, ((uint32_t)j << 16) | (uint32_t)l, Fjlr[n][x] - F3);
-                        if (sel & (2ull << b)) put(a, r, at++, j, ((uint32_t)i << 16) | (uint32_t)l, Fil[n] - F3);
-                        if (sel & (4ull << b)) put(a, r, at++, l, ((uint32_t)i << 16) | (uint32_t)j, jd.F[x] - F3);
+                        const int jraw = jvar(m, x);
+                        const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
+                        const int b = 3 * (4 * n + x);
+                        if (valid && Fjlr[n][x] - F3r[n][x] >= thI) sel |= 1ull << b;
+                        if (valid && Fil[n] - F3r[n][x] >= thJ[x]) sel |= 2ull << b;
+                        if (valid && jd.F[x] - F3r[n][x] >= thL[n]) sel |= 4ull << b;
                     }
+                uint32_t at = reserve_slots(&a.st->n_cand, (uint32_t)__popcll(sel), lane);
+                if (sel) {
+#pragma unroll
+                    for (int n = 0; n < NN; ++n)
+#pragma unroll
+                        for (int x = 0; x < 4; ++x) {
+                            const int j = jvar(m, x), l = lv[n], b = 3 * (4 * n + x);
+                            const float F3 = F3r[n][x];
+                            if (sel & (1ull << b)) put(a, r, at++, i, ((uint32_t)j << 16) | (uint32_t)l, Fjlr[n][x] - F3);
+                            if (sel & (2ull << b)) put(a, r, at++, j, ((uint32_t)i << 16) | (uint32_t)l, Fil[n] - F3);
+                            if (sel & (4ull << b)) put(a, r, at++, l, ((uint32_t)i << 16) | (uint32_t)j, jd.F[x] - F3);
+                        }
+                }
             }
             // j(m, x) appears in this row only: its maximum goes out now
 #pragma unroll
