@@ -346,10 +346,14 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
         }
     };
     // the plain barrier: a fenced one would also drain the fetches still in flight
+    // The LDS wait comes first and on every path, so that the compiler sees this step's
+    // fragments complete wherever the MFMAs are reached and adds no wait of its own there (one
+    // after the next step's fragment reads would serialise them with the MFMAs).
     auto step = [&](int s_, const v4i (&ca)[4], const v4i (&cb)[NN], v4i (&na)[4], v4i (&nb)[NN]) {
+        __builtin_amdgcn_s_waitcnt(0xC07F);                                   // lgkmcnt(0)
         if (s_ + 1 < a.KB) {
-            if (s_ + 2 < a.KB) __builtin_amdgcn_s_waitcnt(0x0070 | LPW);   // vmcnt(LPW) lgkmcnt(0)
-            else __builtin_amdgcn_s_waitcnt(0x0070);                       // vmcnt(0) lgkmcnt(0)
+            if (s_ + 2 < a.KB) __builtin_amdgcn_s_waitcnt(0x0F70 | LPW);   // vmcnt(LPW)
+            else __builtin_amdgcn_s_waitcnt(0x0F70);                       // vmcnt(0)
             __builtin_amdgcn_s_barrier();
             frags(s_ + 1, na, nb);
             if (s_ + 3 < a.KB) issue(s_ + 3);
