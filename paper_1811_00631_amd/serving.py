@@ -13,6 +13,9 @@ releases the GIL, so the sweeps of admitted requests run concurrently on the dev
   quarter for small ones, measured 7% less capacity on the serving trace.)
 * `express` of the slots take only small requests (at most `fuse_tuples` tuples), so small
   requests never wait behind large ones that occupy the other slots.
+* At most `max_large` large requests run at a time (default 1): each fills the GPU by itself, so
+  two together only stretch both latencies; queued large ones keep their arrival order and let
+  small ones pass.
 * Small k = 2 requests waiting behind an admitted small one (same divisions, encoding and engine,
   up to 12, memory permitting) are fused with it into one mdfs_max_ig_batch call: one persistent
   sweep launch over all their tiles.
@@ -86,7 +89,8 @@ def tuples_of(ds: Dataset, req: Request) -> int:
 class Server:
     def __init__(self, device: str = "cuda:0", slots: int = 4, hbm_budget: int | None = None,
                  workgroups: int | None = None, max_bypass: int = 8, fuse: bool = True,
-                 fuse_tuples: float = 5e8, express: int | None = None, code_cache_bytes: int = 2 << 30):
+                 fuse_tuples: float = 5e8, express: int | None = None, code_cache_bytes: int = 2 << 30,
+                 max_large: int | None = 1):
         mdfs.load()
         self.device = torch.device(device)
         self.slots = slots
@@ -100,6 +104,8 @@ class Server:
         self.fuse = fuse
         self.fuse_tuples = fuse_tuples   # requests up to this many tuples may be fused (and are small)
         self.express = express if express is not None else (1 if slots >= 3 else 0)
+        self.max_large = max_large       # large requests running at once (None: no limit)
+        self._large = 0                  # large requests running now
         self.n_fused = 0                 # requests that ran inside a fused batch
         self.code_cache_bytes = code_cache_bytes
         self._codes: collections.OrderedDict = collections.OrderedDict()   # key -> codes (LRU)
@@ -185,8 +191,9 @@ class Server:
         """First queued request whose footprint fits (an express slot: first small one), and the
         fusable ones queued behind it that also fit (called with the lock held)."""
         free = self.budget - self.resident - self._in_use
+        large_full = self.max_large is not None and self._large >= self.max_large
         for idx, req in enumerate(self._queue):
-            if express and not self._small(req):
+            if (express or large_full) and not self._small(req):
                 continue
             if req.footprint <= free:
                 for earlier in list(self._queue)[:idx]:
@@ -223,6 +230,8 @@ class Server:
                     if not group:
                         self._lock.wait()
                 now = self.now()
+                large = len(group) == 1 and not self._small(group[0])
+                self._large += large
                 for req in group:
                     self._in_use += req.footprint
                     req.t_admit = now
@@ -235,6 +244,7 @@ class Server:
                 self._run_fused(group, stream)
             with self._lock:
                 now = self.now()
+                self._large -= large
                 for req in group:
                     self._in_use -= req.footprint
                     req.t_done = now

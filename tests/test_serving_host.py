@@ -31,7 +31,7 @@ def test_first_fit_admission_order():
     from paper_1811_00631_amd.serving import Server
     srv = Server.__new__(Server)
     srv.budget, srv.resident, srv._in_use, srv.max_bypass, srv.fuse = 100, 10, 0, 2, False
-    srv._bypassed = {}
+    srv._bypassed, srv.max_large, srv._large = {}, None, 0
     import collections
     srv._queue = collections.deque([Req(0, 95), Req(1, 30), Req(2, 50)])
     ids = lambda g: [r.id for r in g]   # noqa: E731
@@ -56,6 +56,7 @@ def test_fusion_groups_small_k2_requests():
     srv = Server.__new__(Server)
     srv.budget, srv.resident, srv._in_use, srv.max_bypass = 1000, 0, 0, 8
     srv.fuse, srv.fuse_tuples, srv._bypassed = True, 5e8, {}
+    srv.max_large, srv._large = 1, 0
     small = Dataset.__new__(Dataset)
     big = Dataset.__new__(Dataset)
     for ds, (p, n, n1) in ((small, (100, 500, 250)), (big, (20000, 2000, 1000))):
@@ -74,6 +75,42 @@ def test_fusion_groups_small_k2_requests():
     assert [r.id for r in srv._queue][:3] == [1, 2, 3]           # big, other divisions, k = 3 wait
     srv._queue = collections.deque([req(20, 0, fp=600), req(21, 0, fp=500), req(22, 0, fp=300)])
     assert [r.id for r in srv._take()] == [20, 22]               # 500 no longer fits next to 600
+
+
+def test_one_large_request_at_a_time():
+    # with a large request running, queued large ones wait in arrival order and small ones pass;
+    # express slots take small ones only; without the limit the next large one is taken
+    from paper_1811_00631_amd.serving import Dataset, Request, Server
+    import collections
+
+    srv = Server.__new__(Server)
+    srv.budget, srv.resident, srv._in_use, srv.max_bypass = 1000, 0, 0, 2
+    srv.fuse, srv.fuse_tuples, srv._bypassed = False, 5e8, {}
+    small = Dataset.__new__(Dataset)
+    big = Dataset.__new__(Dataset)
+    for ds, (p, n, n1) in ((small, (100, 500, 250)), (big, (20000, 2000, 1000))):
+        object.__setattr__(ds, "data", np.zeros((p, n)))
+        object.__setattr__(ds, "n1", n1)
+    srv.datasets = {0: small, 1: big}
+
+    def req(i, ds):
+        r = Request(dataset=ds, k=2, divisions=2, n_disc=3)
+        r.id, r.footprint = i, 10
+        return r
+    ids = lambda g: [r.id for r in g]   # noqa: E731
+    srv.max_large, srv._large = 1, 0
+    srv._queue = collections.deque([req(0, 1), req(1, 1), req(2, 0)])
+    assert ids(srv._take(express=True)) == [2]
+    assert ids(srv._take()) == [0]
+    srv._large = 1                                   # request 0 runs
+    srv._queue.extend([req(3, 0), req(4, 0), req(5, 0)])
+    assert ids(srv._take()) == [3] and ids(srv._take()) == [4] and ids(srv._take()) == [5]
+    assert srv._take() == []                         # request 1 waits for the large slot
+    srv._large = 0
+    assert ids(srv._take()) == [1]                   # passed over, still first among the large
+    srv.max_large, srv._large = None, 1
+    srv._queue = collections.deque([req(6, 1)])
+    assert ids(srv._take()) == [6]
 
 
 def test_autotune_candidates_and_buckets():
