@@ -350,7 +350,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
         // F3 of triple (i, j_m, l_n) on the lane pair (e = 0, 1) from the 2 x 2 direct counts dj
         // of (j_m, l_n)
         auto triple = [&](int m, int n, const JData &jd, const uint32_t (&dj)[4]) -> float {
-            const bool valid = i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;
+            const bool valid = (i < jv[m]) & (jv[m] < lv[n]) & (lv[n] < a.p);
             uint32_t Nij[3][3], Nil[3][3], Njl[3][3];
             full3(jd.P, Mi, jd.M, Nij);
             full3(Pil[n], Mi, Ml[n], Nil);
@@ -426,7 +426,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
                 F3r[n] = 0.f;
-                const bool valid = i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;
+                const bool valid = (i < jv[m]) & (jv[m] < lv[n]) & (lv[n] < a.p);
                 // wave-uniform skip of a block without any valid triple (near the diagonal of
                 // the (j, l) blocks and past p): its maxima would stay -inf
                 if (!__any(valid)) continue;
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
                 uint32_t sel = 0;   // bit 3 n + member
 #pragma unroll
                 for (int n = 0; n < 4; ++n) {
-                    const bool valid = e == 0 && i < jv[m] && jv[m] < lv[n] && lv[n] < a.p;   // one lane per triple
+                    const bool valid = (e == 0) & (i < jv[m]) & (jv[m] < lv[n]) & (lv[n] < a.p);   // one lane per triple
                     if (valid && Fjlr[n] - F3r[n] >= thI) sel |= 1u << (3 * n);
                     if (valid && Fil[n] - F3r[n] >= thJ) sel |= 2u << (3 * n);
                     if (valid && jd.F - F3r[n] >= thL[n]) sel |= 4u << (3 * n);
@@ -715,7 +715,7 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
         // F3 of triple (i, j(m, x), l_n) from its direct count D and the pair count Njl of (j, l_n)
         auto triple = [&](int m, int n, int x, const JData &jd, uint32_t D, uint32_t Njl) -> float {
             const int jraw = jvar(m, x);
-            const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
+            const bool valid = (i < jraw) & (jraw < lv[n]) & (lv[n] < a.p);
             uint32_t V[8];
             V[0] = D;                                   // T000
             V[1] = jd.Nij[x] - D;                       // T001
@@ -772,7 +772,7 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
 #pragma unroll
                 for (int x = 0; x < 4; ++x) {
                     const int jraw = jvar(m, x);
-                    const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
+                    const bool valid = (i < jraw) & (jraw < lv[n]) & (lv[n] < a.p);
                     const float F3 = triple(m, n, x, jd, (uint32_t)crow[n][x], Njl[n][x]);
                     F3r[n][x] = F3;
                     mi = fmaxf(mi, valid ? Fjlr[n][x] - F3 : -INFINITY);   // gain of x_i given (x_j, x_l)
@@ -822,7 +822,7 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
 #pragma unroll
                     for (int x = 0; x < 4; ++x) {
                         const int jraw = jvar(m, x);
-                        const bool valid = i < jraw && jraw < lv[n] && lv[n] < a.p;
+                        const bool valid = (i < jraw) & (jraw < lv[n]) & (lv[n] < a.p);
                         const int b = 3 * (4 * n + x);
                         if (valid && Fjlr[n][x] - F3r[n][x] >= thI) sel |= 1ull << b;
                         if (valid && Fil[n] - F3r[n][x] >= thJ[x]) sel |= 2ull << b;
