@@ -545,7 +545,6 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
     const int64_t nrb = a.rows_pad / TILE_ROWS;
     constexpr int kstride = TILE_ROWS * KBLK;
     const int n1blk = a.KB - a.KB0;
-    auto clampv = [&](int v) { return v < a.p ? v : a.p - 1; };
 
     uint32_t taken = 0;   // tiles taken by this workgroup (cancel polling)
     for (;;) {
@@ -673,8 +672,8 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
         int lv[NN];
 #pragma unroll
         for (int n = 0; n < NN; ++n) lv[n] = lb * M1_V + LSPAN * wc + 16 * n + c16;
-        // pair data of (u, v) at byte offset 4 (u p_pad + v), u < v for every valid triple (an
-        // invalid one may read the unwritten lower triangle; its counts are masked below)
+        // pair data of (u, v) at byte offset 4 (u p_pad + v), every u, v < p_pad filled in (the
+        // pair sweep's u < v < p and k_square_pairs' rest): every slot's counts are counts
         const uint32_t pp4 = 4u * (uint32_t)a.p_pad;
         const uint32_t pbytes = pp4 * (uint32_t)a.p_pad;
         // (bases re-read as uniform: a resource must sit in scalar registers)
@@ -683,14 +682,14 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
         const uint32_t io = (uint32_t)i * pp4;
         uint32_t lo4[NN];
 #pragma unroll
-        for (int n = 0; n < NN; ++n) lo4[n] = 4u * (uint32_t)clampv(lv[n]);
+        for (int n = 0; n < NN; ++n) lo4[n] = 4u * (uint32_t)lv[n];
         const uint32_t Mi = repack(margr[(uint32_t)i * C]);
         const uint32_t Ni1 = Ntot - Mi;                     // class sizes of x_i = 1
         uint32_t Ml[NN], Nil[NN];
         float Fil[NN], gL_read[NN];
 #pragma unroll
         for (int n = 0; n < NN; ++n) {
-            const int l = clampv(lv[n]);
+            const int l = lv[n];
             Ml[n] = repack(margr[(uint32_t)l * C]);
             Nil[n] = repack(ld32(rsP, io + lo4[n]));
             Fil[n] = ldf(rsF, io + lo4[n]);
@@ -704,7 +703,7 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
         auto load_j = [&](int m, JData &d) {
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
-                const int j = clampv(jvar(m, x));
+                const int j = jvar(m, x);
                 d.jo[x] = (uint32_t)j * pp4;
                 d.Mj[x] = repack(margr[(uint32_t)j * C]);
                 d.Nij[x] = repack(ld32(rsP, io + 4u * (uint32_t)j));
@@ -713,9 +712,7 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
             }
         };
         // F3 of triple (i, j(m, x), l_n) from its direct count D and the pair count Njl of (j, l_n)
-        auto triple = [&](int m, int n, int x, const JData &jd, uint32_t D, uint32_t Njl) -> float {
-            const int jraw = jvar(m, x);
-            const bool valid = (i < jraw) & (jraw < lv[n]) & (lv[n] < a.p);
+        auto triple = [&](int n, int x, const JData &jd, uint32_t D, uint32_t Njl) -> float {
             uint32_t V[8];
             V[0] = D;                                   // T000
             V[1] = jd.Nij[x] - D;                       // T001
@@ -726,9 +723,6 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
             V[5] = Bj - V[3];                           // T101
             V[6] = (Ml[n] - Nil[n]) - V[3];             // T110
             V[7] = (Ni1 - Bj) - V[6];                   // T111
-            // an invalid triple may combine unrelated tables: its counts are not counts
-#pragma unroll
-            for (int k = 0; k < 8; ++k) V[k] = valid ? V[k] : 0u;
             return vox_sum<T, 8>(V, smem);
         };
 
@@ -773,7 +767,7 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
                 for (int x = 0; x < 4; ++x) {
                     const int jraw = jvar(m, x);
                     const bool valid = (i < jraw) & (jraw < lv[n]) & (lv[n] < a.p);
-                    const float F3 = triple(m, n, x, jd, (uint32_t)crow[n][x], Njl[n][x]);
+                    const float F3 = triple(n, x, jd, (uint32_t)crow[n][x], Njl[n][x]);
                     F3r[n][x] = F3;
                     mi = fmaxf(mi, valid ? Fjlr[n][x] - F3 : -INFINITY);   // gain of x_i given (x_j, x_l)
                     mjx[x] = fmaxf(mjx[x], valid ? Fil[n] - F3 : -INFINITY);  // gain of x_j given (x_i, x_l)
@@ -1012,10 +1006,60 @@ hipError_t launch_tiles3(const Problem &P)
     return hipGetLastError();
 }
 
+// The triple tiles read the pair tables of every (u, v) they touch, u >= v and padding variables
+// (v >= p) included, while the pair sweep writes u < v < p only.  This fills in the rest so that
+// whatever three variables a tile slot names, its derived counts are counts of real variables
+// (non-negative and at most the class sizes), and the epilogue need not mask them: below the
+// diagonal the transpose, on it the variable against itself (M_u(a) where a = b, else 0), and for
+// a padding variable, whose one-hot rows are zero (every object in the last bin), zeros, with the
+// class sizes in the last bin of its marginals.  One launch per chunk of discretisations, for the
+// two-class kernel (8.5% faster without its masks); the three-class one keeps its masks (1.7%
+// faster than this pass plus unmasked slots).
+template <int W>
+__global__ __launch_bounds__(256) void k_square_pairs(uint32_t *ptab, uint32_t *marg, int64_t p, int64_t p_pad, int r0,
+                                                      int nr, uint32_t ntot)
+{
+    constexpr int C = W + 1;
+    const int64_t n = (int64_t)nr * p_pad * p_pad, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n; idx += stride) {
+        const int64_t rr = idx / (p_pad * p_pad), uv = idx - rr * p_pad * p_pad;
+        const int64_t u = uv / p_pad, v = uv - u * p_pad;
+        if (u < v && v < p) continue;   // written by the pair sweep
+        uint32_t *dst = ptab + idx * (W * W);
+        if (u >= p || v >= p) {
+#pragma unroll
+            for (int k = 0; k < W * W; ++k) dst[k] = 0u;
+        } else if (u == v) {
+            const uint32_t *m = marg + ((int64_t)(r0 + rr) * p_pad + u) * C;
+#pragma unroll
+            for (int x = 0; x < W; ++x)
+#pragma unroll
+                for (int y = 0; y < W; ++y) dst[x * W + y] = x == y ? m[x] : 0u;
+        } else {
+            const uint32_t *src = ptab + ((rr * p_pad + v) * p_pad + u) * (W * W);
+#pragma unroll
+            for (int x = 0; x < W; ++x)
+#pragma unroll
+                for (int y = 0; y < W; ++y) dst[x * W + y] = src[y * W + x];
+        }
+    }
+    const int64_t npad = (int64_t)nr * (p_pad - p);
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < npad; idx += stride) {
+        const int64_t rr = idx / (p_pad - p), v = p + (idx - rr * (p_pad - p));
+        marg[((int64_t)(r0 + rr) * p_pad + v) * C + W] = ntot;
+    }
+}
+
 hipError_t launch_sweep3m(const Problem &P, int r0, int nr, bool collect, int32_t *counts_out, int i_sel, int disc_sel)
 {
     hipError_t e = launch_reset_queue(P);
     if (e != hipSuccess) return e;
+    if (P.L.W == 1) {
+        const uint32_t ntot = ((uint32_t)P.N1 << 16) | (uint32_t)P.N0;
+        hipLaunchKernelGGL(k_square_pairs<1>, dim3(1024), dim3(256), 0, P.stream, P.at<uint32_t>(P.L.ptab),
+                           P.at<uint32_t>(P.L.marg), P.L.p, P.L.p_pad, r0, nr, ntot);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     const bool w1 = P.L.W == 1;
     switch (m3_capacity(P)) {
     case 1024: return w1 ? m3_launch<1024, 1>(P, r0, nr, collect, counts_out, i_sel, disc_sel)
