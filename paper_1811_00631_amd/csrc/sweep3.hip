@@ -154,6 +154,18 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
             const int l = l0 + lane;
             const bool act = l < a.p;
             const int lc = act ? l : (a.p - 1);   // in-bounds stand-in for idle lanes
+            // the lane's pair data and marginals, loaded before the count loop so that their
+            // latency overlaps it
+            uint32_t Ml[C], pil[W * W], pjl[W * W];
+#pragma unroll
+            for (int c = 0; c < C; ++c) Ml[c] = margr[(int64_t)lc * C + c];
+#pragma unroll
+            for (int k = 0; k < W * W; ++k) {
+                pil[k] = ptab[((int64_t)i * a.p_pad + lc) * (W * W) + k];
+                pjl[k] = ptab[((int64_t)j * a.p_pad + lc) * (W * W) + k];
+            }
+            const float Fjl = F2[(int64_t)j * a.p_pad + lc], Fil = F2[(int64_t)i * a.p_pad + lc];
+            const float Gl = key_f32(a.G32[lc]);
 
             // ---- counts of the W^3 leading bin triples (class 1, shift, class 0)
             uint32_t cnt[W][W][W];
@@ -228,12 +240,9 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
             }
 
             // ---- full C^3 table from the leading counts, the three pair tables and marginals
-            uint32_t Ml[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) Ml[c] = margr[(int64_t)lc * C + c];
             uint32_t Nil[C][C], Njl[C][C];
-            full_pair<W>(ptab + ((int64_t)i * a.p_pad + lc) * (W * W), Mi, Ml, Nil);
-            full_pair<W>(ptab + ((int64_t)j * a.p_pad + lc) * (W * W), Mj, Ml, Njl);
+            full_pair<W>(pil, Mi, Ml, Nil);
+            full_pair<W>(pjl, Mj, Ml, Njl);
             uint32_t T[C][C][C];
 #pragma unroll
             for (int x = 0; x < W; ++x)
@@ -303,13 +312,11 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
 #pragma unroll
                     for (int z = 0; z < C; ++z) F3 += vox3(T[x][y][z], EA, EB, LQ);
 
-            const float Fjl = F2[(int64_t)j * a.p_pad + lc], Fil = F2[(int64_t)i * a.p_pad + lc];
             const float igi = act ? Fjl - F3 : -INFINITY;    // gain of x_i given (x_j, x_l)
             const float igj = act ? Fil - F3 : -INFINITY;    // gain of x_j given (x_i, x_l)
             const float igl = act ? F2ij - F3 : -INFINITY;   // gain of x_l given (x_i, x_j)
 
             // ---- member l: one value per lane
-            const float Gl = key_f32(a.G32[lc]);
             const bool al = act && igl >= Gl - window3(a.w_abs, Gl);
             if (al && !a.collect && igl > Gl) atomicMax(&a.G32[l], f32_key(igl));
             // ---- members i and j: chunk maxima over the lanes
