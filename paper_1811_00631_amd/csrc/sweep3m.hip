@@ -185,6 +185,59 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
         const int i = ab >> 8, jb = ab & 255;
         const int lb = jb / 2 + (int)(u - a.apref[lo]);
 
+        // The tile's per-l data (and, below, i's): loaded before the K loop, so their latency
+        // overlaps it (the maxima read here are lower bounds of the final ones, as any are).
+        int jv[4], lv[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) jv[m] = jb * M3_JV + 16 * wr + 4 * m + q;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) lv[n] = lb * M3_LV + 32 * wc + 8 * n + (c16 >> 1);
+        // indices past p are clamped for the loads; such triples are invalid and masked
+        auto clampv = [&](int v) { return v < a.p ? v : a.p - 1; };
+        // pair data of (u, v): 2 x 2 counts at byte offset 16 (u p_pad + v), F at 4 (u p_pad + v);
+        // u < v for every valid triple (an invalid one may read the unwritten lower triangle,
+        // and its counts are masked); bases re-read as uniform (a resource sits in scalar registers)
+        const uint32_t pp = (uint32_t)a.p_pad;
+        const __amdgpu_buffer_rsrc_t rsP = rsrc(reinterpret_cast<const void *>(uniform64((int64_t)ptab)), 16u * pp * pp);
+        const __amdgpu_buffer_rsrc_t rsF = rsrc(reinterpret_cast<const void *>(uniform64((int64_t)F2)), 4u * pp * pp);
+        auto pair4 = [&](uint32_t uv, uint32_t (&d)[4]) {
+            const v4i pw = ld128(rsP, 16u * uv);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) d[x] = repack((uint32_t)pw[x]);
+        };
+        uint32_t Mi[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Mi[c] = repack(margr[(int64_t)i * C + c]);
+        // per-l data for the whole tile; per-j data (one m block at a time) loaded in the loops
+        uint32_t Ml[4][3], Pil[4][4], lc[4];
+        float Fil[4], gL[4], gJ[4];
+        struct JData {
+            uint32_t M[3], P[4], jrow;
+            float F;
+        };
+        auto load_j = [&](int m, JData &d) {
+            const int j = clampv(jv[m]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) d.M[c] = repack(margr[(int64_t)j * C + c]);
+            d.jrow = (uint32_t)j * pp;
+            pair4((uint32_t)i * pp + (uint32_t)j, d.P);
+            d.F = ldf(rsF, 4u * ((uint32_t)i * pp + (uint32_t)j));
+        };
+#pragma unroll
+        for (int m = 0; m < 4; ++m) gJ[m] = key_f32(a.G32[clampv(jv[m])]);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const int l = clampv(lv[n]);
+            lc[n] = (uint32_t)l;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Ml[n][c] = repack(margr[(int64_t)l * C + c]);
+            pair4((uint32_t)i * pp + lc[n], Pil[n]);
+            Fil[n] = ldf(rsF, 4u * ((uint32_t)i * pp + lc[n]));
+            const float g = key_f32(a.G32[l]);
+            gL[n] = g;
+        }
+        const float Gi = key_f32(a.G32[i]);
+        // ---------------------------------------------------------------- K loop
         // ---------------------------------------------------------------- K loop
         // operand sources in the panel-major one-hot encoding
         const int8_t *panJ = a.onehot + ((int64_t)r * nrb + jb / 2) * a.KB * kstride + (jb & 1) * M3_JROWS * KBLK;
@@ -296,56 +349,6 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
                     }
                 }
         }
-        int jv[4], lv[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) jv[m] = jb * M3_JV + 16 * wr + 4 * m + q;
-#pragma unroll
-        for (int n = 0; n < 4; ++n) lv[n] = lb * M3_LV + 32 * wc + 8 * n + (c16 >> 1);
-        // indices past p are clamped for the loads; such triples are invalid and masked
-        auto clampv = [&](int v) { return v < a.p ? v : a.p - 1; };
-        // pair data of (u, v): 2 x 2 counts at byte offset 16 (u p_pad + v), F at 4 (u p_pad + v);
-        // u < v for every valid triple (an invalid one may read the unwritten lower triangle,
-        // and its counts are masked); bases re-read as uniform (a resource sits in scalar registers)
-        const uint32_t pp = (uint32_t)a.p_pad;
-        const __amdgpu_buffer_rsrc_t rsP = rsrc(reinterpret_cast<const void *>(uniform64((int64_t)ptab)), 16u * pp * pp);
-        const __amdgpu_buffer_rsrc_t rsF = rsrc(reinterpret_cast<const void *>(uniform64((int64_t)F2)), 4u * pp * pp);
-        auto pair4 = [&](uint32_t uv, uint32_t (&d)[4]) {
-            const v4i pw = ld128(rsP, 16u * uv);
-#pragma unroll
-            for (int x = 0; x < 4; ++x) d[x] = repack((uint32_t)pw[x]);
-        };
-        uint32_t Mi[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Mi[c] = repack(margr[(int64_t)i * C + c]);
-        // per-l data for the whole tile; per-j data (one m block at a time) loaded in the loops
-        uint32_t Ml[4][3], Pil[4][4], lc[4];
-        float Fil[4], gL[4], gJ[4];
-        struct JData {
-            uint32_t M[3], P[4], jrow;
-            float F;
-        };
-        auto load_j = [&](int m, JData &d) {
-            const int j = clampv(jv[m]);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) d.M[c] = repack(margr[(int64_t)j * C + c]);
-            d.jrow = (uint32_t)j * pp;
-            pair4((uint32_t)i * pp + (uint32_t)j, d.P);
-            d.F = ldf(rsF, 4u * ((uint32_t)i * pp + (uint32_t)j));
-        };
-#pragma unroll
-        for (int m = 0; m < 4; ++m) gJ[m] = key_f32(a.G32[clampv(jv[m])]);
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            const int l = clampv(lv[n]);
-            lc[n] = (uint32_t)l;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Ml[n][c] = repack(margr[(int64_t)l * C + c]);
-            pair4((uint32_t)i * pp + lc[n], Pil[n]);
-            Fil[n] = ldf(rsF, 4u * ((uint32_t)i * pp + lc[n]));
-            const float g = key_f32(a.G32[l]);
-            gL[n] = g;
-        }
-        const float Gi = key_f32(a.G32[i]);
 
         // F3 of triple (i, j_m, l_n) on the lane pair (e = 0, 1) from the 2 x 2 direct counts dj
         // of (j_m, l_n)
