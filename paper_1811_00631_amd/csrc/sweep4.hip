@@ -48,6 +48,15 @@ __device__ inline float vox4(uint32_t P, const float *EA, const float *EB, const
     return lq.x - lq.y * (EA[n0] + EB[n1]);
 }
 
+// A value passed through an empty volatile asm: volatile asm statements keep their program
+// order, so work that depends on the result cannot start before the asms ahead of it.
+template <class T>
+__device__ __forceinline__ T ordered4(T x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 __device__ inline float window4(float w_abs, float g)
 {
     const float ag = fabsf(g);
@@ -193,7 +202,11 @@ __global__ __launch_bounds__(S4_THREADS) void k_sweep4(Sweep4Args a)
                 }
             }
 
-            // F of the quadruple and of its four sub-triples (the table summed over one axis)
+            // F of the quadruple and of its four sub-triples (the table summed over one axis).
+            // Table reads go in two groups (the quadruple's 81 voxels, then the sub-triples' 108):
+            // each group's counts pass through an ordered asm after the previous group's sum has,
+            // so the second group's reads wait for the first and the registers they hold stay
+            // fewer (210 VGPRs, two waves per SIMD, where all reads at once took 367 and one).
             float F4 = 0.f, Fjlm = 0.f, Film = 0.f, Fijm = 0.f, Fijl = 0.f;
 #pragma unroll
             for (int x = 0; x < C; ++x)
@@ -202,7 +215,10 @@ __global__ __launch_bounds__(S4_THREADS) void k_sweep4(Sweep4Args a)
 #pragma unroll
                     for (int z = 0; z < C; ++z)
 #pragma unroll
-                        for (int e = 0; e < C; ++e) F4 += vox4(cnt[x][y][z][e], EA, EB, LQ);
+                        for (int e = 0; e < C; ++e) {
+                            F4 += vox4(ordered4(cnt[x][y][z][e]), EA, EB, LQ);
+                            if ((((x * C + y) * C + z) * C + e) % 81 == 80) F4 = ordered4(F4);
+                        }
 #pragma unroll
             for (int s1 = 0; s1 < C; ++s1)
 #pragma unroll
@@ -217,10 +233,16 @@ __global__ __launch_bounds__(S4_THREADS) void k_sweep4(Sweep4Args a)
                             sc += cnt[s1][s2][o][s3];   // over l: (i, j, m)
                             se += cnt[s1][s2][s3][o];   // over m: (i, j, l)
                         }
-                        Fjlm += vox4(sa, EA, EB, LQ);
-                        Film += vox4(sb, EA, EB, LQ);
-                        Fijm += vox4(sc, EA, EB, LQ);
-                        Fijl += vox4(se, EA, EB, LQ);
+                        Fjlm += vox4(ordered4(sa), EA, EB, LQ);
+                        Film += vox4(ordered4(sb), EA, EB, LQ);
+                        Fijm += vox4(ordered4(sc), EA, EB, LQ);
+                        Fijl += vox4(ordered4(se), EA, EB, LQ);
+                        if (((s1 * C + s2) * C + s3) % 9 == 8) {
+                            Fjlm = ordered4(Fjlm);
+                            Film = ordered4(Film);
+                            Fijm = ordered4(Fijm);
+                            Fijl = ordered4(Fijl);
+                        }
                     }
             const float igi = act ? Fjlm - F4 : -INFINITY;
             const float igj = act ? Film - F4 : -INFINITY;
