@@ -203,10 +203,11 @@ __global__ __launch_bounds__(S4_THREADS) void k_sweep4(Sweep4Args a)
             }
 
             // F of the quadruple and of its four sub-triples (the table summed over one axis).
-            // Table reads go in two groups (the quadruple's 81 voxels, then the sub-triples' 108):
-            // each group's counts pass through an ordered asm after the previous group's sum has,
-            // so the second group's reads wait for the first and the registers they hold stay
-            // fewer (210 VGPRs, two waves per SIMD, where all reads at once took 367 and one).
+            // Table reads go in groups (at three classes the quadruple's 81 voxels, then the
+            // sub-triples' voxels 36 at a time): each group's counts pass through an ordered asm
+            // after the previous group's sum has, so a group's reads wait for the one before and
+            // the registers they hold stay fewer (210 VGPRs, two waves per SIMD, where all reads
+            // at once took 367 and one).
             float F4 = 0.f, Fjlm = 0.f, Film = 0.f, Fijm = 0.f, Fijl = 0.f;
 #pragma unroll
             for (int x = 0; x < C; ++x)
