@@ -55,6 +55,15 @@ __device__ inline float vox3(uint32_t P, const float *EA, const float *EB, const
     return lq.x - lq.y * (EA[n0] + EB[n1]);
 }
 
+// A value passed through an empty volatile asm: volatile asm statements keep their program
+// order, so work that depends on the result cannot start before the asms ahead of it.
+template <class T>
+__device__ __forceinline__ T ordered3(T x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 __device__ inline float window3(float w_abs, float g)
 {
     float ag = fabsf(g);
@@ -239,78 +248,62 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
                         }
             }
 
-            // ---- full C^3 table from the leading counts, the three pair tables and marginals
+            // ---- F of the full C^3 table, one slab x at a time (x = bin of i): a slab x < W from
+            // its leading counts and the (i, j), (i, l) tables; the last slab from the (j, l)
+            // table minus the running sums S of the slabs before it.  Slab by slab, each slab's
+            // counts passing through an ordered asm after the previous slab's sum, so that only
+            // one slab's table reads are in flight and the full table is never held at once
+            // (the voxels are summed in the same order as over the full table).
             uint32_t Nil[C][C], Njl[C][C];
             full_pair<W>(pil, Mi, Ml, Nil);
             full_pair<W>(pjl, Mj, Ml, Njl);
-            uint32_t T[C][C][C];
+            uint32_t S[C][C];
 #pragma unroll
-            for (int x = 0; x < W; ++x)
+            for (int y = 0; y < C; ++y)
 #pragma unroll
-                for (int y = 0; y < W; ++y)
-#pragma unroll
-                    for (int z = 0; z < W; ++z) T[x][y][z] = cnt[x][y][z];
-#pragma unroll
-            for (int x = 0; x < W; ++x)
-#pragma unroll
-                for (int y = 0; y < W; ++y) {
-                    uint32_t s = Nij[x][y];
-#pragma unroll
-                    for (int z = 0; z < W; ++z) s -= T[x][y][z];
-                    T[x][y][W] = s;
-                }
-#pragma unroll
-            for (int x = 0; x < W; ++x)
-#pragma unroll
-                for (int z = 0; z < W; ++z) {
-                    uint32_t s = Nil[x][z];
-#pragma unroll
-                    for (int y = 0; y < W; ++y) s -= T[x][y][z];
-                    T[x][W][z] = s;
-                }
-#pragma unroll
-            for (int y = 0; y < W; ++y)
-#pragma unroll
-                for (int z = 0; z < W; ++z) {
-                    uint32_t s = Njl[y][z];
-#pragma unroll
-                    for (int x = 0; x < W; ++x) s -= T[x][y][z];
-                    T[W][y][z] = s;
-                }
-#pragma unroll
-            for (int x = 0; x < W; ++x) {
-                uint32_t s = Nil[x][W];
-#pragma unroll
-                for (int y = 0; y < W; ++y) s -= T[x][y][W];
-                T[x][W][W] = s;
-            }
-#pragma unroll
-            for (int y = 0; y < W; ++y) {
-                uint32_t s = Njl[y][W];
-#pragma unroll
-                for (int x = 0; x < W; ++x) s -= T[x][y][W];
-                T[W][y][W] = s;
-            }
-#pragma unroll
-            for (int z = 0; z < W; ++z) {
-                uint32_t s = Njl[W][z];
-#pragma unroll
-                for (int x = 0; x < W; ++x) s -= T[x][W][z];
-                T[W][W][z] = s;
-            }
-            {
-                uint32_t s = Njl[W][W];
-#pragma unroll
-                for (int x = 0; x < W; ++x) s -= T[x][W][W];
-                T[W][W][W] = s;
-            }
+                for (int z = 0; z < C; ++z) S[y][z] = 0u;
             float F3 = 0.f;
 #pragma unroll
-            for (int x = 0; x < C; ++x)
+            for (int x = 0; x < C; ++x) {
+                uint32_t sl[C][C];
+                if (x < W) {
+#pragma unroll
+                    for (int y = 0; y < W; ++y) {
+                        uint32_t s_ = Nij[x][y];
+#pragma unroll
+                        for (int z = 0; z < W; ++z) {
+                            sl[y][z] = cnt[x][y][z];
+                            s_ -= sl[y][z];
+                        }
+                        sl[y][W] = s_;
+                    }
+#pragma unroll
+                    for (int z = 0; z < W; ++z) {
+                        uint32_t s_ = Nil[x][z];
+#pragma unroll
+                        for (int y = 0; y < W; ++y) s_ -= sl[y][z];
+                        sl[W][z] = s_;
+                    }
+                    uint32_t s_ = Nil[x][W];
+#pragma unroll
+                    for (int y = 0; y < W; ++y) s_ -= sl[y][W];
+                    sl[W][W] = s_;
+#pragma unroll
+                    for (int y = 0; y < C; ++y)
+#pragma unroll
+                        for (int z = 0; z < C; ++z) S[y][z] += sl[y][z];
+                } else {
+#pragma unroll
+                    for (int y = 0; y < C; ++y)
+#pragma unroll
+                        for (int z = 0; z < C; ++z) sl[y][z] = Njl[y][z] - S[y][z];
+                }
 #pragma unroll
                 for (int y = 0; y < C; ++y)
 #pragma unroll
-                    for (int z = 0; z < C; ++z) F3 += vox3(T[x][y][z], EA, EB, LQ);
+                    for (int z = 0; z < C; ++z) F3 += vox3(ordered3(sl[y][z]), EA, EB, LQ);
+                F3 = ordered3(F3);
+            }
 
             const float igi = act ? Fjl - F3 : -INFINITY;    // gain of x_i given (x_j, x_l)
             const float igj = act ? Fil - F3 : -INFINITY;    // gain of x_j given (x_i, x_l)
