@@ -101,6 +101,10 @@ struct Sweep2Batch {
 // Swizzled LDS address of 16-byte chunk j (0..3) of tile row `row` (64 bytes per row).
 __device__ inline int lds_addr(int row, int j) { return row * KBLK + ((j ^ ((row >> 1) & 3)) << 4); }
 
+typedef float vf2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) const float lds_f32;
+typedef __attribute__((address_space(3))) const vf2 lds_f32x2;
+
 // One voxel's n h(p) from the float32 tables, int8 packing n1 << 16 | n0.
 __device__ inline float vox_term(uint32_t P, const float *EA, const float *EB, const float2 *LQ)
 {
@@ -120,25 +124,33 @@ template <int ENC, int NV>
 __device__ inline float sum_vox(const uint32_t (&P)[NV], const char *smem, const float *EA, const float *EB,
                                 const float2 *LQ)
 {
-    float F = 0.f;
     if constexpr (ENC != 0) {
         constexpr int T = ENC;
         float ea[NV], eb[NV];
-        float2 lq[NV];
+        vf2 lq[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const uint32_t a0 = P[v] & 0xffffu, a1 = P[v] >> 16;
-            ea[v] = *reinterpret_cast<const float *>(smem + a0);
-            eb[v] = *reinterpret_cast<const float *>(smem + 4 * T + a1);
-            lq[v] = *reinterpret_cast<const float2 *>(smem + 8 * T + 2 * (a0 + a1));
+            // The sweep kernels declare no static LDS (group segment size 0), so the dynamic
+            // array starts at LDS address 0 and these byte offsets are LDS addresses: each read
+            // takes its offset register as is, the table base going into the instruction's
+            // immediate offset (through `smem` every address would carry the base as one more
+            // add: 4 instead of 3 VALU instructions per voxel).
+            ea[v] = *reinterpret_cast<const lds_f32 *>((uintptr_t)a0);
+            eb[v] = *reinterpret_cast<const lds_f32 *>((uintptr_t)(4 * T + a1));
+            lq[v] = *reinterpret_cast<const lds_f32x2 *>((uintptr_t)(8 * T + 2 * (a0 + a1)));
         }
+        // summed in voxel order, starting from the first term
+        float F = lq[0].x - lq[0].y * (ea[0] + eb[0]);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) F += lq[v].x - lq[v].y * (ea[v] + eb[v]);
+        for (int v = 1; v < NV; ++v) F += lq[v].x - lq[v].y * (ea[v] + eb[v]);
+        return F;
     } else {
+        float F = vox_term(P[0], EA, EB, LQ);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) F += vox_term(P[v], EA, EB, LQ);
+        for (int v = 1; v < NV; ++v) F += vox_term(P[v], EA, EB, LQ);
+        return F;
     }
-    return F;
 }
 
 __device__ inline uint32_t dpp_xor1(uint32_t x) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false); }
@@ -811,6 +823,17 @@ __global__ __launch_bounds__(sw_waves(W) * 64, 2) __attribute__((amdgpu_waves_pe
     sweep2_run<W, SWEEP_MAX, ENC, true>(bt.p[0], &bt);
 }
 
+// The fp4 epilogue reads its tables at LDS addresses equal to their offsets in the dynamic
+// array, which holds while the kernel declares no static LDS (the dynamic array then starts at
+// address 0).  Checked once per kernel before its first launch.
+static hipError_t check_no_static_lds(const void *kern)
+{
+    hipFuncAttributes fa{};
+    hipError_t e = hipFuncGetAttributes(&fa, kern);
+    if (e != hipSuccess) return e;
+    return fa.sharedSizeBytes == 0 ? hipSuccess : hipErrorInvalidDeviceFunction;
+}
+
 // Table capacity of the fp4 layout for these class sizes (0 = does not fit any).
 static int fp4_capacity(const Problem &P)
 {
@@ -889,6 +912,17 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
     auto kern = pair_r >= 0 ? k_sweep2<W, SWEEP_PAIRS, ENC>
                             : (counts_out ? k_sweep2<W, SWEEP_MAX, ENC, true>
                                           : (four ? k_sweep2<W, SWEEP_MAX, ENC, false, 4> : k_sweep2<W, SWEEP_MAX, ENC>));
+    if constexpr (ENC != 0) {
+        static const hipError_t lds_ok = [] {
+            for (const void *k : {(const void *)k_sweep2<W, SWEEP_PAIRS, ENC>, (const void *)k_sweep2<W, SWEEP_MAX, ENC, true>,
+                                  (const void *)k_sweep2<W, SWEEP_MAX, ENC, false, 4>, (const void *)k_sweep2<W, SWEEP_MAX, ENC>}) {
+                const hipError_t e_ = check_no_static_lds(k);
+                if (e_ != hipSuccess) return e_;
+            }
+            return hipSuccess;
+        }();
+        if (lds_ok != hipSuccess) return lds_ok;
+    }
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     // no more workgroups than tile slots (each loads its tables before it takes a tile), at least
@@ -1001,6 +1035,10 @@ static hipError_t batch_launch(const Problem *const *Ps, int n, Status *queue, s
         b.pref[i + 1] = b.pref[i] + b.p[i].n_super;
     }
     auto kern = k_sweep2_batch<W, ENC>;
+    if constexpr (ENC != 0) {
+        static const hipError_t lds_ok = check_no_static_lds((const void *)kern);
+        if (lds_ok != hipSuccess) return lds_ok;
+    }
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int grid = Ps[0]->workgroups > 0 ? Ps[0]->workgroups : XCDS * WG_PER_XCD;

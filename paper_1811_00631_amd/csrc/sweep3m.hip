@@ -101,20 +101,27 @@ __device__ inline int64_t uniform64(int64_t x)
 // Sum of n h(p) over NV packed counts (4 n1) << 16 | 4 n0 with the fixed LDS table layout of
 // capacity T (EA at 0, EB at 4T, (L, Q) pairs at 8T); a packed 0 contributes exactly 0.
 template <int T, int NV>
-__device__ inline float vox_sum(const uint32_t (&P)[NV], const char *tab)
+__device__ inline float vox_sum(const uint32_t (&P)[NV])
 {
+    typedef float vf2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) const float lds_f32;
+    typedef __attribute__((address_space(3))) const vf2 lds_f32x2;
     float ea[NV], eb[NV];
-    float2 lq[NV];
+    vf2 lq[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const uint32_t a0 = P[v] & 0xffffu, a1 = P[v] >> 16;
-        ea[v] = *reinterpret_cast<const float *>(tab + a0);
-        eb[v] = *reinterpret_cast<const float *>(tab + 4 * T + a1);
-        lq[v] = *reinterpret_cast<const float2 *>(tab + 8 * T + 2 * (a0 + a1));
+        // The triple sweeps declare no static LDS (group segment size 0; the launch checks it),
+        // so the tables at the start of the dynamic array sit at LDS address 0 and these byte
+        // offsets are their addresses: no base add per read.
+        ea[v] = *reinterpret_cast<const lds_f32 *>((uintptr_t)a0);
+        eb[v] = *reinterpret_cast<const lds_f32 *>((uintptr_t)(4 * T + a1));
+        lq[v] = *reinterpret_cast<const lds_f32x2 *>((uintptr_t)(8 * T + 2 * (a0 + a1)));
     }
-    float F = 0.f;
+    // summed in voxel order, starting from the first term
+    float F = lq[0].x - lq[0].y * (ea[0] + eb[0]);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) F += lq[v].x - lq[v].y * (ea[v] + eb[v]);
+    for (int v = 1; v < NV; ++v) F += lq[v].x - lq[v].y * (ea[v] + eb[v]);
     return F;
 }
 
@@ -400,7 +407,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
             uint32_t V0[7], V1[7];
 #pragma unroll
             for (int k = 0; k < 7; ++k) { V0[k] = V[k]; V1[k] = V[7 + k]; }
-            const float f = vox_sum<T, 7>(V0, smem) + vox_sum<T, 7>(V1, smem);
+            const float f = vox_sum<T, 7>(V0) + vox_sum<T, 7>(V1);
             return f + swap1f(f);
         };
 
@@ -726,7 +733,7 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
             V[5] = Bj - V[3];                           // T101
             V[6] = (Ml[n] - Nil[n]) - V[3];             // T110
             V[7] = (Ni1 - Bj) - V[6];                   // T111
-            return vox_sum<T, 8>(V, smem);
+            return vox_sum<T, 8>(V);
         };
 
         // One pass, row by row (block row m: the j(m, x) of the lane's q): the row's (j, l) pair
@@ -926,6 +933,19 @@ hipError_t m3_launch(const Problem &P, int r0, int nr, bool collect, int32_t *co
     constexpr int nwv = 4;
     auto kern = W == 1 ? (counts_out ? k_sweep3m1<T, true, nwv> : k_sweep3m1<T, false, nwv>)
                        : (counts_out ? k_sweep3m<T, true> : k_sweep3m<T>);
+    // the epilogue's table reads take LDS addresses equal to their offsets in the dynamic array:
+    // no static LDS may come before it
+    static const hipError_t lds_ok = [] {
+        for (const void *k : {(const void *)k_sweep3m1<T, true, nwv>, (const void *)k_sweep3m1<T, false, nwv>,
+                              (const void *)k_sweep3m<T, true>, (const void *)k_sweep3m<T>}) {
+            hipFuncAttributes fa{};
+            const hipError_t e_ = hipFuncGetAttributes(&fa, k);
+            if (e_ != hipSuccess) return e_;
+            if (fa.sharedSizeBytes != 0) return hipErrorInvalidDeviceFunction;
+        }
+        return hipSuccess;
+    }();
+    if (lds_ok != hipSuccess) return lds_ok;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(P.workgroups > 0 ? P.workgroups : 512), dim3(nwv * 64), lds, P.stream, a);
