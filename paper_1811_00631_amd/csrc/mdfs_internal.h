@@ -9,6 +9,7 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <initializer_list>
 #include <vector>
 
 namespace mdfs {
@@ -152,6 +153,39 @@ __host__ __device__ inline void lex_unrank(uint64_t r, int m, int64_t n, int *c)
 
 // Tie tolerance of the argmax: candidates within tau of the maximum are tied.
 __host__ __device__ inline double tie_tau(double m) { return 1e-9 * (fabs(m) > 1.0 ? fabs(m) : 1.0); }
+
+// n h(p) of one voxel from the entropy tables of the bitset sweeps, which lay EA, EB and the
+// (L, Q) pairs out in that order at the start of their dynamic LDS array.  P4 = (4 n1) << 16 |
+// 4 n0 (the packed count shifted left by 2) holds the counts' byte offsets in its halves; each
+// class has fewer than 16384 objects, as the entropy tables of every sweep must fit in LDS.  The
+// array sits at LDS address 0 when the kernel declares no static LDS (checked at launch by
+// lds_array_at_zero), so 4 n0 is the address of EA[n0]; EB and the pairs follow at byte offsets
+// offB and offL: five VALU instructions per voxel with the shift, where indexing the tables by
+// n0, n1 and n takes seven.
+__device__ inline float vox_lds(uint32_t P4, uint32_t offB, uint32_t offL)
+{
+    typedef float vf2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) const float lds_f32;
+    typedef __attribute__((address_space(3))) const vf2 lds_f32x2;
+    const uint32_t a0 = P4 & 0xffffu, a1 = P4 >> 16;
+    const float ea = *reinterpret_cast<const lds_f32 *>((uintptr_t)a0);
+    const float eb = *reinterpret_cast<const lds_f32 *>((uintptr_t)(offB + a1));
+    const vf2 lq = *reinterpret_cast<const lds_f32x2 *>((uintptr_t)(offL + 2 * (a0 + a1)));
+    return lq.x - lq.y * (ea + eb);
+}
+
+// hipSuccess when none of the kernels declares static LDS, so that each one's dynamic LDS array
+// starts at LDS address 0 (what vox_lds and the fp4 sweeps' table reads rely on).
+inline hipError_t lds_array_at_zero(std::initializer_list<const void *> kernels)
+{
+    for (const void *k : kernels) {
+        hipFuncAttributes fa{};
+        const hipError_t e = hipFuncGetAttributes(&fa, k);
+        if (e != hipSuccess) return e;
+        if (fa.sharedSizeBytes != 0) return hipErrorInvalidDeviceFunction;
+    }
+    return hipSuccess;
+}
 
 // First of the `mine` consecutive candidate slots of this lane: an exclusive prefix sum of the
 // lanes' counts and one device-scope atomic per wave for the wave's total (every lane of the

@@ -823,17 +823,6 @@ __global__ __launch_bounds__(sw_waves(W) * 64, 2) __attribute__((amdgpu_waves_pe
     sweep2_run<W, SWEEP_MAX, ENC, true>(bt.p[0], &bt);
 }
 
-// The fp4 epilogue reads its tables at LDS addresses equal to their offsets in the dynamic
-// array, which holds while the kernel declares no static LDS (the dynamic array then starts at
-// address 0).  Checked once per kernel before its first launch.
-static hipError_t check_no_static_lds(const void *kern)
-{
-    hipFuncAttributes fa{};
-    hipError_t e = hipFuncGetAttributes(&fa, kern);
-    if (e != hipSuccess) return e;
-    return fa.sharedSizeBytes == 0 ? hipSuccess : hipErrorInvalidDeviceFunction;
-}
-
 // Table capacity of the fp4 layout for these class sizes (0 = does not fit any).
 static int fp4_capacity(const Problem &P)
 {
@@ -913,14 +902,10 @@ static hipError_t sweep_launch(const Problem &P, int32_t *counts_out, int disc_s
                             : (counts_out ? k_sweep2<W, SWEEP_MAX, ENC, true>
                                           : (four ? k_sweep2<W, SWEEP_MAX, ENC, false, 4> : k_sweep2<W, SWEEP_MAX, ENC>));
     if constexpr (ENC != 0) {
-        static const hipError_t lds_ok = [] {
-            for (const void *k : {(const void *)k_sweep2<W, SWEEP_PAIRS, ENC>, (const void *)k_sweep2<W, SWEEP_MAX, ENC, true>,
-                                  (const void *)k_sweep2<W, SWEEP_MAX, ENC, false, 4>, (const void *)k_sweep2<W, SWEEP_MAX, ENC>}) {
-                const hipError_t e_ = check_no_static_lds(k);
-                if (e_ != hipSuccess) return e_;
-            }
-            return hipSuccess;
-        }();
+        // the fp4 epilogue reads its tables at LDS addresses equal to their array offsets
+        static const hipError_t lds_ok =
+            lds_array_at_zero({(const void *)k_sweep2<W, SWEEP_PAIRS, ENC>, (const void *)k_sweep2<W, SWEEP_MAX, ENC, true>,
+                               (const void *)k_sweep2<W, SWEEP_MAX, ENC, false, 4>, (const void *)k_sweep2<W, SWEEP_MAX, ENC>});
         if (lds_ok != hipSuccess) return lds_ok;
     }
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1036,7 +1021,7 @@ static hipError_t batch_launch(const Problem *const *Ps, int n, Status *queue, s
     }
     auto kern = k_sweep2_batch<W, ENC>;
     if constexpr (ENC != 0) {
-        static const hipError_t lds_ok = check_no_static_lds((const void *)kern);
+        static const hipError_t lds_ok = lds_array_at_zero({(const void *)kern});
         if (lds_ok != hipSuccess) return lds_ok;
     }
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

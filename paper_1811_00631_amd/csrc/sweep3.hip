@@ -48,13 +48,6 @@ struct Sweep3Args {
 // CU), else 4
 __host__ __device__ constexpr int s3_threads(int W) { return W == 1 ? 512 : 256; }
 
-__device__ inline float vox3(uint32_t P, const float *EA, const float *EB, const float2 *LQ)
-{
-    const uint32_t n0 = P & 0xffffu, n1 = P >> 16;
-    const float2 lq = LQ[n0 + n1];
-    return lq.x - lq.y * (EA[n0] + EB[n1]);
-}
-
 // A value passed through an empty volatile asm: volatile asm statements keep their program
 // order, so work that depends on the result cannot start before the asms ahead of it.
 template <class T>
@@ -123,6 +116,9 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
     for (int i = t; i <= a.N1; i += s3_threads(W)) EB[i] = a.EB[i];
     for (int i = t; i <= a.N; i += s3_threads(W)) LQ[i] = a.LQ[i];
     __syncthreads();
+    // byte offsets of EB and of the (L, Q) pairs from the start of the array (EA)
+    const uint32_t offB = 4u * (uint32_t)(a.N0 + 1);
+    const uint32_t offL = (uint32_t)(reinterpret_cast<char *>(LQ) - reinterpret_cast<char *>(EA));
 
     const int64_t plane = a.p_pad * W;                 // u32 per bitset word plane
 
@@ -301,7 +297,7 @@ __global__ __launch_bounds__(s3_threads(W), W == 1 ? 8 : 1) void k_sweep3(Sweep3
 #pragma unroll
                 for (int y = 0; y < C; ++y)
 #pragma unroll
-                    for (int z = 0; z < C; ++z) F3 += vox3(ordered3(sl[y][z]), EA, EB, LQ);
+                    for (int z = 0; z < C; ++z) F3 += vox_lds(ordered3(sl[y][z] << 2), offB, offL);
                 F3 = ordered3(F3);
             }
 
@@ -372,6 +368,9 @@ static hipError_t sweep3_launch(const Problem &P, int r0, int nr, bool collect, 
     a.cancel = P.cancel;
     size_t lds = sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (L.N + 1) + 16;
     auto kern = counts_out ? k_sweep3<W, true> : k_sweep3<W>;
+    // the epilogue addresses EA by its offset in the dynamic LDS array: no static LDS before it
+    static const hipError_t lds_ok = lds_array_at_zero({(const void *)k_sweep3<W, true>, (const void *)k_sweep3<W>});
+    if (lds_ok != hipSuccess) return lds_ok;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     // resident waves per SIMD: 8 at W = 1 (4 workgroups of 8 waves per CU), 5-6 at W = 2 (6 of

@@ -935,16 +935,9 @@ hipError_t m3_launch(const Problem &P, int r0, int nr, bool collect, int32_t *co
                        : (counts_out ? k_sweep3m<T, true> : k_sweep3m<T>);
     // the epilogue's table reads take LDS addresses equal to their offsets in the dynamic array:
     // no static LDS may come before it
-    static const hipError_t lds_ok = [] {
-        for (const void *k : {(const void *)k_sweep3m1<T, true, nwv>, (const void *)k_sweep3m1<T, false, nwv>,
-                              (const void *)k_sweep3m<T, true>, (const void *)k_sweep3m<T>}) {
-            hipFuncAttributes fa{};
-            const hipError_t e_ = hipFuncGetAttributes(&fa, k);
-            if (e_ != hipSuccess) return e_;
-            if (fa.sharedSizeBytes != 0) return hipErrorInvalidDeviceFunction;
-        }
-        return hipSuccess;
-    }();
+    static const hipError_t lds_ok =
+        lds_array_at_zero({(const void *)k_sweep3m1<T, true, nwv>, (const void *)k_sweep3m1<T, false, nwv>,
+                           (const void *)k_sweep3m<T, true>, (const void *)k_sweep3m<T>});
     if (lds_ok != hipSuccess) return lds_ok;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

@@ -41,13 +41,6 @@ struct Sweep4Args {
 
 constexpr int S4_THREADS = 256;
 
-__device__ inline float vox4(uint32_t P, const float *EA, const float *EB, const float2 *LQ)
-{
-    const uint32_t n0 = P & 0xffffu, n1 = P >> 16;
-    const float2 lq = LQ[n0 + n1];
-    return lq.x - lq.y * (EA[n0] + EB[n1]);
-}
-
 // A value passed through an empty volatile asm: volatile asm statements keep their program
 // order, so work that depends on the result cannot start before the asms ahead of it.
 template <class T>
@@ -115,6 +108,9 @@ __global__ __launch_bounds__(S4_THREADS) void k_sweep4(Sweep4Args a)
     for (int x = t; x <= a.N1; x += S4_THREADS) EB[x] = a.EB[x];
     for (int x = t; x <= a.N; x += S4_THREADS) LQ[x] = a.LQ[x];
     __syncthreads();
+    // byte offsets of EB and of the (L, Q) pairs from the start of the array (EA, LDS address 0)
+    const uint32_t offB = 4u * (uint32_t)(a.N0 + 1);
+    const uint32_t offL = (uint32_t)(reinterpret_cast<char *>(LQ) - reinterpret_cast<char *>(EA));
 
     const int64_t plane = a.p_pad * W;   // u32 per bitset word plane
     const uint32_t *bits1 = a.bits + ((int64_t)a.r * 2 + 1) * a.words_max * plane;
@@ -217,7 +213,7 @@ __global__ __launch_bounds__(S4_THREADS) void k_sweep4(Sweep4Args a)
                     for (int z = 0; z < C; ++z)
 #pragma unroll
                         for (int e = 0; e < C; ++e) {
-                            F4 += vox4(ordered4(cnt[x][y][z][e]), EA, EB, LQ);
+                            F4 += vox_lds(ordered4(cnt[x][y][z][e] << 2), offB, offL);
                             if ((((x * C + y) * C + z) * C + e) % 81 == 80) F4 = ordered4(F4);
                         }
 #pragma unroll
@@ -234,10 +230,10 @@ __global__ __launch_bounds__(S4_THREADS) void k_sweep4(Sweep4Args a)
                             sc += cnt[s1][s2][o][s3];   // over l: (i, j, m)
                             se += cnt[s1][s2][s3][o];   // over m: (i, j, l)
                         }
-                        Fjlm += vox4(ordered4(sa), EA, EB, LQ);
-                        Film += vox4(ordered4(sb), EA, EB, LQ);
-                        Fijm += vox4(ordered4(sc), EA, EB, LQ);
-                        Fijl += vox4(ordered4(se), EA, EB, LQ);
+                        Fjlm += vox_lds(ordered4(sa << 2), offB, offL);
+                        Film += vox_lds(ordered4(sb << 2), offB, offL);
+                        Fijm += vox_lds(ordered4(sc << 2), offB, offL);
+                        Fijl += vox_lds(ordered4(se << 2), offB, offL);
                         if (((s1 * C + s2) * C + s3) % 9 == 8) {
                             Fjlm = ordered4(Fjlm);
                             Film = ordered4(Film);
@@ -313,6 +309,9 @@ hipError_t sweep4_launch(const Problem &P, int r, bool collect)
     a.cancel = P.cancel;
     const size_t lds = sizeof(float) * (size_t)(P.N0 + 1 + P.N1 + 1 + 1) + sizeof(float2) * (L.N + 1) + 16;
     auto kern = k_sweep4<W>;
+    // the epilogue addresses EA by its offset in the dynamic LDS array: no static LDS before it
+    static const hipError_t lds_ok = lds_array_at_zero({(const void *)kern});
+    if (lds_ok != hipSuccess) return lds_ok;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(P.workgroups > 0 ? 2 * P.workgroups : 1024), dim3(S4_THREADS), lds, P.stream, a);

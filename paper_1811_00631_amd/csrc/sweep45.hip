@@ -51,13 +51,6 @@ struct Sweep45Args {
 
 constexpr int S45_THREADS = 256;
 
-__device__ inline float vox45(uint32_t P, const float *EA, const float *EB, const float2 *LQ)
-{
-    const uint32_t n0 = P & 0xffffu, n1 = P >> 16;
-    const float2 lq = LQ[n0 + n1];
-    return lq.x - lq.y * (EA[n0] + EB[n1]);
-}
-
 // A value passed through an empty volatile asm: volatile asm statements keep their program
 // order, so work that depends on the result cannot start before the asms ahead of it.
 template <class T>
@@ -131,6 +124,9 @@ __global__ __launch_bounds__(S45_THREADS) void k_sweep45(Sweep45Args a)
     for (int x = t; x <= a.N1; x += S45_THREADS) EB[x] = a.EB[x];
     for (int x = t; x <= a.N; x += S45_THREADS) LQ[x] = a.LQ[x];
     __syncthreads();
+    // byte offsets of EB and of the (L, Q) pairs from the start of the array (EA, LDS address 0)
+    const uint32_t offB = 4u * (uint32_t)(a.N0 + 1);
+    const uint32_t offL = (uint32_t)(reinterpret_cast<char *>(LQ) - reinterpret_cast<char *>(EA));
 
     const int64_t plane = a.p_pad;       // u32 per bitset word plane
     const uint32_t *bits1 = a.bits + ((int64_t)a.r * 2 + 1) * a.words_max * plane;
@@ -270,7 +266,7 @@ __global__ __launch_bounds__(S45_THREADS) void k_sweep45(Sweep45Args a)
             float FK = 0.f;
 #pragma unroll
             for (int s = 0; s < NC; ++s) {
-                FK += vox45(ordered(g[s]), EA, EB, LQ);
+                FK += vox_lds(ordered(g[s] << 2), offB, offL);
                 if ((s & 7) == 7) FK = ordered(FK);
             }
             float ig[K];
@@ -280,7 +276,7 @@ __global__ __launch_bounds__(S45_THREADS) void k_sweep45(Sweep45Args a)
 #pragma unroll
                 for (int h = 0; h < NC / 2; ++h) {
                     const int lo = h & ((1 << b) - 1), s = ((h >> b) << (b + 1)) | lo;   // bit b clear
-                    Fp += vox45(ordered(g[s] + g[s | (1 << b)]), EA, EB, LQ);
+                    Fp += vox_lds(ordered((g[s] + g[s | (1 << b)]) << 2), offB, offL);
                     if ((h & 7) == 7) Fp = ordered(Fp);
                 }
                 ig[b] = act ? Fp - FK : -INFINITY;
@@ -374,6 +370,9 @@ hipError_t sweep45_launch(const Problem &P, int r, bool collect)
     const size_t lds = sweep45_lds_bytes(P);
     a.tw_off = (int)sweep45_tables_bytes(P);
     auto kern = k_sweep45<K>;
+    // the epilogue addresses EA by its offset in the dynamic LDS array: no static LDS before it
+    static const hipError_t lds_ok = lds_array_at_zero({(const void *)kern});
+    if (lds_ok != hipSuccess) return lds_ok;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(P.workgroups > 0 ? 2 * P.workgroups : 1024), dim3(S45_THREADS), lds, P.stream, a);
