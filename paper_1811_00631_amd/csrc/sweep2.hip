@@ -81,6 +81,8 @@ struct Sweep2Args {
     int r_base;              // first discretisation of this launch
     int snext_off;           // LDS byte offset of the work-item broadcast slot
     uint32_t *ptab;          // pair mode: packed (W x W) counts [r - r_base][p_pad][p_pad][W*W]
+    int pair_x4;             // pair mode: store (4 n1) << 16 | 4 n0 (the matrix-core triple
+                             // sweeps' form) instead of n1 << 16 | n0
     float *F2out;            // pair mode: float32 F of each pair table [r - r_base][p_pad][p_pad]
     const uint32_t *cancel;  // caller's cancel word (nullable)
 };
@@ -516,7 +518,7 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
                         const int64_t pc = (int64_t)(r - a.r_base) * a.p_pad * a.p_pad + rv * a.p_pad + cv;
                         uint32_t *o = a.ptab + pc * (W * W);
 #pragma unroll
-                        for (int x = 0; x < 4; ++x) o[x * W + b] = dec(vx[x]);
+                        for (int x = 0; x < 4; ++x) o[x * W + b] = a.pair_x4 ? dec(vx[x]) << 2 : dec(vx[x]);
                         if (b == 0) a.F2out[pc] = F2;
                     }
                     continue;
@@ -695,7 +697,10 @@ __device__ __forceinline__ void sweep2_run(Sweep2Args a, const Sweep2Batch *bt)
 #pragma unroll
                         for (int x = 0; x < W; ++x)
 #pragma unroll
-                            for (int y = 0; y < W; ++y) o[x * W + y] = F4 ? tab[x][y] >> 2 : tab[x][y];
+                            for (int y = 0; y < W; ++y) {
+                                const uint32_t v = F4 ? tab[x][y] >> 2 : tab[x][y];   // n1 << 16 | n0
+                                o[x * W + y] = a.pair_x4 ? v << 2 : v;
+                            }
                         a.F2out[pc] = F2;
                     }
                     continue;
@@ -874,6 +879,7 @@ static Sweep2Args sweep_args(const Problem &P, int32_t *counts_out, int disc_sel
     a.n_super = a.super_per_r * (pair_r >= 0 ? pair_nr : L.R);
     a.r_base = pair_r >= 0 ? pair_r : 0;
     a.ptab = pair_r >= 0 ? P.at<uint32_t>(L.ptab) : nullptr;
+    a.pair_x4 = pair_r >= 0 && P.k3_mfma ? 1 : 0;
     a.F2out = pair_r >= 0 ? P.at<float>(L.F2) : nullptr;
     a.G32 = P.at<uint32_t>(L.G32);
     a.cand = P.at<Cand>(L.cand);

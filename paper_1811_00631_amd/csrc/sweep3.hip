@@ -398,9 +398,11 @@ hipError_t launch_sweep3(const Problem &P, int r0, int nr, bool collect, int32_t
 // other cell follows exactly from the three pair tables of the same discretisation (their W x W
 // counts in the workspace, completed from the marginals) by subtracting the cells already known
 // along one axis, the same relations the sweeps use.  One thread per (j, l), i_sel < j < l.
+// The pair counts are n1 << 16 | n0 shifted left by pshift (2 when the matrix-core triple sweep
+// is their reader).
 template <int C>
 __global__ __launch_bounds__(256) void k_complete_triples(int32_t *counts, const uint32_t *ptab, const uint32_t *marg,
-                                                          int r, int i_sel, int64_t p, int64_t p_pad)
+                                                          int r, int i_sel, int64_t p, int64_t p_pad, int pshift)
 {
     constexpr int W = C - 1;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -415,7 +417,7 @@ __global__ __launch_bounds__(256) void k_complete_triples(int32_t *counts, const
         auto pair = [&](int64_t a_, int64_t b_, int32_t (&n)[C][C]) {
             const uint32_t *pw = ptab + (a_ * p_pad + b_) * (W * W);
             for (int x = 0; x < W; ++x)
-                for (int y = 0; y < W; ++y) n[x][y] = part(pw[x * W + y]);
+                for (int y = 0; y < W; ++y) n[x][y] = part(pw[x * W + y] >> pshift);
             for (int x = 0; x < W; ++x) {
                 int32_t s = part(M[a_ * C + x]);
                 for (int y = 0; y < W; ++y) s -= n[x][y];
@@ -478,10 +480,14 @@ hipError_t launch_complete_triples(const Problem &P, int32_t *counts, int r, int
     const dim3 grid((unsigned)((n + 255) / 256));
     const uint32_t *ptab = P.at<uint32_t>(P.L.ptab) + (int64_t)(r - r0) * P.L.p_pad * P.L.p_pad * P.L.W * P.L.W;
     const uint32_t *marg = P.at<uint32_t>(P.L.marg);
+    const int pshift = P.k3_mfma ? 2 : 0;   // the pair sweep's stored form for that engine
     switch (P.L.C) {
-    case 2: hipLaunchKernelGGL(k_complete_triples<2>, grid, dim3(256), 0, P.stream, counts, ptab, marg, r, i_sel, P.L.p, P.L.p_pad); break;
-    case 3: hipLaunchKernelGGL(k_complete_triples<3>, grid, dim3(256), 0, P.stream, counts, ptab, marg, r, i_sel, P.L.p, P.L.p_pad); break;
-    case 5: hipLaunchKernelGGL(k_complete_triples<5>, grid, dim3(256), 0, P.stream, counts, ptab, marg, r, i_sel, P.L.p, P.L.p_pad); break;
+    case 2: hipLaunchKernelGGL(k_complete_triples<2>, grid, dim3(256), 0, P.stream, counts, ptab, marg, r, i_sel, P.L.p, P.L.p_pad,
+                               pshift); break;
+    case 3: hipLaunchKernelGGL(k_complete_triples<3>, grid, dim3(256), 0, P.stream, counts, ptab, marg, r, i_sel, P.L.p, P.L.p_pad,
+                               pshift); break;
+    case 5: hipLaunchKernelGGL(k_complete_triples<5>, grid, dim3(256), 0, P.stream, counts, ptab, marg, r, i_sel, P.L.p, P.L.p_pad,
+                               pshift); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

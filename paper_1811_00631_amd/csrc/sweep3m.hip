@@ -37,7 +37,9 @@ constexpr int M3_NSTAGE = 2;   // operand stages, fetched one K block ahead (3 s
 
 struct Sweep3mArgs {
     const int8_t *onehot;
-    const uint32_t *ptab;    // [nr][p_pad][p_pad][W*W] packed (n1 << 16 | n0) W x W counts of pairs
+    const uint32_t *ptab;    // [nr][p_pad][p_pad][W*W] packed ((4 n1) << 16 | 4 n0: byte offsets
+                             // of the tables, as the pair sweep stores them for this engine)
+                             // W x W counts of pairs
     const float *F2;         // [nr][p_pad][p_pad] float32 F of pairs
     int64_t ptab_stride, f2_stride;   // elements per discretisation of ptab and F2
     const uint32_t *marg;    // [R][p_pad][3]
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(M3_THREADS, 2) void k_sweep3m(Sweep3mArgs a)
         auto pair4 = [&](uint32_t uv, uint32_t (&d)[4]) {
             const v4i pw = ld128(rsP, 16u * uv);
 #pragma unroll
-            for (int x = 0; x < 4; ++x) d[x] = repack((uint32_t)pw[x]);
+            for (int x = 0; x < 4; ++x) d[x] = (uint32_t)pw[x];
         };
         uint32_t Mi[3];
 #pragma unroll
@@ -701,7 +703,7 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
         for (int n = 0; n < NN; ++n) {
             const int l = lv[n];
             Ml[n] = repack(margr[(uint32_t)l * C]);
-            Nil[n] = repack(ld32(rsP, io + lo4[n]));
+            Nil[n] = ld32(rsP, io + lo4[n]);
             Fil[n] = ldf(rsF, io + lo4[n]);
             gL_read[n] = key_f32(a.G32[l]);
         }
@@ -716,7 +718,7 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
                 const int j = jvar(m, x);
                 d.jo[x] = (uint32_t)j * pp4;
                 d.Mj[x] = repack(margr[(uint32_t)j * C]);
-                d.Nij[x] = repack(ld32(rsP, io + 4u * (uint32_t)j));
+                d.Nij[x] = ld32(rsP, io + 4u * (uint32_t)j);
                 d.F[x] = ldf(rsF, io + 4u * (uint32_t)j);
                 d.g[x] = key_f32(a.G32[j]);
             }
@@ -762,7 +764,7 @@ __global__ __launch_bounds__(NWV * 64, 2) void k_sweep3m1(Sweep3mArgs a)
 #pragma unroll
                 for (int x = 0; x < 4; ++x) {
                     const uint32_t o = jd.jo[x] + lo4[n];
-                    Njl[n][x] = repack(ld32(rsP, o));
+                    Njl[n][x] = ld32(rsP, o);
                     Fjlr[n][x] = ldf(rsF, o);
                 }
 #pragma unroll
@@ -1026,7 +1028,8 @@ hipError_t launch_tiles3(const Problem &P)
 // (v >= p) included, while the pair sweep writes u < v < p only.  This fills in the rest so that
 // whatever three variables a tile slot names, its derived counts are counts of real variables
 // (non-negative and at most the class sizes), and the epilogue need not mask them: below the
-// diagonal the transpose, on it the variable against itself (M_u(a) where a = b, else 0), and for
+// diagonal the transpose, on it the variable against itself (4 M_u(a) where a = b, else 0: the
+// counts are stored as byte offsets, (4 n1) << 16 | 4 n0, for this engine), and for
 // a padding variable, whose one-hot rows are zero (every object in the last bin), zeros, with the
 // class sizes in the last bin of its marginals.  One launch per chunk of discretisations, for the
 // two-class kernel (8.5% faster without its masks); the three-class one keeps its masks (1.7%
@@ -1050,7 +1053,7 @@ __global__ __launch_bounds__(256) void k_square_pairs(uint32_t *ptab, uint32_t *
 #pragma unroll
             for (int x = 0; x < W; ++x)
 #pragma unroll
-                for (int y = 0; y < W; ++y) dst[x * W + y] = x == y ? m[x] : 0u;
+                for (int y = 0; y < W; ++y) dst[x * W + y] = x == y ? m[x] << 2 : 0u;
         } else {
             const uint32_t *src = ptab + ((rr * p_pad + v) * p_pad + u) * (W * W);
 #pragma unroll
