@@ -66,3 +66,24 @@ def test_random_shape_matches_oracle(mdfs_gpu, case):
     got = [t.cpu().numpy() for t in got]
     ref = oracle.max_ig_all(w.data, w.y, k, div, n_disc, rng, xi, seed, n_threads=8)
     assert_ig_parity(*got, ref, name)
+
+
+# The bitset engines keep EA, EB and the (L, Q) pairs (16 N bytes) at the start of their LDS
+# array and address them by byte offsets of the counts; near the largest object count whose
+# tables fit in LDS (the pair sweep's int8 layout bounds N at about 7000) those offsets are
+# largest.  Unbalanced classes, so that both per-class tables are long.
+LARGE_N = [(3, 4, 8), (4, 1, 9), (4, 2, 8), (5, 1, 8)]
+
+
+@pytest.mark.parametrize("k,div,n_var", LARGE_N, ids=[f"k{k}_d{d + 1}" for k, d, _ in LARGE_N])
+def test_bitset_engines_at_large_n(mdfs_gpu, k, div, n_var):
+    n_obj, ones = 6800, 2900
+    w = dataclasses.replace(workloads.null_data(77 + k + div, n_obj, n_var, ones=ones), divisions=div, n_disc=1,
+                            xi=0.25, range_=0.5, seed=77)
+    print(f"large N k={k} d={div + 1} N={n_obj} p={n_var} ones={ones}", flush=True)
+    data, y = to_dev(w)
+    got = mdfs_gpu.mdfs_max_ig(data, y, k, div, 1, 0.25, 0.5, 77, 0, engine="bitset")
+    torch.cuda.synchronize()
+    got = [t.cpu().numpy() for t in got]
+    ref = oracle.max_ig_all(w.data, w.y, k, div, 1, 0.5, 0.25, 77, n_threads=8)
+    assert_ig_parity(*got, ref, f"large N k={k} d={div + 1}")
