@@ -822,10 +822,15 @@ __global__ __launch_bounds__(NWV * 64, 2) __attribute__((amdgpu_waves_per_eu(NWV
     sweep2_run<W, MODE, ENC, false, EXPORT, NWV>(a, nullptr);
 }
 
+// Waves per workgroup of the fused batch sweep: 4 for every class count.  With three classes the
+// batch path needs a few more registers than 128, so 8-wave workgroups would fit one per CU; 4-wave
+// ones (64 x 64 outputs per wave) fit two, as the LDS allows.
+__host__ __device__ constexpr int batch_waves(int) { return 4; }
+
 template <int W, int ENC>
-__global__ __launch_bounds__(sw_waves(W) * 64, 2) __attribute__((amdgpu_waves_per_eu(sw_waves(W) / 2, sw_waves(W) / 2))) void k_sweep2_batch(Sweep2Batch bt)
+__global__ __launch_bounds__(batch_waves(W) * 64, 2) __attribute__((amdgpu_waves_per_eu(batch_waves(W) / 2, batch_waves(W) / 2))) void k_sweep2_batch(Sweep2Batch bt)
 {
-    sweep2_run<W, SWEEP_MAX, ENC, true>(bt.p[0], &bt);
+    sweep2_run<W, SWEEP_MAX, ENC, true, false, batch_waves(W)>(bt.p[0], &bt);
 }
 
 // Table capacity of the fp4 layout for these class sizes (0 = does not fit any).
@@ -1033,7 +1038,7 @@ static hipError_t batch_launch(const Problem *const *Ps, int n, Status *queue, s
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int grid = Ps[0]->workgroups > 0 ? Ps[0]->workgroups : XCDS * WG_PER_XCD;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sw_waves(W) * 64), lds, Ps[0]->stream, b);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(batch_waves(W) * 64), lds, Ps[0]->stream, b);
     return hipGetLastError();
 }
 
